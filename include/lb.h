@@ -1,0 +1,248 @@
+/*
+ * lb.h -- C ABI of the load-balanced sparse library for AMD MI355X (gfx950).
+ *
+ * The library implements the load-balancing programming model of Osama,
+ * Porumbescu and Owens, "A Programming Model for GPU Load Balancing"
+ * (PPoPP'23): a sparse matrix is a tile set whose tiles are rows and whose
+ * work atoms are nonzeros (Sec. 3.1, Sec. 4.1 CSR listing); a schedule maps
+ * tiles and atoms to GPU threads (Sec. 3.2, Sec. 4.2, Sec. 5.2); the
+ * computation consumes the per-thread ranges (Sec. 3.3, Sec. 4.3).  The
+ * computation offered here is CSR sparse matrix-vector product y = A x
+ * (Sec. 1, Sec. 4.3 SpMV listing), its multi-right-hand-side form Y = A X
+ * (Sec. 5.3 SpMM listing), its backward pass, and a batched form.
+ *
+ * Conventions for every entry point:
+ *  - Device buffers, the workspace and the stream are owned by the caller.
+ *    The library allocates no device memory in these calls and keeps no
+ *    device state between them.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls are asynchronous on `stream` unless stated otherwise.
+ *  - Index arrays are int32.  rows + nnz must stay below 2^31 - 1 (merge-path
+ *    coordinates are int32); larger inputs return LB_ERR_OVERFLOW.
+ *  - Every host-checkable precondition is checked before any launch; on
+ *    error nothing is launched and the outputs are untouched.
+ *  - Device-only preconditions (row_offsets[0] == 0, non-decreasing,
+ *    row_offsets[rows] == nnz, 0 <= col_idx < cols) are not checked by the
+ *    compute calls; violating them is undefined behaviour.  lb_validate_csr
+ *    checks them (synchronously) for debugging.
+ *  - Errors are status codes; nothing throws across this boundary.
+ */
+#ifndef LB_H
+#define LB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LB_ABI_VERSION 1
+#define LB_API __attribute__((visibility("default")))
+
+typedef enum lb_status_t {
+    LB_OK = 0,
+    LB_ERR_INVALID_ARG = 1,          /* null pointer with nonzero extent, negative size, bad field */
+    LB_ERR_UNSUPPORTED = 2,          /* dtype / schedule / parameter combination not built */
+    LB_ERR_OVERFLOW = 3,             /* rows + nnz (or a batch's totals) exceed int32 coordinates */
+    LB_ERR_WORKSPACE_TOO_SMALL = 4,  /* workspace_bytes below lb_workspace_size() */
+    LB_ERR_HIP = 5,                  /* a HIP call or launch failed; see lb_last_hip_error() */
+    LB_ERR_INVALID_CSR = 6           /* lb_validate_csr found a violated device-only precondition */
+} lb_status_t;
+
+/* Element types.  LB_BF16 buffers hold bfloat16 bit patterns (the upper 16
+ * bits of an IEEE binary32).  LB_F64 is declared for the ABI but not built. */
+typedef enum lb_dtype_t { LB_F32 = 0, LB_BF16 = 1, LB_F64 = 2 } lb_dtype_t;
+
+/* Schedules (Sec. 4.2, Sec. 5.2).  One identifier selects one (Sec. 6.2). */
+typedef enum lb_sched_kind_t {
+    LB_THREAD_MAPPED = 0,  /* tile r -> one thread, grid-stride over tiles (Sec. 4.2 listing) */
+    LB_GROUP_MAPPED = 1,   /* tiles -> groups of G lanes (Sec. 5.2.2, Sec. 5.2.3) */
+    LB_MERGE_PATH = 2,     /* rows + nnz split evenly over threads (Sec. 5.2.1) */
+    LB_AUTO = 3            /* heuristic of Sec. 6.2 (alpha = 500, beta = 10000), or a tuned pick */
+} lb_sched_kind_t;
+
+/* A CSR matrix in device memory (Sec. 4.1): row_offsets[rows + 1],
+ * col_idx[nnz], values[nnz] of value_dtype.  row_offsets may be NULL only
+ * when rows == 0; col_idx and values may be NULL only when nnz == 0. */
+typedef struct lb_csr_t {
+    int64_t rows;
+    int64_t cols;
+    int64_t nnz;
+    const int32_t *row_offsets;
+    const int32_t *col_idx;
+    const void *values;
+    lb_dtype_t value_dtype;
+} lb_csr_t;
+
+/* Schedule parameters.  A zero field takes the default noted.
+ *  group_size        LB_GROUP_MAPPED: lanes per group, a power of two in
+ *                    [1, 1024] (default 64, one wavefront).
+ *  tiles_per_group   LB_GROUP_MAPPED: 1 = one tile per group at a time, lanes
+ *                    stride its atoms (Sec. 5.2.2); equal to group_size = the
+ *                    group takes that many tiles, prefix-sums their sizes in
+ *                    LDS and its lanes walk the flattened atoms, each finding
+ *                    its tile by binary search (Sec. 5.2.3).  Default 1.
+ *  items_per_thread  LB_MERGE_PATH: merge items (row ends + nonzeros) per
+ *                    thread, one of 4, 8, 12, 16 (default 8).
+ *  block_size        threads per block: thread-mapped 64..1024 (default 256);
+ *                    merge-path one of 128, 256, 512 (default 256);
+ *                    group-mapped derived from group_size (ignored).
+ *  grid_size         blocks; 0 = one block per chunk of work. */
+typedef struct lb_schedule_t {
+    lb_sched_kind_t kind;
+    int32_t group_size;
+    int32_t tiles_per_group;
+    int32_t items_per_thread;
+    int32_t block_size;
+    int32_t grid_size;
+} lb_schedule_t;
+
+/* Independent CSR matrices stored back to back (a block-diagonal matrix).
+ *  row_offsets   int32[total_rows + 1]: the block-diagonal matrix's offsets
+ *                into the concatenated nonzeros (matrix b's rows occupy
+ *                [mat_row_base[b], mat_row_base[b+1])).
+ *  col_idx       int32[total_nnz], local to each matrix: in [0, n_b).
+ *  values        total_nnz elements of value_dtype.
+ *  mat_row_base, mat_nnz_base, mat_col_base: int64[count + 1] device arrays,
+ *                prefix sums of m_b, nnz_b and n_b (first entry 0).
+ *  The host-side totals duplicate the last prefix entries so the library
+ *  can size work without reading device memory. */
+typedef struct lb_batch_t {
+    int64_t count;
+    int64_t total_rows;
+    int64_t total_cols;
+    int64_t total_nnz;
+    const int32_t *row_offsets;
+    const int32_t *col_idx;
+    const void *values;
+    lb_dtype_t value_dtype;
+    const int64_t *mat_row_base;
+    const int64_t *mat_nnz_base;
+    const int64_t *mat_col_base;
+} lb_batch_t;
+
+/* Version of this header the library was built from (LB_ABI_VERSION). */
+LB_API int lb_abi_version(void);
+
+/* Static, human-readable text for a status code. */
+LB_API const char *lb_status_string(lb_status_t status);
+
+/* Text of the most recent HIP failure on the calling thread ("" if none). */
+LB_API const char *lb_last_hip_error(void);
+
+/* Resolve LB_AUTO and zero fields of *in into concrete parameters for the
+ * matrix A and k right-hand sides.  Host-only; reads no device memory.
+ * LB_AUTO follows Sec. 6.2: merge-path unless (rows < 500 or cols < 500) and
+ * nnz < 10000, in which case thread-mapped when the mean row length is below
+ * 8, else group-mapped with the next power of two of the mean row length
+ * (at most 64) as group size.  A schedule stored by lb_autotune for the same
+ * matrix shape takes precedence. */
+LB_API lb_status_t lb_resolve_schedule(const lb_csr_t *A, int32_t k, const lb_schedule_t *in,
+                                       lb_schedule_t *out);
+
+/* Device workspace bytes that lb_spmv (k == 1), lb_spmm (k >= 1) or
+ * lb_spmv_backward (k == 0) need for A under schedule s.  Host-only. */
+LB_API lb_status_t lb_workspace_size(const lb_csr_t *A, const lb_schedule_t *s, int32_t k,
+                                     size_t *bytes);
+
+/* y = A x (Sec. 1; Sec. 4.3 SpMV listing).  x: cols elements of x_dtype
+ * (must equal A->value_dtype); y: rows float32, overwritten (rows with no
+ * nonzeros get 0).  Products and sums are float32 for both input types.
+ * For a fixed schedule the result is bit-reproducible run to run (no
+ * atomics).  workspace: device memory of at least lb_workspace_size(A, s, 1)
+ * bytes (may be NULL when that is 0), contents on entry irrelevant. */
+LB_API lb_status_t lb_spmv(const lb_csr_t *A, const void *x, lb_dtype_t x_dtype, float *y,
+                           const lb_schedule_t *s, void *workspace, size_t workspace_bytes,
+                           void *stream);
+
+/* Y = A X with k right-hand sides (Sec. 5.3 SpMM listing, reading its
+ * B(nz, col) as B(col_idx[nz], col)).  X row-major cols x k with leading
+ * dimension ldx >= k; Y row-major rows x k float32 with ldy >= k,
+ * overwritten.  1 <= k <= 64.  Same numerics and workspace rules as lb_spmv
+ * (workspace from lb_workspace_size(A, s, k)). */
+LB_API lb_status_t lb_spmm(const lb_csr_t *A, const void *X, lb_dtype_t x_dtype, int32_t k,
+                           int64_t ldx, float *Y, int64_t ldy, const lb_schedule_t *s,
+                           void *workspace, size_t workspace_bytes, void *stream);
+
+/* Backward of y = A x.  dx = A^T dy (cols float32, zeroed by the call and
+ * accumulated with float atomics: not bit-reproducible) and
+ * dvalues[j] = dy[row(j)] * x[col_idx[j]] (nnz float32, a single rounding
+ * of the exact product).  Either output may be NULL to skip it.  x is read
+ * only for dvalues.  Runs over the merge-path split of A (s->kind must be
+ * LB_MERGE_PATH or LB_AUTO); workspace from lb_workspace_size(A, s, 0). */
+LB_API lb_status_t lb_spmv_backward(const lb_csr_t *A, const void *x, lb_dtype_t x_dtype,
+                                    const float *dy, float *dx, float *dvalues,
+                                    const lb_schedule_t *s, void *workspace,
+                                    size_t workspace_bytes, void *stream);
+
+/* Workspace bytes for lb_batched_spmm with k right-hand sides.  Host-only. */
+LB_API lb_status_t lb_batched_workspace_size(const lb_batch_t *B, const lb_schedule_t *s,
+                                             int32_t k, size_t *bytes);
+
+/* For every matrix b of the batch, Y_b = A_b X_b.  X holds the matrices'
+ * right-hand sides back to back, row-major total_cols x k; Y row-major
+ * total_rows x k float32, overwritten.  All matrices run in one persistent
+ * launch over a single merge path of sum(m_b + nnz_b) items (Sec. 5.1
+ * persistent ranges), followed by one carry fix-up launch.  s->kind must be
+ * LB_MERGE_PATH or LB_AUTO.  1 <= k <= 64. */
+LB_API lb_status_t lb_batched_spmm(const lb_batch_t *B, const void *X, lb_dtype_t x_dtype,
+                                   int32_t k, float *Y, const lb_schedule_t *s, void *workspace,
+                                   size_t workspace_bytes, void *stream);
+
+/* The merge-path split (Sec. 5.2.1): for t in [0, num_units], the number of
+ * row ends out_row[t] and of nonzeros out_nz[t] that precede diagonal
+ * d_t = min(t * items_per_unit, rows + nnz) of the merge of the row-end list
+ * row_offsets[1..rows] with the nonzero indices 0..nnz-1, where row end r is
+ * taken before nonzero j when row_offsets[r+1] <= j.  Device arrays;
+ * out_row/out_nz hold num_units + 1 int32 each. */
+LB_API lb_status_t lb_merge_path_partition(const int32_t *row_offsets, int64_t rows, int64_t nnz,
+                                           int64_t items_per_unit, int64_t num_units,
+                                           int32_t *out_row, int32_t *out_nz, void *stream);
+
+/* Group-mapped tile lookup (Sec. 5.2.3 get_tile): for groups of
+ * tiles_per_group consecutive tiles of A, write for every nonzero j the
+ * index, within its group, of the tile that owns it, found by binary search
+ * in the group's LDS prefix sum of tile sizes.  owner: nnz int32, device.
+ * tiles_per_group must be a power of two in [2, 1024]. */
+LB_API lb_status_t lb_group_tile_owner(const lb_csr_t *A, int32_t tiles_per_group, int32_t *owner,
+                                       void *stream);
+
+/* Time candidate schedules for A with k right-hand sides on `stream`
+ * (synchronizing) using the caller's x/X, y/Y and workspace (at least
+ * lb_autotune_workspace_size bytes), store the fastest in a process-wide
+ * cache keyed by (rows, cols, nnz, k, dtype) that lb_resolve_schedule
+ * consults for LB_AUTO, and return it in *best.  If the environment variable
+ * LB_AUTOTUNE_CACHE names a file, the cache is loaded from and saved to it. */
+LB_API lb_status_t lb_autotune_workspace_size(const lb_csr_t *A, int32_t k, size_t *bytes);
+LB_API lb_status_t lb_autotune(const lb_csr_t *A, const void *X, lb_dtype_t x_dtype, int32_t k,
+                               float *Y, void *workspace, size_t workspace_bytes,
+                               lb_schedule_t *best, void *stream);
+
+/* Same for a batch (merge-path items_per_thread and block_size). */
+LB_API lb_status_t lb_batched_autotune(const lb_batch_t *B, const void *X, lb_dtype_t x_dtype,
+                                       int32_t k, float *Y, void *workspace,
+                                       size_t workspace_bytes, lb_schedule_t *best, void *stream);
+
+/* Forget every tuned schedule (process-wide). */
+LB_API void lb_autotune_clear(void);
+
+/* Debug check of the device-only CSR preconditions; synchronizes `stream`.
+ * Returns LB_OK or LB_ERR_INVALID_CSR. */
+LB_API lb_status_t lb_validate_csr(const lb_csr_t *A, void *stream);
+
+/* Kernel timing.  While enabled, every launch made by this library records a
+ * pair of HIP events on its stream.  lb_profile_read synchronizes those
+ * events and returns, for the kernel family `name` ("merge_partition",
+ * "merge_consume", "merge_fixup", "thread_mapped", "group_mapped",
+ * "backward", "batched_consume", "batched_fixup", "fill"), the summed
+ * duration in milliseconds and the launch count since the last reset. */
+LB_API void lb_profile_enable(int on);
+LB_API void lb_profile_reset(void);
+LB_API lb_status_t lb_profile_read(const char *name, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LB_H */

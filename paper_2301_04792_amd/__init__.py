@@ -1,0 +1,361 @@
+"""Load-balanced sparse kernels for AMD MI355X (gfx950).
+
+Python binding of liblb.so (include/lb.h): argument marshalling only.  Every
+step of the computation runs in the library's HIP kernels; PyTorch provides
+device memory and the current stream.  Importing this package loads the
+library and fails if it is missing.
+
+    A = CSR(row_offsets, col_idx, values, shape)     # device tensors
+    y = spmv(A, x, schedule="merge_path")            # or thread_mapped / group_mapped / auto
+    Y = spmm(A, X)                                   # X: cols x k, row-major
+    y = SpMV.apply(values, x, pattern, "merge_path") # differentiable in values and x
+    Y = batched_spmm(batch, X)                       # one persistent launch
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import LBError  # noqa: F401
+
+_lib = _abi.load()
+
+__all__ = ["CSR", "Pattern", "Batch", "spmv", "spmm", "spmv_backward", "SpMV", "spmv_diff",
+           "batched_spmm", "tune", "tune_batched", "merge_path_partition", "group_tile_owner",
+           "validate", "resolve_schedule", "profile_enable", "profile_reset", "profile_read", "LBError"]
+
+_DT = {torch.float32: _abi.F32, torch.bfloat16: _abi.BF16, torch.float64: _abi.F64}
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    try:
+        return _DT[t.dtype]
+    except KeyError:
+        raise TypeError(f"unsupported element type {t.dtype}") from None
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(device: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def make_schedule(schedule="merge_path", group_size=0, tiles_per_group=0, items_per_thread=0,
+                  block_size=0, grid_size=0) -> _abi.Schedule:
+    if isinstance(schedule, _abi.Schedule):
+        return schedule
+    kind = _abi.KIND_BY_NAME[schedule] if isinstance(schedule, str) else int(schedule)
+    return _abi.Schedule(kind, group_size, tiles_per_group, items_per_thread, block_size, grid_size)
+
+
+class Pattern:
+    """Sparsity pattern of a CSR matrix: int32 row_offsets[m+1], col_idx[nnz]."""
+
+    def __init__(self, row_offsets: torch.Tensor, col_idx: torch.Tensor, shape):
+        if row_offsets.dtype != torch.int32 or col_idx.dtype != torch.int32:
+            raise TypeError("row_offsets and col_idx must be int32")
+        self.row_offsets = row_offsets.contiguous()
+        self.col_idx = col_idx.contiguous()
+        self.shape = (int(shape[0]), int(shape[1]))
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col_idx.numel())
+
+    @property
+    def device(self):
+        return self.row_offsets.device
+
+    def with_values(self, values: torch.Tensor) -> "CSR":
+        return CSR(self.row_offsets, self.col_idx, values, self.shape)
+
+
+class CSR(Pattern):
+    """A CSR matrix in device memory (values float32 or bfloat16)."""
+
+    def __init__(self, row_offsets, col_idx, values, shape):
+        super().__init__(row_offsets, col_idx, shape)
+        self.values = values.contiguous()
+        if self.values.numel() != self.col_idx.numel():
+            raise ValueError("values and col_idx differ in length")
+        if self.row_offsets.numel() != self.shape[0] + 1:
+            raise ValueError("row_offsets must hold rows + 1 entries")
+
+    @classmethod
+    def from_host(cls, host, device="cuda", dtype=torch.float32) -> "CSR":
+        """From a host CSR (numpy arrays row_offsets, col_idx, values, shape)."""
+        vals = host.values
+        if vals.dtype == np.uint16:  # BF16 bit patterns
+            v = torch.from_numpy(vals.view(np.int16).copy()).view(torch.bfloat16)
+        else:
+            v = torch.from_numpy(np.ascontiguousarray(vals)).to(dtype)
+        return cls(torch.from_numpy(np.ascontiguousarray(host.row_offsets)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(host.col_idx)).to(device),
+                   v.to(device), host.shape)
+
+    def c_struct(self) -> _abi.CSR:
+        return _abi.CSR(self.shape[0], self.shape[1], self.nnz, self.row_offsets.data_ptr(),
+                        self.col_idx.data_ptr(), self.values.data_ptr(), _dtype_code(self.values))
+
+    @property
+    def pattern(self) -> Pattern:
+        return Pattern(self.row_offsets, self.col_idx, self.shape)
+
+
+def _workspace(nbytes: int, device, workspace=None):
+    if nbytes == 0:
+        return None
+    if workspace is not None:
+        if workspace.numel() * workspace.element_size() < nbytes:
+            raise ValueError(f"workspace too small: need {nbytes} bytes")
+        return workspace
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+def resolve_schedule(A: CSR, schedule="merge_path", k: int = 1, **params) -> dict:
+    s = make_schedule(schedule, **params)
+    out = _abi.Schedule()
+    _abi.check(_lib.lb_resolve_schedule(ctypes.byref(A.c_struct()), k, ctypes.byref(s), ctypes.byref(out)),
+               "lb_resolve_schedule")
+    return out.as_dict()
+
+
+def workspace_size(A: CSR, schedule="merge_path", k: int = 1, **params) -> int:
+    s = make_schedule(schedule, **params)
+    n = ctypes.c_size_t(0)
+    _abi.check(_lib.lb_workspace_size(ctypes.byref(A.c_struct()), ctypes.byref(s), k, ctypes.byref(n)),
+               "lb_workspace_size")
+    return int(n.value)
+
+
+def spmv(A: CSR, x: torch.Tensor, schedule="merge_path", y: torch.Tensor | None = None,
+         workspace: torch.Tensor | None = None, **params) -> torch.Tensor:
+    """y = A x (float32 y)."""
+    if x.dim() != 1 or x.numel() != A.shape[1]:
+        raise ValueError("x must be a vector of length cols")
+    x = x.contiguous()
+    s = make_schedule(schedule, **params)
+    c = A.c_struct()
+    n = ctypes.c_size_t(0)
+    _abi.check(_lib.lb_workspace_size(ctypes.byref(c), ctypes.byref(s), 1, ctypes.byref(n)), "lb_workspace_size")
+    if y is None:
+        y = torch.empty(A.shape[0], dtype=torch.float32, device=A.device)
+    ws = _workspace(n.value, A.device, workspace)
+    _abi.check(_lib.lb_spmv(ctypes.byref(c), _ptr(x), _dtype_code(x), _ptr(y), ctypes.byref(s), _ptr(ws),
+                            n.value, _stream(A.device)), "lb_spmv")
+    return y
+
+
+def spmm(A: CSR, X: torch.Tensor, schedule="merge_path", Y: torch.Tensor | None = None,
+         workspace: torch.Tensor | None = None, **params) -> torch.Tensor:
+    """Y = A X with X row-major (cols x k); Y float32 (rows x k)."""
+    if X.dim() != 2 or X.shape[0] != A.shape[1]:
+        raise ValueError("X must be cols x k")
+    if X.stride(1) != 1:
+        X = X.contiguous()
+    k = int(X.shape[1])
+    s = make_schedule(schedule, **params)
+    c = A.c_struct()
+    n = ctypes.c_size_t(0)
+    _abi.check(_lib.lb_workspace_size(ctypes.byref(c), ctypes.byref(s), k, ctypes.byref(n)), "lb_workspace_size")
+    if Y is None:
+        Y = torch.empty((A.shape[0], k), dtype=torch.float32, device=A.device)
+    ws = _workspace(n.value, A.device, workspace)
+    _abi.check(_lib.lb_spmm(ctypes.byref(c), _ptr(X), _dtype_code(X), k, X.stride(0), _ptr(Y), Y.stride(0),
+                            ctypes.byref(s), _ptr(ws), n.value, _stream(A.device)), "lb_spmm")
+    return Y
+
+
+def spmv_backward(A: CSR, x: torch.Tensor, dy: torch.Tensor, need_dx: bool = True, need_dvalues: bool = True,
+                  schedule="merge_path", **params):
+    """(dx, dvalues) of y = A x: dx = A^T dy, dvalues[j] = dy[row(j)] x[col(j)] (float32)."""
+    dy = dy.contiguous().to(torch.float32)
+    x = x.contiguous()
+    s = make_schedule(schedule, **params)
+    c = A.c_struct()
+    n = ctypes.c_size_t(0)
+    _abi.check(_lib.lb_workspace_size(ctypes.byref(c), ctypes.byref(s), 0, ctypes.byref(n)), "lb_workspace_size")
+    dx = torch.empty(A.shape[1], dtype=torch.float32, device=A.device) if need_dx else None
+    dv = torch.empty(A.nnz, dtype=torch.float32, device=A.device) if need_dvalues else None
+    ws = _workspace(max(n.value, 1), A.device)
+    _abi.check(_lib.lb_spmv_backward(ctypes.byref(c), _ptr(x), _dtype_code(x), _ptr(dy), _ptr(dx), _ptr(dv),
+                                     ctypes.byref(s), _ptr(ws), max(n.value, 1), _stream(A.device)),
+               "lb_spmv_backward")
+    return dx, dv
+
+
+class SpMV(torch.autograd.Function):
+    """y = A(values) x, differentiable in values and x.
+
+    forward: lb_spmv with the given schedule; backward: lb_spmv_backward
+    (dx = A^T dy by merge-path scatter, dvalues = dy[row] * x[col])."""
+
+    @staticmethod
+    def forward(ctx, values, x, pattern: Pattern, schedule="merge_path"):
+        A = pattern.with_values(values)
+        y = spmv(A, x, schedule)
+        ctx.save_for_backward(values, x)
+        ctx.pattern = pattern
+        return y
+
+    @staticmethod
+    def backward(ctx, dy):
+        values, x = ctx.saved_tensors
+        A = ctx.pattern.with_values(values)
+        need_dv, need_dx = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        dx, dv = spmv_backward(A, x, dy, need_dx=need_dx, need_dvalues=need_dv)
+        if dv is not None and dv.dtype != values.dtype:
+            dv = dv.to(values.dtype)
+        if dx is not None and dx.dtype != x.dtype:
+            dx = dx.to(x.dtype)
+        return dv, dx, None, None
+
+
+def spmv_diff(pattern: Pattern, values: torch.Tensor, x: torch.Tensor, schedule="merge_path") -> torch.Tensor:
+    return SpMV.apply(values, x, pattern, schedule)
+
+
+class Batch:
+    """Independent CSR matrices stored back to back (see lb_batch_t)."""
+
+    def __init__(self, row_offsets, col_idx, values, mat_row_base, mat_nnz_base, mat_col_base):
+        self.row_offsets = row_offsets.contiguous()
+        self.col_idx = col_idx.contiguous()
+        self.values = values.contiguous()
+        self.mat_row_base = mat_row_base.to(torch.int64).contiguous()
+        self.mat_nnz_base = mat_nnz_base.to(torch.int64).contiguous()
+        self.mat_col_base = mat_col_base.to(torch.int64).contiguous()
+        rb = self.mat_row_base.cpu()
+        self.count = int(rb.numel() - 1)
+        self.total_rows = int(rb[-1])
+        self.total_cols = int(self.mat_col_base[-1].item())
+        self.total_nnz = int(self.mat_nnz_base[-1].item())
+
+    @classmethod
+    def from_host(cls, host, device="cuda", dtype=torch.float32) -> "Batch":
+        vals = host.values
+        if vals.dtype == np.uint16:
+            v = torch.from_numpy(vals.view(np.int16).copy()).view(torch.bfloat16)
+        else:
+            v = torch.from_numpy(np.ascontiguousarray(vals)).to(dtype)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)  # noqa: E731
+        return cls(t(host.row_offsets), t(host.col_idx), v.to(device), t(host.mat_row_base),
+                   t(host.mat_nnz_base), t(host.mat_col_base))
+
+    @property
+    def device(self):
+        return self.row_offsets.device
+
+    def c_struct(self) -> _abi.Batch:
+        return _abi.Batch(self.count, self.total_rows, self.total_cols, self.total_nnz,
+                          self.row_offsets.data_ptr(), self.col_idx.data_ptr(), self.values.data_ptr(),
+                          _dtype_code(self.values), self.mat_row_base.data_ptr(), self.mat_nnz_base.data_ptr(),
+                          self.mat_col_base.data_ptr())
+
+
+def batched_spmm(batch: Batch, X: torch.Tensor, schedule="auto", Y=None, workspace=None, **params):
+    """Y_b = A_b X_b for every matrix; X is total_cols x k (or a vector for k = 1)."""
+    vec = X.dim() == 1
+    X2 = X.reshape(-1, 1) if vec else X
+    if X2.shape[0] != batch.total_cols:
+        raise ValueError("X must have total_cols rows")
+    X2 = X2.contiguous()
+    k = int(X2.shape[1])
+    s = make_schedule(schedule, **params)
+    c = batch.c_struct()
+    n = ctypes.c_size_t(0)
+    _abi.check(_lib.lb_batched_workspace_size(ctypes.byref(c), ctypes.byref(s), k, ctypes.byref(n)),
+               "lb_batched_workspace_size")
+    if Y is None:
+        Y = torch.empty((batch.total_rows, k), dtype=torch.float32, device=batch.device)
+    ws = _workspace(n.value, batch.device, workspace)
+    _abi.check(_lib.lb_batched_spmm(ctypes.byref(c), _ptr(X2), _dtype_code(X2), k, _ptr(Y), ctypes.byref(s),
+                                    _ptr(ws), n.value, _stream(batch.device)), "lb_batched_spmm")
+    return Y.reshape(-1) if vec else Y
+
+
+def tune(A: CSR, k: int = 1) -> dict:
+    """Time the candidate schedules on A (k right-hand sides), remember the
+    fastest for schedule="auto", and return it."""
+    n = ctypes.c_size_t(0)
+    c = A.c_struct()
+    _abi.check(_lib.lb_autotune_workspace_size(ctypes.byref(c), k, ctypes.byref(n)), "lb_autotune_workspace_size")
+    X = torch.rand((A.shape[1], k), device=A.device).to(A.values.dtype)
+    Y = torch.empty((A.shape[0], k), dtype=torch.float32, device=A.device)
+    ws = _workspace(max(n.value, 1), A.device)
+    best = _abi.Schedule()
+    _abi.check(_lib.lb_autotune(ctypes.byref(c), _ptr(X), _dtype_code(X), k, _ptr(Y), _ptr(ws), max(n.value, 1),
+                                ctypes.byref(best), _stream(A.device)), "lb_autotune")
+    return best.as_dict()
+
+
+def tune_batched(batch: Batch, k: int = 1) -> dict:
+    c = batch.c_struct()
+    need = 0
+    for b in (128, 256, 512):
+        for it in (4, 8, 12, 16):
+            if b * it > 4096:
+                continue
+            n = ctypes.c_size_t(0)
+            s = make_schedule("merge_path", items_per_thread=it, block_size=b)
+            if _lib.lb_batched_workspace_size(ctypes.byref(c), ctypes.byref(s), k, ctypes.byref(n)) == _abi.OK:
+                need = max(need, n.value)
+    X = torch.rand((batch.total_cols, k), device=batch.device).to(batch.values.dtype)
+    Y = torch.empty((batch.total_rows, k), dtype=torch.float32, device=batch.device)
+    ws = _workspace(max(need, 1), batch.device)
+    best = _abi.Schedule()
+    _abi.check(_lib.lb_batched_autotune(ctypes.byref(c), _ptr(X), _dtype_code(X), k, _ptr(Y), _ptr(ws),
+                                        max(need, 1), ctypes.byref(best), _stream(batch.device)),
+               "lb_batched_autotune")
+    return best.as_dict()
+
+
+def autotune_clear():
+    _lib.lb_autotune_clear()
+
+
+def merge_path_partition(row_offsets: torch.Tensor, nnz: int, items_per_unit: int, num_units: int):
+    """(row, nz) split at diagonals min(t * items_per_unit, rows + nnz), t in [0, num_units]."""
+    rows = row_offsets.numel() - 1
+    oi = torch.empty(num_units + 1, dtype=torch.int32, device=row_offsets.device)
+    oj = torch.empty(num_units + 1, dtype=torch.int32, device=row_offsets.device)
+    _abi.check(_lib.lb_merge_path_partition(_ptr(row_offsets), rows, int(nnz), int(items_per_unit), int(num_units),
+                                            _ptr(oi), _ptr(oj), _stream(row_offsets.device)),
+               "lb_merge_path_partition")
+    return oi, oj
+
+
+def group_tile_owner(A: CSR, tiles_per_group: int) -> torch.Tensor:
+    owner = torch.empty(A.nnz, dtype=torch.int32, device=A.device)
+    _abi.check(_lib.lb_group_tile_owner(ctypes.byref(A.c_struct()), int(tiles_per_group), _ptr(owner),
+                                        _stream(A.device)), "lb_group_tile_owner")
+    return owner
+
+
+def validate(A: CSR) -> bool:
+    st = _lib.lb_validate_csr(ctypes.byref(A.c_struct()), _stream(A.device))
+    if st == _abi.ERR_INVALID_CSR:
+        return False
+    _abi.check(st, "lb_validate_csr")
+    return True
+
+
+def profile_enable(on: bool = True):
+    _lib.lb_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    _lib.lb_profile_reset()
+
+
+def profile_read(name: str):
+    """(total_ms, launches) recorded for a kernel family since the last reset."""
+    ms = ctypes.c_double(0)
+    n = ctypes.c_int64(0)
+    _abi.check(_lib.lb_profile_read(name.encode(), ctypes.byref(ms), ctypes.byref(n)), "lb_profile_read")
+    return float(ms.value), int(n.value)

@@ -1,0 +1,112 @@
+// Backward of y = A x over the merge-path split, for gfx950.
+//
+//   dvalues[j] = dy[row(j)] * x[col_idx[j]]     (one product per nonzero)
+//   dx[c]     += values[j] * dy[row(j)]         (scatter: dx = A^T dy)
+//
+// Both need each nonzero's row.  Block b owns the same merge-path unit as
+// in the forward pass; its threads walk their ITEMS merge items inside the
+// LDS copy of the block's row ends and label every nonzero they pass with
+// its row (the atom -> tile map that group-mapped gets from get_tile).  The
+// block then streams its nonzeros coalesced: dvalues is written in order,
+// and dx receives hardware float atomics (atomic order varies, so dx is not
+// bit-reproducible run to run; dvalues is).
+#include "lb_device.h"
+#include "lb_internal.h"
+
+namespace lbk {
+using namespace lb;
+
+template <int BLOCK, int ITEMS, typename VT, bool WANT_DX, bool WANT_DV>
+__global__ __launch_bounds__(BLOCK) void merge_backward_kernel(
+    const int32_t *__restrict__ ro, const int32_t *__restrict__ ci, const VT *__restrict__ val,
+    const VT *__restrict__ x, const float *__restrict__ dy, float *__restrict__ dx, float *__restrict__ dvalues,
+    const int32_t *__restrict__ part_i, const int32_t *__restrict__ part_j) {
+    constexpr int W = BLOCK * ITEMS;
+    __shared__ int32_t s_buf[W];  // row ends [0, nrows), then row labels [nrows, nrows + nnzs)
+
+    const int tid = threadIdx.x;
+    const int b = blockIdx.x;
+    const int32_t i0 = part_i[b], j0 = part_j[b];
+    const int32_t i1 = part_i[b + 1], j1 = part_j[b + 1];
+    const int32_t nrows = i1 - i0, nnzs = j1 - j0;
+    int32_t *s_re = s_buf;
+    int32_t *s_row = s_buf + nrows;
+    for (int k = tid; k < nrows; k += BLOCK) s_re[k] = ro[i0 + 1 + k] - j0;
+    __syncthreads();
+
+    const int32_t total = nrows + nnzs;
+    const int32_t d = tid * ITEMS < total ? tid * ITEMS : total;
+    const int32_t dend = d + ITEMS < total ? d + ITEMS : total;
+    int32_t lo = d - nnzs > 0 ? d - nnzs : 0;
+    int32_t hi = d < nrows ? d : nrows;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (s_re[mid] + mid < d)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    int32_t it = lo, jt = d - lo;
+    for (int32_t q = d; q < dend; ++q) {
+        if (it < nrows && s_re[it] <= jt)
+            ++it;
+        else
+            s_row[jt++] = it;
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int u = 0; u < ITEMS; ++u) {
+        const int k = tid + u * BLOCK;
+        if (k < nnzs) {
+            const int64_t j = static_cast<int64_t>(j0) + k;
+            const float g = dy[i0 + s_row[k]];
+            const int32_t c = ld_stream(ci + j);
+            if constexpr (WANT_DV) dvalues[j] = g * to_f32(x[c]);
+            if constexpr (WANT_DX) unsafeAtomicAdd(dx + c, to_f32(ld_stream(val + j)) * g);
+        }
+    }
+}
+
+template <int BLOCK, int ITEMS, typename VT>
+static hipError_t run_backward(const csr_dev &A, const void *x, const float *dy, float *dx, float *dvalues, void *ws,
+                               hipStream_t s) {
+    constexpr int W = BLOCK * ITEMS;
+    const int64_t T = merge_units(A.rows, A.nnz, W);
+    merge_ws w = merge_ws_carve(ws, T);
+    hipError_t e = merge_partition(A.ro, A.rows, A.nnz, W, static_cast<int32_t>(T), w.part_i, w.part_j, s);
+    if (e != hipSuccess) return e;
+    prof_scope p(s, "backward");
+    const dim3 g(static_cast<uint32_t>(T));
+    const VT *xv = static_cast<const VT *>(x);
+    const VT *vv = static_cast<const VT *>(A.val);
+    if (dx && dvalues)
+        hipLaunchKernelGGL((merge_backward_kernel<BLOCK, ITEMS, VT, true, true>), g, dim3(BLOCK), 0, s, A.ro, A.ci, vv,
+                           xv, dy, dx, dvalues, w.part_i, w.part_j);
+    else if (dx)
+        hipLaunchKernelGGL((merge_backward_kernel<BLOCK, ITEMS, VT, true, false>), g, dim3(BLOCK), 0, s, A.ro, A.ci,
+                           vv, xv, dy, dx, dvalues, w.part_i, w.part_j);
+    else
+        hipLaunchKernelGGL((merge_backward_kernel<BLOCK, ITEMS, VT, false, true>), g, dim3(BLOCK), 0, s, A.ro, A.ci,
+                           vv, xv, dy, dx, dvalues, w.part_i, w.part_j);
+    return hipGetLastError();
+}
+
+#define LB_MERGE_CONFIGS(X) \
+    X(128, 4) X(128, 8) X(128, 12) X(128, 16) \
+    X(256, 4) X(256, 8) X(256, 12) X(256, 16) \
+    X(512, 4) X(512, 8) X(512, 12) X(512, 16)
+
+hipError_t merge_backward(const csr_dev &A, const void *x, const float *dy, float *dx, float *dvalues, int block,
+                          int items, void *ws, hipStream_t s) {
+#define X_(B, I)                                                                                 \
+    if (block == B && items == I) {                                                              \
+        if (A.dt == LB_BF16) return run_backward<B, I, bf16_bits>(A, x, dy, dx, dvalues, ws, s); \
+        return run_backward<B, I, float>(A, x, dy, dx, dvalues, ws, s);                          \
+    }
+    LB_MERGE_CONFIGS(X_)
+#undef X_
+    return hipErrorInvalidValue;
+}
+
+}  // namespace lbk

@@ -1,0 +1,241 @@
+// Merge-path SpMV for gfx950 (Sec. 5.2.1).
+//
+// Merge-path treats a row end and a nonzero as one unit of work each and
+// cuts the merged sequence of rows + nnz units into equal pieces.  With the
+// row-end list R[r] = row_offsets[r + 1] and the nonzero list N[j] = j, row
+// end r is taken before nonzero j when R[r] <= j, so row end r sits at
+// merged position r + row_offsets[r + 1]; the split at diagonal d is
+//   i(d) = #{ r : row_offsets[r + 1] + r < d },  j(d) = d - i(d).
+//
+// Three launches:
+//  1. merge_partition_kernel: the split at every unit boundary d_t = t * W
+//     (W = BLOCK * ITEMS), one wavefront per boundary doing a 64-ary search
+//     (each step, 64 lanes probe 64 evenly spaced rows and a ballot narrows
+//     the range 64-fold: about 4 steps for 2M rows instead of 21).
+//  2. merge_spmv_consume: block b owns units [d_b, d_{b+1}): rows
+//     [i_b, i_{b+1}) end in it and nonzeros [j_b, j_{b+1}) are consumed in
+//     it.  Setup stages the block's row ends and the products
+//     values[j] * x[col_idx[j]] in LDS (coalesced, non-temporal streams);
+//     each thread searches its own diagonal tid * ITEMS inside that LDS
+//     window and walks ITEMS merge items: a row end closes a row ("complete"
+//     tile), the trailing open row is its carry ("partial" tile).  A block
+//     segmented scan of the carries (wave64 shuffles + LDS across waves)
+//     supplies each thread the partial sum earlier threads hold for the first
+//     row it closes.  The block's own trailing partial goes to carry[b].
+//  3. merge_fixup: rows that cross block boundaries receive the carries of
+//     the blocks before them, summed in block order (deterministic; no
+//     atomics on y).
+#include "lb_device.h"
+#include "lb_internal.h"
+
+namespace lbk {
+using namespace lb;
+
+// ------------------------------------------------------------------ partition
+
+__global__ __launch_bounds__(256) void merge_partition_kernel(const int32_t *__restrict__ ro,
+                                                              int32_t rows, int32_t nnz, int32_t W,
+                                                              int32_t T, int32_t *__restrict__ part_i,
+                                                              int32_t *__restrict__ part_j) {
+    const int lane = lane_id();
+    const int64_t t = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+    if (t > T) return;  // whole wavefront leaves together
+    const int64_t total = static_cast<int64_t>(rows) + nnz;
+    const int64_t d64 = t * W < total ? t * W : total;
+    const int32_t d = static_cast<int32_t>(d64);
+    // The answer lies in [lo, hi]; p(r) < d for r < lo and p(r) >= d for r >= hi.
+    int32_t lo = d - nnz > 0 ? d - nnz : 0;
+    int32_t hi = d < rows ? d : rows;
+    while (hi - lo > kWave) {
+        const int32_t step = (hi - lo + kWave - 1) / kWave;
+        const int32_t r = lo + (lane + 1) * step - 1;
+        const bool below = r < hi && ro[r + 1] + r < d;  // true on a lane prefix
+        const int32_t c = __popcll(__ballot(below));
+        const int32_t nlo = lo + c * step;
+        const int32_t rc = lo + (c + 1) * step - 1;      // first probe not below d
+        hi = rc < hi ? rc : hi;
+        lo = nlo;
+    }
+    const int32_t r = lo + lane;
+    const bool below = r < hi && ro[r + 1] + r < d;
+    const int32_t i = lo + __popcll(__ballot(below));
+    if (lane == 0) {
+        part_i[t] = i;
+        part_j[t] = d - i;
+    }
+}
+
+hipError_t merge_partition(const int32_t *ro, int32_t rows, int32_t nnz, int32_t W, int32_t T,
+                           int32_t *part_i, int32_t *part_j, hipStream_t s) {
+    prof_scope p(s, "merge_partition");
+    const int64_t waves = static_cast<int64_t>(T) + 1;
+    const int64_t blocks = (waves * kWave + 255) / 256;
+    hipLaunchKernelGGL(merge_partition_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s,
+                       ro, rows, nnz, W, T, part_i, part_j);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ consume
+
+template <int BLOCK, int ITEMS, typename VT, typename XT>
+__global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
+    const int32_t *__restrict__ ro, const int32_t *__restrict__ ci, const VT *__restrict__ val,
+    const XT *__restrict__ x, float *__restrict__ y, const int32_t *__restrict__ part_i,
+    const int32_t *__restrict__ part_j, int32_t *__restrict__ carry_row, float *__restrict__ carry_val) {
+    constexpr int W = BLOCK * ITEMS;
+    __shared__ int32_t s_buf[W];  // row ends [0, nrows), then products [nrows, nrows + nnzs)
+    __shared__ seg_t s_wave[BLOCK / kWave];
+
+    const int tid = threadIdx.x;
+    const int b = blockIdx.x;
+    const int32_t i0 = part_i[b], j0 = part_j[b];
+    const int32_t i1 = part_i[b + 1], j1 = part_j[b + 1];
+    const int32_t nrows = i1 - i0, nnzs = j1 - j0;
+    int32_t *s_re = s_buf;
+    float *s_pv = reinterpret_cast<float *>(s_buf + nrows);
+
+    // Setup: row ends relative to j0 (in [0, nnzs]) and products, coalesced.
+    for (int k = tid; k < nrows; k += BLOCK) s_re[k] = ro[i0 + 1 + k] - j0;
+    int32_t c[ITEMS];
+    VT v[ITEMS];
+#pragma unroll
+    for (int u = 0; u < ITEMS; ++u) {
+        const int k = tid + u * BLOCK;
+        if (k < nnzs) {
+            c[u] = ld_stream(ci + j0 + k);
+            v[u] = ld_stream(val + j0 + k);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < ITEMS; ++u) {
+        const int k = tid + u * BLOCK;
+        if (k < nnzs) s_pv[k] = to_f32(v[u]) * to_f32(x[c[u]]);
+    }
+    __syncthreads();
+
+    // Thread diagonal inside the block's window: local row end k sits at
+    // local merged position k + s_re[k].
+    const int32_t total = nrows + nnzs;
+    const int32_t d = tid * ITEMS < total ? tid * ITEMS : total;
+    const int32_t dend = d + ITEMS < total ? d + ITEMS : total;
+    int32_t lo = d - nnzs > 0 ? d - nnzs : 0;
+    int32_t hi = d < nrows ? d : nrows;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (s_re[mid] + mid < d)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    int32_t it = lo, jt = d - lo;
+
+    // Walk: complete rows are written; the first one waits for the carry-in.
+    float acc = 0.f;
+    int32_t first = -1;
+    float first_sum = 0.f;
+    for (int32_t q = d; q < dend; ++q) {
+        if (it < nrows && s_re[it] <= jt) {
+            if (first < 0) {
+                first = it;
+                first_sum = acc;
+            } else {
+                y[i0 + it] = acc;
+            }
+            acc = 0.f;
+            ++it;
+        } else {
+            acc += s_pv[jt];
+            ++jt;
+        }
+    }
+
+    seg_t tot;
+    const seg_t in = block_seg_scan_excl<BLOCK>(seg_t{acc, first >= 0}, s_wave, tot);
+    if (first >= 0) y[i0 + first] = first_sum + in.v;
+    if (tid == 0) {
+        carry_row[b] = i1;  // the row still open at the block's end (rows if none)
+        carry_val[b] = tot.v;
+    }
+}
+
+// ------------------------------------------------------------------ fix-up
+
+// One thread per carry; the first carry of each run of equal rows adds the
+// run's sum (in block order, 16 at a time) to y[row].
+__global__ __launch_bounds__(256) void merge_fixup(int32_t T, int32_t rows, int32_t kc,
+                                                   const int32_t *__restrict__ carry_row,
+                                                   const float *__restrict__ carry_val,
+                                                   float *__restrict__ y, int64_t ldy) {
+    const int64_t b = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= T) return;
+    const int32_t r = carry_row[b];
+    if (r >= rows) return;
+    if (b > 0 && carry_row[b - 1] == r) return;
+    int64_t e = b + 1;
+    while (e < T && carry_row[e] == r) ++e;
+    for (int32_t c = 0; c < kc; ++c) {
+        float total = 0.f;
+        for (int64_t s = b; s < e; s += 16) {
+            float part = 0.f;
+            const int64_t se = s + 16 < e ? s + 16 : e;
+            for (int64_t q = s; q < se; ++q) part += carry_val[q * kc + c];
+            total += part;
+        }
+        y[static_cast<int64_t>(r) * ldy + c] += total;
+    }
+}
+
+hipError_t launch_fixup(int64_t T, int32_t rows, int32_t kc, const int32_t *carry_row,
+                        const float *carry_val, float *y, int64_t ldy, hipStream_t s, const char *tag) {
+    if (T <= 0) return hipSuccess;
+    prof_scope p(s, tag);
+    hipLaunchKernelGGL(merge_fixup, dim3(static_cast<uint32_t>((T + 255) / 256)), dim3(256), 0, s,
+                       static_cast<int32_t>(T), rows, kc, carry_row, carry_val, y, ldy);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ dispatch
+
+template <int BLOCK, int ITEMS, typename VT>
+static hipError_t run_merge_spmv(const csr_dev &A, const void *x, float *y, void *ws, hipStream_t s) {
+    constexpr int W = BLOCK * ITEMS;
+    const int64_t T = merge_units(A.rows, A.nnz, W);
+    merge_ws w = merge_ws_carve(ws, T);
+    hipError_t e = merge_partition(A.ro, A.rows, A.nnz, W, static_cast<int32_t>(T), w.part_i, w.part_j, s);
+    if (e != hipSuccess) return e;
+    {
+        prof_scope p(s, "merge_consume");
+        hipLaunchKernelGGL((merge_spmv_consume<BLOCK, ITEMS, VT, VT>), dim3(static_cast<uint32_t>(T)),
+                           dim3(BLOCK), 0, s, A.ro, A.ci, static_cast<const VT *>(A.val),
+                           static_cast<const VT *>(x), y, w.part_i, w.part_j, w.carry_row, w.carry_val);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return launch_fixup(T, A.rows, 1, w.carry_row, w.carry_val, y, 1, s, "merge_fixup");
+}
+
+#define LB_MERGE_CONFIGS(X) \
+    X(128, 4) X(128, 8) X(128, 12) X(128, 16) \
+    X(256, 4) X(256, 8) X(256, 12) X(256, 16) \
+    X(512, 4) X(512, 8) X(512, 12) X(512, 16)
+
+bool merge_config_supported(int block, int items) {
+#define X(B, I) if (block == B && items == I) return true;
+    LB_MERGE_CONFIGS(X)
+#undef X
+    return false;
+}
+
+hipError_t merge_spmv(const csr_dev &A, const void *x, float *y, int block, int items, void *ws,
+                      hipStream_t s) {
+#define X(B, I)                                                                  \
+    if (block == B && items == I) {                                              \
+        if (A.dt == LB_BF16) return run_merge_spmv<B, I, bf16_bits>(A, x, y, ws, s); \
+        return run_merge_spmv<B, I, float>(A, x, y, ws, s);                      \
+    }
+    LB_MERGE_CONFIGS(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+}  // namespace lbk

@@ -1,0 +1,664 @@
+// C ABI of the load-balanced sparse library: argument checks, schedule
+// resolution (Sec. 6.2 heuristic, tuned picks), workspace sizing, dispatch
+// to the kernel launchers, kernel timing and the autotuner.
+//
+// Every check that can be made on the host runs before the first HIP call,
+// so invalid arguments never reach the device (and can be tested without a
+// GPU).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "lb.h"
+#include "lb_internal.h"
+
+namespace {
+
+constexpr int64_t kMaxCoord = 0x7ffffffe;  // rows + nnz must stay below this (int32 merge coordinates)
+constexpr int kDefaultBlock = 256;
+constexpr int kDefaultItems = 8;
+constexpr int kDefaultGroup = 64;
+constexpr int kMaxK = 64;
+constexpr int kMaxSpmmUnit = 4096;  // SpMM / batched: block_size * items_per_thread (LDS budget)
+
+thread_local std::string g_last_hip;
+
+lb_status_t hip_status(hipError_t e) {
+    if (e == hipSuccess) return LB_OK;
+    g_last_hip = hipGetErrorString(e);
+    return LB_ERR_HIP;
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+bool dtype_built(lb_dtype_t d) { return d == LB_F32 || d == LB_BF16; }
+
+lb_status_t check_csr(const lb_csr_t *A) {
+    if (!A) return LB_ERR_INVALID_ARG;
+    if (A->rows < 0 || A->cols < 0 || A->nnz < 0) return LB_ERR_INVALID_ARG;
+    if (A->rows > 0 && !A->row_offsets) return LB_ERR_INVALID_ARG;
+    if (A->nnz > 0 && (!A->col_idx || !A->values)) return LB_ERR_INVALID_ARG;
+    if (A->nnz > 0 && A->cols == 0) return LB_ERR_INVALID_ARG;
+    if (A->value_dtype != LB_F32 && A->value_dtype != LB_BF16 && A->value_dtype != LB_F64)
+        return LB_ERR_INVALID_ARG;
+    if (!dtype_built(A->value_dtype)) return LB_ERR_UNSUPPORTED;
+    if (A->rows + A->nnz > kMaxCoord || A->cols > kMaxCoord) return LB_ERR_OVERFLOW;
+    return LB_OK;
+}
+
+lbk::csr_dev to_dev(const lb_csr_t *A) {
+    lbk::csr_dev d;
+    d.rows = static_cast<int32_t>(A->rows);
+    d.cols = static_cast<int32_t>(A->cols);
+    d.nnz = static_cast<int32_t>(A->nnz);
+    d.ro = A->row_offsets;
+    d.ci = A->col_idx;
+    d.val = A->values;
+    d.dt = A->value_dtype;
+    return d;
+}
+
+// ------------------------------------------------------------------ autotune cache
+
+struct tune_key {
+    int64_t rows, cols, nnz;
+    int32_t k;
+    int32_t dtype;
+    int32_t batched;
+    bool operator<(const tune_key &o) const {
+        return std::tie(rows, cols, nnz, k, dtype, batched) < std::tie(o.rows, o.cols, o.nnz, o.k, o.dtype, o.batched);
+    }
+};
+
+std::mutex g_tune_mu;
+std::map<tune_key, lb_schedule_t> g_tune;
+bool g_tune_loaded = false;
+
+const char *tune_path() { return std::getenv("LB_AUTOTUNE_CACHE"); }
+
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *p = tune_path();
+    if (!p || !*p) return;
+    std::ifstream f(p);
+    std::string line;
+    // one entry per line: rows cols nnz k dtype batched kind group tiles items block grid
+    while (std::getline(f, line)) {
+        std::istringstream ss(line);
+        tune_key key{};
+        lb_schedule_t s{};
+        int kind = 0;
+        if (ss >> key.rows >> key.cols >> key.nnz >> key.k >> key.dtype >> key.batched >> kind >> s.group_size >>
+            s.tiles_per_group >> s.items_per_thread >> s.block_size >> s.grid_size) {
+            s.kind = static_cast<lb_sched_kind_t>(kind);
+            g_tune[key] = s;
+        }
+    }
+}
+
+void tune_save_locked() {
+    const char *p = tune_path();
+    if (!p || !*p) return;
+    std::ofstream f(p, std::ios::trunc);
+    for (const auto &kv : g_tune) {
+        const tune_key &k = kv.first;
+        const lb_schedule_t &s = kv.second;
+        f << k.rows << ' ' << k.cols << ' ' << k.nnz << ' ' << k.k << ' ' << k.dtype << ' ' << k.batched << ' '
+          << static_cast<int>(s.kind) << ' ' << s.group_size << ' ' << s.tiles_per_group << ' '
+          << s.items_per_thread << ' ' << s.block_size << ' ' << s.grid_size << '\n';
+    }
+}
+
+bool tune_lookup(const tune_key &key, lb_schedule_t *out) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    tune_load_locked();
+    auto it = g_tune.find(key);
+    if (it == g_tune.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+void tune_store(const tune_key &key, const lb_schedule_t &s) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    tune_load_locked();
+    g_tune[key] = s;
+    tune_save_locked();
+}
+
+// ------------------------------------------------------------------ schedule checks
+
+lb_status_t fill_defaults(const lb_schedule_t *in, lb_schedule_t *out) {
+    lb_schedule_t s = *in;
+    if (s.group_size < 0 || s.tiles_per_group < 0 || s.items_per_thread < 0 || s.block_size < 0 || s.grid_size < 0)
+        return LB_ERR_INVALID_ARG;
+    switch (s.kind) {
+        case LB_THREAD_MAPPED:
+            if (s.block_size == 0) s.block_size = kDefaultBlock;
+            if (s.block_size % 64 != 0 || s.block_size > 1024) return LB_ERR_INVALID_ARG;
+            break;
+        case LB_GROUP_MAPPED:
+            if (s.group_size == 0) s.group_size = kDefaultGroup;
+            if (!is_pow2(s.group_size) || s.group_size > 1024) return LB_ERR_INVALID_ARG;
+            if (s.tiles_per_group == 0) s.tiles_per_group = 1;
+            if (s.tiles_per_group != 1 && s.tiles_per_group != s.group_size) return LB_ERR_UNSUPPORTED;
+            s.block_size = s.group_size > 64 ? s.group_size : 256;
+            break;
+        case LB_MERGE_PATH:
+            if (s.block_size == 0) s.block_size = kDefaultBlock;
+            if (s.items_per_thread == 0) s.items_per_thread = kDefaultItems;
+            if (!lbk::merge_config_supported(s.block_size, s.items_per_thread)) return LB_ERR_UNSUPPORTED;
+            break;
+        default:
+            return LB_ERR_INVALID_ARG;
+    }
+    *out = s;
+    return LB_OK;
+}
+
+// Sec. 6.2: merge-path unless (rows < alpha or cols < alpha) and nnz < beta.
+lb_schedule_t heuristic(const lb_csr_t *A) {
+    constexpr int64_t alpha = 500, beta = 10000;
+    lb_schedule_t s{};
+    if ((A->rows < alpha || A->cols < alpha) && A->nnz < beta) {
+        const double mean = A->rows ? static_cast<double>(A->nnz) / static_cast<double>(A->rows) : 0.0;
+        if (mean < 8.0) {
+            s.kind = LB_THREAD_MAPPED;
+        } else {
+            int g = 1;
+            while (g < mean && g < 64) g <<= 1;
+            s.kind = LB_GROUP_MAPPED;
+            s.group_size = g;
+            s.tiles_per_group = 1;
+        }
+    } else {
+        s.kind = LB_MERGE_PATH;
+    }
+    return s;
+}
+
+lb_status_t resolve(const lb_csr_t *A, int32_t k, const lb_schedule_t *in, lb_schedule_t *out) {
+    if (!in || !out) return LB_ERR_INVALID_ARG;
+    lb_schedule_t s = *in;
+    if (s.kind == LB_AUTO) {
+        lb_schedule_t tuned;
+        const tune_key key{A->rows, A->cols, A->nnz, k, static_cast<int32_t>(A->value_dtype), 0};
+        if (tune_lookup(key, &tuned))
+            s = tuned;
+        else
+            s = heuristic(A);
+    }
+    return fill_defaults(&s, out);
+}
+
+int spmm_pass_cols(int32_t k) { return k >= 8 ? 8 : (k >= 4 ? 4 : (k >= 2 ? 2 : 1)); }
+
+size_t ws_bytes_for(const lb_csr_t *A, const lb_schedule_t &s, int32_t k) {
+    if (s.kind != LB_MERGE_PATH) return 0;
+    const int64_t W = static_cast<int64_t>(s.block_size) * s.items_per_thread;
+    const int64_t T = lbk::merge_units(A->rows, A->nnz, W);
+    return lbk::merge_ws_bytes(T, k <= 0 ? 1 : spmm_pass_cols(k));
+}
+
+// ------------------------------------------------------------------ profiling
+
+struct prof_rec {
+    std::string name;
+    hipEvent_t start, stop;
+    bool closed;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<prof_rec> g_prof;
+
+}  // namespace
+
+namespace lbk {
+
+bool profiling_enabled() { return g_prof_on; }
+
+void profile_mark(hipStream_t s, const char *name, bool begin) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, s);
+    if (begin) {
+        g_prof.push_back({name, e, nullptr, false});
+        return;
+    }
+    for (auto it = g_prof.rbegin(); it != g_prof.rend(); ++it) {
+        if (!it->closed && it->name == name) {
+            it->stop = e;
+            it->closed = true;
+            return;
+        }
+    }
+    (void)hipEventDestroy(e);
+}
+
+}  // namespace lbk
+
+namespace {
+
+std::vector<lb_schedule_t> candidates(const lb_csr_t *A, int32_t k) {
+    std::vector<lb_schedule_t> c;
+    for (int b : {128, 256, 512})
+        for (int it : {4, 8, 12, 16})
+            if (k == 1 || b * it <= kMaxSpmmUnit) c.push_back({LB_MERGE_PATH, 0, 0, it, b, 0});
+    c.push_back({LB_THREAD_MAPPED, 0, 0, 0, 256, 0});
+    if (k == 1) {
+        for (int g : {8, 16, 32, 64, 256, 1024}) {
+            c.push_back({LB_GROUP_MAPPED, g, 1, 0, 0, 0});
+            c.push_back({LB_GROUP_MAPPED, g, g, 0, 0, 0});
+        }
+    }
+    (void)A;
+    return c;
+}
+
+template <typename F>
+lb_status_t time_call(F &&f, hipStream_t hs, float *ms_out) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return LB_ERR_HIP;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return LB_ERR_HIP;
+    }
+    lb_status_t st = f();  // warm-up
+    std::vector<float> t;
+    for (int rep = 0; rep < 5 && st == LB_OK; ++rep) {
+        (void)hipEventRecord(a, hs);
+        st = f();
+        (void)hipEventRecord(b, hs);
+        if (hipEventSynchronize(b) != hipSuccess) st = LB_ERR_HIP;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        t.push_back(ms);
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st != LB_OK) return st;
+    std::sort(t.begin(), t.end());
+    *ms_out = t[t.size() / 2];
+    return LB_OK;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+
+extern "C" {
+
+LB_API int lb_abi_version(void) { return LB_ABI_VERSION; }
+
+LB_API const char *lb_status_string(lb_status_t st) {
+    switch (st) {
+        case LB_OK: return "ok";
+        case LB_ERR_INVALID_ARG: return "invalid argument";
+        case LB_ERR_UNSUPPORTED: return "unsupported dtype, schedule or parameter";
+        case LB_ERR_OVERFLOW: return "size exceeds int32 merge coordinates";
+        case LB_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+        case LB_ERR_HIP: return "HIP error";
+        case LB_ERR_INVALID_CSR: return "CSR arrays violate a device-side precondition";
+    }
+    return "unknown status";
+}
+
+LB_API const char *lb_last_hip_error(void) { return g_last_hip.c_str(); }
+
+LB_API lb_status_t lb_resolve_schedule(const lb_csr_t *A, int32_t k, const lb_schedule_t *in, lb_schedule_t *out) {
+    lb_status_t st = check_csr(A);
+    if (st != LB_OK) return st;
+    return resolve(A, k, in, out);
+}
+
+LB_API lb_status_t lb_workspace_size(const lb_csr_t *A, const lb_schedule_t *s, int32_t k, size_t *bytes) {
+    if (!bytes || k < 0 || k > kMaxK) return LB_ERR_INVALID_ARG;
+    lb_status_t st = check_csr(A);
+    if (st != LB_OK) return st;
+    lb_schedule_t r;
+    st = resolve(A, k, s, &r);
+    if (st != LB_OK) return st;
+    if (k == 0) {  // backward always runs on the merge-path split
+        if (r.kind != LB_MERGE_PATH) {
+            lb_schedule_t m{};
+            m.kind = LB_MERGE_PATH;
+            fill_defaults(&m, &r);
+        }
+    }
+    *bytes = ws_bytes_for(A, r, k);
+    return LB_OK;
+}
+
+LB_API lb_status_t lb_spmv(const lb_csr_t *A, const void *x, lb_dtype_t x_dtype, float *y, const lb_schedule_t *s,
+                           void *workspace, size_t workspace_bytes, void *stream) {
+    lb_status_t st = check_csr(A);
+    if (st != LB_OK) return st;
+    if (A->rows > 0 && !y) return LB_ERR_INVALID_ARG;
+    if (A->nnz > 0 && !x) return LB_ERR_INVALID_ARG;
+    if (x_dtype != A->value_dtype) return LB_ERR_UNSUPPORTED;
+    lb_schedule_t r;
+    st = resolve(A, 1, s, &r);
+    if (st != LB_OK) return st;
+    const size_t need = ws_bytes_for(A, r, 1);
+    if (need > 0 && (workspace_bytes < need || !workspace)) return LB_ERR_WORKSPACE_TOO_SMALL;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    if (A->rows == 0) return LB_OK;
+    if (A->nnz == 0) return hip_status(lbk::fill_f32(y, A->rows, 0.f, hs));
+    const lbk::csr_dev d = to_dev(A);
+    switch (r.kind) {
+        case LB_THREAD_MAPPED: return hip_status(lbk::thread_mapped_spmv(d, x, y, r.block_size, r.grid_size, hs));
+        case LB_GROUP_MAPPED:
+            return hip_status(lbk::group_mapped_spmv(d, x, y, r.group_size, r.tiles_per_group, r.grid_size, hs));
+        case LB_MERGE_PATH:
+            return hip_status(lbk::merge_spmv(d, x, y, r.block_size, r.items_per_thread, workspace, hs));
+        default: return LB_ERR_INVALID_ARG;
+    }
+}
+
+LB_API lb_status_t lb_spmm(const lb_csr_t *A, const void *X, lb_dtype_t x_dtype, int32_t k, int64_t ldx, float *Y,
+                           int64_t ldy, const lb_schedule_t *s, void *workspace, size_t workspace_bytes,
+                           void *stream) {
+    lb_status_t st = check_csr(A);
+    if (st != LB_OK) return st;
+    if (k < 1 || k > kMaxK || ldx < k || ldy < k) return LB_ERR_INVALID_ARG;
+    if (A->rows > 0 && !Y) return LB_ERR_INVALID_ARG;
+    if (A->nnz > 0 && !X) return LB_ERR_INVALID_ARG;
+    if (x_dtype != A->value_dtype) return LB_ERR_UNSUPPORTED;
+    if (A->cols * ldx > (int64_t(1) << 40) || A->rows * ldy > (int64_t(1) << 40)) return LB_ERR_OVERFLOW;
+    lb_schedule_t r;
+    st = resolve(A, k, s, &r);
+    if (st != LB_OK) return st;
+    if (r.kind == LB_GROUP_MAPPED) return LB_ERR_UNSUPPORTED;
+    if (r.kind == LB_MERGE_PATH && r.block_size * r.items_per_thread > kMaxSpmmUnit) return LB_ERR_UNSUPPORTED;
+    const size_t need = ws_bytes_for(A, r, k);
+    if (need > 0 && (workspace_bytes < need || !workspace)) return LB_ERR_WORKSPACE_TOO_SMALL;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    if (A->rows == 0) return LB_OK;
+    const lbk::csr_dev d = to_dev(A);
+    if (A->nnz == 0) {
+        if (ldy == k) return hip_status(lbk::fill_f32(Y, A->rows * k, 0.f, hs));
+        // strided Y: use the thread-mapped kernel, which writes every (row, col) (rows are empty)
+        return hip_status(lbk::thread_mapped_spmm(d, X, k, ldx, Y, ldy, kDefaultBlock, 0, hs));
+    }
+    if (r.kind == LB_THREAD_MAPPED)
+        return hip_status(lbk::thread_mapped_spmm(d, X, k, ldx, Y, ldy, r.block_size, r.grid_size, hs));
+    return hip_status(lbk::merge_spmm(d, X, k, ldx, Y, ldy, r.block_size, r.items_per_thread, workspace, hs));
+}
+
+LB_API lb_status_t lb_spmv_backward(const lb_csr_t *A, const void *x, lb_dtype_t x_dtype, const float *dy, float *dx,
+                                    float *dvalues, const lb_schedule_t *s, void *workspace, size_t workspace_bytes,
+                                    void *stream) {
+    lb_status_t st = check_csr(A);
+    if (st != LB_OK) return st;
+    if (A->rows > 0 && A->nnz > 0 && !dy && (dx || dvalues)) return LB_ERR_INVALID_ARG;
+    if (dvalues && A->nnz > 0 && !x) return LB_ERR_INVALID_ARG;
+    if (x_dtype != A->value_dtype) return LB_ERR_UNSUPPORTED;
+    lb_schedule_t in = s ? *s : lb_schedule_t{LB_MERGE_PATH, 0, 0, 0, 0, 0};
+    if (in.kind == LB_AUTO) in.kind = LB_MERGE_PATH;
+    if (in.kind != LB_MERGE_PATH) return LB_ERR_UNSUPPORTED;
+    lb_schedule_t r;
+    st = fill_defaults(&in, &r);
+    if (st != LB_OK) return st;
+    const size_t need = ws_bytes_for(A, r, 0);
+    if (workspace_bytes < need || !workspace) return LB_ERR_WORKSPACE_TOO_SMALL;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    if (dx) {
+        hipError_t e = lbk::fill_f32(dx, A->cols, 0.f, hs);
+        if (e != hipSuccess) return hip_status(e);
+    }
+    if (A->nnz == 0 || (!dx && !dvalues)) return LB_OK;
+    const lbk::csr_dev d = to_dev(A);
+    return hip_status(lbk::merge_backward(d, x, dy, dx, dvalues, r.block_size, r.items_per_thread, workspace, hs));
+}
+
+// ------------------------------------------------------------------ batched
+
+static lb_status_t check_batch(const lb_batch_t *B) {
+    if (!B) return LB_ERR_INVALID_ARG;
+    if (B->count < 0 || B->total_rows < 0 || B->total_cols < 0 || B->total_nnz < 0) return LB_ERR_INVALID_ARG;
+    if (B->count > 0 && (!B->mat_row_base || !B->mat_nnz_base || !B->mat_col_base)) return LB_ERR_INVALID_ARG;
+    if (B->total_rows > 0 && !B->row_offsets) return LB_ERR_INVALID_ARG;
+    if (B->total_nnz > 0 && (!B->col_idx || !B->values)) return LB_ERR_INVALID_ARG;
+    if (B->value_dtype != LB_F32 && B->value_dtype != LB_BF16 && B->value_dtype != LB_F64) return LB_ERR_INVALID_ARG;
+    if (!dtype_built(B->value_dtype)) return LB_ERR_UNSUPPORTED;
+    if (B->total_rows + B->total_nnz > kMaxCoord || B->total_cols > kMaxCoord || B->count > kMaxCoord)
+        return LB_ERR_OVERFLOW;
+    return LB_OK;
+}
+
+static lbk::batch_dev to_dev(const lb_batch_t *B) {
+    lbk::batch_dev d;
+    d.count = static_cast<int32_t>(B->count);
+    d.total_rows = static_cast<int32_t>(B->total_rows);
+    d.total_cols = static_cast<int32_t>(B->total_cols);
+    d.total_nnz = static_cast<int32_t>(B->total_nnz);
+    d.ro = B->row_offsets;
+    d.ci = B->col_idx;
+    d.val = B->values;
+    d.dt = B->value_dtype;
+    d.row_base = B->mat_row_base;
+    d.nnz_base = B->mat_nnz_base;
+    d.col_base = B->mat_col_base;
+    return d;
+}
+
+static lb_status_t resolve_batched(const lb_batch_t *B, int32_t k, const lb_schedule_t *s, lb_schedule_t *out) {
+    lb_schedule_t in = s ? *s : lb_schedule_t{LB_AUTO, 0, 0, 0, 0, 0};
+    if (in.kind == LB_AUTO) {
+        lb_schedule_t tuned;
+        const tune_key key{B->total_rows, B->total_cols, B->total_nnz, k, static_cast<int32_t>(B->value_dtype), 1};
+        if (tune_lookup(key, &tuned))
+            in = tuned;
+        else
+            in = lb_schedule_t{LB_MERGE_PATH, 0, 0, 0, 0, 0};
+    }
+    if (in.kind != LB_MERGE_PATH) return LB_ERR_UNSUPPORTED;
+    lb_status_t st = fill_defaults(&in, out);
+    if (st == LB_OK && out->block_size * out->items_per_thread > kMaxSpmmUnit) return LB_ERR_UNSUPPORTED;
+    return st;
+}
+
+LB_API lb_status_t lb_batched_workspace_size(const lb_batch_t *B, const lb_schedule_t *s, int32_t k, size_t *bytes) {
+    if (!bytes || k < 1 || k > kMaxK) return LB_ERR_INVALID_ARG;
+    lb_status_t st = check_batch(B);
+    if (st != LB_OK) return st;
+    lb_schedule_t r;
+    st = resolve_batched(B, k, s, &r);
+    if (st != LB_OK) return st;
+    *bytes = lbk::batched_ws_bytes(to_dev(B), r.block_size, r.items_per_thread, k);
+    return LB_OK;
+}
+
+LB_API lb_status_t lb_batched_spmm(const lb_batch_t *B, const void *X, lb_dtype_t x_dtype, int32_t k, float *Y,
+                                   const lb_schedule_t *s, void *workspace, size_t workspace_bytes, void *stream) {
+    lb_status_t st = check_batch(B);
+    if (st != LB_OK) return st;
+    if (k < 1 || k > kMaxK) return LB_ERR_INVALID_ARG;
+    if (B->total_rows > 0 && !Y) return LB_ERR_INVALID_ARG;
+    if (B->total_nnz > 0 && !X) return LB_ERR_INVALID_ARG;
+    if (x_dtype != B->value_dtype) return LB_ERR_UNSUPPORTED;
+    lb_schedule_t r;
+    st = resolve_batched(B, k, s, &r);
+    if (st != LB_OK) return st;
+    const lbk::batch_dev d = to_dev(B);
+    const size_t need = lbk::batched_ws_bytes(d, r.block_size, r.items_per_thread, k);
+    if (need > 0 && (workspace_bytes < need || !workspace)) return LB_ERR_WORKSPACE_TOO_SMALL;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    if (B->total_rows == 0) return LB_OK;
+    if (B->total_nnz == 0) return hip_status(lbk::fill_f32(Y, B->total_rows * k, 0.f, hs));
+    return hip_status(lbk::batched_spmm(d, X, k, Y, r.block_size, r.items_per_thread, workspace, hs));
+}
+
+// ------------------------------------------------------------------ test hooks
+
+LB_API lb_status_t lb_merge_path_partition(const int32_t *row_offsets, int64_t rows, int64_t nnz,
+                                           int64_t items_per_unit, int64_t num_units, int32_t *out_row,
+                                           int32_t *out_nz, void *stream) {
+    if (rows < 0 || nnz < 0 || items_per_unit < 1 || num_units < 0) return LB_ERR_INVALID_ARG;
+    if (!row_offsets || !out_row || !out_nz) return LB_ERR_INVALID_ARG;
+    if (rows + nnz > kMaxCoord || items_per_unit > kMaxCoord || num_units > kMaxCoord) return LB_ERR_OVERFLOW;
+    return hip_status(lbk::merge_partition(row_offsets, static_cast<int32_t>(rows), static_cast<int32_t>(nnz),
+                                           static_cast<int32_t>(items_per_unit), static_cast<int32_t>(num_units),
+                                           out_row, out_nz, static_cast<hipStream_t>(stream)));
+}
+
+LB_API lb_status_t lb_group_tile_owner(const lb_csr_t *A, int32_t tiles_per_group, int32_t *owner, void *stream) {
+    lb_status_t st = check_csr(A);
+    if (st != LB_OK) return st;
+    if (!is_pow2(tiles_per_group) || tiles_per_group < 2 || tiles_per_group > 1024) return LB_ERR_INVALID_ARG;
+    if (A->nnz > 0 && !owner) return LB_ERR_INVALID_ARG;
+    if (A->rows == 0 || A->nnz == 0) return LB_OK;
+    return hip_status(lbk::group_tile_owner(to_dev(A), tiles_per_group, owner, static_cast<hipStream_t>(stream)));
+}
+
+static __device__ int32_t g_validate_flags;
+
+LB_API lb_status_t lb_validate_csr(const lb_csr_t *A, void *stream) {
+    lb_status_t st = check_csr(A);
+    if (st != LB_OK) return st;
+    if (!A->row_offsets) return LB_ERR_INVALID_ARG;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    int32_t *flags = nullptr;
+    hipError_t e = hipGetSymbolAddress(reinterpret_cast<void **>(&flags), HIP_SYMBOL(g_validate_flags));
+    if (e != hipSuccess) return hip_status(e);
+    int32_t zero = 0, host = 0;
+    e = hipMemcpyAsync(flags, &zero, sizeof zero, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess) e = lbk::validate_csr(to_dev(A), flags, hs);
+    if (e == hipSuccess) e = hipMemcpyAsync(&host, flags, sizeof host, hipMemcpyDeviceToHost, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) return hip_status(e);
+    return host ? LB_ERR_INVALID_CSR : LB_OK;
+}
+
+// ------------------------------------------------------------------ autotune
+
+LB_API lb_status_t lb_autotune_workspace_size(const lb_csr_t *A, int32_t k, size_t *bytes) {
+    if (!bytes || k < 1 || k > kMaxK) return LB_ERR_INVALID_ARG;
+    lb_status_t st = check_csr(A);
+    if (st != LB_OK) return st;
+    // the largest candidate workspace: the smallest merge-path unit
+    const int64_t T = lbk::merge_units(A->rows, A->nnz, 128 * 4);
+    *bytes = lbk::merge_ws_bytes(T, spmm_pass_cols(k));
+    return LB_OK;
+}
+
+
+LB_API lb_status_t lb_autotune(const lb_csr_t *A, const void *X, lb_dtype_t x_dtype, int32_t k, float *Y,
+                               void *workspace, size_t workspace_bytes, lb_schedule_t *best, void *stream) {
+    lb_status_t st = check_csr(A);
+    if (st != LB_OK) return st;
+    if (!best || k < 1 || k > kMaxK) return LB_ERR_INVALID_ARG;
+    size_t need = 0;
+    lb_autotune_workspace_size(A, k, &need);
+    if (workspace_bytes < need || !workspace) return LB_ERR_WORKSPACE_TOO_SMALL;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    float best_ms = 1e30f;
+    lb_schedule_t best_s = heuristic(A);
+    fill_defaults(&best_s, &best_s);
+    for (const lb_schedule_t &c : candidates(A, k)) {
+        float ms = 0.f;
+        auto run = [&]() -> lb_status_t {
+            if (k == 1) return lb_spmv(A, X, x_dtype, Y, &c, workspace, workspace_bytes, stream);
+            return lb_spmm(A, X, x_dtype, k, k, Y, k, &c, workspace, workspace_bytes, stream);
+        };
+        st = time_call(run, hs, &ms);
+        if (st == LB_ERR_HIP) return st;
+        if (st != LB_OK) continue;
+        if (ms < best_ms) {
+            best_ms = ms;
+            fill_defaults(&c, &best_s);
+        }
+    }
+    tune_store(tune_key{A->rows, A->cols, A->nnz, k, static_cast<int32_t>(A->value_dtype), 0}, best_s);
+    *best = best_s;
+    return LB_OK;
+}
+
+LB_API lb_status_t lb_batched_autotune(const lb_batch_t *B, const void *X, lb_dtype_t x_dtype, int32_t k, float *Y,
+                                       void *workspace, size_t workspace_bytes, lb_schedule_t *best, void *stream) {
+    lb_status_t st = check_batch(B);
+    if (st != LB_OK) return st;
+    if (!best || k < 1 || k > kMaxK) return LB_ERR_INVALID_ARG;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    float best_ms = 1e30f;
+    lb_schedule_t best_s{};
+    bool any = false;
+    for (int b : {128, 256, 512}) {
+        for (int it : {4, 8, 12, 16}) {
+            if (b * it > kMaxSpmmUnit) continue;
+            const lb_schedule_t c{LB_MERGE_PATH, 0, 0, it, b, 0};
+            size_t need = 0;
+            if (lb_batched_workspace_size(B, &c, k, &need) != LB_OK || need > workspace_bytes) continue;
+            float ms = 0.f;
+            auto run = [&]() -> lb_status_t {
+                return lb_batched_spmm(B, X, x_dtype, k, Y, &c, workspace, workspace_bytes, stream);
+            };
+            st = time_call(run, hs, &ms);
+            if (st == LB_ERR_HIP) return st;
+            if (st != LB_OK) continue;
+            if (ms < best_ms) {
+                best_ms = ms;
+                fill_defaults(&c, &best_s);
+                any = true;
+            }
+        }
+    }
+    if (!any) return LB_ERR_WORKSPACE_TOO_SMALL;
+    tune_store(tune_key{B->total_rows, B->total_cols, B->total_nnz, k, static_cast<int32_t>(B->value_dtype), 1},
+               best_s);
+    *best = best_s;
+    return LB_OK;
+}
+
+LB_API void lb_autotune_clear(void) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune.clear();
+    g_tune_loaded = true;  // do not reload the file after an explicit clear
+}
+
+// ------------------------------------------------------------------ profiling
+
+LB_API void lb_profile_enable(int on) { g_prof_on = on != 0; }
+
+LB_API void lb_profile_reset(void) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (auto &r : g_prof) {
+        (void)hipEventSynchronize(r.closed ? r.stop : r.start);
+        (void)hipEventDestroy(r.start);
+        if (r.closed) (void)hipEventDestroy(r.stop);
+    }
+    g_prof.clear();
+}
+
+LB_API lb_status_t lb_profile_read(const char *name, double *total_ms, int64_t *launches) {
+    if (!name || !total_ms || !launches) return LB_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    double t = 0.0;
+    int64_t n = 0;
+    for (auto &r : g_prof) {
+        if (!r.closed || r.name != name) continue;
+        hipError_t e = hipEventSynchronize(r.stop);
+        if (e != hipSuccess) return hip_status(e);
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, r.start, r.stop);
+        if (e != hipSuccess) return hip_status(e);
+        t += ms;
+        ++n;
+    }
+    *total_ms = t;
+    *launches = n;
+    return LB_OK;
+}
+
+}  // extern "C"

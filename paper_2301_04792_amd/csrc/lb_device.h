@@ -1,0 +1,212 @@
+// Device-side vocabulary of the load-balancing model for gfx950 (wave64).
+//
+//  * element loads: float32 and BF16 bit patterns widened to float; the
+//    nonzero streams (col_idx, values) are read with non-temporal loads so
+//    they do not evict the gathered x from L2;
+//  * ranges (Sec. 5.1): step_range drives the grid-, block- and wave-stride
+//    loops of the schedules;
+//  * tile sets (Sec. 3.1, Sec. 4.1): a CSR matrix's tiles are its rows and
+//    the atoms of tile r are the nonzeros [row_offsets[r], row_offsets[r+1]);
+//  * schedules (Sec. 4.2): thread-mapped tiles()/atoms(tile);
+//  * wave64 collectives: group sums, prefix sums and the segmented scan that
+//    merge-path and group-mapped use to combine partial tile results.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lb {
+
+constexpr int kWave = 64;
+
+using bf16_bits = uint16_t;
+
+__device__ __forceinline__ float to_f32(float v) { return v; }
+__device__ __forceinline__ float to_f32(bf16_bits v) {
+    return __uint_as_float(static_cast<uint32_t>(v) << 16);
+}
+
+// Streamed once: keep out of the caches' retained set.
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T *p) {
+    return __builtin_nontemporal_load(p);
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+__device__ __forceinline__ int wave_id() { return threadIdx.x / kWave; }
+
+// ---------------------------------------------------------------- ranges (Sec. 5.1)
+
+// [begin, end) in steps of `step`; 64-bit so a grid stride never wraps.
+struct step_range {
+    int64_t b, e, s;
+    struct iterator {
+        int64_t v, s;
+        __device__ int64_t operator*() const { return v; }
+        __device__ iterator &operator++() {
+            v += s;
+            return *this;
+        }
+        __device__ bool operator!=(const iterator &o) const { return v < o.v; }
+    };
+    __device__ iterator begin() const { return {b, s}; }
+    __device__ iterator end() const { return {e, s}; }
+};
+
+__device__ __forceinline__ step_range grid_stride_range(int64_t begin, int64_t end) {
+    return {static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x + begin, end,
+            static_cast<int64_t>(gridDim.x) * blockDim.x};
+}
+
+// ---------------------------------------------------------------- tile sets (Sec. 4.1)
+
+// CSR as a tile set: tiles are rows, atoms are nonzeros, and the atoms of a
+// tile are the offsets range [row_offsets[t], row_offsets[t + 1]).
+struct csr_tile_set {
+    const int32_t *row_offsets;
+    int64_t num_tiles;
+    int64_t num_atoms;
+    __device__ int32_t atoms_begin(int64_t t) const { return row_offsets[t]; }
+    __device__ int32_t atoms_end(int64_t t) const { return row_offsets[t + 1]; }
+    __device__ int32_t atom_count(int64_t t) const { return row_offsets[t + 1] - row_offsets[t]; }
+};
+
+// ---------------------------------------------------------------- schedules (Sec. 4.2)
+
+// Tile r goes to global thread r; threads stride by the grid; a thread walks
+// its tile's atoms one after another.
+struct thread_mapped_schedule {
+    csr_tile_set ts;
+    __device__ step_range tiles() const { return grid_stride_range(0, ts.num_tiles); }
+    __device__ step_range atoms(int64_t tile) const { return {ts.atoms_begin(tile), ts.atoms_end(tile), 1}; }
+};
+
+// ---------------------------------------------------------------- wave64 collectives
+
+// Sum over aligned groups of G lanes (G a power of two <= 64); every lane of
+// the group gets the total.  Fixed butterfly order: deterministic.
+template <int G>
+__device__ __forceinline__ float group_sum(float v) {
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+    return v;
+}
+
+// Inclusive prefix sum over aligned groups of G lanes (G <= 64).
+template <int G>
+__device__ __forceinline__ int32_t group_scan_incl(int32_t v) {
+    const int gl = threadIdx.x & (G - 1);
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) {
+        const int32_t o = __shfl_up(v, off, G);
+        if (gl >= off) v += o;
+    }
+    return v;
+}
+
+// A segmented-scan element: value and "a segment starts here" flag.  The
+// operator drops everything before a flagged element:
+//   (va, fa) . (vb, fb) = (fb ? vb : va + vb, fa | fb)
+// Merge-path uses it with flag = "this thread finished a row", so the scan
+// of the threads' trailing partial sums gives each thread the partial sum
+// that earlier threads hold for the row it finishes first.
+struct seg_t {
+    float v;
+    int f;
+};
+
+__device__ __forceinline__ seg_t seg_combine(seg_t a, seg_t b) {
+    return {b.f ? b.v : a.v + b.v, a.f | b.f};
+}
+
+// Inclusive segmented scan over aligned groups of G lanes (G <= 64).
+template <int G>
+__device__ __forceinline__ seg_t group_seg_scan_incl(seg_t x) {
+    const int gl = threadIdx.x & (G - 1);
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) {
+        const float v = __shfl_up(x.v, off, G);
+        const int f = __shfl_up(x.f, off, G);
+        if (gl >= off) x = seg_combine(seg_t{v, f}, x);
+    }
+    return x;
+}
+
+// Block-wide inclusive segmented scan; s_wave holds BLOCK/64 entries.  All
+// threads of the block must call it.  Ends with a barrier so s_wave can be
+// reused.  Also returns the block total.
+template <int BLOCK>
+__device__ __forceinline__ seg_t block_seg_scan_incl(seg_t x, seg_t *s_wave, seg_t &total) {
+    constexpr int NW = BLOCK / kWave;
+    const int lane = lane_id(), w = wave_id();
+    seg_t inc = group_seg_scan_incl<kWave>(x);
+    if (lane == kWave - 1) s_wave[w] = inc;
+    __syncthreads();
+    seg_t pre{0.f, 0};
+    seg_t tot{0.f, 0};
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        const seg_t s = s_wave[k];
+        if (k < w) pre = seg_combine(pre, s);
+        tot = seg_combine(tot, s);
+    }
+    __syncthreads();
+    total = tot;
+    return w ? seg_combine(pre, inc) : inc;
+}
+
+// Block-wide exclusive segmented scan (lane 0 of the block gets {0, 0}).
+template <int BLOCK>
+__device__ __forceinline__ seg_t block_seg_scan_excl(seg_t x, seg_t *s_wave, seg_t &total) {
+    constexpr int NW = BLOCK / kWave;
+    const int lane = lane_id(), w = wave_id();
+    const seg_t inc = group_seg_scan_incl<kWave>(x);
+    if (lane == kWave - 1) s_wave[w] = inc;
+    __syncthreads();
+    seg_t pre{0.f, 0};
+    seg_t tot{0.f, 0};
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        const seg_t s = s_wave[k];
+        if (k < w) pre = seg_combine(pre, s);
+        tot = seg_combine(tot, s);
+    }
+    __syncthreads();
+    total = tot;
+    const float pv = __shfl_up(inc.v, 1, kWave);
+    const int pf = __shfl_up(inc.f, 1, kWave);
+    return lane ? seg_combine(pre, seg_t{pv, pf}) : pre;
+}
+
+// Block-wide sum (all threads call; every thread gets the total).  s_red
+// holds BLOCK/64 floats.  Waves are added in index order: deterministic.
+template <int BLOCK>
+__device__ __forceinline__ float block_sum(float v, float *s_red) {
+    constexpr int NW = BLOCK / kWave;
+    v = group_sum<kWave>(v);
+    if (lane_id() == 0) s_red[wave_id()] = v;
+    __syncthreads();
+    float t = 0.f;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) t += s_red[k];
+    __syncthreads();
+    return t;
+}
+
+// Block-wide inclusive prefix sum of int32 (all threads call).
+template <int BLOCK>
+__device__ __forceinline__ int32_t block_scan_incl(int32_t v, int32_t *s_wave) {
+    constexpr int NW = BLOCK / kWave;
+    const int w = wave_id();
+    v = group_scan_incl<kWave>(v);
+    if (lane_id() == kWave - 1) s_wave[w] = v;
+    __syncthreads();
+    int32_t pre = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k)
+        if (k < w) pre += s_wave[k];
+    __syncthreads();
+    return v + pre;
+}
+
+}  // namespace lb

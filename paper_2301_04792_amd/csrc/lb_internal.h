@@ -1,0 +1,118 @@
+// Host-side interface between the C ABI (lb_api.cpp) and the kernel files.
+// Every launcher enqueues work on `stream` and returns the launch status; it
+// assumes its arguments were validated by the caller.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "lb.h"
+
+namespace lbk {
+
+struct csr_dev {
+    int32_t rows, cols, nnz;
+    const int32_t *ro;
+    const int32_t *ci;
+    const void *val;
+    lb_dtype_t dt;
+};
+
+// ---- kernel timing (lb_profile_*) ---------------------------------------------------
+bool profiling_enabled();
+void profile_mark(hipStream_t s, const char *name, bool begin);
+
+struct prof_scope {
+    hipStream_t s;
+    const char *name;
+    bool on;
+    prof_scope(hipStream_t st, const char *n) : s(st), name(n), on(profiling_enabled()) {
+        if (on) profile_mark(s, name, true);
+    }
+    ~prof_scope() {
+        if (on) profile_mark(s, name, false);
+    }
+};
+
+inline size_t align256(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
+
+// ---- merge-path split ---------------------------------------------------------------
+// Work units of W merge items; T = ceil((rows + nnz) / W) units.
+inline int64_t merge_units(int64_t rows, int64_t nnz, int64_t W) { return (rows + nnz + W - 1) / W; }
+
+// Workspace: part_i[T+1], part_j[T+1], carry_row[T], carry_val[T * kc].
+struct merge_ws {
+    int32_t *part_i;
+    int32_t *part_j;
+    int32_t *carry_row;
+    float *carry_val;
+};
+inline size_t merge_ws_bytes(int64_t T, int kc) {
+    return 2 * align256(static_cast<size_t>(T + 1) * 4) + align256(static_cast<size_t>(T) * 4) +
+           align256(static_cast<size_t>(T) * 4 * kc);
+}
+inline merge_ws merge_ws_carve(void *base, int64_t T) {
+    char *p = static_cast<char *>(base);
+    merge_ws w;
+    w.part_i = reinterpret_cast<int32_t *>(p);
+    p += align256(static_cast<size_t>(T + 1) * 4);
+    w.part_j = reinterpret_cast<int32_t *>(p);
+    p += align256(static_cast<size_t>(T + 1) * 4);
+    w.carry_row = reinterpret_cast<int32_t *>(p);
+    p += align256(static_cast<size_t>(T) * 4);
+    w.carry_val = reinterpret_cast<float *>(p);
+    return w;
+}
+
+hipError_t merge_partition(const int32_t *ro, int32_t rows, int32_t nnz, int32_t W, int32_t T,
+                           int32_t *part_i, int32_t *part_j, hipStream_t s);
+
+// True if (block, items) is an instantiated merge-path configuration.
+bool merge_config_supported(int block, int items);
+
+// Deterministic carry fix-up: for each run of equal carry_row entries (rows
+// < rows only), adds the run's carry_val sums (kc columns, row-major with
+// leading dimension ldy) to y.
+hipError_t launch_fixup(int64_t T, int32_t rows, int32_t kc, const int32_t *carry_row,
+                        const float *carry_val, float *y, int64_t ldy, hipStream_t s, const char *tag);
+
+hipError_t merge_spmv(const csr_dev &A, const void *x, float *y, int block, int items, void *ws,
+                      hipStream_t s);
+
+hipError_t merge_spmm(const csr_dev &A, const void *X, int32_t k, int64_t ldx, float *Y, int64_t ldy,
+                      int block, int items, void *ws, hipStream_t s);
+
+hipError_t merge_backward(const csr_dev &A, const void *x, const float *dy, float *dx, float *dvalues,
+                          int block, int items, void *ws, hipStream_t s);
+
+// ---- batched ------------------------------------------------------------------------
+struct batch_dev {
+    int32_t count, total_rows, total_cols, total_nnz;
+    const int32_t *ro;
+    const int32_t *ci;
+    const void *val;
+    lb_dtype_t dt;
+    const int64_t *row_base;
+    const int64_t *nnz_base;
+    const int64_t *col_base;
+};
+size_t batched_ws_bytes(const batch_dev &B, int block, int items, int k);
+hipError_t batched_spmm(const batch_dev &B, const void *X, int32_t k, float *Y, int block, int items,
+                        void *ws, hipStream_t s);
+
+// ---- thread- and group-mapped ---------------------------------------------------------
+hipError_t thread_mapped_spmv(const csr_dev &A, const void *x, float *y, int block, int grid,
+                              hipStream_t s);
+hipError_t thread_mapped_spmm(const csr_dev &A, const void *X, int32_t k, int64_t ldx, float *Y,
+                              int64_t ldy, int block, int grid, hipStream_t s);
+hipError_t group_mapped_spmv(const csr_dev &A, const void *x, float *y, int group_size,
+                             int tiles_per_group, int grid, hipStream_t s);
+hipError_t group_tile_owner(const csr_dev &A, int tiles_per_group, int32_t *owner, hipStream_t s);
+
+// ---- utilities ------------------------------------------------------------------------
+hipError_t fill_f32(float *p, int64_t n, float v, hipStream_t s);
+// Writes violation flags (bit 0: offsets, bit 1: columns) into *flags_dev.
+hipError_t validate_csr(const csr_dev &A, int32_t *flags_dev, hipStream_t s);
+
+}  // namespace lbk

@@ -1,0 +1,308 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle: SpMV under
+every schedule, the merge-path split, get_tile, BF16, SpMM, backward,
+autograd and batched, at sizes the oracle finishes in seconds."""
+import numpy as np
+import pytest
+
+import oracle
+import synthetic as S
+from tests.gpu_util import assert_rows_close, oracle_spmm, oracle_spmv
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2301_04792_amd as lb  # noqa: E402
+
+DEV = "cuda:0"
+
+MERGE_CONFIGS = [(b, i) for b in (128, 256, 512) for i in (4, 8, 12, 16)]
+GROUP_CONFIGS = [(g, k) for g in (1, 2, 8, 32, 64, 128, 256, 1024) for k in (1, g) if not (k == g == 1)] + [(1, 1)]
+
+SCHEDULES = ([("thread_mapped", {}), ("thread_mapped", {"block_size": 64}), ("auto", {})]
+             + [("group_mapped", {"group_size": g, "tiles_per_group": k}) for g, k in GROUP_CONFIGS]
+             + [("merge_path", {"block_size": b, "items_per_thread": i}) for b, i in MERGE_CONFIGS])
+SCHED_IDS = [f"{n}-{'-'.join(f'{k}{v}' for k, v in p.items())}" for n, p in SCHEDULES]
+
+
+def upload(A, x, dtype=torch.float32):
+    Ad = lb.CSR.from_host(A, DEV, dtype)
+    if x.dtype == np.uint16:
+        xd = torch.from_numpy(x.view(np.int16).copy()).view(torch.bfloat16).to(DEV)
+    else:
+        xd = torch.from_numpy(x).to(DEV).to(dtype)
+    return Ad, xd
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return S.config_c1()
+
+
+@pytest.mark.parametrize("name,params", SCHEDULES, ids=SCHED_IDS)
+def test_c1_all_schedules(c1, name, params):
+    A, x = c1
+    Ad, xd = upload(A, x)
+    y = lb.spmv(Ad, xd, name, **params)
+    ref, scale = oracle_spmv(A, x)
+    print(f"[c1 {name} {params}]", flush=True)
+    assert_rows_close(y.cpu().numpy(), ref, scale, what=f"{name} {params}")
+
+
+@pytest.mark.parametrize("mname", sorted(S.special_matrices().keys()))
+@pytest.mark.parametrize("name,params", [("thread_mapped", {}), ("group_mapped", {"group_size": 64}),
+                                         ("group_mapped", {"group_size": 16, "tiles_per_group": 16}),
+                                         ("group_mapped", {"group_size": 256, "tiles_per_group": 256}),
+                                         ("merge_path", {}), ("merge_path", {"block_size": 128, "items_per_thread": 4}),
+                                         ("merge_path", {"block_size": 512, "items_per_thread": 16})])
+def test_special_shapes(mname, name, params):
+    A, x = S.special_matrices()[mname]
+    Ad, xd = upload(A, x)
+    y = lb.spmv(Ad, xd, name, **params)
+    torch.cuda.synchronize()
+    ref, scale = oracle_spmv(A, x)
+    assert_rows_close(y.cpu().numpy(), ref, scale, what=f"{mname} {name} {params}")
+
+
+@pytest.fixture(scope="module")
+def integer_powerlaw():
+    A, _ = S.powerlaw_csr(77, 60_000, 50_000, 1.5, 40_000, 0.1)
+    return S.integer_valued(A, 3)
+
+
+@pytest.mark.parametrize("name,params", SCHEDULES, ids=SCHED_IDS)
+def test_integer_inputs_bit_exact(integer_powerlaw, name, params):
+    """Integer values and x keep every partial sum exact in FP32, so every
+    schedule must equal the oracle bit for bit (long rows cross many units)."""
+    A, x = integer_powerlaw
+    Ad, xd = upload(A, x)
+    y = lb.spmv(Ad, xd, name, **params).cpu().numpy().astype(np.float64)
+    ref, _ = oracle_spmv(A, x)
+    assert np.array_equal(y, ref), f"{name} {params}: {int((y != ref).sum())} rows differ"
+
+
+def test_merge_path_bit_reproducible(c1):
+    A, x = S.powerlaw_csr(5, 200_000, 200_000, 1.8, 50_000, 0.1)
+    Ad, xd = upload(A, x)
+    y1 = lb.spmv(Ad, xd, "merge_path")
+    y2 = lb.spmv(Ad, xd, "merge_path")
+    assert torch.equal(y1, y2)
+
+
+def _partition_cases():
+    out = [(n, A) for n, (A, _) in S.special_matrices().items()]
+    out.append(("c1", S.config_c1()[0]))
+    out.append(("powerlaw", S.powerlaw_csr(9, 30_000, 30_000, 1.6, 20_000, 0.1)[0]))
+    return out
+
+
+@pytest.mark.parametrize("name,A", _partition_cases(), ids=[n for n, _ in _partition_cases()])
+def test_partition_bit_exact(name, A):
+    ro = torch.from_numpy(A.row_offsets).to(DEV)
+    total = A.m + A.nnz
+    for W in (1, 2, 7, 64, 97, 1024, 2048, 3072, 8192, total + 5):
+        T = max(1, -(-total // W))
+        if T > 3_000_000:
+            continue
+        gi, gj = lb.merge_path_partition(ro, A.nnz, W, T)
+        oi, oj = oracle.merge_walk(A.row_offsets, A.nnz, W, T)
+        assert np.array_equal(gi.cpu().numpy(), oi), (name, W)
+        assert np.array_equal(gj.cpu().numpy(), oj), (name, W)
+
+
+@pytest.mark.parametrize("K", [2, 8, 64, 256, 1024])
+def test_group_get_tile(K):
+    A, _ = S.powerlaw_csr(13, 20_000, 20_000, 1.7, 3_000, 0.2)
+    Ad = lb.CSR.from_host(A, DEV)
+    owner = lb.group_tile_owner(Ad, K).cpu().numpy()
+    L = np.diff(A.row_offsets)
+    expect = np.concatenate([oracle.get_tile_brute(L[g:g + K]) for g in range(0, A.m, K)])
+    assert np.array_equal(owner, expect)
+
+
+@pytest.mark.parametrize("name,params", [("thread_mapped", {}), ("group_mapped", {"group_size": 32}),
+                                         ("group_mapped", {"group_size": 64, "tiles_per_group": 64}),
+                                         ("merge_path", {}), ("merge_path", {"block_size": 512, "items_per_thread": 16})])
+def test_bf16_inputs(name, params):
+    """BF16 values and x, FP32 products and sums, against the oracle on the
+    same BF16 inputs (1e-5 rule) and on the FP32 originals (quantisation
+    bound (2u + u^2) sum|a x| + accumulation, u = 2^-8)."""
+    A, x = S.powerlaw_csr(21, 100_000, 100_000, 1.8, 30_000, 0.1)
+    Ab = A.with_values(S.to_bf16_bits(A.values))
+    xb = S.to_bf16_bits(x)
+    Ad, xd = upload(Ab, xb, torch.bfloat16)
+    y = lb.spmv(Ad, xd, name, **params).cpu().numpy()
+    ref, scale = oracle_spmv(Ab, xb)
+    assert_rows_close(y, ref, scale, what=f"bf16 {name}")
+    ref32, scale32 = oracle_spmv(A, x)
+    u = 2.0 ** -8
+    assert_rows_close(y, ref32, scale32, rtol=2 * u + u * u + 2e-5, what="bf16 vs fp32 inputs")
+
+
+def test_laplacian_bf16_exact_values():
+    A, x = S.laplacian_5pt(3, 256)
+    Ab = A.with_values(S.to_bf16_bits(A.values))
+    assert np.array_equal(S.bf16_bits_to_f32(Ab.values), A.values)  # 4 and -1 are exact
+    xb = S.to_bf16_bits(x)
+    Ad, xd = upload(Ab, xb, torch.bfloat16)
+    y = lb.spmv(Ad, xd, "merge_path").cpu().numpy()
+    ref, scale = oracle_spmv(Ab, xb)
+    assert_rows_close(y, ref, scale, what="laplacian bf16")
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 8, 13])
+@pytest.mark.parametrize("name,params", [("merge_path", {}), ("merge_path", {"block_size": 128, "items_per_thread": 16}),
+                                         ("thread_mapped", {})])
+def test_spmm(k, name, params):
+    A, _ = S.powerlaw_csr(31, 20_000, 15_000, 1.7, 12_000, 0.1)
+    X = S.random_vector(8, A.n * k).reshape(A.n, k)
+    Ad, _ = upload(A, X[:, 0].copy())
+    Xd = torch.from_numpy(X).to(DEV)
+    Y = lb.spmm(Ad, Xd, name, **params).cpu().numpy()
+    ref, scale = oracle_spmm(A, X)
+    assert_rows_close(Y, ref, scale, what=f"spmm k={k} {name}")
+
+
+def test_spmm_strided_and_special():
+    A, _ = S.config_c1()
+    X = S.random_vector(3, A.n * 10).reshape(A.n, 10)
+    Xd = torch.from_numpy(X).to(DEV)[:, 1:6]  # ldx = 10, k = 5
+    Y = torch.full((A.m, 8), 7.0, device=DEV)
+    lb.spmm(lb.CSR.from_host(A, DEV), Xd, "merge_path", Y=Y[:, 2:7])
+    ref, scale = oracle_spmm(A, X[:, 1:6])
+    Yh = Y.cpu().numpy()
+    assert_rows_close(Yh[:, 2:7], ref, scale, what="strided spmm")
+    assert np.all(Yh[:, :2] == 7.0) and np.all(Yh[:, 7:] == 7.0)
+    for mname, (Am, _) in S.special_matrices().items():
+        Xm = S.random_vector(4, Am.n * 3).reshape(Am.n, 3)
+        Ym = lb.spmm(lb.CSR.from_host(Am, DEV), torch.from_numpy(Xm).to(DEV), "merge_path").cpu().numpy()
+        ref, scale = oracle_spmm(Am, Xm)
+        assert_rows_close(Ym, ref, scale, what=f"spmm {mname}")
+
+
+def _backward_ref(A, x, dy):
+    dx = oracle.spmv_transpose(A.row_offsets, A.col_idx, A.values, dy, A.n)
+    dxs = oracle.spmv_transpose(A.row_offsets, A.col_idx, A.values, dy, A.n, abs_terms=True)
+    dv = oracle.dvalues(A.row_offsets, A.col_idx, dy, x)
+    return dx, dxs, dv
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_backward(dtype):
+    A, x = S.powerlaw_csr(41, 50_000, 40_000, 1.8, 20_000, 0.1)
+    dy = S.random_vector(42, A.m)
+    if dtype == "bf16":
+        A = A.with_values(S.to_bf16_bits(A.values))
+        x = S.to_bf16_bits(x)
+    Ad, xd = upload(A, x, torch.bfloat16 if dtype == "bf16" else torch.float32)
+    dx, dv = lb.spmv_backward(Ad, xd, torch.from_numpy(dy).to(DEV))
+    rdx, rdxs, rdv = _backward_ref(A, x, dy.astype(np.float64))
+    assert_rows_close(dx.cpu().numpy(), rdx, rdxs, what="dx")
+    # one FP32 product of two FP32 numbers: exactly one correct result
+    assert np.array_equal(dv.cpu().numpy(), rdv.astype(np.float32)), "dvalues not bit-exact"
+    for special, (As, xs) in S.special_matrices().items():
+        dys = S.random_vector(5, As.m)
+        Asd, xsd = upload(As, xs)
+        dx, dv = lb.spmv_backward(Asd, xsd, torch.from_numpy(dys).to(DEV))
+        rdx, rdxs, rdv = _backward_ref(As, xs, dys.astype(np.float64))
+        assert_rows_close(dx.cpu().numpy(), rdx, rdxs, what=f"dx {special}")
+        assert np.array_equal(dv.cpu().numpy(), rdv.astype(np.float32)), special
+
+
+def test_backward_integer_exact_and_partial_outputs():
+    A, _ = S.powerlaw_csr(43, 30_000, 20_000, 1.6, 10_000, 0.1)
+    Ai, xi = S.integer_valued(A, 11)
+    dy = np.random.default_rng(1).integers(-3, 4, A.m).astype(np.float32)
+    Ad, xd = upload(Ai, xi)
+    dyd = torch.from_numpy(dy).to(DEV)
+    dx, dv = lb.spmv_backward(Ad, xd, dyd)
+    rdx, _, rdv = _backward_ref(Ai, xi, dy.astype(np.float64))
+    assert np.array_equal(dx.cpu().numpy().astype(np.float64), rdx)  # exact in any atomic order
+    assert np.array_equal(dv.cpu().numpy().astype(np.float64), rdv)
+    dx2, dv2 = lb.spmv_backward(Ad, xd, dyd, need_dx=False)
+    assert dx2 is None and torch.equal(dv2, dv)
+    dx3, dv3 = lb.spmv_backward(Ad, xd, dyd, need_dvalues=False)
+    assert dv3 is None and torch.equal(dx3, dx)
+
+
+def test_autograd_function():
+    A, x = S.config_c1(seed=6)
+    Ad, xd = upload(A, x)
+    values = Ad.values.clone().requires_grad_(True)
+    xg = xd.clone().requires_grad_(True)
+    w = torch.from_numpy(S.random_vector(7, A.m)).to(DEV)
+    y = lb.SpMV.apply(values, xg, Ad.pattern, "merge_path")
+    (y * w).sum().backward()
+    rdx, rdxs, rdv = _backward_ref(A, x, w.cpu().numpy().astype(np.float64))
+    assert_rows_close(xg.grad.cpu().numpy(), rdx, rdxs, what="autograd dx")
+    assert np.array_equal(values.grad.cpu().numpy(), rdv.astype(np.float32))
+    yr, sr = oracle_spmv(A, x)
+    assert_rows_close(y.detach().cpu().numpy(), yr, sr, what="autograd forward")
+
+
+@pytest.mark.parametrize("k", [1, 8, 3])
+def test_batched(k):
+    B = S.batched_powerlaw(51, 40, 100, 20_000, 1.8, 0.05)
+    X = S.random_vector(52, B.total_cols * k).reshape(B.total_cols, k)
+    Bd = lb.Batch.from_host(B, DEV)
+    for params in ({}, {"block_size": 128, "items_per_thread": 4}, {"block_size": 512, "items_per_thread": 8}):
+        Y = lb.batched_spmm(Bd, torch.from_numpy(X).to(DEV), "merge_path", **params).cpu().numpy()
+        ref = oracle.batched_spmm(B, X)
+        scale = np.concatenate([oracle.spmm(B.matrix(b).row_offsets, B.matrix(b).col_idx, B.matrix(b).values,
+                                            X[B.mat_col_base[b]:B.mat_col_base[b + 1]], abs_terms=True)
+                                for b in range(B.count)])
+        assert_rows_close(Y, ref, scale, what=f"batched k={k} {params}")
+
+
+def test_batched_tiny_and_empty_matrices():
+    # matrices of 1 row, empty rows and zero-row members cross unit boundaries
+    mats = [S.special_matrices()[n][0] for n in ("m1_n1", "all_empty", "trailing_empty", "leading_empty", "ragged")]
+    mats += [S.uniform_csr(60 + i, 3 + i, 5 + i, 4)[0] for i in range(30)]
+    ro = [np.zeros(1, np.int64)]
+    off = 0
+    for A in mats:
+        ro.append(A.row_offsets[1:].astype(np.int64) + off)
+        off += A.nnz
+    rb = np.concatenate([[0], np.cumsum([A.m for A in mats])]).astype(np.int64)
+    nb = np.concatenate([[0], np.cumsum([A.nnz for A in mats])]).astype(np.int64)
+    cb = np.concatenate([[0], np.cumsum([A.n for A in mats])]).astype(np.int64)
+    B = S.BatchHost(np.concatenate(ro).astype(np.int32), np.concatenate([A.col_idx for A in mats]),
+                    np.concatenate([A.values for A in mats]), rb, nb, cb)
+    X = S.random_vector(3, B.total_cols * 2).reshape(-1, 2)
+    Y = lb.batched_spmm(lb.Batch.from_host(B, DEV), torch.from_numpy(X).to(DEV), "merge_path",
+                        block_size=128, items_per_thread=4).cpu().numpy()
+    ref = oracle.batched_spmm(B, X)
+    assert np.allclose(Y, ref, rtol=0, atol=1e-5 * (np.abs(ref).max() + 1))
+
+
+def test_autotune_and_auto():
+    A, x = S.powerlaw_csr(61, 100_000, 100_000, 1.8, 20_000, 0.1)
+    Ad, xd = upload(A, x)
+    lb.autotune_clear()
+    best = lb.tune(Ad)
+    assert best["schedule"] in ("merge_path", "group_mapped", "thread_mapped")
+    assert lb.resolve_schedule(Ad, "auto") == best
+    y = lb.spmv(Ad, xd, "auto")
+    ref, scale = oracle_spmv(A, x)
+    assert_rows_close(y.cpu().numpy(), ref, scale, what="auto after tune")
+    B = S.batched_powerlaw(62, 16, 100, 5000)
+    Bd = lb.Batch.from_host(B, DEV)
+    bb = lb.tune_batched(Bd, k=1)
+    assert bb["schedule"] == "merge_path"
+    lb.autotune_clear()
+
+
+def test_validate_csr():
+    A, _ = S.config_c1()
+    Ad = lb.CSR.from_host(A, DEV)
+    assert lb.validate(Ad)
+    bad = A.col_idx.copy()
+    bad[100] = A.n + 3
+    Ab = lb.CSR(Ad.row_offsets, torch.from_numpy(bad).to(DEV), Ad.values, A.shape)
+    assert not lb.validate(Ab)
+    ro = A.row_offsets.copy()
+    ro[10], ro[11] = ro[11], ro[10] - 1
+    Ar = lb.CSR(torch.from_numpy(ro).to(DEV), Ad.col_idx, Ad.values, A.shape)
+    assert not lb.validate(Ar)
