@@ -1,0 +1,343 @@
+#!/usr/bin/env python3
+"""Throughput of load-balanced CSR SpMV on one MI355X.
+
+One step = one y = A x over the power-law matrix (m = n = 2,000,000, row
+lengths min(Zipf(1.8), 200,000), 10 % empty rows, uniform columns, FP32)
+with the merge-path schedule (what the Sec. 6.2 heuristic picks for it):
+partition, consume and carry fix-up.  `value` is effective HBM GB/s over
+algorithmic bytes B = nnz*(s_v + 4) + (m + 1)*4 + n*s_x + m*4 for K
+back-to-back steps with the inputs already in HBM.
+
+The same JSON line carries the roofline of the dominant kernel (merge-path
+consume, timed by the library's HIP events on the launch stream), the FP64
+oracle timed on the host cores, and per-schedule, BF16, forward+backward
+and batched figures on the other workloads (skip them with --quick).
+
+    python bench.py [--steps K] [--warmup W] [--quick]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_GBS = 8000.0
+METRIC = "SpMV effective HBM GB/s (% of peak) per schedule; fwd+bwd and batched GB/s"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "merge_consume_powerlaw2M_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2301_04792_amd", "csrc", f) for f in ("k_merge.hip", "lb_device.h")]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def spmv_bytes(m, n, nnz, sv=4, sx=4, k=1):
+    return nnz * (sv + 4) + (m + 1) * 4 + n * sx * k + m * 4 * k
+
+
+def backward_bytes(m, n, nnz, sv=4, sx=4):
+    # values + col_idx read, dvalues written, row_offsets, dy, x read, dx written
+    return nnz * (sv + 4) + nnz * 4 + (m + 1) * 4 + m * 4 + n * sx + n * 4
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--quick", action="store_true", help="headline workload only")
+    ap.add_argument("--items", type=int, default=0, help="merge-path items per thread (0 = default)")
+    ap.add_argument("--block", type=int, default=0, help="merge-path block size (0 = default)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--schedule", default="auto",
+                    help="headline schedule: auto (autotuned) or merge_path / group_mapped / thread_mapped")
+    ap.add_argument("--pmc-calib", action="store_true",
+                    help="also run one 256 MiB device copy (known bytes) to scale rocprofv3 FETCH/WRITE_SIZE")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus > 1 or world > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the split would shard the merge path across GPUs, see DESIGN.md).", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2301_04792_amd as lb
+    import synthetic as S
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB, larger than L2 + MALL
+
+    def timed(fn, steps, warmup):
+        """ms per step over `steps` back-to-back calls (events on the launch stream)."""
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    def cold(fn, reps):
+        """median ms of single calls, each after a 1 GiB write that evicts L2 and MALL."""
+        out = []
+        for r in range(reps):
+            flush.fill_(float(r))
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            out.append(a.elapsed_time(b))
+        return float(np.median(out))
+
+    def kernel_avg_ms(fn, steps, name):
+        lb.profile_reset()
+        lb.profile_enable(True)
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        lb.profile_enable(False)
+        ms, n = lb.profile_read(name)
+        lb.profile_reset()
+        return ms / max(n, 1), n
+
+    # ------------------------------------------------------------ headline workload
+    t0 = time.time()
+    A, x = S.config_c2()
+    log(f"[bench] power-law 2M generated: nnz={A.nnz} in {time.time() - t0:.1f}s")
+    Ad = lb.CSR.from_host(A, dev)
+    xd = torch.from_numpy(x).to(dev)
+    y = torch.empty(A.m, dtype=torch.float32, device=dev)
+    params = {}
+    if args.items:
+        params["items_per_thread"] = args.items
+    if args.block:
+        params["block_size"] = args.block
+    head = args.schedule
+    if head == "auto" and not params:
+        lb.autotune_clear()
+        t0 = time.time()
+        lb.tune(Ad)  # schedule and tile size picked by timing the candidates on this matrix
+        log(f"[bench] autotuned in {time.time() - t0:.1f}s")
+    elif head == "auto":
+        head = "merge_path"
+    sched = lb.resolve_schedule(Ad, head, **params)
+    ws = torch.empty(max(lb.workspace_size(Ad, head, **params), 1), dtype=torch.uint8, device=dev)
+    dominant = {"merge_path": "merge_consume", "group_mapped": "group_mapped",
+                "thread_mapped": "thread_mapped"}[sched["schedule"]]
+
+    def step():
+        lb.spmv(Ad, xd, head, y=y, workspace=ws, **params)
+
+    B = spmv_bytes(A.m, A.n, A.nnz)
+    ms = timed(step, args.steps, args.warmup)
+    value = B / (ms * 1e-3) / 1e9
+    log(f"[bench] {sched}: {ms * 1e3:.1f} us/step, {value:.0f} GB/s")
+    ms_cold = cold(step, 10)
+    consume_ms, launches = kernel_avg_ms(step, args.steps, dominant)
+    others = {}
+    if dominant == "merge_consume":
+        others = {n: round(kernel_avg_ms(step, args.steps, n)[0], 5) for n in ("merge_partition", "merge_fixup")}
+    achieved = B / (consume_ms * 1e-3) / 1e9
+    log(f"[bench] {dominant} {consume_ms * 1e3:.1f} us ({achieved:.0f} GB/s), others {others}, "
+        f"cold call {ms_cold * 1e3:.1f} us")
+    if args.pmc_calib:
+        src = torch.ones(1 << 26, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)  # reads and writes exactly 256 MiB
+        torch.cuda.synchronize()
+        del src, dst
+
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        try:
+            with open(TRAFFIC_FILE) as f:
+                tr = json.load(f)
+            if tr.get("kernel_source_hash") == kernel_source_hash() and tr.get("nnz") == A.nnz and \
+                    tr.get("items_per_thread") == sched["items_per_thread"] and tr.get("block_size") == sched["block_size"]:
+                traffic = tr.get("hbm_bytes_per_launch")
+        except (OSError, ValueError):
+            traffic = None
+
+    result = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "powerlaw_m2M_zipf1.8_cap200k_empty10pct", "m": A.m, "n": A.n, "nnz": A.nnz,
+                   "seed": 2, "schedule": sched["schedule"], "block_size": sched["block_size"],
+                   "items_per_thread": sched["items_per_thread"]},
+        "pct_of_peak": round(100 * value / PEAK_GBS, 2),
+        "gflops": round(2 * A.nnz / (ms * 1e-3) / 1e9, 2),
+        "algorithmic_bytes": B,
+        "cold_ms_per_call": round(ms_cold, 5),
+        "cold_gbs": round(B / (ms_cold * 1e-3) / 1e9, 2),
+        "roofline": {"kernel": dominant, "bound": "hbm", "achieved": round(achieved, 2),
+                     "peak": PEAK_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_GBS, 4),
+                     "traffic": traffic, "avg_launch_ms": round(consume_ms, 5), "launches": launches,
+                     "algorithmic_bytes_per_launch": B, "other_kernels_ms": others},
+    }
+
+    # ------------------------------------------------------------ CPU oracle baseline
+    if not args.no_cpu:
+        import oracle
+
+        orc = oracle.default()
+        orc.spmv(A.row_offsets, A.col_idx, A.values, x)  # warm-up
+        reps, t_all = 0, []
+        start = time.time()
+        while reps < 5 and time.time() - start < 20:
+            t1 = time.perf_counter()
+            orc.spmv(A.row_offsets, A.col_idx, A.values, x)
+            t_all.append(time.perf_counter() - t1)
+            reps += 1
+        cpu_s = float(np.median(t_all))
+        result["cpu_baseline"] = {"value": round(B / cpu_s / 1e9, 3), "unit": "GB/s", "cores": orc.num_threads(),
+                                  "kind": "oracle", "ms_per_call": round(cpu_s * 1e3, 2),
+                                  "sample": f"full power-law 2M matrix, FP64 oracle SpMV, median of {reps} calls"}
+        log(f"[bench] cpu oracle: {cpu_s * 1e3:.0f} ms/call on {orc.num_threads()} threads")
+
+    if args.quick:
+        print(json.dumps(result), flush=True)
+        return 0
+
+    extra_steps = max(3, min(args.steps, 10))
+
+    # ------------------------------------------------------------ per schedule on the same matrix
+    per = {}
+    for name, p in (("merge_path", {}), ("merge_path", {"block_size": 512, "items_per_thread": 8}),
+                    ("thread_mapped", {}), ("group_mapped", {"group_size": 64}),
+                    ("group_mapped", {"group_size": 256}), ("group_mapped", {"group_size": 32, "tiles_per_group": 32})):
+        wsz = lb.workspace_size(Ad, name, **p)
+        w2 = torch.empty(max(wsz, 1), dtype=torch.uint8, device=dev)
+        f = (lambda name=name, p=p, w2=w2: lb.spmv(Ad, xd, name, y=y, workspace=w2, **p))
+        t = timed(f, 3 if name == "thread_mapped" else extra_steps, 1)
+        key = name + ("" if not p else "_" + "_".join(f"{k}{v}" for k, v in p.items()))
+        per[key] = {"ms": round(t, 4), "gbs": round(B / (t * 1e-3) / 1e9, 2),
+                    "pct_of_peak": round(100 * B / (t * 1e-3) / 1e9 / PEAK_GBS, 2)}
+        log(f"[bench] {key}: {t * 1e3:.1f} us")
+    result["schedules_powerlaw2M"] = per
+
+    # ------------------------------------------------------------ BF16
+    import oracle
+
+    bf = {}
+    Ab = A.with_values(S.to_bf16_bits(A.values))
+    xb = S.to_bf16_bits(x)
+    Abd = lb.CSR.from_host(Ab, dev)
+    xbd = torch.from_numpy(xb.view(np.int16).copy()).view(torch.bfloat16).to(dev)
+    wsb = torch.empty(lb.workspace_size(Abd, "merge_path"), dtype=torch.uint8, device=dev)
+    t = timed(lambda: lb.spmv(Abd, xbd, "merge_path", y=y, workspace=wsb), extra_steps, 2)
+    Bb = spmv_bytes(A.m, A.n, A.nnz, 2, 2)
+    yb = y.cpu().numpy().astype(np.float64)
+    ref_b = oracle.spmv(Ab.row_offsets, Ab.col_idx, Ab.values, xb)
+    sc_b = oracle.spmv(Ab.row_offsets, Ab.col_idx, Ab.values, xb, abs_terms=True)
+    ref_f = oracle.spmv(A.row_offsets, A.col_idx, A.values, x)
+    sc_f = oracle.spmv(A.row_offsets, A.col_idx, A.values, x, abs_terms=True)
+    nz = sc_b > 0
+    bf["powerlaw2M"] = {"ms": round(t, 4), "gbs": round(Bb / (t * 1e-3) / 1e9, 2), "fp32_gbs": round(value, 2),
+                        "max_err_vs_bf16_oracle": float((np.abs(yb - ref_b)[nz] / sc_b[nz]).max()),
+                        "max_err_vs_fp32_oracle": float((np.abs(yb - ref_f)[sc_f > 0] / sc_f[sc_f > 0]).max())}
+    del Abd, xbd
+    L, xl = S.config_c3_laplacian()
+    Ld = lb.CSR.from_host(L, dev)
+    xld = torch.from_numpy(xl).to(dev)
+    yl = torch.empty(L.m, dtype=torch.float32, device=dev)
+    wsl = torch.empty(lb.workspace_size(Ld, "merge_path"), dtype=torch.uint8, device=dev)
+    tl = timed(lambda: lb.spmv(Ld, xld, "merge_path", y=yl, workspace=wsl), extra_steps, 2)
+    tlc = cold(lambda: lb.spmv(Ld, xld, "merge_path", y=yl, workspace=wsl), 5)
+    Lb = L.with_values(S.to_bf16_bits(L.values))
+    xlb = S.to_bf16_bits(xl)
+    Lbd = lb.CSR.from_host(Lb, dev)
+    xlbd = torch.from_numpy(xlb.view(np.int16).copy()).view(torch.bfloat16).to(dev)
+    tlb = timed(lambda: lb.spmv(Lbd, xlbd, "merge_path", y=yl, workspace=wsl), extra_steps, 2)
+    tlbc = cold(lambda: lb.spmv(Lbd, xlbd, "merge_path", y=yl, workspace=wsl), 5)
+    ylb = yl.cpu().numpy().astype(np.float64)
+    rl = oracle.spmv(L.row_offsets, L.col_idx, L.values, xl)
+    sl = oracle.spmv(L.row_offsets, L.col_idx, L.values, xl, abs_terms=True)
+    BL, BLb = spmv_bytes(L.m, L.n, L.nnz), spmv_bytes(L.m, L.n, L.nnz, 2, 2)
+    bf["laplacian2048"] = {"nnz": L.nnz, "fp32_ms": round(tl, 4), "fp32_gbs": round(BL / (tl * 1e-3) / 1e9, 2),
+                           "fp32_cold_gbs": round(BL / (tlc * 1e-3) / 1e9, 2),
+                           "bf16_ms": round(tlb, 4), "bf16_gbs": round(BLb / (tlb * 1e-3) / 1e9, 2),
+                           "bf16_cold_gbs": round(BLb / (tlbc * 1e-3) / 1e9, 2),
+                           "bf16_max_err_vs_fp32_oracle": float((np.abs(ylb - rl) / sl).max())}
+    result["bf16"] = bf
+    log(f"[bench] bf16: {bf}")
+    del Ld, Lbd, xld, xlbd, yl
+
+    # ------------------------------------------------------------ forward + backward (1M)
+    C4, x4 = S.config_c4()
+    C4d = lb.CSR.from_host(C4, dev)
+    x4d = torch.from_numpy(x4).to(dev)
+    dy4 = torch.from_numpy(S.random_vector(44, C4.m)).to(dev)
+    y4 = torch.empty(C4.m, dtype=torch.float32, device=dev)
+    ws4 = torch.empty(lb.workspace_size(C4d, "merge_path"), dtype=torch.uint8, device=dev)
+    tf = timed(lambda: lb.spmv(C4d, x4d, "merge_path", y=y4, workspace=ws4), extra_steps, 2)
+    tb = timed(lambda: lb.spmv_backward(C4d, x4d, dy4), extra_steps, 2)
+    bw_ms, _ = kernel_avg_ms(lambda: lb.spmv_backward(C4d, x4d, dy4), extra_steps, "backward")
+    Bf4, Bb4 = spmv_bytes(C4.m, C4.n, C4.nnz), backward_bytes(C4.m, C4.n, C4.nnz)
+    result["fwd_bwd_powerlaw1M"] = {"nnz": C4.nnz, "fwd_ms": round(tf, 4), "bwd_ms": round(tb, 4),
+                                    "fwd_gbs": round(Bf4 / (tf * 1e-3) / 1e9, 2),
+                                    "bwd_gbs": round(Bb4 / (tb * 1e-3) / 1e9, 2),
+                                    "bwd_kernel_ms": round(bw_ms, 4),
+                                    "fwd_bwd_gbs": round((Bf4 + Bb4) / ((tf + tb) * 1e-3) / 1e9, 2)}
+    log(f"[bench] fwd+bwd: {result['fwd_bwd_powerlaw1M']}")
+    del C4d, x4d, dy4, y4, ws4
+
+    # ------------------------------------------------------------ batched (512 matrices)
+    t0 = time.time()
+    BH = S.config_c5()
+    log(f"[bench] batched generated: {BH.count} matrices, nnz={BH.nnz} in {time.time() - t0:.1f}s")
+    Bd = lb.Batch.from_host(BH, dev)
+    bres = {"count": BH.count, "total_rows": BH.total_rows, "nnz": BH.nnz}
+    for k in (1, 8):
+        Xk = torch.from_numpy(S.random_vector(55, BH.total_cols * k).reshape(-1, k)).to(dev)
+        Yk = torch.empty((BH.total_rows, k), dtype=torch.float32, device=dev)
+        tuned = lb.tune_batched(Bd, k)
+        tk = timed(lambda: lb.batched_spmm(Bd, Xk, "auto", Y=Yk), extra_steps, 2)
+        Bk = BH.nnz * 8 + (BH.total_rows + 1) * 4 + BH.total_cols * 4 * k + BH.total_rows * 4 * k
+        bres[f"k{k}"] = {"ms": round(tk, 4), "gbs": round(Bk / (tk * 1e-3) / 1e9, 2),
+                         "gflops": round(2 * BH.nnz * k / (tk * 1e-3) / 1e9, 2), "schedule": tuned}
+        del Xk, Yk
+        log(f"[bench] batched k={k}: {bres[f'k{k}']}")
+    result["batched_512"] = bres
+
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -69,7 +69,8 @@ def _bind(lib):
     lib.orc_spmv_transpose.argtypes = [I64, I64, P, P, P, INT, P, INT, P]
     lib.orc_dvalues.argtypes = [I64, P, P, P, P, INT, P]
     lib.orc_merge_walk.argtypes = [I64, I64, P, I64, I64, P, P]
-    for f in ("orc_spmv", "orc_spmm", "orc_spmv_transpose", "orc_dvalues", "orc_merge_walk"):
+    lib.orc_num_threads.argtypes = []
+    for f in ("orc_spmv", "orc_spmm", "orc_spmv_transpose", "orc_dvalues", "orc_merge_walk", "orc_num_threads"):
         getattr(lib, f).restype = INT
     return lib
 
@@ -151,6 +152,9 @@ class Oracle:
         if rc:
             raise ValueError("orc_merge_walk rejected its arguments")
         return oi, oj
+
+    def num_threads(self) -> int:
+        return int(self.lib.orc_num_threads())
 
     def batched_spmm(self, batch, X):
         """Per-matrix SpMM; X holds the matrices' right-hand sides back to back

@@ -51,6 +51,20 @@ static int orc_dtype_ok(int dt) { return dt == ORC_F32 || dt == ORC_BF16 || dt =
 
 int orc_abi_version(void) { return 1; }
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads the parallel loops below use (1 without OpenMP). */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* y[r] = sum_j values[j] * x[col_idx[j]] over row r; optionally with |.| of
  * every term (abs_terms != 0), which gives the per-row tolerance scale. */
 int orc_spmv(int64_t m, const int32_t *row_offsets, const int32_t *col_idx,

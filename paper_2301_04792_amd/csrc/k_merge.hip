@@ -9,9 +9,9 @@
 //
 // Three launches:
 //  1. merge_partition_kernel: the split at every unit boundary d_t = t * W
-//     (W = BLOCK * ITEMS), one wavefront per boundary doing a 64-ary search
-//     (each step, 64 lanes probe 64 evenly spaced rows and a ballot narrows
-//     the range 64-fold: about 4 steps for 2M rows instead of 21).
+//     (W = BLOCK * ITEMS), one group of 16 lanes per boundary doing a 16-ary
+//     search (each round the lanes probe 16 evenly spaced rows and a ballot
+//     narrows the range 16-fold: 6 rounds for 2M rows instead of 21).
 //  2. merge_spmv_consume: block b owns units [d_b, d_{b+1}): rows
 //     [i_b, i_{b+1}) end in it and nonzeros [j_b, j_{b+1}) are consumed in
 //     it.  Setup stages the block's row ends and the products
@@ -33,33 +33,20 @@ using namespace lb;
 
 // ------------------------------------------------------------------ partition
 
+// One group of PG lanes per unit boundary (group_merge_search).
+constexpr int PG = 16;
+
 __global__ __launch_bounds__(256) void merge_partition_kernel(const int32_t *__restrict__ ro,
                                                               int32_t rows, int32_t nnz, int32_t W,
                                                               int32_t T, int32_t *__restrict__ part_i,
                                                               int32_t *__restrict__ part_j) {
-    const int lane = lane_id();
-    const int64_t t = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
-    if (t > T) return;  // whole wavefront leaves together
+    const int64_t t = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / PG;
+    const bool live = t <= T;  // uniform per group; every lane still takes part in the ballots
     const int64_t total = static_cast<int64_t>(rows) + nnz;
-    const int64_t d64 = t * W < total ? t * W : total;
-    const int32_t d = static_cast<int32_t>(d64);
-    // The answer lies in [lo, hi]; p(r) < d for r < lo and p(r) >= d for r >= hi.
-    int32_t lo = d - nnz > 0 ? d - nnz : 0;
-    int32_t hi = d < rows ? d : rows;
-    while (hi - lo > kWave) {
-        const int32_t step = (hi - lo + kWave - 1) / kWave;
-        const int32_t r = lo + (lane + 1) * step - 1;
-        const bool below = r < hi && ro[r + 1] + r < d;  // true on a lane prefix
-        const int32_t c = __popcll(__ballot(below));
-        const int32_t nlo = lo + c * step;
-        const int32_t rc = lo + (c + 1) * step - 1;      // first probe not below d
-        hi = rc < hi ? rc : hi;
-        lo = nlo;
-    }
-    const int32_t r = lo + lane;
-    const bool below = r < hi && ro[r + 1] + r < d;
-    const int32_t i = lo + __popcll(__ballot(below));
-    if (lane == 0) {
+    const int64_t tt = live ? t : T;
+    const int32_t d = static_cast<int32_t>(tt * W < total ? tt * W : total);
+    const int32_t i = group_merge_search<PG>(ro, rows, nnz, d);
+    if (live && (threadIdx.x & (PG - 1)) == 0) {
         part_i[t] = i;
         part_j[t] = d - i;
     }
@@ -68,8 +55,7 @@ __global__ __launch_bounds__(256) void merge_partition_kernel(const int32_t *__r
 hipError_t merge_partition(const int32_t *ro, int32_t rows, int32_t nnz, int32_t W, int32_t T,
                            int32_t *part_i, int32_t *part_j, hipStream_t s) {
     prof_scope p(s, "merge_partition");
-    const int64_t waves = static_cast<int64_t>(T) + 1;
-    const int64_t blocks = (waves * kWave + 255) / 256;
+    const int64_t blocks = ((static_cast<int64_t>(T) + 1) * PG + 255) / 256;
     hipLaunchKernelGGL(merge_partition_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s,
                        ro, rows, nnz, W, T, part_i, part_j);
     return hipGetLastError();
@@ -77,6 +63,10 @@ hipError_t merge_partition(const int32_t *ro, int32_t rows, int32_t nnz, int32_t
 
 // ------------------------------------------------------------------ consume
 
+// One block per unit (the hardware dispatcher balances blocks over CUs):
+// the kernel stays at ~20 VGPRs and full occupancy, which hides the stream
+// and gather latency better than a register prefetch pipeline that costs
+// occupancy.
 template <int BLOCK, int ITEMS, typename VT, typename XT>
 __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
     const int32_t *__restrict__ ro, const int32_t *__restrict__ ci, const VT *__restrict__ val,
@@ -94,7 +84,9 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
     int32_t *s_re = s_buf;
     float *s_pv = reinterpret_cast<float *>(s_buf + nrows);
 
-    // Setup: row ends relative to j0 (in [0, nnzs]) and products, coalesced.
+    // Setup: row ends relative to j0 (in [0, nnzs]) and products, coalesced;
+    // consecutive lanes take consecutive nonzeros so that the x gathers of a
+    // long row with sorted columns share cache lines.
     for (int k = tid; k < nrows; k += BLOCK) s_re[k] = ro[i0 + 1 + k] - j0;
     int32_t c[ITEMS];
     VT v[ITEMS];
@@ -160,28 +152,32 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
 
 // ------------------------------------------------------------------ fix-up
 
-// One thread per carry; the first carry of each run of equal rows adds the
-// run's sum (in block order, 16 at a time) to y[row].
+// One wavefront per carry entry b that starts a run of equal rows (b == 0 or
+// carry_row[b - 1] != carry_row[b]); other wavefronts leave at once.  The
+// wavefront reads the run 64 entries at a time (coalesced), adds each chunk
+// with a fixed butterfly and the chunks in order, and adds the total to the
+// row of y (kc columns).  Deterministic: no atomics.
 __global__ __launch_bounds__(256) void merge_fixup(int32_t T, int32_t rows, int32_t kc,
                                                    const int32_t *__restrict__ carry_row,
                                                    const float *__restrict__ carry_val,
                                                    float *__restrict__ y, int64_t ldy) {
-    const int64_t b = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int lane = lane_id();
+    const int64_t b = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
     if (b >= T) return;
     const int32_t r = carry_row[b];
-    if (r >= rows) return;
-    if (b > 0 && carry_row[b - 1] == r) return;
-    int64_t e = b + 1;
-    while (e < T && carry_row[e] == r) ++e;
+    if (r >= rows || (b > 0 && carry_row[b - 1] == r)) return;  // uniform across the wavefront
     for (int32_t c = 0; c < kc; ++c) {
         float total = 0.f;
-        for (int64_t s = b; s < e; s += 16) {
-            float part = 0.f;
-            const int64_t se = s + 16 < e ? s + 16 : e;
-            for (int64_t q = s; q < se; ++q) part += carry_val[q * kc + c];
-            total += part;
+        for (int64_t s = b;; s += kWave) {
+            const int64_t q = s + lane;
+            const bool in = q < T && carry_row[q] == r;
+            float v = in ? carry_val[q * kc + c] : 0.f;
+            v = group_sum<kWave>(v);
+            total += v;
+            // the run is contiguous: it ends inside this chunk unless every lane matched
+            if (__popcll(__ballot(in)) < kWave) break;
         }
-        y[static_cast<int64_t>(r) * ldy + c] += total;
+        if (lane == 0) y[static_cast<int64_t>(r) * ldy + c] += total;
     }
 }
 
@@ -189,7 +185,8 @@ hipError_t launch_fixup(int64_t T, int32_t rows, int32_t kc, const int32_t *carr
                         const float *carry_val, float *y, int64_t ldy, hipStream_t s, const char *tag) {
     if (T <= 0) return hipSuccess;
     prof_scope p(s, tag);
-    hipLaunchKernelGGL(merge_fixup, dim3(static_cast<uint32_t>((T + 255) / 256)), dim3(256), 0, s,
+    const int64_t blocks = (T * kWave + 255) / 256;
+    hipLaunchKernelGGL(merge_fixup, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s,
                        static_cast<int32_t>(T), rows, kc, carry_row, carry_val, y, ldy);
     return hipGetLastError();
 }
@@ -205,9 +202,9 @@ static hipError_t run_merge_spmv(const csr_dev &A, const void *x, float *y, void
     if (e != hipSuccess) return e;
     {
         prof_scope p(s, "merge_consume");
-        hipLaunchKernelGGL((merge_spmv_consume<BLOCK, ITEMS, VT, VT>), dim3(static_cast<uint32_t>(T)),
-                           dim3(BLOCK), 0, s, A.ro, A.ci, static_cast<const VT *>(A.val),
-                           static_cast<const VT *>(x), y, w.part_i, w.part_j, w.carry_row, w.carry_val);
+        hipLaunchKernelGGL((merge_spmv_consume<BLOCK, ITEMS, VT, VT>), dim3(static_cast<uint32_t>(T)), dim3(BLOCK), 0,
+                           s, A.ro, A.ci, static_cast<const VT *>(A.val), static_cast<const VT *>(x), y, w.part_i,
+                           w.part_j, w.carry_row, w.carry_val);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -23,27 +23,6 @@
 namespace lbk {
 using namespace lb;
 
-// 64-ary merge-path search by one wavefront: the number of row ends of the
-// merge that precede diagonal d (see k_merge.hip).
-__device__ __forceinline__ int32_t wave_merge_search(const int32_t *__restrict__ ro, int32_t rows, int32_t nnz,
-                                                     int32_t d) {
-    const int lane = lane_id();
-    int32_t lo = d - nnz > 0 ? d - nnz : 0;
-    int32_t hi = d < rows ? d : rows;
-    while (hi - lo > kWave) {
-        const int32_t step = (hi - lo + kWave - 1) / kWave;
-        const int32_t r = lo + (lane + 1) * step - 1;
-        const bool below = r < hi && ro[r + 1] + r < d;
-        const int32_t c = __popcll(__ballot(below));
-        const int32_t rc = lo + (c + 1) * step - 1;
-        hi = rc < hi ? rc : hi;
-        lo = lo + c * step;
-    }
-    const int32_t r = lo + lane;
-    const bool below = r < hi && ro[r + 1] + r < d;
-    return lo + __popcll(__ballot(below));
-}
-
 template <int BLOCK, int ITEMS, int KC, bool BATCHED, typename VT>
 __global__ __launch_bounds__(BLOCK) void merge_spmm_consume(
     int32_t rows, int32_t nnz, int32_t T, const int32_t *__restrict__ ro, const int32_t *__restrict__ ci,

@@ -81,6 +81,47 @@ struct thread_mapped_schedule {
     __device__ step_range atoms(int64_t tile) const { return {ts.atoms_begin(tile), ts.atoms_end(tile), 1}; }
 };
 
+// ---------------------------------------------------------------- merge-path split (Sec. 5.2.1)
+
+// Number of row ends of the merge of row_offsets[1..rows] with the nonzero
+// indices 0..nnz-1 that precede diagonal d (row end r is the
+// (r + row_offsets[r + 1])-th merge item), found by an aligned group of G
+// lanes (G a power of two <= 64) with a G-ary search: each step the G lanes
+// probe G evenly spaced rows and a ballot narrows the range G-fold.  All
+// lanes of the wavefront must execute it (the ballot spans the wavefront);
+// every lane of a group returns the same value.
+template <int G>
+__device__ __forceinline__ int32_t group_merge_search(const int32_t *__restrict__ ro, int32_t rows, int32_t nnz,
+                                                      int32_t d) {
+    const int gl = threadIdx.x & (G - 1);
+    const int shift = (threadIdx.x & (kWave - 1)) & ~(G - 1);
+    const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1);
+    // p(r) < d for r < lo, p(r) >= d for r >= hi; the answer lies in [lo, hi]
+    int32_t lo = d - nnz > 0 ? d - nnz : 0;
+    int32_t hi = d < rows ? d : rows;
+    for (;;) {
+        const bool wide = hi - lo > G;
+        if (__ballot(wide) == 0) break;  // every group of the wavefront has narrowed down
+        const int32_t step = wide ? (hi - lo + G - 1) / G : 1;
+        const int32_t r = lo + (gl + 1) * step - 1;
+        const bool below = wide && r < hi && ro[r + 1] + r < d;  // true on a prefix of the group
+        const int32_t c = __popcll((__ballot(below) >> shift) & gmask);
+        if (wide) {
+            const int32_t rc = lo + (c + 1) * step - 1;  // first probe not below d
+            hi = rc < hi ? rc : hi;
+            lo = lo + c * step;
+        }
+    }
+    const int32_t r = lo + gl;
+    const bool below = r < hi && ro[r + 1] + r < d;
+    return lo + __popcll((__ballot(below) >> shift) & gmask);
+}
+
+__device__ __forceinline__ int32_t wave_merge_search(const int32_t *__restrict__ ro, int32_t rows, int32_t nnz,
+                                                     int32_t d) {
+    return group_merge_search<kWave>(ro, rows, nnz, d);
+}
+
 // ---------------------------------------------------------------- wave64 collectives
 
 // Sum over aligned groups of G lanes (G a power of two <= 64); every lane of

@@ -1,0 +1,126 @@
+"""Parity at the full workload sizes, in the launch configurations the bench
+times, checked row by row against the FP64 oracle (fast enough at these
+sizes with the OpenMP oracle)."""
+import numpy as np
+import pytest
+
+import oracle
+import synthetic as S
+from tests.gpu_util import assert_rows_close, oracle_spmv
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2301_04792_amd as lb  # noqa: E402
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def powerlaw2m():
+    A, x = S.config_c2()
+    ref, scale = oracle_spmv(A, x)
+    return A, x, ref, scale
+
+
+@pytest.mark.parametrize("name,params", [("merge_path", {}), ("merge_path", {"block_size": 512, "items_per_thread": 8}),
+                                         ("merge_path", {"block_size": 256, "items_per_thread": 12}),
+                                         ("group_mapped", {"group_size": 64}), ("thread_mapped", {})])
+def test_powerlaw2m(powerlaw2m, name, params):
+    A, x, ref, scale = powerlaw2m
+    print(f"[powerlaw2M nnz={A.nnz} {name} {params}]", flush=True)
+    Ad = lb.CSR.from_host(A, DEV)
+    y = lb.spmv(Ad, torch.from_numpy(x).to(DEV), name, **params)
+    worst = assert_rows_close(y.cpu().numpy(), ref, scale, what=f"powerlaw2M {name}")
+    print(f"  max err / sum|a x| = {worst:.3e}", flush=True)
+
+
+def test_powerlaw2m_tuned(powerlaw2m):
+    A, x, ref, scale = powerlaw2m
+    Ad = lb.CSR.from_host(A, DEV)
+    xd = torch.from_numpy(x).to(DEV)
+    lb.autotune_clear()
+    best = lb.tune(Ad)
+    print(f"[powerlaw2M tuned: {best}]", flush=True)
+    y1 = lb.spmv(Ad, xd, "auto")
+    y2 = lb.spmv(Ad, xd, "auto")
+    assert_rows_close(y1.cpu().numpy(), ref, scale, what="powerlaw2M tuned")
+    if best["schedule"] == "merge_path":
+        assert torch.equal(y1, y2)  # deterministic forward
+    lb.autotune_clear()
+
+
+def test_powerlaw2m_bf16(powerlaw2m):
+    A, x, ref32, scale32 = powerlaw2m
+    Ab = A.with_values(S.to_bf16_bits(A.values))
+    xb = S.to_bf16_bits(x)
+    Ad = lb.CSR.from_host(Ab, DEV)
+    xd = torch.from_numpy(xb.view(np.int16).copy()).view(torch.bfloat16).to(DEV)
+    y = lb.spmv(Ad, xd, "merge_path").cpu().numpy()
+    ref, scale = oracle_spmv(Ab, xb)
+    assert_rows_close(y, ref, scale, what="powerlaw2M bf16")
+    u = 2.0 ** -8
+    worst = assert_rows_close(y, ref32, scale32, rtol=2 * u + u * u + 2e-5, what="bf16 vs fp32 inputs")
+    print(f"  bf16 vs fp32-input oracle: max err / sum|a x| = {worst:.3e}", flush=True)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_laplacian2048(dtype):
+    L, x = S.config_c3_laplacian()
+    if dtype == "bf16":
+        L = L.with_values(S.to_bf16_bits(L.values))
+        xh = S.to_bf16_bits(x)
+        xd = torch.from_numpy(xh.view(np.int16).copy()).view(torch.bfloat16).to(DEV)
+    else:
+        xh = x
+        xd = torch.from_numpy(x).to(DEV)
+    Ld = lb.CSR.from_host(L, DEV)
+    for params in ({}, {"block_size": 256, "items_per_thread": 12}):
+        y = lb.spmv(Ld, xd, "merge_path", **params).cpu().numpy()
+        ref, scale = oracle_spmv(L, xh)
+        assert_rows_close(y, ref, scale, what=f"laplacian {dtype} {params}")
+
+
+def test_powerlaw1m_forward_backward():
+    A, x = S.config_c4()
+    dy = S.random_vector(44, A.m)
+    Ad = lb.CSR.from_host(A, DEV)
+    xd = torch.from_numpy(x).to(DEV)
+    y = lb.spmv(Ad, xd, "merge_path").cpu().numpy()
+    ref, scale = oracle_spmv(A, x)
+    assert_rows_close(y, ref, scale, what="powerlaw1M forward")
+    dx, dv = lb.spmv_backward(Ad, xd, torch.from_numpy(dy).to(DEV))
+    d64 = dy.astype(np.float64)
+    rdx = oracle.spmv_transpose(A.row_offsets, A.col_idx, A.values, d64, A.n)
+    rdxs = oracle.spmv_transpose(A.row_offsets, A.col_idx, A.values, d64, A.n, abs_terms=True)
+    assert_rows_close(dx.cpu().numpy(), rdx, rdxs, what="powerlaw1M dx")
+    rdv = oracle.dvalues(A.row_offsets, A.col_idx, d64, x)
+    assert np.array_equal(dv.cpu().numpy(), rdv.astype(np.float32)), "dvalues not bit-exact"
+
+
+@pytest.fixture(scope="module")
+def batch512():
+    return S.config_c5()
+
+
+@pytest.mark.parametrize("k", [1, 8])
+def test_batched512(batch512, k):
+    B = batch512
+    print(f"[batched {B.count} matrices nnz={B.nnz} k={k}]", flush=True)
+    X = S.random_vector(55, B.total_cols * k).reshape(-1, k)
+    Bd = lb.Batch.from_host(B, DEV)
+    Xd = torch.from_numpy(X).to(DEV)
+    lb.autotune_clear()
+    best = lb.tune_batched(Bd, k)
+    Y = lb.batched_spmm(Bd, Xd, "auto").cpu().numpy().reshape(-1, k)
+    lb.autotune_clear()
+    ref = oracle.batched_spmm(B, X)
+    scale = np.empty_like(ref)
+    for b in range(B.count):
+        Ab = B.matrix(b)
+        c0, r0 = int(B.mat_col_base[b]), int(B.mat_row_base[b])
+        scale[r0:r0 + Ab.m] = oracle.spmm(Ab.row_offsets, Ab.col_idx, Ab.values, X[c0:c0 + Ab.n], abs_terms=True)
+    assert_rows_close(Y, ref, scale, what=f"batched k={k} {best}")
