@@ -18,7 +18,7 @@ using namespace lb;
 
 template <int BLOCK, int ITEMS, typename VT, bool WANT_DX, bool WANT_DV>
 __global__ __launch_bounds__(BLOCK) void merge_backward_kernel(
-    const int32_t *__restrict__ ro, const int32_t *__restrict__ ci, const VT *__restrict__ val,
+    int32_t rows, int32_t nnz, const int32_t *__restrict__ ro, const int32_t *__restrict__ ci, const VT *__restrict__ val,
     const VT *__restrict__ x, const float *__restrict__ dy, float *__restrict__ dx, float *__restrict__ dvalues,
     const int32_t *__restrict__ part_i, const int32_t *__restrict__ part_j) {
     constexpr int W = BLOCK * ITEMS;
@@ -31,7 +31,26 @@ __global__ __launch_bounds__(BLOCK) void merge_backward_kernel(
     const int32_t nrows = i1 - i0, nnzs = j1 - j0;
     int32_t *s_re = s_buf;
     int32_t *s_row = s_buf + nrows;
-    for (int k = tid; k < nrows; k += BLOCK) s_re[k] = ro[i0 + 1 + k] - j0;
+    // Row ends, and this thread's share of the nonzero streams: unconditional
+    // loads with indices clamped into the unit (see k_merge.hip).
+    const int32_t re_last = i1 > i0 ? i1 : i0 + 1 <= rows ? i0 + 1 : rows;
+    const int32_t nz_last = nnzs > 0 ? j1 - 1 : (j0 < nnz ? j0 : nnz - 1);
+    int32_t re[ITEMS], cc[ITEMS];
+    VT vv[ITEMS];
+#pragma unroll
+    for (int u = 0; u < ITEMS; ++u) {
+        const int32_t k = tid + u * BLOCK;
+        const int32_t rk = i0 + 1 + k;
+        const int32_t jk = j0 + k;
+        re[u] = ro[rk < re_last ? rk : re_last];
+        cc[u] = ld_stream(ci + (jk < nz_last ? jk : nz_last));
+        if constexpr (WANT_DX) vv[u] = ld_stream(val + (jk < nz_last ? jk : nz_last));
+    }
+#pragma unroll
+    for (int u = 0; u < ITEMS; ++u) {
+        const int k = tid + u * BLOCK;
+        if (k < nrows) s_re[k] = re[u] - j0;
+    }
     __syncthreads();
 
     const int32_t total = nrows + nnzs;
@@ -55,15 +74,23 @@ __global__ __launch_bounds__(BLOCK) void merge_backward_kernel(
     }
     __syncthreads();
 
+    float g[ITEMS], xv[ITEMS];
+#pragma unroll
+    for (int u = 0; u < ITEMS; ++u) {
+        const int k = tid + u * BLOCK;
+        // labels exist for k < nnzs; other lanes read a valid row and discard it
+        const int32_t lab = nnzs > 0 ? s_row[k < nnzs ? k : nnzs - 1] : 0;
+        const int32_t r = i0 + lab < rows ? i0 + lab : rows - 1;
+        g[u] = dy[r];
+        if constexpr (WANT_DV) xv[u] = to_f32(x[cc[u]]);
+    }
 #pragma unroll
     for (int u = 0; u < ITEMS; ++u) {
         const int k = tid + u * BLOCK;
         if (k < nnzs) {
             const int64_t j = static_cast<int64_t>(j0) + k;
-            const float g = dy[i0 + s_row[k]];
-            const int32_t c = ld_stream(ci + j);
-            if constexpr (WANT_DV) dvalues[j] = g * to_f32(x[c]);
-            if constexpr (WANT_DX) unsafeAtomicAdd(dx + c, to_f32(ld_stream(val + j)) * g);
+            if constexpr (WANT_DV) dvalues[j] = g[u] * xv[u];
+            if constexpr (WANT_DX) unsafeAtomicAdd(dx + cc[u], to_f32(vv[u]) * g[u]);
         }
     }
 }
@@ -81,13 +108,13 @@ static hipError_t run_backward(const csr_dev &A, const void *x, const float *dy,
     const VT *xv = static_cast<const VT *>(x);
     const VT *vv = static_cast<const VT *>(A.val);
     if (dx && dvalues)
-        hipLaunchKernelGGL((merge_backward_kernel<BLOCK, ITEMS, VT, true, true>), g, dim3(BLOCK), 0, s, A.ro, A.ci, vv,
+        hipLaunchKernelGGL((merge_backward_kernel<BLOCK, ITEMS, VT, true, true>), g, dim3(BLOCK), 0, s, A.rows, A.nnz, A.ro, A.ci, vv,
                            xv, dy, dx, dvalues, w.part_i, w.part_j);
     else if (dx)
-        hipLaunchKernelGGL((merge_backward_kernel<BLOCK, ITEMS, VT, true, false>), g, dim3(BLOCK), 0, s, A.ro, A.ci,
+        hipLaunchKernelGGL((merge_backward_kernel<BLOCK, ITEMS, VT, true, false>), g, dim3(BLOCK), 0, s, A.rows, A.nnz, A.ro, A.ci,
                            vv, xv, dy, dx, dvalues, w.part_i, w.part_j);
     else
-        hipLaunchKernelGGL((merge_backward_kernel<BLOCK, ITEMS, VT, false, true>), g, dim3(BLOCK), 0, s, A.ro, A.ci,
+        hipLaunchKernelGGL((merge_backward_kernel<BLOCK, ITEMS, VT, false, true>), g, dim3(BLOCK), 0, s, A.rows, A.nnz, A.ro, A.ci,
                            vv, xv, dy, dx, dvalues, w.part_i, w.part_j);
     return hipGetLastError();
 }

@@ -69,7 +69,7 @@ hipError_t merge_partition(const int32_t *ro, int32_t rows, int32_t nnz, int32_t
 // occupancy.
 template <int BLOCK, int ITEMS, typename VT, typename XT>
 __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
-    const int32_t *__restrict__ ro, const int32_t *__restrict__ ci, const VT *__restrict__ val,
+    int32_t rows, int32_t nnz, const int32_t *__restrict__ ro, const int32_t *__restrict__ ci, const VT *__restrict__ val,
     const XT *__restrict__ x, float *__restrict__ y, const int32_t *__restrict__ part_i,
     const int32_t *__restrict__ part_j, int32_t *__restrict__ carry_row, float *__restrict__ carry_val) {
     constexpr int W = BLOCK * ITEMS;
@@ -86,22 +86,33 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
 
     // Setup: row ends relative to j0 (in [0, nnzs]) and products, coalesced;
     // consecutive lanes take consecutive nonzeros so that the x gathers of a
-    // long row with sorted columns share cache lines.
-    for (int k = tid; k < nrows; k += BLOCK) s_re[k] = ro[i0 + 1 + k] - j0;
-    int32_t c[ITEMS];
+    // long row with sorted columns share cache lines.  Every stream load is
+    // issued before the first wait, then every gather, then the LDS writes
+    // (nrows <= W, so ITEMS row ends per thread cover the unit).
+    // Loads are unconditional with indices clamped into the unit (repeats hit
+    // the same cache line), so the compiler's wait counts stay exact and all
+    // ITEMS gathers of a lane are in flight together.
+    const int32_t re_last = i1 > i0 ? i1 : i0 + 1 <= rows ? i0 + 1 : rows;  // a valid row_offsets index
+    const int32_t nz_last = nnzs > 0 ? j1 - 1 : (j0 < nnz ? j0 : nnz - 1);  // a valid nonzero index
+    int32_t re[ITEMS], c[ITEMS];
     VT v[ITEMS];
+    float xv[ITEMS];
 #pragma unroll
     for (int u = 0; u < ITEMS; ++u) {
-        const int k = tid + u * BLOCK;
-        if (k < nnzs) {
-            c[u] = ld_stream(ci + j0 + k);
-            v[u] = ld_stream(val + j0 + k);
-        }
+        const int32_t k = tid + u * BLOCK;
+        const int32_t rk = i0 + 1 + k;
+        const int32_t jk = j0 + k;
+        re[u] = ro[rk < re_last ? rk : re_last];
+        c[u] = ld_stream(ci + (jk < nz_last ? jk : nz_last));
+        v[u] = ld_stream(val + (jk < nz_last ? jk : nz_last));
     }
 #pragma unroll
+    for (int u = 0; u < ITEMS; ++u) xv[u] = to_f32(x[c[u]]);
+#pragma unroll
     for (int u = 0; u < ITEMS; ++u) {
         const int k = tid + u * BLOCK;
-        if (k < nnzs) s_pv[k] = to_f32(v[u]) * to_f32(x[c[u]]);
+        if (k < nrows) s_re[k] = re[u] - j0;
+        if (k < nnzs) s_pv[k] = to_f32(v[u]) * xv[u];
     }
     __syncthreads();
 
@@ -203,7 +214,7 @@ static hipError_t run_merge_spmv(const csr_dev &A, const void *x, float *y, void
     {
         prof_scope p(s, "merge_consume");
         hipLaunchKernelGGL((merge_spmv_consume<BLOCK, ITEMS, VT, VT>), dim3(static_cast<uint32_t>(T)), dim3(BLOCK), 0,
-                           s, A.ro, A.ci, static_cast<const VT *>(A.val), static_cast<const VT *>(x), y, w.part_i,
+                           s, A.rows, A.nnz, A.ro, A.ci, static_cast<const VT *>(A.val), static_cast<const VT *>(x), y, w.part_i,
                            w.part_j, w.carry_row, w.carry_val);
         e = hipGetLastError();
         if (e != hipSuccess) return e;

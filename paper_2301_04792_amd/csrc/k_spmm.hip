@@ -65,13 +65,27 @@ __global__ __launch_bounds__(BLOCK) void merge_spmm_consume(
         const int32_t nrows = i1 - i0, nnzs = j1 - j0;
         int32_t *s_re = s_buf;
         int32_t *s_col = s_buf + nrows;
-        for (int k = tid; k < nrows; k += BLOCK) s_re[k] = ro[i0 + 1 + k] - j0;
+        // unconditional loads, indices clamped into the unit (see k_merge.hip)
+        const int32_t re_last = i1 > i0 ? i1 : i0 + 1 <= rows ? i0 + 1 : rows;
+        const int32_t nz_last = nnzs > 0 ? j1 - 1 : (j0 < nnz ? j0 : nnz - 1);
+        int32_t re[ITEMS], cc[ITEMS];
+        VT vv[ITEMS];
+#pragma unroll
+        for (int q = 0; q < ITEMS; ++q) {
+            const int32_t k = tid + q * BLOCK;
+            const int32_t rk = i0 + 1 + k;
+            const int32_t jk = j0 + k;
+            re[q] = ro[rk < re_last ? rk : re_last];
+            cc[q] = ld_stream(ci + (jk < nz_last ? jk : nz_last));
+            vv[q] = ld_stream(val + (jk < nz_last ? jk : nz_last));
+        }
 #pragma unroll
         for (int q = 0; q < ITEMS; ++q) {
             const int k = tid + q * BLOCK;
+            if (k < nrows) s_re[k] = re[q] - j0;
             if (k < nnzs) {
-                s_col[k] = ld_stream(ci + j0 + k);
-                s_val[k] = to_f32(ld_stream(val + j0 + k));
+                s_col[k] = cc[q];
+                s_val[k] = to_f32(vv[q]);
             }
         }
         __syncthreads();
