@@ -55,6 +55,121 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+# ---------------------------------------------------------------- rocprofv3 summaries
+
+def _read_csv(path):
+    import csv
+
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def _find(dirpath, suffix):
+    for root, _, files in os.walk(dirpath):
+        for fn in sorted(files):
+            if fn.endswith(suffix):
+                return os.path.join(root, fn)
+    return None
+
+
+def _counter_per_dispatch(rows, kernel_substr, counter):
+    """Mean counter value per dispatch of the matching kernel instance that
+    was dispatched most often (the timed configuration)."""
+    by_name = {}
+    for r in rows:
+        if kernel_substr in r.get("Kernel_Name", "") and r.get("Counter_Name") == counter:
+            by_name.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    if not by_name:
+        return None, 0, ""
+    name = max(by_name, key=lambda k: len(by_name[k]))
+    vals = by_name[name]
+    return sum(vals) / len(vals), len(vals), name
+
+
+def summarize_profiles(out_dir, prof_root):
+    """Write profiles/*.md and the traffic JSON from rocprofv3 CSV output
+    (made by the commands recorded in each summary)."""
+    os.makedirs(out_dir, exist_ok=True)
+    cmd_trace = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_trace -o trace -- "
+                 "python3 bench.py --quick --no-cpu --schedule merge_path --steps 10 --warmup 3")
+    stats = _find(os.path.join(prof_root, "prof_trace"), "kernel_stats.csv")
+    if stats:
+        rows = _read_csv(stats)
+        lines = ["# Kernel trace: power-law 2M SpMV, merge-path (bench --quick)", "",
+                 f"Command: `{cmd_trace}`", "",
+                 "| kernel | calls | avg µs | min µs | max µs | % time |", "|---|---|---|---|---|---|"]
+        for r in rows[:12]:
+            name = r["Name"]
+            name = name if len(name) < 110 else name[:107] + "..."
+            lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                         f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+        with open(os.path.join(out_dir, "merge_consume_powerlaw2M_kernel_trace.md"), "w") as f:
+            f.write("\n".join(lines) + "\n")
+    fetch = _find(os.path.join(prof_root, "prof_fetch"), "counter_collection.csv")
+    write = _find(os.path.join(prof_root, "prof_write"), "counter_collection.csv")
+    if fetch and write:
+        fr, wr = _read_csv(fetch), _read_csv(write)
+        kern = "merge_spmv_consume"
+        f_k, nf, name_f = _counter_per_dispatch(fr, kern, "FETCH_SIZE")
+        w_k, nw, name_w = _counter_per_dispatch(wr, kern, "WRITE_SIZE")
+        # calibration: the 256 MiB device copy run by bench.py --pmc-calib (reads and writes 2^28 bytes)
+        copy_f = [float(r["Counter_Value"]) for r in fr if r.get("Counter_Name") == "FETCH_SIZE"
+                  and "copy" in r.get("Kernel_Name", "").lower()]
+        copy_w = [float(r["Counter_Value"]) for r in wr if r.get("Counter_Name") == "WRITE_SIZE"
+                  and "copy" in r.get("Kernel_Name", "").lower()]
+        if f_k is not None and w_k is not None and copy_f and copy_w and name_f == name_w:
+            known = float(1 << 28)
+            ff = known / (max(copy_f) * 1024.0)
+            fw = known / (max(copy_w) * 1024.0)
+            read_b = f_k * 1024.0 * ff
+            write_b = w_k * 1024.0 * fw
+            name = name_f
+            import re as _re
+
+            m = _re.search(r"merge_spmv_consume<(\d+), (\d+),", name)
+            data = {"kernel": kern, "workload": "powerlaw_m2M_zipf1.8_cap200k_empty10pct",
+                    "kernel_source_hash": kernel_source_hash(),
+                    "block_size": int(m.group(1)) if m else None, "items_per_thread": int(m.group(2)) if m else None,
+                    "fetch_kb_per_dispatch": f_k, "write_kb_per_dispatch": w_k, "dispatches": [nf, nw],
+                    "copy_calibration": {"known_bytes": known, "fetch_kb": max(copy_f), "write_kb": max(copy_w),
+                                         "fetch_factor": ff, "write_factor": fw},
+                    "hbm_read_bytes_per_launch": read_b, "hbm_write_bytes_per_launch": write_b,
+                    "hbm_bytes_per_launch": read_b + write_b,
+                    "commands": [
+                        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof_fetch -o fetch -- "
+                        "python3 bench.py --quick --no-cpu --schedule merge_path --steps 3 --warmup 1 --pmc-calib",
+                        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof_write -o write -- "
+                        "python3 bench.py --quick --no-cpu --schedule merge_path --steps 3 --warmup 1 --pmc-calib"]}
+            try:
+                import synthetic as S
+
+                A, _ = S.config_c2()
+                data["nnz"] = A.nnz
+                data["algorithmic_bytes_per_launch"] = spmv_bytes(A.m, A.n, A.nnz)
+            except Exception:  # noqa: BLE001
+                pass
+            with open(TRAFFIC_FILE, "w") as f:
+                json.dump(data, f, indent=1)
+            lines = ["# HBM traffic of merge_spmv_consume on the power-law 2M matrix (rocprofv3 PMC)", "",
+                     *[f"Command: `{c}`" for c in data["commands"]], "",
+                     f"kernel: `{name[:120]}`", "",
+                     f"- FETCH_SIZE per dispatch: {f_k:.0f} KB; WRITE_SIZE per dispatch: {w_k:.0f} KB ({nf}/{nw} dispatches)",
+                     f"- calibration copy (2^28 bytes read and written): FETCH_SIZE {max(copy_f):.0f} KB, "
+                     f"WRITE_SIZE {max(copy_w):.0f} KB -> factors {ff:.3f} (read), {fw:.3f} (write)",
+                     f"- HBM bytes per launch: read {read_b / 1e6:.1f} MB + write {write_b / 1e6:.1f} MB = "
+                     f"{(read_b + write_b) / 1e6:.1f} MB",
+                     f"- algorithmic bytes per launch: {data.get('algorithmic_bytes_per_launch', 0) / 1e6:.1f} MB",
+                     "",
+                     "FETCH_SIZE counts the bytes L2 fetches over the fabric (from the Infinity Cache or HBM).",
+                     "On the copy and on the 1 GiB streaming probe it reads about half the known bytes, so the",
+                     "scale factor assumes every fetch is counted like those streaming fetches; the consume",
+                     "kernel's fetches are dominated by full-line fills for random x gathers, so the scaled",
+                     "figure is an upper estimate and the unscaled one a lower estimate."]
+            with open(os.path.join(out_dir, "merge_consume_powerlaw2M_pmc_traffic.md"), "w") as f:
+                f.write("\n".join(lines) + "\n")
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,7 +183,11 @@ def main():
                     help="headline schedule: auto (autotuned) or merge_path / group_mapped / thread_mapped")
     ap.add_argument("--pmc-calib", action="store_true",
                     help="also run one 256 MiB device copy (known bytes) to scale rocprofv3 FETCH/WRITE_SIZE")
+    ap.add_argument("--summarize-profiles", metavar="DIR",
+                    help="write profiles/ summaries from rocprofv3 CSV output under DIR and exit")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        return summarize_profiles(os.path.join(ROOT, "profiles"), args.summarize_profiles)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
@@ -173,6 +292,18 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    # ceilings measured live: streaming read of 1 GiB, and the x gather alone
+    pout = torch.empty(lb._lib.lb_probe_default_grid() * 256, dtype=torch.float32, device=dev)
+    lb.probe_stream_read(flush, pout)
+    stream_ms, _ = kernel_avg_ms(lambda: lb.probe_stream_read(flush, pout), 5, "probe_stream")
+    gather_ms, _ = kernel_avg_ms(lambda: lb.probe_gather(Ad.col_idx, xd, pout), 5, "probe_gather")
+    ceilings = {"stream_read_gbs": round(flush.numel() * 4 / (stream_ms * 1e-3) / 1e9, 1),
+                "gather_only_ms": round(gather_ms, 5),
+                "gather_bound_gbs": round(B / (gather_ms * 1e-3) / 1e9, 1),
+                "note": "gather_only = sum of x[col_idx[j]] over all nonzeros; no SpMV kernel on this "
+                        "matrix can finish faster, so gather_bound_gbs caps its effective bandwidth"}
+    log(f"[bench] ceilings: {ceilings}")
+
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         try:
@@ -205,6 +336,7 @@ def main():
         "algorithmic_bytes": B,
         "cold_ms_per_call": round(ms_cold, 5),
         "cold_gbs": round(B / (ms_cold * 1e-3) / 1e9, 2),
+        "ceilings": ceilings,
         "roofline": {"kernel": dominant, "bound": "hbm", "achieved": round(achieved, 2),
                      "peak": PEAK_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_GBS, 4),
                      "traffic": traffic, "avg_launch_ms": round(consume_ms, 5), "launches": launches,

@@ -86,7 +86,9 @@ typedef struct lb_csr_t {
  *  items_per_thread  LB_MERGE_PATH: merge items (row ends + nonzeros) per
  *                    thread, one of 4, 8, 12, 16 (default 8).
  *  block_size        threads per block: thread-mapped 64..1024 (default 256);
- *                    merge-path one of 128, 256, 512 (default 256);
+ *                    merge-path one of 128, 256, 512 (default 256); SpMM
+ *                    and batched passes take up to 8 columns of X at a
+ *                    time, fewer for large block_size * items_per_thread;
  *                    group-mapped derived from group_size (ignored).
  *  grid_size         blocks; 0 = one block per chunk of work. */
 typedef struct lb_schedule_t {
@@ -182,9 +184,10 @@ LB_API lb_status_t lb_batched_workspace_size(const lb_batch_t *B, const lb_sched
 
 /* For every matrix b of the batch, Y_b = A_b X_b.  X holds the matrices'
  * right-hand sides back to back, row-major total_cols x k; Y row-major
- * total_rows x k float32, overwritten.  All matrices run in one persistent
- * launch over a single merge path of sum(m_b + nnz_b) items (Sec. 5.1
- * persistent ranges), followed by one carry fix-up launch.  s->kind must be
+ * total_rows x k float32, overwritten.  One launch splits the single merge
+ * path of sum(m_b + nnz_b) items into units, one persistent launch (Sec. 5.1
+ * persistent ranges) consumes every unit of every matrix, and one launch
+ * adds the carries (per pass of up to 8 columns).  s->kind must be
  * LB_MERGE_PATH or LB_AUTO.  1 <= k <= 64. */
 LB_API lb_status_t lb_batched_spmm(const lb_batch_t *B, const void *X, lb_dtype_t x_dtype,
                                    int32_t k, float *Y, const lb_schedule_t *s, void *workspace,
@@ -230,6 +233,22 @@ LB_API void lb_autotune_clear(void);
 /* Debug check of the device-only CSR preconditions; synchronizes `stream`.
  * Returns LB_OK or LB_ERR_INVALID_CSR. */
 LB_API lb_status_t lb_validate_csr(const lb_csr_t *A, void *stream);
+
+/* Measurement hooks (not part of the method): the ceilings a kernel of this
+ * library is compared with.
+ *  lb_probe_stream_read: reads `bytes` (a multiple of 16, 16-byte aligned
+ *    device buffer) with non-temporal 16-byte loads and writes one partial
+ *    sum per thread to out[grid * 256] (grid = 0 picks CUs x 8); the
+ *    streaming-read ceiling of HBM.
+ *  lb_probe_gather: sum over j of x[idx[j]] for j in [0, n) (idx read
+ *    non-temporally, x gathered through the caches), one partial sum per
+ *    thread to out[grid * 256]; with a matrix's col_idx as idx it times the
+ *    x gather alone, the floor of any SpMV kernel on that matrix.
+ * Both are asynchronous on `stream`; idx values must lie in x's range. */
+LB_API lb_status_t lb_probe_stream_read(const void *buf, size_t bytes, float *out, int32_t grid, void *stream);
+LB_API lb_status_t lb_probe_gather(const int32_t *idx, int64_t n, const float *x, float *out, int32_t grid,
+                                   void *stream);
+LB_API int32_t lb_probe_default_grid(void);
 
 /* Kernel timing.  While enabled, every launch made by this library records a
  * pair of HIP events on its stream.  lb_profile_read synchronizes those

@@ -299,8 +299,6 @@ def tune_batched(batch: Batch, k: int = 1) -> dict:
     need = 0
     for b in (128, 256, 512):
         for it in (4, 8, 12, 16):
-            if b * it > 4096:
-                continue
             n = ctypes.c_size_t(0)
             s = make_schedule("merge_path", items_per_thread=it, block_size=b)
             if _lib.lb_batched_workspace_size(ctypes.byref(c), ctypes.byref(s), k, ctypes.byref(n)) == _abi.OK:
@@ -343,6 +341,24 @@ def validate(A: CSR) -> bool:
         return False
     _abi.check(st, "lb_validate_csr")
     return True
+
+
+def probe_stream_read(buf: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Launch the streaming-read probe over `buf` (measurement hook)."""
+    grid = _lib.lb_probe_default_grid()
+    out = out if out is not None else torch.empty(grid * 256, dtype=torch.float32, device=buf.device)
+    _abi.check(_lib.lb_probe_stream_read(_ptr(buf), buf.numel() * buf.element_size(), _ptr(out), grid,
+                                         _stream(buf.device)), "lb_probe_stream_read")
+    return out
+
+
+def probe_gather(idx: torch.Tensor, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Launch the gather probe: partial sums of x[idx] (measurement hook)."""
+    grid = _lib.lb_probe_default_grid()
+    out = out if out is not None else torch.empty(grid * 256, dtype=torch.float32, device=x.device)
+    _abi.check(_lib.lb_probe_gather(_ptr(idx), idx.numel(), _ptr(x), _ptr(out), grid, _stream(x.device)),
+               "lb_probe_gather")
+    return out
 
 
 def profile_enable(on: bool = True):

@@ -86,6 +86,9 @@ SIGNATURES = {
     "lb_batched_autotune": (ST, [PBATCH, P, ST, I32, P, P, SZ, PSCHED, P]),
     "lb_autotune_clear": (None, []),
     "lb_validate_csr": (ST, [PCSR, P]),
+    "lb_probe_stream_read": (ST, [P, SZ, P, I32, P]),
+    "lb_probe_gather": (ST, [P, I64, P, P, I32, P]),
+    "lb_probe_default_grid": (I32, []),
     "lb_profile_enable": (None, [ctypes.c_int]),
     "lb_profile_reset": (None, []),
     "lb_profile_read": (ST, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]),

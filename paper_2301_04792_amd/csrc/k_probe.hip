@@ -1,0 +1,51 @@
+// Measurement probes: the streaming-read ceiling of HBM and the cost of the
+// x gather alone, used to place the SpMV kernels on a roofline.
+#include "lb_device.h"
+#include "lb_internal.h"
+
+namespace lbk {
+using namespace lb;
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void probe_stream_kernel(const f32x4 *__restrict__ p, int64_t n4,
+                                                           float *__restrict__ out) {
+    float a = 0.f;
+    for (int64_t i : grid_stride_range(0, n4)) {
+        const f32x4 v = __builtin_nontemporal_load(p + i);
+        a += (v.x + v.y) + (v.z + v.w);
+    }
+    out[static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x] = a;
+}
+
+__global__ __launch_bounds__(256) void probe_gather_kernel(const int32_t *__restrict__ idx, int64_t n,
+                                                           const float *__restrict__ x, float *__restrict__ out) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const int32_t c0 = ld_stream(idx + i), c1 = ld_stream(idx + i + stride);
+        const int32_t c2 = ld_stream(idx + i + 2 * stride), c3 = ld_stream(idx + i + 3 * stride);
+        a0 += x[c0];
+        a1 += x[c1];
+        a2 += x[c2];
+        a3 += x[c3];
+    }
+    for (; i < n; i += stride) a0 += x[ld_stream(idx + i)];
+    out[static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x] = (a0 + a1) + (a2 + a3);
+}
+
+hipError_t probe_stream_read(const void *buf, size_t bytes, float *out, int grid, hipStream_t s) {
+    prof_scope p(s, "probe_stream");
+    hipLaunchKernelGGL(probe_stream_kernel, dim3(grid), dim3(256), 0, s, static_cast<const f32x4 *>(buf),
+                       static_cast<int64_t>(bytes / 16), out);
+    return hipGetLastError();
+}
+
+hipError_t probe_gather(const int32_t *idx, int64_t n, const float *x, float *out, int grid, hipStream_t s) {
+    prof_scope p(s, "probe_gather");
+    hipLaunchKernelGGL(probe_gather_kernel, dim3(grid), dim3(256), 0, s, idx, n, x, out);
+    return hipGetLastError();
+}
+
+}  // namespace lbk

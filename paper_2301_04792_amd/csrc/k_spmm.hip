@@ -2,70 +2,139 @@
 //
 // Y[r, :] = sum_j values[j] * X[col_idx[j], :].  The SpMM listing of
 // Sec. 5.3 wraps the SpMV loop in a loop over B's columns; here the column
-// loop sits inside the atom loop instead, so each nonzero's (col, value) is
-// read once per pass and KC (<= 8) contiguous columns of X are gathered per
-// nonzero.  k > KC runs ceil(k / KC) passes over the matrix.
+// loop sits inside the atom loop instead: a pass handles KC contiguous
+// columns of X, gathering KC values per nonzero, and k > KC runs
+// ceil(k / KC) passes over the matrix.
 //
-// The merge-path split and carry handling are those of k_merge.hip, with KC
-// partial sums per thread and per carry.
+// Per unit (the merge-path split and carry handling of k_merge.hip):
+// row ends and the KC products values[j] * X[col_idx[j], c] of every
+// nonzero are staged in LDS with all loads of a lane issued before the
+// first wait; the threads then walk their ITEMS merge items over LDS with
+// KC partial sums each.  KC is the largest of 8, 4, 2, 1 whose products fit
+// the LDS budget (W * KC * 4 bytes <= 48 KB) and keep ITEMS * KC <= 32
+// gathers per lane in registers.
 //
-// Batched: matrices stored back to back form one block-diagonal matrix whose
-// merged sequence of sum(m_b) row ends and sum(nnz_b) nonzeros is cut into
-// units of W items.  One persistent launch (grid = CUs x resident blocks)
-// loops over the units (Sec. 5.1 persistent ranges; every block leaves once
-// the unit index passes the last unit).  Each unit's split is searched
-// inside the kernel by two wavefronts (64-ary search, as in the partition
-// kernel).  A nonzero's X row is col_base[b] + col_idx[j] for the matrix b
-// that owns its row; each thread tracks b as it walks rows.
+// Batched: matrices stored back to back form one block-diagonal matrix
+// whose merged sequence of sum(m_b) row ends and sum(nnz_b) nonzeros is cut
+// into units of W items by the split launch.  One persistent launch (grid =
+// CUs x resident blocks) then loops over the units (Sec. 5.1 persistent
+// ranges; every block leaves once its unit index passes the last unit).
+// A nonzero's X row is col_base[b] + col_idx[j] for the matrix b that owns
+// it: two wavefronts find the matrices of the unit's first and last rows;
+// only a unit that straddles matrices searches the owner per nonzero.
 #include "lb_device.h"
 #include "lb_internal.h"
 
 namespace lbk {
 using namespace lb;
 
-template <int BLOCK, int ITEMS, int KC, bool BATCHED, typename VT>
+template <int BLOCK, int ITEMS>
+struct spmm_shape {
+    static constexpr int W = BLOCK * ITEMS;
+    static constexpr int LDS_KC = W * 8 * 4 <= 49152 ? 8 : W * 4 * 4 <= 49152 ? 4 : W * 2 * 4 <= 49152 ? 2 : 1;
+    static constexpr int REG_KC = ITEMS <= 4 ? 8 : ITEMS <= 8 ? 4 : 2;
+    static constexpr int KC = LDS_KC < REG_KC ? LDS_KC : REG_KC;  // columns per pass (max)
+};
+
+// Number of entries of the sorted int64 array a[0..n) that are <= key, by
+// one wavefront (64-ary search); every lane returns it.
+__device__ __forceinline__ int32_t wave_count_le(const int64_t *__restrict__ a, int32_t n, int64_t key) {
+    const int lane = lane_id();
+    int32_t lo = 0, hi = n;  // a[r] <= key for r < lo, a[r] > key for r >= hi
+    while (__ballot(hi - lo > kWave) != 0) {
+        const int32_t step = (hi - lo + kWave - 1) / kWave;
+        const int32_t r = lo + (lane + 1) * step - 1;
+        const bool le = r < hi && a[r] <= key;
+        const int32_t c = __popcll(__ballot(le));
+        const int32_t rc = lo + (c + 1) * step - 1;
+        hi = rc < hi ? rc : hi;
+        lo = lo + c * step;
+    }
+    const int32_t r = lo + lane;
+    return lo + __popcll(__ballot(r < hi && a[r] <= key));
+}
+
+// KC consecutive values of one X row; VECX: the row start is aligned to the
+// load width (16 bytes, or 4 * KC bytes for narrower rows), so whole vectors
+// are read.
+template <int KC, bool VECX>
+__device__ __forceinline__ void load_row(const float *p, float (&o)[KC]) {
+    if constexpr (VECX && KC % 4 == 0) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+        for (int c = 0; c < KC; c += 4) {
+            const f4 v = *reinterpret_cast<const f4 *>(p + c);
+            o[c] = v.x, o[c + 1] = v.y, o[c + 2] = v.z, o[c + 3] = v.w;
+        }
+    } else if constexpr (VECX && KC == 2) {
+        typedef float f2 __attribute__((ext_vector_type(2)));
+        const f2 v = *reinterpret_cast<const f2 *>(p);
+        o[0] = v.x, o[1] = v.y;
+    } else {
+#pragma unroll
+        for (int c = 0; c < KC; ++c) o[c] = p[c];
+    }
+}
+
+template <int KC, bool VECX>
+__device__ __forceinline__ void load_row(const bf16_bits *p, float (&o)[KC]) {
+    if constexpr (VECX && KC % 8 == 0) {
+        typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+        for (int c = 0; c < KC; c += 8) {
+            const u4 v = *reinterpret_cast<const u4 *>(p + c);
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) o[c + 2 * e] = __uint_as_float(w[e] << 16), o[c + 2 * e + 1] = __uint_as_float(w[e] & 0xffff0000u);
+        }
+    } else if constexpr (VECX && KC == 4) {
+        typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+        const u2 v = *reinterpret_cast<const u2 *>(p);
+        o[0] = __uint_as_float(v.x << 16), o[1] = __uint_as_float(v.x & 0xffff0000u);
+        o[2] = __uint_as_float(v.y << 16), o[3] = __uint_as_float(v.y & 0xffff0000u);
+    } else if constexpr (VECX && KC == 2) {
+        const uint32_t v = *reinterpret_cast<const uint32_t *>(p);
+        o[0] = __uint_as_float(v << 16), o[1] = __uint_as_float(v & 0xffff0000u);
+    } else {
+#pragma unroll
+        for (int c = 0; c < KC; ++c) o[c] = to_f32(p[c]);
+    }
+}
+
+template <int BLOCK, int ITEMS, int KC, bool BATCHED, bool VECX, typename VT>
 __global__ __launch_bounds__(BLOCK) void merge_spmm_consume(
     int32_t rows, int32_t nnz, int32_t T, const int32_t *__restrict__ ro, const int32_t *__restrict__ ci,
     const VT *__restrict__ val, const VT *__restrict__ X, int64_t ldx, float *__restrict__ Y, int64_t ldy,
     const int32_t *__restrict__ part_i, const int32_t *__restrict__ part_j, int32_t *__restrict__ carry_row,
     float *__restrict__ carry_val, int32_t count, const int64_t *__restrict__ row_base,
-    const int64_t *__restrict__ col_base) {
+    const int64_t *__restrict__ nnz_base, const int64_t *__restrict__ col_base) {
     constexpr int W = BLOCK * ITEMS;
-    __shared__ int32_t s_buf[W];  // row ends [0, nrows), then column indices [nrows, nrows + nnzs)
-    __shared__ float s_val[W];
+    __shared__ float s_buf[W * KC];  // row ends (int) [0, nrows), then products [nrows + k * KC + c]
     __shared__ seg_t s_wave[BLOCK / kWave];
-    __shared__ int32_t s_split[4];
+    __shared__ int32_t s_mat[2];
 
     const int tid = threadIdx.x;
-    for (int64_t u = blockIdx.x; u < T; u += gridDim.x) {  // one unit per block without BATCHED
-        int32_t i0, j0, i1, j1;
+    for (int32_t u = blockIdx.x; u < T; u += gridDim.x) {  // one unit per block unless persistent
+        const int32_t i0 = part_i[u], j0 = part_j[u], i1 = part_i[u + 1], j1 = part_j[u + 1];
+        const int32_t nrows = i1 - i0, nnzs = j1 - j0;
+        int32_t *s_re = reinterpret_cast<int32_t *>(s_buf);
+        float *s_pv = s_buf + nrows;
+
+        int32_t mat_lo = 0, mat_hi = 0;
         if constexpr (BATCHED) {
-            const int64_t total = static_cast<int64_t>(rows) + nnz;
             const int w = wave_id();
             if (w < 2) {
-                const int64_t d64 = (u + w) * W < total ? (u + w) * W : total;
-                const int32_t d = static_cast<int32_t>(d64);
-                const int32_t i = wave_merge_search(ro, rows, nnz, d);
-                if (lane_id() == 0) {
-                    s_split[2 * w] = i;
-                    s_split[2 * w + 1] = d - i;
-                }
+                const int64_t r = w == 0 ? i0 : (i1 < rows ? i1 : rows - 1);
+                int32_t m = wave_count_le(row_base, count + 1, r) - 1;  // last b with row_base[b] <= r
+                m = m < 0 ? 0 : (m > count - 1 ? count - 1 : m);
+                if (lane_id() == 0) s_mat[w] = m;
             }
             __syncthreads();
-            i0 = s_split[0];
-            j0 = s_split[1];
-            i1 = s_split[2];
-            j1 = s_split[3];
-        } else {
-            i0 = part_i[u];
-            j0 = part_j[u];
-            i1 = part_i[u + 1];
-            j1 = part_j[u + 1];
+            mat_lo = s_mat[0];
+            mat_hi = s_mat[1];
         }
-        const int32_t nrows = i1 - i0, nnzs = j1 - j0;
-        int32_t *s_re = s_buf;
-        int32_t *s_col = s_buf + nrows;
-        // unconditional loads, indices clamped into the unit (see k_merge.hip)
+
+        // Unconditional loads with indices clamped into the unit.
         const int32_t re_last = i1 > i0 ? i1 : i0 + 1 <= rows ? i0 + 1 : rows;
         const int32_t nz_last = nnzs > 0 ? j1 - 1 : (j0 < nnz ? j0 : nnz - 1);
         int32_t re[ITEMS], cc[ITEMS];
@@ -79,13 +148,43 @@ __global__ __launch_bounds__(BLOCK) void merge_spmm_consume(
             cc[q] = ld_stream(ci + (jk < nz_last ? jk : nz_last));
             vv[q] = ld_stream(val + (jk < nz_last ? jk : nz_last));
         }
+        int64_t xrow[ITEMS];
+        if constexpr (BATCHED) {
+            if (mat_lo == mat_hi) {
+                const int64_t cb = col_base[mat_lo];
+#pragma unroll
+                for (int q = 0; q < ITEMS; ++q) xrow[q] = cb + cc[q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < ITEMS; ++q) {
+                    const int32_t jk = j0 + tid + q * BLOCK;
+                    const int64_t j = jk < nz_last ? jk : nz_last;
+                    int32_t lo = mat_lo, hi = mat_hi;  // nnz_base[mat_lo] <= j
+                    while (lo < hi) {
+                        const int32_t mid = (lo + hi + 1) >> 1;
+                        if (nnz_base[mid] <= j)
+                            lo = mid;
+                        else
+                            hi = mid - 1;
+                    }
+                    xrow[q] = col_base[lo] + cc[q];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < ITEMS; ++q) xrow[q] = cc[q];
+        }
+        float g[ITEMS][KC];
+#pragma unroll
+        for (int q = 0; q < ITEMS; ++q) load_row<KC, VECX>(X + xrow[q] * ldx, g[q]);
 #pragma unroll
         for (int q = 0; q < ITEMS; ++q) {
             const int k = tid + q * BLOCK;
             if (k < nrows) s_re[k] = re[q] - j0;
             if (k < nnzs) {
-                s_col[k] = cc[q];
-                s_val[k] = to_f32(vv[q]);
+                const float v = to_f32(vv[q]);
+#pragma unroll
+                for (int c = 0; c < KC; ++c) s_pv[k * KC + c] = v * g[q][c];
             }
         }
         __syncthreads();
@@ -104,63 +203,33 @@ __global__ __launch_bounds__(BLOCK) void merge_spmm_consume(
         }
         int32_t it = lo, jt = d - lo;
 
-        // Matrix owning the current row (batched only).
-        int32_t mat = 0;
-        int64_t next_base = 0x7fffffffffffffffLL, cbase = 0;
-        if constexpr (BATCHED) {
-            const int64_t r0 = static_cast<int64_t>(i0) + it;
-            // first matrix with row_base[b + 1] > r0
-            int32_t blo = 0, bhi = count;
-            while (blo < bhi) {
-                const int32_t mid = (blo + bhi) >> 1;
-                if (row_base[mid + 1] <= r0)
-                    blo = mid + 1;
-                else
-                    bhi = mid;
-            }
-            mat = blo < count ? blo : count - 1;
-            next_base = row_base[mat + 1];
-            cbase = col_base[mat];
-        }
-
-        float acc[KC];
-        float first_sum[KC];
+        float acc[KC], first_sum[KC];
 #pragma unroll
         for (int c = 0; c < KC; ++c) acc[c] = first_sum[c] = 0.f;
         int32_t first = -1;
         for (int32_t q = d; q < dend; ++q) {
             if (it < nrows && s_re[it] <= jt) {
-                float *yrow = Y + static_cast<int64_t>(i0 + it) * ldy;
                 if (first < 0) {
                     first = it;
 #pragma unroll
                     for (int c = 0; c < KC; ++c) first_sum[c] = acc[c];
                 } else {
+                    float *yrow = Y + static_cast<int64_t>(i0 + it) * ldy;
 #pragma unroll
                     for (int c = 0; c < KC; ++c) yrow[c] = acc[c];
                 }
 #pragma unroll
                 for (int c = 0; c < KC; ++c) acc[c] = 0.f;
                 ++it;
-                if constexpr (BATCHED) {
-                    while (static_cast<int64_t>(i0) + it >= next_base && mat + 1 < count) {
-                        ++mat;
-                        next_base = row_base[mat + 1];
-                        cbase = col_base[mat];
-                    }
-                }
             } else {
-                const float v = s_val[jt];
-                const VT *xr = X + (cbase + s_col[jt]) * ldx;
 #pragma unroll
-                for (int c = 0; c < KC; ++c) acc[c] += v * to_f32(xr[c]);
+                for (int c = 0; c < KC; ++c) acc[c] += s_pv[jt * KC + c];
                 ++jt;
             }
         }
 
         const int flag = first >= 0;
-        float in[KC];
-        float tot[KC];
+        float in[KC], tot[KC];
 #pragma unroll
         for (int c = 0; c < KC; ++c) {
             seg_t t;
@@ -175,144 +244,123 @@ __global__ __launch_bounds__(BLOCK) void merge_spmm_consume(
         if (tid == 0) {
             carry_row[u] = i1;
 #pragma unroll
-            for (int c = 0; c < KC; ++c) carry_val[u * KC + c] = tot[c];
+            for (int c = 0; c < KC; ++c) carry_val[static_cast<int64_t>(u) * KC + c] = tot[c];
         }
-        __syncthreads();  // LDS is reused by the next unit
+        // block_seg_scan_excl ended with a barrier: LDS is free for the next unit
     }
 }
 
-template <int BLOCK, int ITEMS, int KC, typename VT>
-static hipError_t run_spmm_pass(const csr_dev &A, const VT *X, int64_t ldx, float *Y, int64_t ldy, void *ws,
-                                bool partitioned, hipStream_t s) {
-    constexpr int W = BLOCK * ITEMS;
-    const int64_t T = merge_units(A.rows, A.nnz, W);
-    merge_ws w = merge_ws_carve(ws, T);
-    if (!partitioned) {
-        hipError_t e = merge_partition(A.ro, A.rows, A.nnz, W, static_cast<int32_t>(T), w.part_i, w.part_j, s);
-        if (e != hipSuccess) return e;
-    }
-    {
-        prof_scope p(s, "merge_consume");
-        hipLaunchKernelGGL((merge_spmm_consume<BLOCK, ITEMS, KC, false, VT>), dim3(static_cast<uint32_t>(T)),
-                           dim3(BLOCK), 0, s, A.rows, A.nnz, static_cast<int32_t>(T), A.ro, A.ci,
-                           static_cast<const VT *>(A.val), X, ldx, Y, ldy, w.part_i, w.part_j, w.carry_row,
-                           w.carry_val, 0, nullptr, nullptr);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return launch_fixup(T, A.rows, KC, w.carry_row, w.carry_val, Y, ldy, s, "merge_fixup");
-}
-
-template <int BLOCK, int ITEMS, typename VT>
-static hipError_t run_spmm(const csr_dev &A, const VT *X, int32_t k, int64_t ldx, float *Y, int64_t ldy, void *ws,
-                           hipStream_t s) {
-    int32_t c0 = 0;
-    bool partitioned = false;
-    while (c0 < k) {
-        const int32_t left = k - c0;
-        hipError_t e;
-        if (left >= 8)
-            e = run_spmm_pass<BLOCK, ITEMS, 8, VT>(A, X + c0, ldx, Y + c0, ldy, ws, partitioned, s), c0 += 8;
-        else if (left >= 4)
-            e = run_spmm_pass<BLOCK, ITEMS, 4, VT>(A, X + c0, ldx, Y + c0, ldy, ws, partitioned, s), c0 += 4;
-        else if (left >= 2)
-            e = run_spmm_pass<BLOCK, ITEMS, 2, VT>(A, X + c0, ldx, Y + c0, ldy, ws, partitioned, s), c0 += 2;
-        else
-            e = run_spmm_pass<BLOCK, ITEMS, 1, VT>(A, X + c0, ldx, Y + c0, ldy, ws, partitioned, s), c0 += 1;
-        if (e != hipSuccess) return e;
-        partitioned = true;  // the split depends only on the matrix
-    }
-    return hipSuccess;
-}
-
-// W = BLOCK * ITEMS <= 4096 keeps the two LDS arrays within 32 KB.
-#define LB_MERGE_CONFIGS(X) \
-    X(128, 4) X(128, 8) X(128, 12) X(128, 16) \
-    X(256, 4) X(256, 8) X(256, 12) X(256, 16) \
-    X(512, 4) X(512, 8)
-
-hipError_t merge_spmm(const csr_dev &A, const void *X, int32_t k, int64_t ldx, float *Y, int64_t ldy, int block,
-                      int items, void *ws, hipStream_t s) {
-#define X_(B, I)                                                                                               \
-    if (block == B && items == I) {                                                                            \
-        if (A.dt == LB_BF16)                                                                                   \
-            return run_spmm<B, I, bf16_bits>(A, static_cast<const bf16_bits *>(X), k, ldx, Y, ldy, ws, s);     \
-        return run_spmm<B, I, float>(A, static_cast<const float *>(X), k, ldx, Y, ldy, ws, s);                 \
-    }
-    LB_MERGE_CONFIGS(X_)
-#undef X_
-    return hipErrorInvalidValue;
-}
-
-// ------------------------------------------------------------------ batched
-
-// Resident blocks per CU for the persistent grid, from the occupancy API.
+// Resident blocks (CUs x occupancy) for the persistent launch.
 template <typename K>
-static int persistent_grid(K kernel, int block, int64_t units) {
+static int resident_grid(K kernel, int block) {
     int dev = 0, cus = 256, per_cu = 1;
     if (hipGetDevice(&dev) == hipSuccess) {
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0);
     }
-    int64_t g = static_cast<int64_t>(cus) * (per_cu > 0 ? per_cu : 1);
-    if (g > units) g = units;
-    return static_cast<int>(g < 1 ? 1 : g);
+    return cus * (per_cu > 0 ? per_cu : 1);
 }
 
-size_t batched_ws_bytes(const batch_dev &B, int block, int items, int k) {
-    const int64_t T = merge_units(B.total_rows, B.total_nnz, static_cast<int64_t>(block) * items);
-    const int kc = k >= 8 ? 8 : (k >= 4 ? 4 : (k >= 2 ? 2 : 1));
-    return merge_ws_bytes(T, kc);
+struct spmm_problem {
+    int32_t rows, nnz;
+    const int32_t *ro, *ci;
+    const void *val;
+    int32_t count;
+    const int64_t *row_base, *nnz_base, *col_base;
+};
+
+template <int BLOCK, int ITEMS, int KC, bool BATCHED, bool VECX, typename VT>
+static hipError_t spmm_launch(const spmm_problem &P, const merge_ws &w, int64_t T, const VT *X, int64_t ldx, float *Y,
+                              int64_t ldy, hipStream_t s) {
+    auto kern = merge_spmm_consume<BLOCK, ITEMS, KC, BATCHED, VECX, VT>;
+    int64_t grid = T;
+    if (BATCHED) {
+        static const int resident = resident_grid(kern, BLOCK);
+        grid = T < resident ? T : resident;
+    }
+    prof_scope p(s, BATCHED ? "batched_consume" : "merge_consume");
+    hipLaunchKernelGGL(kern, dim3(static_cast<uint32_t>(grid)), dim3(BLOCK), 0, s, P.rows, P.nnz,
+                       static_cast<int32_t>(T), P.ro, P.ci, static_cast<const VT *>(P.val), X, ldx, Y, ldy, w.part_i,
+                       w.part_j, w.carry_row, w.carry_val, P.count, P.row_base, P.nnz_base, P.col_base);
+    return hipGetLastError();
 }
 
-template <int BLOCK, int ITEMS, int KC, typename VT>
-static hipError_t run_batched_pass(const batch_dev &B, const VT *X, int32_t k, float *Y, void *ws, hipStream_t s) {
+template <int BLOCK, int ITEMS, int KC, bool BATCHED, typename VT>
+static hipError_t spmm_pass(const spmm_problem &P, const merge_ws &w, int64_t T, const VT *X, int64_t ldx, float *Y,
+                            int64_t ldy, hipStream_t s) {
+    // whole-vector X rows: the pass's first column and the row stride keep
+    // every row start aligned to the vector width
+    constexpr size_t vbytes = KC * sizeof(VT) < 16 ? KC * sizeof(VT) : 16;
+    const bool vecx = KC > 1 && reinterpret_cast<uintptr_t>(X) % vbytes == 0 &&
+                      (static_cast<size_t>(ldx) * sizeof(VT)) % vbytes == 0;
+    const hipError_t e = vecx ? spmm_launch<BLOCK, ITEMS, KC, BATCHED, true, VT>(P, w, T, X, ldx, Y, ldy, s)
+                              : spmm_launch<BLOCK, ITEMS, KC, BATCHED, false, VT>(P, w, T, X, ldx, Y, ldy, s);
+    if (e != hipSuccess) return e;
+    return launch_fixup(T, P.rows, KC, w.carry_row, w.carry_val, Y, ldy, s, BATCHED ? "batched_fixup" : "merge_fixup");
+}
+
+// One split launch, then passes of at most KC columns.
+template <int BLOCK, int ITEMS, bool BATCHED, typename VT>
+static hipError_t run_spmm(const spmm_problem &P, const VT *X, int32_t k, int64_t ldx, float *Y, int64_t ldy, void *ws,
+                           hipStream_t s) {
     constexpr int W = BLOCK * ITEMS;
-    const int64_t T = merge_units(B.total_rows, B.total_nnz, W);
-    merge_ws w = merge_ws_carve(ws, T);
-    auto kern = merge_spmm_consume<BLOCK, ITEMS, KC, true, VT>;
-    const int grid = persistent_grid(kern, BLOCK, T);
-    {
-        prof_scope p(s, "batched_consume");
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), 0, s, B.total_rows, B.total_nnz, static_cast<int32_t>(T),
-                           B.ro, B.ci, static_cast<const VT *>(B.val), X, static_cast<int64_t>(k), Y,
-                           static_cast<int64_t>(k), nullptr, nullptr, w.carry_row, w.carry_val, B.count, B.row_base,
-                           B.col_base);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return launch_fixup(T, B.total_rows, KC, w.carry_row, w.carry_val, Y, k, s, "batched_fixup");
-}
-
-template <int BLOCK, int ITEMS, typename VT>
-static hipError_t run_batched(const batch_dev &B, const VT *X, int32_t k, float *Y, void *ws, hipStream_t s) {
-    int32_t c0 = 0;
-    while (c0 < k) {
+    constexpr int KC = spmm_shape<BLOCK, ITEMS>::KC;
+    const int64_t T = merge_units(P.rows, P.nnz, W);
+    const merge_ws w = merge_ws_carve(ws, T);
+    hipError_t e = merge_partition(P.ro, P.rows, P.nnz, W, static_cast<int32_t>(T), w.part_i, w.part_j, s);
+    for (int32_t c0 = 0; c0 < k && e == hipSuccess;) {
         const int32_t left = k - c0;
-        hipError_t e;
-        if (left >= 8)
-            e = run_batched_pass<BLOCK, ITEMS, 8, VT>(B, X + c0, k, Y + c0, ws, s), c0 += 8;
-        else if (left >= 4)
-            e = run_batched_pass<BLOCK, ITEMS, 4, VT>(B, X + c0, k, Y + c0, ws, s), c0 += 4;
-        else if (left >= 2)
-            e = run_batched_pass<BLOCK, ITEMS, 2, VT>(B, X + c0, k, Y + c0, ws, s), c0 += 2;
-        else
-            e = run_batched_pass<BLOCK, ITEMS, 1, VT>(B, X + c0, k, Y + c0, ws, s), c0 += 1;
-        if (e != hipSuccess) return e;
+        if (KC >= 8 && left >= 8) {
+            e = spmm_pass<BLOCK, ITEMS, (KC >= 8 ? 8 : 1), BATCHED, VT>(P, w, T, X + c0, ldx, Y + c0, ldy, s);
+            c0 += 8;
+        } else if (KC >= 4 && left >= 4) {
+            e = spmm_pass<BLOCK, ITEMS, (KC >= 4 ? 4 : 1), BATCHED, VT>(P, w, T, X + c0, ldx, Y + c0, ldy, s);
+            c0 += 4;
+        } else if (KC >= 2 && left >= 2) {
+            e = spmm_pass<BLOCK, ITEMS, (KC >= 2 ? 2 : 1), BATCHED, VT>(P, w, T, X + c0, ldx, Y + c0, ldy, s);
+            c0 += 2;
+        } else {
+            e = spmm_pass<BLOCK, ITEMS, 1, BATCHED, VT>(P, w, T, X + c0, ldx, Y + c0, ldy, s);
+            c0 += 1;
+        }
     }
-    return hipSuccess;
+    return e;
 }
 
-hipError_t batched_spmm(const batch_dev &B, const void *X, int32_t k, float *Y, int block, int items, void *ws,
-                        hipStream_t s) {
-#define X_(B_, I)                                                                                           \
-    if (block == B_ && items == I) {                                                                        \
-        if (B.dt == LB_BF16) return run_batched<B_, I, bf16_bits>(B, static_cast<const bf16_bits *>(X), k, Y, ws, s); \
-        return run_batched<B_, I, float>(B, static_cast<const float *>(X), k, Y, ws, s);                    \
+#define LB_MERGE_CONFIGS(X) \
+    X(128, 4) X(128, 8) X(128, 12) X(128, 16) \
+    X(256, 4) X(256, 8) X(256, 12) X(256, 16) \
+    X(512, 4) X(512, 8) X(512, 12) X(512, 16)
+
+template <bool BATCHED>
+static hipError_t dispatch(const spmm_problem &P, lb_dtype_t dt, const void *X, int32_t k, int64_t ldx, float *Y,
+                           int64_t ldy, int block, int items, void *ws, hipStream_t s) {
+#define X_(B, I)                                                                                                  \
+    if (block == B && items == I) {                                                                               \
+        if (dt == LB_BF16)                                                                                        \
+            return run_spmm<B, I, BATCHED, bf16_bits>(P, static_cast<const bf16_bits *>(X), k, ldx, Y, ldy, ws, s); \
+        return run_spmm<B, I, BATCHED, float>(P, static_cast<const float *>(X), k, ldx, Y, ldy, ws, s);           \
     }
     LB_MERGE_CONFIGS(X_)
 #undef X_
     return hipErrorInvalidValue;
+}
+
+hipError_t merge_spmm(const csr_dev &A, const void *X, int32_t k, int64_t ldx, float *Y, int64_t ldy, int block,
+                      int items, void *ws, hipStream_t s) {
+    const spmm_problem P{A.rows, A.nnz, A.ro, A.ci, A.val, 0, nullptr, nullptr, nullptr};
+    return dispatch<false>(P, A.dt, X, k, ldx, Y, ldy, block, items, ws, s);
+}
+
+size_t batched_ws_bytes(const batch_dev &B, int block, int items, int k) {
+    const int64_t T = merge_units(B.total_rows, B.total_nnz, static_cast<int64_t>(block) * items);
+    return merge_ws_bytes(T, k >= 8 ? 8 : (k >= 4 ? 4 : (k >= 2 ? 2 : 1)));
+}
+
+hipError_t batched_spmm(const batch_dev &B, const void *X, int32_t k, float *Y, int block, int items, void *ws,
+                        hipStream_t s) {
+    const spmm_problem P{B.total_rows, B.total_nnz, B.ro, B.ci, B.val, B.count, B.row_base, B.nnz_base, B.col_base};
+    return dispatch<true>(P, B.dt, X, k, static_cast<int64_t>(k), Y, static_cast<int64_t>(k), block, items, ws, s);
 }
 
 }  // namespace lbk

@@ -110,6 +110,10 @@ hipError_t group_mapped_spmv(const csr_dev &A, const void *x, float *y, int grou
                              int tiles_per_group, int grid, hipStream_t s);
 hipError_t group_tile_owner(const csr_dev &A, int tiles_per_group, int32_t *owner, hipStream_t s);
 
+// ---- measurement probes -----------------------------------------------------------------
+hipError_t probe_stream_read(const void *buf, size_t bytes, float *out, int grid, hipStream_t s);
+hipError_t probe_gather(const int32_t *idx, int64_t n, const float *x, float *out, int grid, hipStream_t s);
+
 // ---- utilities ------------------------------------------------------------------------
 hipError_t fill_f32(float *p, int64_t n, float v, hipStream_t s);
 // Writes violation flags (bit 0: offsets, bit 1: columns) into *flags_dev.

@@ -141,7 +141,7 @@ def test_spmm_backward_batched_host_checks():
     assert L.lb_spmm(ctypes.byref(A), FAKE, _abi.F32, 0, 1, FAKE, 1, ctypes.byref(s), FAKE, 1 << 30, None) == _abi.ERR_INVALID_ARG
     assert L.lb_spmm(ctypes.byref(A), FAKE, _abi.F32, 4, 2, FAKE, 4, ctypes.byref(s), FAKE, 1 << 30, None) == _abi.ERR_INVALID_ARG
     big = sched("merge_path", block_size=512, items_per_thread=16)
-    assert L.lb_spmm(ctypes.byref(A), FAKE, _abi.F32, 4, 4, FAKE, 4, ctypes.byref(big), FAKE, 1 << 30, None) == _abi.ERR_UNSUPPORTED
+    assert L.lb_spmm(ctypes.byref(A), FAKE, _abi.F32, 4, 4, FAKE, 4, ctypes.byref(big), FAKE, 16, None) == _abi.ERR_WORKSPACE_TOO_SMALL
     gm = sched("group_mapped")
     assert L.lb_spmm(ctypes.byref(A), FAKE, _abi.F32, 4, 4, FAKE, 4, ctypes.byref(gm), FAKE, 1 << 30, None) == _abi.ERR_UNSUPPORTED
     assert L.lb_spmv_backward(ctypes.byref(A), FAKE, _abi.F32, FAKE, FAKE, FAKE, ctypes.byref(gm), FAKE, 1 << 30, None) == _abi.ERR_UNSUPPORTED
