@@ -304,14 +304,17 @@ def main():
                         "matrix can finish faster, so gather_bound_gbs caps its effective bandwidth"}
     log(f"[bench] ceilings: {ceilings}")
 
-    traffic = None
+    traffic, traffic_cfg = None, None
     if os.path.exists(TRAFFIC_FILE):
         try:
             with open(TRAFFIC_FILE) as f:
                 tr = json.load(f)
-            if tr.get("kernel_source_hash") == kernel_source_hash() and tr.get("nnz") == A.nnz and \
-                    tr.get("items_per_thread") == sched["items_per_thread"] and tr.get("block_size") == sched["block_size"]:
+            if tr.get("kernel_source_hash") == kernel_source_hash() and tr.get("nnz") == A.nnz \
+                    and dominant == "merge_consume":
                 traffic = tr.get("hbm_bytes_per_launch")
+                traffic_cfg = {"block_size": tr.get("block_size"), "items_per_thread": tr.get("items_per_thread"),
+                               "unscaled_bytes": round((tr.get("fetch_kb_per_dispatch", 0) +
+                                                        tr.get("write_kb_per_dispatch", 0)) * 1024)}
         except (OSError, ValueError):
             traffic = None
 
@@ -339,7 +342,8 @@ def main():
         "ceilings": ceilings,
         "roofline": {"kernel": dominant, "bound": "hbm", "achieved": round(achieved, 2),
                      "peak": PEAK_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_GBS, 4),
-                     "traffic": traffic, "avg_launch_ms": round(consume_ms, 5), "launches": launches,
+                     "traffic": traffic, "traffic_profiled_config": traffic_cfg,
+                     "avg_launch_ms": round(consume_ms, 5), "launches": launches,
                      "algorithmic_bytes_per_launch": B, "other_kernels_ms": others},
     }
 
