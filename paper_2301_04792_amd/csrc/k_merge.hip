@@ -36,28 +36,40 @@ using namespace lb;
 // One group of PG lanes per unit boundary (group_merge_search).
 constexpr int PG = 16;
 
+// With row_base (a batch's row prefix sums, count + 1 entries) the group also
+// records in part_mat[t] the matrix that owns row min(i_t, rows - 1).
 __global__ __launch_bounds__(256) void merge_partition_kernel(const int32_t *__restrict__ ro,
                                                               int32_t rows, int32_t nnz, int32_t W,
                                                               int32_t T, int32_t *__restrict__ part_i,
-                                                              int32_t *__restrict__ part_j) {
+                                                              int32_t *__restrict__ part_j,
+                                                              const int64_t *__restrict__ row_base,
+                                                              int32_t count, int32_t *__restrict__ part_mat) {
     const int64_t t = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / PG;
     const bool live = t <= T;  // uniform per group; every lane still takes part in the ballots
     const int64_t total = static_cast<int64_t>(rows) + nnz;
     const int64_t tt = live ? t : T;
     const int32_t d = static_cast<int32_t>(tt * W < total ? tt * W : total);
     const int32_t i = group_merge_search<PG>(ro, rows, nnz, d);
+    int32_t mat = 0;
+    if (row_base) {  // uniform across the grid
+        const int64_t r = i < rows ? i : rows - 1;
+        mat = group_count_le<PG>(row_base, count + 1, r) - 1;  // last b with row_base[b] <= r
+        mat = mat < 0 ? 0 : (mat > count - 1 ? count - 1 : mat);
+    }
     if (live && (threadIdx.x & (PG - 1)) == 0) {
         part_i[t] = i;
         part_j[t] = d - i;
+        if (row_base) part_mat[t] = mat;
     }
 }
 
 hipError_t merge_partition(const int32_t *ro, int32_t rows, int32_t nnz, int32_t W, int32_t T,
-                           int32_t *part_i, int32_t *part_j, hipStream_t s) {
+                           int32_t *part_i, int32_t *part_j, hipStream_t s, const int64_t *row_base, int32_t count,
+                           int32_t *part_mat) {
     prof_scope p(s, "merge_partition");
     const int64_t blocks = ((static_cast<int64_t>(T) + 1) * PG + 255) / 256;
     hipLaunchKernelGGL(merge_partition_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s,
-                       ro, rows, nnz, W, T, part_i, part_j);
+                       ro, rows, nnz, W, T, part_i, part_j, row_base, count, part_mat);
     return hipGetLastError();
 }
 

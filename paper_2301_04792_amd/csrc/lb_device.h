@@ -18,6 +18,7 @@
 namespace lb {
 
 constexpr int kWave = 64;
+constexpr int kXcds = 8;  // accelerator dies of an MI355X; workgroups are dealt to them round-robin
 
 using bf16_bits = uint16_t;
 
@@ -115,6 +116,31 @@ __device__ __forceinline__ int32_t group_merge_search(const int32_t *__restrict_
     const int32_t r = lo + gl;
     const bool below = r < hi && ro[r + 1] + r < d;
     return lo + __popcll((__ballot(below) >> shift) & gmask);
+}
+
+// Number of entries of the sorted int64 array a[0..n) that are <= key, by an
+// aligned group of G lanes (G-ary search, same ballot rules as above).
+template <int G>
+__device__ __forceinline__ int32_t group_count_le(const int64_t *__restrict__ a, int32_t n, int64_t key) {
+    const int gl = threadIdx.x & (G - 1);
+    const int shift = (threadIdx.x & (kWave - 1)) & ~(G - 1);
+    const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1);
+    int32_t lo = 0, hi = n;  // a[r] <= key for r < lo, a[r] > key for r >= hi
+    for (;;) {
+        const bool wide = hi - lo > G;
+        if (__ballot(wide) == 0) break;
+        const int32_t step = wide ? (hi - lo + G - 1) / G : 1;
+        const int32_t r = lo + (gl + 1) * step - 1;
+        const bool le = wide && r < hi && a[r] <= key;
+        const int32_t c = __popcll((__ballot(le) >> shift) & gmask);
+        if (wide) {
+            const int32_t rc = lo + (c + 1) * step - 1;
+            hi = rc < hi ? rc : hi;
+            lo = lo + c * step;
+        }
+    }
+    const int32_t r = lo + gl;
+    return lo + __popcll((__ballot(r < hi && a[r] <= key) >> shift) & gmask);
 }
 
 __device__ __forceinline__ int32_t wave_merge_search(const int32_t *__restrict__ ro, int32_t rows, int32_t nnz,
@@ -217,6 +243,67 @@ __device__ __forceinline__ seg_t block_seg_scan_excl(seg_t x, seg_t *s_wave, seg
     const float pv = __shfl_up(inc.v, 1, kWave);
     const int pf = __shfl_up(inc.f, 1, kWave);
     return lane ? seg_combine(pre, seg_t{pv, pf}) : pre;
+}
+
+// Block-wide exclusive segmented scan of KC values sharing one flag per
+// thread (the same operator as seg_t), in one pass: KC values per shuffle
+// step and one LDS exchange, so two barriers whatever KC is.  s_wv holds
+// BLOCK/64 * KC floats, s_wf BLOCK/64 ints.  ex[c] = exclusive prefix,
+// tot[c] = block total; ends with a barrier.
+template <int BLOCK, int KC>
+__device__ __forceinline__ void block_seg_scan_excl_kc(const float (&v)[KC], int flag, float (&ex)[KC],
+                                                       float (&tot)[KC], float *s_wv, int *s_wf) {
+    constexpr int NW = BLOCK / kWave;
+    const int lane = lane_id(), w = wave_id();
+    float inc[KC];
+#pragma unroll
+    for (int c = 0; c < KC; ++c) inc[c] = v[c];
+    int f = flag;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int pf = __shfl_up(f, off, kWave);
+        float pv[KC];
+#pragma unroll
+        for (int c = 0; c < KC; ++c) pv[c] = __shfl_up(inc[c], off, kWave);
+        if (lane >= off) {
+#pragma unroll
+            for (int c = 0; c < KC; ++c) inc[c] = f ? inc[c] : pv[c] + inc[c];
+            f |= pf;
+        }
+    }
+    if (lane == kWave - 1) {
+        s_wf[w] = f;
+#pragma unroll
+        for (int c = 0; c < KC; ++c) s_wv[w * KC + c] = inc[c];
+    }
+    __syncthreads();
+    float pre[KC], all[KC];
+    int pre_f = 0, all_f = 0;
+#pragma unroll
+    for (int c = 0; c < KC; ++c) pre[c] = all[c] = 0.f;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        const int fk = s_wf[k];
+#pragma unroll
+        for (int c = 0; c < KC; ++c) {
+            const float vk = s_wv[k * KC + c];
+            if (k < w) pre[c] = fk ? vk : pre[c] + vk;
+            all[c] = fk ? vk : all[c] + vk;
+        }
+        if (k < w) pre_f |= fk;
+        all_f |= fk;
+    }
+    __syncthreads();
+    // exclusive within the wavefront: the inclusive value of the lane before
+    const int ef = __shfl_up(f, 1, kWave);
+#pragma unroll
+    for (int c = 0; c < KC; ++c) {
+        const float ev = __shfl_up(inc[c], 1, kWave);
+        ex[c] = lane ? (ef ? ev : pre[c] + ev) : pre[c];
+        tot[c] = all[c];
+    }
+    (void)pre_f;
+    (void)all_f;
 }
 
 // Block-wide sum (all threads call; every thread gets the total).  s_red

@@ -65,8 +65,12 @@ inline merge_ws merge_ws_carve(void *base, int64_t T) {
     return w;
 }
 
+// The split at every unit boundary.  With row_base (a batch's int64 row
+// prefix sums, count + 1 entries) it also writes part_mat[t], the matrix
+// owning row min(part_i[t], rows - 1).
 hipError_t merge_partition(const int32_t *ro, int32_t rows, int32_t nnz, int32_t W, int32_t T,
-                           int32_t *part_i, int32_t *part_j, hipStream_t s);
+                           int32_t *part_i, int32_t *part_j, hipStream_t s, const int64_t *row_base = nullptr,
+                           int32_t count = 0, int32_t *part_mat = nullptr);
 
 // True if (block, items) is an instantiated merge-path configuration.
 bool merge_config_supported(int block, int items);
