@@ -33,11 +33,14 @@ using namespace lb;
 
 // ------------------------------------------------------------------ partition
 
-// One group of PG lanes per unit boundary (group_merge_search).
-constexpr int PG = 16;
+// One group of PG lanes per unit boundary (group_merge_search).  16 lanes
+// measured faster than 32 or 64: more boundaries per wavefront outweigh the
+// extra search levels (6 instead of 4 on 2M rows).
+constexpr int kPartitionGroup = 16;
 
 // With row_base (a batch's row prefix sums, count + 1 entries) the group also
 // records in part_mat[t] the matrix that owns row min(i_t, rows - 1).
+template <int PG>
 __global__ __launch_bounds__(256) void merge_partition_kernel(const int32_t *__restrict__ ro,
                                                               int32_t rows, int32_t nnz, int32_t W,
                                                               int32_t T, int32_t *__restrict__ part_i,
@@ -67,8 +70,8 @@ hipError_t merge_partition(const int32_t *ro, int32_t rows, int32_t nnz, int32_t
                            int32_t *part_i, int32_t *part_j, hipStream_t s, const int64_t *row_base, int32_t count,
                            int32_t *part_mat) {
     prof_scope p(s, "merge_partition");
-    const int64_t blocks = ((static_cast<int64_t>(T) + 1) * PG + 255) / 256;
-    hipLaunchKernelGGL(merge_partition_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s,
+    const int64_t blocks = ((static_cast<int64_t>(T) + 1) * kPartitionGroup + 255) / 256;
+    hipLaunchKernelGGL(merge_partition_kernel<kPartitionGroup>, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s,
                        ro, rows, nnz, W, T, part_i, part_j, row_base, count, part_mat);
     return hipGetLastError();
 }
@@ -175,32 +178,48 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
 
 // ------------------------------------------------------------------ fix-up
 
-// One wavefront per carry entry b that starts a run of equal rows (b == 0 or
-// carry_row[b - 1] != carry_row[b]); other wavefronts leave at once.  The
-// wavefront reads the run 64 entries at a time (coalesced), adds each chunk
-// with a fixed butterfly and the chunks in order, and adds the total to the
-// row of y (kc columns).  Deterministic: no atomics.
+// One wavefront per chunk of 64 consecutive carry entries.  carry_row is
+// non-decreasing, so entries of one row form a run.  The runs that start in
+// the chunk are summed by its wavefront: inside the chunk by a segmented scan
+// (fixed butterfly), and the chunk's last run, when it goes on past the
+// chunk, by reading on 64 entries at a time, adding each chunk in order.  A
+// run that began in an earlier chunk belongs to that chunk's wavefront.  The
+// run total is added to its row of y (kc columns).  Deterministic: no
+// atomics, one writer per row.
 __global__ __launch_bounds__(256) void merge_fixup(int32_t T, int32_t rows, int32_t kc,
                                                    const int32_t *__restrict__ carry_row,
                                                    const float *__restrict__ carry_val,
                                                    float *__restrict__ y, int64_t ldy) {
     const int lane = lane_id();
-    const int64_t b = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
-    if (b >= T) return;
-    const int32_t r = carry_row[b];
-    if (r >= rows || (b > 0 && carry_row[b - 1] == r)) return;  // uniform across the wavefront
+    const int64_t base = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave * kWave;
+    if (base >= T) return;  // uniform across the wavefront
+    const int64_t b = base + lane;
+    const bool in = b < T;
+    const int32_t r = in ? carry_row[b] : -1;
+    const bool head = in && (b == 0 || carry_row[b - 1] != r);
+    const bool tail = in && (b + 1 == T || carry_row[b + 1] != r);
+    // the last lane's run goes on into the next chunk
+    const bool open = __ballot(lane == kWave - 1 && in && !tail) != 0;
+    const int32_t r_open = __shfl(r, kWave - 1);
     for (int32_t c = 0; c < kc; ++c) {
-        float total = 0.f;
-        for (int64_t s = b;; s += kWave) {
-            const int64_t q = s + lane;
-            const bool in = q < T && carry_row[q] == r;
-            float v = in ? carry_val[q * kc + c] : 0.f;
-            v = group_sum<kWave>(v);
-            total += v;
-            // the run is contiguous: it ends inside this chunk unless every lane matched
-            if (__popcll(__ballot(in)) < kWave) break;
+        const seg_t sc = group_seg_scan_incl<kWave>(seg_t{in ? carry_val[b * kc + c] : 0.f, head});
+        // sc.f: some run starts at or before this lane inside the chunk, so
+        // a tail lane with sc.f ends a run that this chunk owns
+        if (tail && sc.f && r < rows) y[static_cast<int64_t>(r) * ldy + c] += sc.v;
+        if (open) {
+            const bool owned = __shfl(static_cast<int>(sc.f), kWave - 1) != 0;
+            if (owned && r_open < rows) {  // uniform
+                float total = __shfl(sc.v, kWave - 1);
+                for (int64_t s = base + kWave;; s += kWave) {
+                    const int64_t q = s + lane;
+                    const bool match = q < T && carry_row[q] == r_open;
+                    total += group_sum<kWave>(match ? carry_val[q * kc + c] : 0.f);
+                    // the run is contiguous: it ends inside this chunk unless every lane matched
+                    if (__popcll(__ballot(match)) < kWave) break;
+                }
+                if (lane == 0) y[static_cast<int64_t>(r_open) * ldy + c] += total;
+            }
         }
-        if (lane == 0) y[static_cast<int64_t>(r) * ldy + c] += total;
     }
 }
 
@@ -208,7 +227,7 @@ hipError_t launch_fixup(int64_t T, int32_t rows, int32_t kc, const int32_t *carr
                         const float *carry_val, float *y, int64_t ldy, hipStream_t s, const char *tag) {
     if (T <= 0) return hipSuccess;
     prof_scope p(s, tag);
-    const int64_t blocks = (T * kWave + 255) / 256;
+    const int64_t blocks = (T + 255) / 256;  // one wavefront per 64 entries
     hipLaunchKernelGGL(merge_fixup, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s,
                        static_cast<int32_t>(T), rows, kc, carry_row, carry_val, y, ldy);
     return hipGetLastError();
