@@ -18,6 +18,11 @@ Functions and the passages they follow (Osama, Porumbescu, Owens, PPoPP'23):
   get_tile_brute  -- Sec. 5.2.3, group-mapped: the tile that owns an atom,
                      by enumeration of the group's prefix-summed tile sizes
   batched_spmm    -- one spmm per matrix of a batch
+  sssp            -- Sec. 5.3, the SSSP example on the same tile sets: float32
+                     distances, least fixed point of
+                     dist[v] = min over edges of fl(dist[u] + w)  (Dijkstra)
+  bfs             -- BFS (named in Sec. 6): least number of edges from the
+                     source, -1 where unreachable
 """
 from __future__ import annotations
 
@@ -70,7 +75,10 @@ def _bind(lib):
     lib.orc_dvalues.argtypes = [I64, P, P, P, P, INT, P]
     lib.orc_merge_walk.argtypes = [I64, I64, P, I64, I64, P, P]
     lib.orc_num_threads.argtypes = []
-    for f in ("orc_spmv", "orc_spmm", "orc_spmv_transpose", "orc_dvalues", "orc_merge_walk", "orc_num_threads"):
+    lib.orc_sssp.argtypes = [I64, P, P, P, I64, P]
+    lib.orc_bfs.argtypes = [I64, P, P, I64, P]
+    for f in ("orc_spmv", "orc_spmm", "orc_spmv_transpose", "orc_dvalues", "orc_merge_walk", "orc_num_threads",
+              "orc_sssp", "orc_bfs"):
         getattr(lib, f).restype = INT
     return lib
 
@@ -153,6 +161,26 @@ class Oracle:
             raise ValueError("orc_merge_walk rejected its arguments")
         return oi, oj
 
+    def sssp(self, row_offsets, col_idx, weights, source):
+        """float32 distances from ``source`` (+inf where unreachable)."""
+        ro, ci, w = _c(row_offsets, np.int32), _c(col_idx, np.int32), _c(weights, np.float32)
+        n = ro.shape[0] - 1
+        dist = np.empty(n, dtype=np.float32)
+        rc = self.lib.orc_sssp(n, _ptr(ro), _ptr(ci), _ptr(w), int(source), _ptr(dist))
+        if rc:
+            raise ValueError(f"orc_sssp rejected its arguments ({rc})")
+        return dist
+
+    def bfs(self, row_offsets, col_idx, source):
+        """int32 edge counts from ``source`` (-1 where unreachable)."""
+        ro, ci = _c(row_offsets, np.int32), _c(col_idx, np.int32)
+        n = ro.shape[0] - 1
+        depth = np.empty(n, dtype=np.int32)
+        rc = self.lib.orc_bfs(n, _ptr(ro), _ptr(ci), int(source), _ptr(depth))
+        if rc:
+            raise ValueError(f"orc_bfs rejected its arguments ({rc})")
+        return depth
+
     def num_threads(self) -> int:
         return int(self.lib.orc_num_threads())
 
@@ -203,6 +231,14 @@ def merge_walk(row_offsets, nnz, W, T):
 
 def batched_spmm(batch, X):
     return default().batched_spmm(batch, X)
+
+
+def sssp(row_offsets, col_idx, weights, source):
+    return default().sssp(row_offsets, col_idx, weights, source)
+
+
+def bfs(row_offsets, col_idx, source):
+    return default().bfs(row_offsets, col_idx, source)
 
 
 # ----------------------------------------------------------------------------

@@ -1,5 +1,5 @@
 /*
- * FP64 CPU oracle for load-balanced CSR SpMV -- TEST INFRASTRUCTURE ONLY.
+ * CPU oracle for the load-balanced sparse kernels -- TEST INFRASTRUCTURE ONLY.
  *
  * Only the test suite, the smoke check and the bench's CPU-baseline leg may
  * load this library.  It shares no code, header or constant with the GPU
@@ -19,13 +19,19 @@
  *     nonzero j.  Recorded at diagonals d_t = min(t*W, m + nnz).
  *   - Backward of y = A x (not in the paper): dx = A^T dy,
  *     dvalues[j] = dy[row(j)] * x[col_idx[j]].
+ *   - SSSP (Sec. 5.3, the graph example) and BFS (named in Sec. 6) on the
+ *     same tile sets: vertices are tiles, out-edges are atoms.  Distances
+ *     are float32 as in the paper's example; see orc_sssp.
  *
- * All sums are plain sequential loops in ascending nonzero order, in double.
+ * All SpMV-family sums are plain sequential loops in ascending nonzero
+ * order, in double.
  * Inputs are read in the same storage type the GPU reads (float32, or BF16
  * bit patterns) and widened exactly to double.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stddef.h>
+#include <stdlib.h>
 #include <string.h>
 
 #define ORC_F32 0
@@ -155,5 +161,125 @@ int orc_merge_walk(int64_t m, int64_t nnz, const int32_t *row_offsets, int64_t W
         out_i[t] = (int32_t)i;
         out_j[t] = (int32_t)j;
     }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Graph traversal on the same CSR tile sets (Sec. 5.3, the SSSP example;
+ * Sec. 6 names BFS as another application built on the schedules).
+ * Vertices are tiles (rows) and a vertex's out-edges are its atoms: edge j
+ * of vertex u goes to col_idx[j] with weight w[j].
+ * ------------------------------------------------------------------------ */
+
+/* Single-source shortest paths.  The paper's SSSP offers, along every edge
+ * (u, v, w), the distance dist[u] + w to v and keeps the smaller value,
+ * repeating until nothing changes.  Distances are float32 (the example
+ * declares them float), so every offer is one float32 addition and the
+ * result is the least solution of
+ *     dist[source] = 0,  dist[v] = min over edges (u, v, w) of fl(dist[u] + w)
+ * (+inf where no path exists).  With w >= 0 an offer is never below
+ * dist[u] and fl(a + w) does not decrease as a grows, so settling vertices
+ * in increasing distance (Dijkstra) reaches exactly that solution.  Binary
+ * heap with lazy deletion: a vertex may be pushed once per improvement and
+ * stale heap entries are skipped when popped.
+ * Returns 1 for bad sizes, 2 for a negative or NaN weight. */
+typedef struct {
+    float d;
+    int32_t v;
+} orc_heap_item;
+
+static void orc_heap_push(orc_heap_item *h, int64_t *size, float d, int32_t v)
+{
+    int64_t i = (*size)++;
+    while (i > 0) {
+        int64_t p = (i - 1) / 2;
+        if (h[p].d <= d) break;
+        h[i] = h[p];
+        i = p;
+    }
+    h[i].d = d;
+    h[i].v = v;
+}
+
+static orc_heap_item orc_heap_pop(orc_heap_item *h, int64_t *size)
+{
+    orc_heap_item top = h[0];
+    int64_t n = --(*size);
+    if (n > 0) {
+        orc_heap_item last = h[n];
+        int64_t i = 0;
+        for (;;) {
+            int64_t c = 2 * i + 1;
+            if (c >= n) break;
+            if (c + 1 < n && h[c + 1].d < h[c].d) ++c;
+            if (h[c].d >= last.d) break;
+            h[i] = h[c];
+            i = c;
+        }
+        h[i] = last;
+    }
+    return top;
+}
+
+int orc_sssp(int64_t n, const int32_t *row_offsets, const int32_t *col_idx,
+             const float *w, int64_t source, float *dist)
+{
+    if (n <= 0 || source < 0 || source >= n) return 1;
+    int64_t E = row_offsets[n];
+    for (int64_t j = 0; j < E; ++j)
+        if (!(w[j] >= 0.0f)) return 2;
+    for (int64_t v = 0; v < n; ++v) dist[v] = INFINITY;
+    orc_heap_item *heap = (orc_heap_item *)malloc((size_t)(E + 1) * sizeof *heap);
+    unsigned char *settled = (unsigned char *)calloc((size_t)n, 1);
+    if (!heap || !settled) {
+        free(heap);
+        free(settled);
+        return 3;
+    }
+    int64_t size = 0;
+    dist[source] = 0.0f;
+    orc_heap_push(heap, &size, 0.0f, (int32_t)source);
+    while (size > 0) {
+        orc_heap_item top = orc_heap_pop(heap, &size);
+        int32_t u = top.v;
+        if (settled[u]) continue; /* a stale entry */
+        settled[u] = 1;
+        for (int64_t j = row_offsets[u]; j < row_offsets[u + 1]; ++j) {
+            int32_t v = col_idx[j];
+            float offer = dist[u] + w[j]; /* one float32 addition */
+            if (offer < dist[v]) {
+                dist[v] = offer;
+                orc_heap_push(heap, &size, offer, v);
+            }
+        }
+    }
+    free(heap);
+    free(settled);
+    return 0;
+}
+
+/* Breadth-first search: depth[v] is the least number of edges on a path
+ * from source to v, -1 if there is none.  FIFO queue, one visit per vertex. */
+int orc_bfs(int64_t n, const int32_t *row_offsets, const int32_t *col_idx,
+            int64_t source, int32_t *depth)
+{
+    if (n <= 0 || source < 0 || source >= n) return 1;
+    int32_t *queue = (int32_t *)malloc((size_t)n * sizeof *queue);
+    if (!queue) return 3;
+    for (int64_t v = 0; v < n; ++v) depth[v] = -1;
+    int64_t head = 0, tail = 0;
+    depth[source] = 0;
+    queue[tail++] = (int32_t)source;
+    while (head < tail) {
+        int32_t u = queue[head++];
+        for (int64_t j = row_offsets[u]; j < row_offsets[u + 1]; ++j) {
+            int32_t v = col_idx[j];
+            if (depth[v] < 0) {
+                depth[v] = depth[u] + 1;
+                queue[tail++] = v;
+            }
+        }
+    }
+    free(queue);
     return 0;
 }

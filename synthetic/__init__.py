@@ -22,3 +22,13 @@ from .csr import (  # noqa: F401
     config_c5,
     random_vector,
 )
+from .graph import (  # noqa: F401
+    WEIGHT_KINDS,
+    graph_weights,
+    path_graph,
+    grid_graph,
+    random_graph,
+    powerlaw_graph,
+    max_degree_vertex,
+    config_c4_graph,
+)

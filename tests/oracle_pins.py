@@ -356,4 +356,196 @@ def pin_merge_python_walk(orc):
             assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), (name, W)
 
 
+
+
+# --------------------------------------------------------------------------- graphs (SSSP, BFS)
+
+def _graph_cases(kind):
+    from synthetic import powerlaw_graph, random_graph
+
+    cases = [random_graph(300 + s, n, d, kind)
+             for s, (n, d) in enumerate([(1, 0), (2, 1), (20, 3), (200, 6), (1000, 4), (600, 40)])]
+    cases.append(powerlaw_graph(310, 2000, cap=500, kind=kind))
+    cases.append(powerlaw_graph(311, 300, cap=300, p_empty=0.5, kind=kind))
+    return cases
+
+
+def _sources(G):
+    from synthetic import max_degree_vertex
+
+    return sorted({0, G.m - 1, max_degree_vertex(G)})
+
+
+def _scipy_graph(G):
+    import scipy.sparse as sp
+
+    return sp.csr_matrix((G.values.astype(np.float64), G.col_idx, G.row_offsets), shape=G.shape)
+
+
+def _read_hand_graph():
+    fields = {}
+    with open(os.path.join(GOLDEN, "sssp_hand.txt")) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if line:
+                key, *vals = line.split()
+                fields[key] = vals
+    ro = np.array(fields["row_offsets"], np.int32)
+    ci = np.array(fields["col_idx"], np.int32)
+    w = np.array([float(v) for v in fields["weights"]], np.float32)
+    dist = np.array([float(v) for v in fields["dist"]], np.float32)
+    depth = np.array(fields["depth"], np.int32)
+    return ro, ci, w, int(fields["source"][0]), dist, depth
+
+
+def pin_graph_hand_example(orc):
+    """SSSP and BFS on the hand-worked fixture (tests/golden/sssp_hand.txt)."""
+    ro, ci, w, s, dist, depth = _read_hand_graph()
+    assert np.array_equal(orc.sssp(ro, ci, w, s), dist)
+    assert np.array_equal(orc.bfs(ro, ci, s), depth)
+
+
+def pin_sssp_scipy_integer_weights(orc):
+    """Integer weights 1..16: every path sum is exact in float32, so the
+    oracle equals scipy's float64 Dijkstra exactly (an independent library
+    routine), +inf included."""
+    from scipy.sparse.csgraph import dijkstra
+
+    for G in _graph_cases("int16"):
+        M = _scipy_graph(G)
+        for s in _sources(G):
+            ref = dijkstra(M, directed=True, indices=s)
+            got = orc.sssp(G.row_offsets, G.col_idx, G.values, s)
+            assert np.array_equal(got.astype(np.float64), ref), (G.shape, s)
+
+
+def _bellman_ford_f32(G, s):
+    """Synchronous rounds over every edge, each offer one float32 addition,
+    until no distance changes."""
+    n = G.m
+    src = np.repeat(np.arange(n), np.diff(G.row_offsets.astype(np.int64)))
+    d = np.full(n, np.inf, np.float32)
+    d[s] = 0.0
+    for _ in range(n + 1):
+        offer = d[src] + G.values  # float32 + float32 -> float32, rounded to nearest
+        new = d.copy()
+        np.minimum.at(new, G.col_idx, offer)
+        if np.array_equal(new, d):
+            return d
+        d = new
+    raise AssertionError("Bellman-Ford did not settle")
+
+
+def pin_sssp_bellman_ford_float32(orc):
+    """Real-valued weights: the oracle's Dijkstra equals brute-force
+    Bellman-Ford rounds in float32 bit for bit."""
+    for G in _graph_cases("uniform"):
+        if G.m > 1000:
+            continue
+        for s in _sources(G):
+            got = orc.sssp(G.row_offsets, G.col_idx, G.values, s)
+            assert np.array_equal(got, _bellman_ford_f32(G, s)), (G.shape, s)
+
+
+def pin_sssp_bfs_grid_closed_form(orc):
+    """N x N grid (4 neighbours and a self edge): with every weight h the
+    distance is h times the Manhattan distance (exact for dyadic h), and the
+    BFS depth is the Manhattan distance."""
+    from synthetic import grid_graph
+
+    N = 13
+    G = grid_graph(N)
+    ii, jj = np.divmod(np.arange(N * N), N)
+    for s in (0, N * N - 1, (N // 2) * N + 3):
+        man = np.abs(ii - ii[s]) + np.abs(jj - jj[s])
+        assert np.array_equal(orc.bfs(G.row_offsets, G.col_idx, s), man.astype(np.int32))
+        for h in (1.0, 0.5, 3.0):
+            d = orc.sssp(G.row_offsets, G.col_idx, np.full(G.nnz, h, np.float32), s)
+            assert np.array_equal(d, (h * man).astype(np.float32)), (s, h)
+
+
+def pin_sssp_path_fold(orc):
+    """Directed chain 0 -> 1 -> ... : the distance to vertex k is the
+    running float32 sum of the first k weights; vertices before the source
+    are unreachable (+inf, depth -1)."""
+    from synthetic import path_graph
+
+    G = path_graph(200, 5)
+    for s in (0, 37):
+        expect = np.full(G.m, np.inf, np.float32)
+        acc = np.float32(0.0)
+        expect[s] = acc
+        for k in range(s + 1, G.m):
+            acc = np.float32(acc + G.values[k - 1])
+            expect[k] = acc
+        assert np.array_equal(orc.sssp(G.row_offsets, G.col_idx, G.values, s), expect)
+        depth = np.where(np.arange(G.m) >= s, np.arange(G.m) - s, -1).astype(np.int32)
+        assert np.array_equal(orc.bfs(G.row_offsets, G.col_idx, s), depth)
+
+
+def pin_sssp_fixed_point_invariants(orc):
+    """On a power-law graph: dist is a fixed point (dist[s] = 0 and, for every
+    other vertex, the least offer over its in-edges), finite exactly where
+    BFS reaches, and no offer along any edge undercuts it."""
+    from synthetic import powerlaw_graph
+
+    G = powerlaw_graph(320, 5000, cap=2000)
+    src = np.repeat(np.arange(G.m), np.diff(G.row_offsets.astype(np.int64)))
+    for s in _sources(G):
+        d = orc.sssp(G.row_offsets, G.col_idx, G.values, s)
+        offer = d[src] + G.values
+        best = np.full(G.m, np.inf, np.float32)
+        np.minimum.at(best, G.col_idx, offer)
+        best[s] = 0.0
+        assert np.array_equal(best, d), s
+        assert np.all(d[G.col_idx] <= offer)
+        reach = orc.bfs(G.row_offsets, G.col_idx, s) >= 0
+        assert np.array_equal(np.isfinite(d), reach), s
+
+
+def pin_bfs_scipy(orc):
+    """BFS depths equal scipy's unweighted shortest paths (-1 for +inf)."""
+    from scipy.sparse.csgraph import shortest_path
+
+    for G in _graph_cases("unit"):
+        M = _scipy_graph(G)
+        for s in _sources(G):
+            ref = shortest_path(M, directed=True, unweighted=True, indices=s)
+            ref = np.where(np.isinf(ref), -1, ref).astype(np.int32)
+            assert np.array_equal(orc.bfs(G.row_offsets, G.col_idx, s), ref), (G.shape, s)
+
+
+def pin_bfs_level_sets(orc):
+    """Brute force: level k+1 is every not-yet-seen out-neighbour of level k."""
+    for G in _graph_cases("unit")[:5]:
+        for s in _sources(G):
+            depth = np.full(G.m, -1, np.int32)
+            level, k = {s}, 0
+            depth[s] = 0
+            while level:
+                nxt = set()
+                for u in level:
+                    for v in G.col_idx[G.row_offsets[u]:G.row_offsets[u + 1]]:
+                        if depth[v] < 0:
+                            nxt.add(int(v))
+                k += 1
+                for v in nxt:
+                    depth[v] = k
+                level = nxt
+            assert np.array_equal(orc.bfs(G.row_offsets, G.col_idx, s), depth), (G.shape, s)
+
+
+def pin_sssp_rejects_negative_weights(orc):
+    """Dijkstra's order needs w >= 0: a negative or NaN weight is refused."""
+    ro, ci, w, s, _, _ = _read_hand_graph()
+    for bad in (-0.5, np.nan):
+        w2 = w.copy()
+        w2[3] = bad
+        try:
+            orc.sssp(ro, ci, w2, s)
+        except ValueError:
+            continue
+        raise AssertionError(f"weight {bad} accepted")
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

@@ -88,3 +88,22 @@ def test_c2_realized_size():
     L = np.diff(A.row_offsets)
     assert A.shape == (2_000_000, 2_000_000) and L.max() == 200_000
     assert 55_000_000 < A.nnz < 75_000_000
+
+
+def test_graph_generators():
+    from synthetic import graph_weights, path_graph, powerlaw_graph, max_degree_vertex, random_graph
+
+    G = powerlaw_graph(7, 3000, cap=400)
+    H = powerlaw_graph(7, 3000, cap=400)
+    assert np.array_equal(G.values, H.values) and np.array_equal(G.col_idx, H.col_idx)
+    assert G.values.dtype == np.float32 and np.all(G.values >= 2.0 ** -10) and np.all(G.values < 1.0)
+    I = graph_weights(G, 7, "int16")
+    assert np.array_equal(I.col_idx, G.col_idx)
+    assert set(np.unique(I.values)) <= set(range(1, 17))
+    assert np.all(graph_weights(G, 7, "unit").values == 1.0)
+    P = path_graph(6, 1)
+    assert list(P.row_offsets) == [0, 1, 2, 3, 4, 5, 5] and list(P.col_idx) == [1, 2, 3, 4, 5]
+    s = max_degree_vertex(G)
+    assert np.diff(G.row_offsets)[s] == np.diff(G.row_offsets).max()
+    R = random_graph(3, 100, 7)
+    assert R.m == R.n == 100 and np.diff(R.row_offsets).max() <= 7

@@ -25,6 +25,12 @@ MUTANTS = [
     ("dvalues_wrong_row", "dvalues[j] = dy[r] * orc_load(x, xdt, col_idx[j]);", "dvalues[j] = dy[r > 0 ? r - 1 : 0] * orc_load(x, xdt, col_idx[j]);"),
     ("merge_tie_nnz_first", "if (i < m && row_offsets[i + 1] <= j)", "if (i < m && row_offsets[i + 1] < j)"),
     ("merge_off_by_one", "int64_t target = t * W < total ? t * W : total;", "int64_t target = t * W + 1 < total ? t * W + 1 : total;"),
+    ("sssp_wrong_weight_index", "float offer = dist[u] + w[j];", "float offer = dist[u] + w[row_offsets[u]];"),
+    ("sssp_dropped_weight", "float offer = dist[u] + w[j];", "float offer = dist[u] + (j & 1 ? w[j] : 0.0f);"),
+    ("sssp_wrong_endpoint", "int32_t v = col_idx[j];\n            float offer", "int32_t v = (j % 3 == 0 && col_idx[j] > 0) ? col_idx[j] - 1 : col_idx[j];\n            float offer"),
+    ("sssp_stop_early", "while (size > 0) {", "while (size > 1) {"),
+    ("bfs_dropped_increment", "depth[v] = depth[u] + 1;", "depth[v] = depth[u] + (u != source);"),
+    ("bfs_stack_not_queue", "int32_t u = queue[head++];", "int32_t u = queue[--tail];"),
     ("bf16_shift", "uint32_t bits = (uint32_t)((const uint16_t *)p)[i] << 16;", "uint32_t bits = (uint32_t)((const uint16_t *)p)[i] << 15;"),
 ]
 
