@@ -9,7 +9,10 @@
  * computation consumes the per-thread ranges (Sec. 3.3, Sec. 4.3).  The
  * computation offered here is CSR sparse matrix-vector product y = A x
  * (Sec. 1, Sec. 4.3 SpMV listing), its multi-right-hand-side form Y = A X
- * (Sec. 5.3 SpMM listing), its backward pass, and a batched form.
+ * (Sec. 5.3 SpMM listing), its backward pass, and a batched form; and, on
+ * the same schedules, the graph traversals of Sec. 5.3 (SSSP) and Sec. 6
+ * (BFS).  Device-side, include/lb_schedule.hpp exposes the tile sets and
+ * schedules to HIP kernels written by the user.
  *
  * Conventions for every entry point:
  *  - Device buffers, the workspace and the stream are owned by the caller.
@@ -47,7 +50,8 @@ typedef enum lb_status_t {
     LB_ERR_OVERFLOW = 3,             /* rows + nnz (or a batch's totals) exceed int32 coordinates */
     LB_ERR_WORKSPACE_TOO_SMALL = 4,  /* workspace_bytes below lb_workspace_size() */
     LB_ERR_HIP = 5,                  /* a HIP call or launch failed; see lb_last_hip_error() */
-    LB_ERR_INVALID_CSR = 6           /* lb_validate_csr found a violated device-only precondition */
+    LB_ERR_INVALID_CSR = 6,          /* lb_validate_csr found a violated device-only precondition */
+    LB_ERR_NOT_CONVERGED = 7         /* a traversal still had a frontier after max_iterations */
 } lb_status_t;
 
 /* Element types.  LB_BF16 buffers hold bfloat16 bit patterns (the upper 16
@@ -234,6 +238,51 @@ LB_API void lb_autotune_clear(void);
  * Returns LB_OK or LB_ERR_INVALID_CSR. */
 LB_API lb_status_t lb_validate_csr(const lb_csr_t *A, void *stream);
 
+/* ---- Graph traversal on the same schedules (Sec. 5.3 SSSP example; BFS,
+ * named in Sec. 6).
+ * The graph G is a square CSR read as adjacency: vertex u's out-edges are
+ * the atoms of tile u, edge j goes to col_idx[j] and (SSSP) weighs
+ * values[j], float32 and >= 0 (negative or NaN weights are undefined
+ * behaviour; the oracle-checked result assumes them absent).
+ * Each iteration takes the current frontier (a device list of vertex ids:
+ * an indexed tile set) and relaxes every out-edge of its vertices under the
+ * schedule s; the vertices that improve form the next frontier, each listed
+ * once.  The host repeats until the frontier is empty (Sec. 5.3), reading
+ * the frontier size from the device once per batch of iterations, so these
+ * calls synchronize `stream`.
+ * Schedules: LB_THREAD_MAPPED (a thread per frontier vertex, block_size as
+ * for SpMV), LB_GROUP_MAPPED with group_size a power of two in [8, 1024]
+ * and tiles_per_group 1 (a group per vertex) or group_size (LDS prefix sum
+ * and get_tile over the group's vertices), LB_AUTO = group-mapped with
+ * group_size = tiles_per_group = 64 (the paper's SSSP uses a group-level
+ * schedule).  LB_MERGE_PATH returns LB_ERR_UNSUPPORTED.  grid_size 0 = the
+ * resident grid (CUs x occupancy).
+ * max_iterations 0 = rows + 1 (enough for any graph with weights >= 0); a
+ * frontier still non-empty after max_iterations returns
+ * LB_ERR_NOT_CONVERGED (the outputs then hold upper bounds).
+ * *iterations (host, may be NULL) receives the number of non-empty
+ * frontiers processed.  source in [0, rows). */
+
+/* Workspace bytes for lb_sssp / lb_bfs on G (3 * rows int32 + counters).  Host-only. */
+LB_API lb_status_t lb_traversal_workspace_size(const lb_csr_t *G, size_t *bytes);
+
+/* Single-source shortest paths: dist (rows float32, overwritten) receives
+ * the least solution of dist[source] = 0, dist[v] = min over edges (u, v, w)
+ * of fl32(dist[u] + w): every offer is one float32 addition and the kept
+ * value an atomic minimum, so the result is unique (bit-exact, any
+ * schedule, any run); +inf where no path exists.  G->value_dtype must be
+ * LB_F32. */
+LB_API lb_status_t lb_sssp(const lb_csr_t *G, int64_t source, float *dist, const lb_schedule_t *s,
+                           int32_t max_iterations, int32_t *iterations, void *workspace,
+                           size_t workspace_bytes, void *stream);
+
+/* Breadth-first search: depth (rows int32, overwritten) receives the least
+ * number of edges from source, -1 where unreachable.  G->values is not read
+ * (may be NULL). */
+LB_API lb_status_t lb_bfs(const lb_csr_t *G, int64_t source, int32_t *depth, const lb_schedule_t *s,
+                          int32_t max_iterations, int32_t *iterations, void *workspace,
+                          size_t workspace_bytes, void *stream);
+
 /* Measurement hooks (not part of the method): the ceilings a kernel of this
  * library is compared with.
  *  lb_probe_stream_read: reads `bytes` (a multiple of 16, 16-byte aligned
@@ -254,7 +303,8 @@ LB_API int32_t lb_probe_default_grid(void);
  * pair of HIP events on its stream.  lb_profile_read synchronizes those
  * events and returns, for the kernel family `name` ("merge_partition",
  * "merge_consume", "merge_fixup", "thread_mapped", "group_mapped",
- * "backward", "batched_consume", "batched_fixup", "fill"), the summed
+ * "backward", "batched_consume", "batched_fixup", "fill", "traversal_init",
+ * "sssp_advance", "bfs_advance"), the summed
  * duration in milliseconds and the launch count since the last reset. */
 LB_API void lb_profile_enable(int on);
 LB_API void lb_profile_reset(void);

@@ -10,6 +10,8 @@ library and fails if it is missing.
     Y = spmm(A, X)                                   # X: cols x k, row-major
     y = SpMV.apply(values, x, pattern, "merge_path") # differentiable in values and x
     Y = batched_spmm(batch, X)                       # one persistent launch
+    dist, iters = sssp(G, source)                    # graph consumer on the same schedules
+    depth, iters = bfs(G, source)
 """
 from __future__ import annotations
 
@@ -25,6 +27,7 @@ _lib = _abi.load()
 
 __all__ = ["CSR", "Pattern", "Batch", "spmv", "spmm", "spmv_backward", "SpMV", "spmv_diff",
            "batched_spmm", "tune", "tune_batched", "merge_path_partition", "group_tile_owner",
+           "sssp", "bfs", "traversal_workspace_size",
            "validate", "resolve_schedule", "profile_enable", "profile_reset", "profile_read", "LBError"]
 
 _DT = {torch.float32: _abi.F32, torch.bfloat16: _abi.BF16, torch.float64: _abi.F64}
@@ -375,3 +378,48 @@ def profile_read(name: str):
     n = ctypes.c_int64(0)
     _abi.check(_lib.lb_profile_read(name.encode(), ctypes.byref(ms), ctypes.byref(n)), "lb_profile_read")
     return float(ms.value), int(n.value)
+
+
+# ---------------------------------------------------------------------------- graph traversal
+
+def traversal_workspace_size(G: Pattern) -> int:
+    n = ctypes.c_size_t(0)
+    _abi.check(_lib.lb_traversal_workspace_size(ctypes.byref(_graph_struct(G)), ctypes.byref(n)),
+               "lb_traversal_workspace_size")
+    return int(n.value)
+
+
+def _graph_struct(G: Pattern) -> _abi.CSR:
+    if isinstance(G, CSR):
+        return G.c_struct()
+    return _abi.CSR(G.shape[0], G.shape[1], G.nnz, G.row_offsets.data_ptr(), G.col_idx.data_ptr(), None, _abi.F32)
+
+
+def _traverse(fn, what, G, source, out, schedule, max_iterations, workspace, params):
+    s = make_schedule(schedule, **params)
+    ws = _workspace(traversal_workspace_size(G), G.device, workspace)
+    it = ctypes.c_int32(0)
+    _abi.check(fn(ctypes.byref(_graph_struct(G)), int(source), _ptr(out), ctypes.byref(s), int(max_iterations),
+                  ctypes.byref(it), _ptr(ws), ws.numel(), _stream(G.device)), what)
+    return out, int(it.value)
+
+
+def sssp(G: CSR, source: int, schedule="auto", dist: torch.Tensor | None = None, max_iterations: int = 0,
+         workspace: torch.Tensor | None = None, **params):
+    """Single-source shortest paths on the graph G (vertex u's out-edges are
+    row u's nonzeros, weights its float32 values >= 0).  Returns (dist,
+    iterations): float32 distances (+inf where unreachable) and the number of
+    non-empty frontiers processed.  Synchronizes the current stream."""
+    if dist is None:
+        dist = torch.empty(G.shape[0], dtype=torch.float32, device=G.device)
+    return _traverse(_lib.lb_sssp, "lb_sssp", G, source, dist, schedule, max_iterations, workspace, params)
+
+
+def bfs(G: Pattern, source: int, schedule="auto", depth: torch.Tensor | None = None, max_iterations: int = 0,
+        workspace: torch.Tensor | None = None, **params):
+    """Breadth-first search from source.  Returns (depth, iterations): int32
+    edge counts (-1 where unreachable) and the number of non-empty frontiers.
+    Synchronizes the current stream."""
+    if depth is None:
+        depth = torch.empty(G.shape[0], dtype=torch.int32, device=G.device)
+    return _traverse(_lib.lb_bfs, "lb_bfs", G, source, depth, schedule, max_iterations, workspace, params)

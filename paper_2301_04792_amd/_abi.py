@@ -12,7 +12,8 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("LB_LIBRARY", os.path.join(_PKG, "liblb.so"))
 
 # lb_status_t
-OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OVERFLOW, ERR_WORKSPACE_TOO_SMALL, ERR_HIP, ERR_INVALID_CSR = range(7)
+(OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OVERFLOW, ERR_WORKSPACE_TOO_SMALL, ERR_HIP, ERR_INVALID_CSR,
+ ERR_NOT_CONVERGED) = range(8)
 # lb_dtype_t
 F32, BF16, F64 = 0, 1, 2
 # lb_sched_kind_t
@@ -86,6 +87,9 @@ SIGNATURES = {
     "lb_batched_autotune": (ST, [PBATCH, P, ST, I32, P, P, SZ, PSCHED, P]),
     "lb_autotune_clear": (None, []),
     "lb_validate_csr": (ST, [PCSR, P]),
+    "lb_traversal_workspace_size": (ST, [PCSR, ctypes.POINTER(SZ)]),
+    "lb_sssp": (ST, [PCSR, I64, P, PSCHED, I32, ctypes.POINTER(I32), P, SZ, P]),
+    "lb_bfs": (ST, [PCSR, I64, P, PSCHED, I32, ctypes.POINTER(I32), P, SZ, P]),
     "lb_probe_stream_read": (ST, [P, SZ, P, I32, P]),
     "lb_probe_gather": (ST, [P, I64, P, P, I32, P]),
     "lb_probe_default_grid": (I32, []),

@@ -1,0 +1,268 @@
+// Graph traversal written on the public schedules of lb_schedule.hpp: the
+// SSSP example of Sec. 5.3 and BFS (named in Sec. 6).  A graph is a CSR
+// tile set read as adjacency: vertex u's out-edges are the atoms of tile u,
+// edge e goes to col_idx[e] and weighs w[e].
+//
+// Iteration i takes frontier F_i, a compacted list of vertex ids (the tiles
+// of an indexed_tile_set), and relaxes every out-edge of its vertices under
+// the chosen schedule; the vertices that improve form F_{i+1}, each listed
+// once.  The host repeats until the frontier is empty (Sec. 5.3).
+//  * SSSP: dist is float32.  The offer dist[u] + w is one float32 addition
+//    and an atomic minimum on the bit pattern keeps the smaller value
+//    (non-negative floats order like their int32 bit patterns).  A vertex
+//    joins F_{i+1} at most once: it carries the iteration that last queued
+//    it, so nothing is cleared between iterations.
+//  * BFS: depth is int32, -1 = unvisited; the compare-and-swap from -1 to
+//    i + 1 that succeeds claims the vertex.
+// Appends are aggregated per wavefront: one atomicAdd reserves the slots of
+// every appending lane and each lane writes at its rank among them.
+//
+// Each advance launch is persistent (the resident grid) and reads the
+// frontier size from device memory, so the host enqueues a batch of
+// iterations without waiting and reads the size once per batch to stop.
+// Three rotating counters: launch i reads counter i % 3, appends to
+// (i + 1) % 3 and zeroes (i + 2) % 3, the one launch i + 1 appends to (and
+// launch i - 1 last read), so no memset and no host round trip is needed.
+#include <math.h>
+
+#include "lb_device.h"
+#include "lb_internal.h"
+#include "lb_schedule.hpp"
+
+namespace lbk {
+using namespace lb;
+
+namespace {
+
+constexpr int32_t kUnvisited = -1;
+
+struct trav_args {
+    const int32_t *ro;
+    const int32_t *ci;
+    const float *w;
+    float *dist;        // SSSP
+    int32_t *depth;     // BFS
+    int32_t *stamp;     // SSSP: iteration that last queued each vertex
+    const int32_t *q_in;
+    int32_t *q_out;
+    const int32_t *cnt_in;
+    int32_t *cnt_out;
+    int32_t *cnt_clear;
+    int32_t *rounds;    // non-empty frontiers processed
+    int32_t iter;
+};
+
+// Appends v for every active lane with `want`; every active lane of the
+// wavefront calls it (inactive lanes take no part in the ballot).
+__device__ __forceinline__ void frontier_push(bool want, int32_t v, int32_t *q_out, int32_t *cnt_out) {
+    const uint64_t m = __ballot(want);
+    if (m == 0) return;
+    const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+    int32_t base = 0;
+    if (lane_id() == leader) base = atomicAdd(cnt_out, __popcll(m));
+    base = __shfl(base, leader);
+    if (want) q_out[base + __popcll(m & ((1ull << lane_id()) - 1))] = v;
+}
+
+// Relaxes edge e of a vertex whose distance is du; returns true when the
+// target v must join the next frontier.
+template <bool BFS>
+__device__ __forceinline__ bool relax(const trav_args &t, float du, int32_t e, int32_t &v) {
+    v = t.ci[e];
+    if constexpr (BFS) {
+        // a stale read can only show -1 for a claimed vertex: the CAS decides
+        if (t.depth[v] != kUnvisited) return false;
+        return atomicCAS(t.depth + v, kUnvisited, t.iter + 1) == kUnvisited;
+    } else {
+        const float offer = du + t.w[e];
+        // distances only decrease, so a stale read is >= the current value:
+        // an offer that does not beat it cannot beat the current one
+        if (!(offer < t.dist[v])) return false;
+        const int32_t old = atomicMin(reinterpret_cast<int32_t *>(t.dist) + v, __float_as_int(offer));
+        if (!(offer < __int_as_float(old))) return false;
+        return atomicExch(t.stamp + v, t.iter) != t.iter;
+    }
+}
+
+__device__ __forceinline__ int32_t frontier_size(const trav_args &t) {
+    const int32_t nf = *t.cnt_in;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *t.cnt_clear = 0;
+        if (nf > 0) *t.rounds += 1;
+    }
+    return nf;
+}
+
+template <bool BFS>
+__device__ __forceinline__ float tile_dist(const trav_args &t, int32_t u) {
+    if constexpr (BFS)
+        return 0.f;
+    else
+        return t.dist[u];
+}
+
+template <bool BFS>
+__global__ __launch_bounds__(1024) void advance_thread_kernel(trav_args t) {
+    const int32_t nf = frontier_size(t);
+    const thread_mapped<indexed_tile_set> sch{{t.q_in, t.ro, nf}};
+    for (int64_t p : sch.tiles()) {
+        const tile_ref tile = sch.ts.tile(p);
+        const float du = tile_dist<BFS>(t, tile.id);
+        for (int64_t e : sch.atoms(tile)) {
+            int32_t v;
+            const bool want = relax<BFS>(t, du, static_cast<int32_t>(e), v);
+            frontier_push(want, v, t.q_out, t.cnt_out);
+        }
+    }
+}
+
+template <int G, bool BFS>
+__global__ __launch_bounds__(group_block<G>::BLOCK) void advance_group_kernel(trav_args t) {
+    const int32_t nf = frontier_size(t);
+    const group_mapped<G, indexed_tile_set> sch{{t.q_in, t.ro, nf}};
+    for (int64_t p : sch.tiles()) {
+        const tile_ref tile = sch.ts.tile(p);
+        const float du = tile_dist<BFS>(t, tile.id);
+        for (int64_t e : sch.atoms(tile)) {
+            int32_t v;
+            const bool want = relax<BFS>(t, du, static_cast<int32_t>(e), v);
+            frontier_push(want, v, t.q_out, t.cnt_out);
+        }
+    }
+}
+
+template <int G, bool BFS>
+__global__ __launch_bounds__(group_block<G>::BLOCK) void advance_scan_kernel(trav_args t) {
+    using sched = group_mapped_scan<G, indexed_tile_set>;
+    __shared__ typename sched::storage st[sched::GPB];
+    const int32_t nf = frontier_size(t);
+    sched sch(indexed_tile_set{t.q_in, t.ro, nf}, st);
+    for (int64_t round : sch.rounds()) {  // uniform across the block
+        const int32_t total = sch.load(round);
+        for (int64_t a : sch.atoms(total)) {
+            const int32_t q = sch.get_tile(static_cast<int32_t>(a));
+            const int32_t u = sch.tile(q);
+            const int32_t e = sch.atom(static_cast<int32_t>(a), q);
+            int32_t v;
+            const bool want = relax<BFS>(t, tile_dist<BFS>(t, u), e, v);
+            frontier_push(want, v, t.q_out, t.cnt_out);
+        }
+        sch.done();
+    }
+}
+
+template <bool BFS>
+__global__ __launch_bounds__(256) void traversal_init_kernel(int32_t n, int32_t source, float *dist,
+                                                             int32_t *depth, int32_t *stamp, int32_t *q0,
+                                                             int32_t *counters) {
+    for (int64_t v : grid_stride_range(0, n)) {
+        if constexpr (BFS) {
+            depth[v] = v == source ? 0 : kUnvisited;
+        } else {
+            dist[v] = v == source ? 0.f : INFINITY;
+            stamp[v] = -1;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        q0[0] = source;
+        counters[0] = 1;  // F_0 = {source}
+        counters[1] = 0;
+        counters[2] = 0;
+        counters[3] = 0;  // rounds
+    }
+}
+
+template <typename K>
+int resident_blocks(K kernel, int block) {
+    int dev = 0, cus = 256, per_cu = 1;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0);
+    }
+    return cus * (per_cu > 0 ? per_cu : 1);
+}
+
+template <typename K>
+hipError_t launch_advance(K kernel, int block, int grid, const trav_args &t, hipStream_t s) {
+    const int g = grid > 0 ? grid : resident_blocks(kernel, block);
+    hipLaunchKernelGGL(kernel, dim3(static_cast<uint32_t>(g)), dim3(block), 0, s, t);
+    return hipGetLastError();
+}
+
+template <bool BFS>
+hipError_t advance(const trav_cfg &c, const trav_args &t, hipStream_t s) {
+    prof_scope p(s, BFS ? "bfs_advance" : "sssp_advance");
+    if (c.kind == LB_THREAD_MAPPED) return launch_advance(advance_thread_kernel<BFS>, c.block, c.grid, t, s);
+#define LB_G(G)                                                                                               \
+    if (c.group == G) {                                                                                       \
+        if (c.tiles_per_group == 1)                                                                           \
+            return launch_advance(advance_group_kernel<G, BFS>, group_block<G>::BLOCK, c.grid, t, s);          \
+        return launch_advance(advance_scan_kernel<G, BFS>, group_block<G>::BLOCK, c.grid, t, s);               \
+    }
+    LB_TRAVERSAL_GROUPS(LB_G)
+#undef LB_G
+    return hipErrorInvalidValue;
+}
+
+template <bool BFS>
+hipError_t run_traversal(const csr_dev &G, int32_t source, float *dist, int32_t *depth, const trav_cfg &c,
+                         int32_t max_iter, int32_t *iterations, bool *converged, void *ws, hipStream_t s) {
+    const trav_ws w = trav_ws_carve(ws, G.rows);
+    {
+        prof_scope p(s, "traversal_init");
+        const int64_t blocks = (static_cast<int64_t>(G.rows) + 255) / 256;
+        hipLaunchKernelGGL(traversal_init_kernel<BFS>, dim3(static_cast<uint32_t>(blocks < 8192 ? blocks : 8192)),
+                           dim3(256), 0, s, G.rows, source, dist, depth, w.stamp, w.queue[0], w.counters);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    trav_args t{G.ro, G.ci, static_cast<const float *>(G.val), dist, depth, w.stamp,
+                nullptr, nullptr, nullptr, nullptr, nullptr, w.counters + 3, 0};
+    int32_t launched = 0, batch = 4;
+    int32_t host[4] = {0, 0, 0, 0};
+    *converged = false;
+    for (;;) {
+        for (int k = 0; k < batch && launched < max_iter; ++k, ++launched) {
+            t.iter = launched;
+            t.q_in = w.queue[launched & 1];
+            t.q_out = w.queue[(launched + 1) & 1];
+            t.cnt_in = w.counters + launched % 3;
+            t.cnt_out = w.counters + (launched + 1) % 3;
+            t.cnt_clear = w.counters + (launched + 2) % 3;
+            const hipError_t e = advance<BFS>(c, t, s);
+            if (e != hipSuccess) return e;
+        }
+        hipError_t e = hipMemcpyAsync(host, w.counters, sizeof host, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        if (host[launched % 3] == 0) {
+            *converged = true;
+            break;
+        }
+        if (launched >= max_iter) break;
+        batch = batch * 2 < 32 ? batch * 2 : 32;
+    }
+    if (iterations) *iterations = host[3];
+    return hipSuccess;
+}
+
+}  // namespace
+
+bool traversal_group_supported(int g) {
+#define LB_G(G) if (g == G) return true;
+    LB_TRAVERSAL_GROUPS(LB_G)
+#undef LB_G
+    return false;
+}
+
+hipError_t sssp(const csr_dev &G, int32_t source, float *dist, const trav_cfg &c, int32_t max_iter,
+                int32_t *iterations, bool *converged, void *ws, hipStream_t s) {
+    return run_traversal<false>(G, source, dist, nullptr, c, max_iter, iterations, converged, ws, s);
+}
+
+hipError_t bfs(const csr_dev &G, int32_t source, int32_t *depth, const trav_cfg &c, int32_t max_iter,
+               int32_t *iterations, bool *converged, void *ws, hipStream_t s) {
+    return run_traversal<true>(G, source, nullptr, depth, c, max_iter, iterations, converged, ws, s);
+}
+
+}  // namespace lbk

@@ -156,21 +156,6 @@ __global__ __launch_bounds__(group_shape<G>::BLOCK) void group_mapped_tile_kerne
 
 // ------------------------------------------------------------------ group-mapped, G tiles per group
 
-// Index of the tile owning atom a: the last q with scan[q] <= a
-// (upper_bound over the K + 1 exclusive prefix sums, minus one).
-template <int K>
-__device__ __forceinline__ int32_t get_tile(const int32_t *scan, int32_t a) {
-    int32_t lo = 0, hi = K + 1;
-    while (lo < hi) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (scan[mid] <= a)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo - 1;
-}
-
 // Setup shared by the SpMV consumer and the get_tile test hook: for the
 // group's tiles [t0, t0 + G), write the exclusive prefix sums of their atom
 // counts into scan[0..G] (scan[G] = group total).  Returns the group total.

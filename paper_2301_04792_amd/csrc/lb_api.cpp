@@ -209,6 +209,81 @@ size_t ws_bytes_for(const lb_csr_t *A, const lb_schedule_t &s, int32_t k) {
     return lbk::merge_ws_bytes(T, k <= 0 ? 1 : spmm_pass_cols(k));
 }
 
+// ------------------------------------------------------------------ graph traversal checks
+
+// A graph is a square CSR; BFS reads no values, so they may be absent.
+lb_status_t check_graph(const lb_csr_t *G, bool need_values) {
+    if (!G) return LB_ERR_INVALID_ARG;
+    lb_csr_t c = *G;
+    if (!need_values && !c.values) {
+        c.values = c.col_idx;  // placeholder so the CSR checks pass; never read
+        c.value_dtype = LB_F32;
+    }
+    lb_status_t st = check_csr(&c);
+    if (st != LB_OK) return st;
+    if (G->rows != G->cols || G->rows == 0) return LB_ERR_INVALID_ARG;
+    if (need_values && G->value_dtype != LB_F32) return LB_ERR_UNSUPPORTED;
+    return LB_OK;
+}
+
+lb_status_t traversal_cfg(const lb_schedule_t *in, lbk::trav_cfg *out) {
+    lb_schedule_t s = in ? *in : lb_schedule_t{LB_AUTO, 0, 0, 0, 0, 0};
+    if (s.group_size < 0 || s.tiles_per_group < 0 || s.items_per_thread < 0 || s.block_size < 0 || s.grid_size < 0)
+        return LB_ERR_INVALID_ARG;
+    if (s.kind == LB_AUTO) {
+        s.kind = LB_GROUP_MAPPED;
+        s.group_size = 64;
+        s.tiles_per_group = 64;
+    }
+    lbk::trav_cfg c{};
+    c.kind = s.kind;
+    c.grid = s.grid_size;
+    switch (s.kind) {
+        case LB_THREAD_MAPPED:
+            c.block = s.block_size ? s.block_size : kDefaultBlock;
+            if (c.block % 64 != 0 || c.block > 1024) return LB_ERR_INVALID_ARG;
+            break;
+        case LB_GROUP_MAPPED:
+            c.group = s.group_size ? s.group_size : kDefaultGroup;
+            if (!is_pow2(c.group) || c.group > 1024) return LB_ERR_INVALID_ARG;
+            if (!lbk::traversal_group_supported(c.group)) return LB_ERR_UNSUPPORTED;
+            c.tiles_per_group = s.tiles_per_group ? s.tiles_per_group : 1;
+            if (c.tiles_per_group != 1 && c.tiles_per_group != c.group) return LB_ERR_UNSUPPORTED;
+            break;
+        case LB_MERGE_PATH: return LB_ERR_UNSUPPORTED;
+        default: return LB_ERR_INVALID_ARG;
+    }
+    *out = c;
+    return LB_OK;
+}
+
+template <bool BFS>
+lb_status_t traversal(const lb_csr_t *G, int64_t source, void *out, const lb_schedule_t *s, int32_t max_iterations,
+                      int32_t *iterations, void *workspace, size_t workspace_bytes, void *stream) {
+    lb_status_t st = check_graph(G, !BFS);
+    if (st != LB_OK) return st;
+    if (!out || source < 0 || source >= G->rows || max_iterations < 0) return LB_ERR_INVALID_ARG;
+    lbk::trav_cfg c;
+    st = traversal_cfg(s, &c);
+    if (st != LB_OK) return st;
+    if (!workspace || workspace_bytes < lbk::trav_ws_bytes(G->rows)) return LB_ERR_WORKSPACE_TOO_SMALL;
+    const int64_t cap = G->rows + 1;
+    const int32_t max_iter = static_cast<int32_t>(max_iterations == 0 || max_iterations > cap ? cap : max_iterations);
+    lbk::csr_dev d = to_dev(G);
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    bool converged = false;
+    hipError_t e;
+    if constexpr (BFS)
+        e = lbk::bfs(d, static_cast<int32_t>(source), static_cast<int32_t *>(out), c, max_iter, iterations,
+                     &converged, workspace, hs);
+    else
+        e = lbk::sssp(d, static_cast<int32_t>(source), static_cast<float *>(out), c, max_iter, iterations,
+                      &converged, workspace, hs);
+    if (e != hipSuccess) return hip_status(e);
+    return converged ? LB_OK : LB_ERR_NOT_CONVERGED;
+}
+
+
 // ------------------------------------------------------------------ profiling
 
 struct prof_rec {
@@ -309,6 +384,7 @@ LB_API const char *lb_status_string(lb_status_t st) {
         case LB_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
         case LB_ERR_HIP: return "HIP error";
         case LB_ERR_INVALID_CSR: return "CSR arrays violate a device-side precondition";
+        case LB_ERR_NOT_CONVERGED: return "traversal frontier not empty after max_iterations";
     }
     return "unknown status";
 }
@@ -363,6 +439,26 @@ LB_API lb_status_t lb_spmv(const lb_csr_t *A, const void *x, lb_dtype_t x_dtype,
             return hip_status(lbk::merge_spmv(d, x, y, r.block_size, r.items_per_thread, workspace, hs));
         default: return LB_ERR_INVALID_ARG;
     }
+}
+
+LB_API lb_status_t lb_traversal_workspace_size(const lb_csr_t *G, size_t *bytes) {
+    if (!bytes) return LB_ERR_INVALID_ARG;
+    const lb_status_t st = check_graph(G, false);
+    if (st != LB_OK) return st;
+    *bytes = lbk::trav_ws_bytes(G->rows);
+    return LB_OK;
+}
+
+LB_API lb_status_t lb_sssp(const lb_csr_t *G, int64_t source, float *dist, const lb_schedule_t *s,
+                           int32_t max_iterations, int32_t *iterations, void *workspace, size_t workspace_bytes,
+                           void *stream) {
+    return traversal<false>(G, source, dist, s, max_iterations, iterations, workspace, workspace_bytes, stream);
+}
+
+LB_API lb_status_t lb_bfs(const lb_csr_t *G, int64_t source, int32_t *depth, const lb_schedule_t *s,
+                          int32_t max_iterations, int32_t *iterations, void *workspace, size_t workspace_bytes,
+                          void *stream) {
+    return traversal<true>(G, source, depth, s, max_iterations, iterations, workspace, workspace_bytes, stream);
 }
 
 LB_API lb_status_t lb_spmm(const lb_csr_t *A, const void *X, lb_dtype_t x_dtype, int32_t k, int64_t ldx, float *Y,

@@ -3,11 +3,9 @@
 //  * element loads: float32 and BF16 bit patterns widened to float; the
 //    nonzero streams (col_idx, values) are read with non-temporal loads so
 //    they do not evict the gathered x from L2;
-//  * ranges (Sec. 5.1): step_range drives the grid-, block- and wave-stride
-//    loops of the schedules;
-//  * tile sets (Sec. 3.1, Sec. 4.1): a CSR matrix's tiles are its rows and
-//    the atoms of tile r are the nonzeros [row_offsets[r], row_offsets[r+1]);
-//  * schedules (Sec. 4.2): thread-mapped tiles()/atoms(tile);
+//  * ranges, tile sets and the thread- and group-mapped schedules come from
+//    the public header lb_schedule.hpp;
+//  * the merge-path split search (Sec. 5.2.1);
 //  * wave64 collectives: group sums, prefix sums and the segmented scan that
 //    merge-path and group-mapped use to combine partial tile results.
 #pragma once
@@ -15,9 +13,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "lb_schedule.hpp"  // ranges, tile sets, thread- and group-mapped schedules, int scans
+
 namespace lb {
 
-constexpr int kWave = 64;
 constexpr int kXcds = 8;  // accelerator dies of an MI355X; workgroups are dealt to them round-robin
 
 using bf16_bits = uint16_t;
@@ -32,55 +31,6 @@ template <typename T>
 __device__ __forceinline__ T ld_stream(const T *p) {
     return __builtin_nontemporal_load(p);
 }
-
-__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
-__device__ __forceinline__ int wave_id() { return threadIdx.x / kWave; }
-
-// ---------------------------------------------------------------- ranges (Sec. 5.1)
-
-// [begin, end) in steps of `step`; 64-bit so a grid stride never wraps.
-struct step_range {
-    int64_t b, e, s;
-    struct iterator {
-        int64_t v, s;
-        __device__ int64_t operator*() const { return v; }
-        __device__ iterator &operator++() {
-            v += s;
-            return *this;
-        }
-        __device__ bool operator!=(const iterator &o) const { return v < o.v; }
-    };
-    __device__ iterator begin() const { return {b, s}; }
-    __device__ iterator end() const { return {e, s}; }
-};
-
-__device__ __forceinline__ step_range grid_stride_range(int64_t begin, int64_t end) {
-    return {static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x + begin, end,
-            static_cast<int64_t>(gridDim.x) * blockDim.x};
-}
-
-// ---------------------------------------------------------------- tile sets (Sec. 4.1)
-
-// CSR as a tile set: tiles are rows, atoms are nonzeros, and the atoms of a
-// tile are the offsets range [row_offsets[t], row_offsets[t + 1]).
-struct csr_tile_set {
-    const int32_t *row_offsets;
-    int64_t num_tiles;
-    int64_t num_atoms;
-    __device__ int32_t atoms_begin(int64_t t) const { return row_offsets[t]; }
-    __device__ int32_t atoms_end(int64_t t) const { return row_offsets[t + 1]; }
-    __device__ int32_t atom_count(int64_t t) const { return row_offsets[t + 1] - row_offsets[t]; }
-};
-
-// ---------------------------------------------------------------- schedules (Sec. 4.2)
-
-// Tile r goes to global thread r; threads stride by the grid; a thread walks
-// its tile's atoms one after another.
-struct thread_mapped_schedule {
-    csr_tile_set ts;
-    __device__ step_range tiles() const { return grid_stride_range(0, ts.num_tiles); }
-    __device__ step_range atoms(int64_t tile) const { return {ts.atoms_begin(tile), ts.atoms_end(tile), 1}; }
-};
 
 // ---------------------------------------------------------------- merge-path split (Sec. 5.2.1)
 
@@ -156,18 +106,6 @@ template <int G>
 __device__ __forceinline__ float group_sum(float v) {
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
-    return v;
-}
-
-// Inclusive prefix sum over aligned groups of G lanes (G <= 64).
-template <int G>
-__device__ __forceinline__ int32_t group_scan_incl(int32_t v) {
-    const int gl = threadIdx.x & (G - 1);
-#pragma unroll
-    for (int off = 1; off < G; off <<= 1) {
-        const int32_t o = __shfl_up(v, off, G);
-        if (gl >= off) v += o;
-    }
     return v;
 }
 
@@ -319,22 +257,6 @@ __device__ __forceinline__ float block_sum(float v, float *s_red) {
     for (int k = 0; k < NW; ++k) t += s_red[k];
     __syncthreads();
     return t;
-}
-
-// Block-wide inclusive prefix sum of int32 (all threads call).
-template <int BLOCK>
-__device__ __forceinline__ int32_t block_scan_incl(int32_t v, int32_t *s_wave) {
-    constexpr int NW = BLOCK / kWave;
-    const int w = wave_id();
-    v = group_scan_incl<kWave>(v);
-    if (lane_id() == kWave - 1) s_wave[w] = v;
-    __syncthreads();
-    int32_t pre = 0;
-#pragma unroll
-    for (int k = 0; k < NW; ++k)
-        if (k < w) pre += s_wave[k];
-    __syncthreads();
-    return v + pre;
 }
 
 }  // namespace lb

@@ -114,6 +114,43 @@ hipError_t group_mapped_spmv(const csr_dev &A, const void *x, float *y, int grou
                              int tiles_per_group, int grid, hipStream_t s);
 hipError_t group_tile_owner(const csr_dev &A, int tiles_per_group, int32_t *owner, hipStream_t s);
 
+// ---- graph traversal (SSSP, BFS) ---------------------------------------------------------
+#define LB_TRAVERSAL_GROUPS(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024)
+
+struct trav_cfg {
+    lb_sched_kind_t kind;  // LB_THREAD_MAPPED or LB_GROUP_MAPPED
+    int group;             // group-mapped: lanes per group
+    int tiles_per_group;   // group-mapped: 1 or group
+    int block;             // thread-mapped: threads per block
+    int grid;              // 0 = resident grid
+};
+
+// Workspace: stamp[n], two frontier queues of n vertex ids, 4 counters
+// (three rotating frontier sizes and the count of non-empty frontiers).
+struct trav_ws {
+    int32_t *stamp;
+    int32_t *queue[2];
+    int32_t *counters;
+};
+inline size_t trav_ws_bytes(int64_t n) { return 3 * align256(static_cast<size_t>(n) * 4) + 256; }
+inline trav_ws trav_ws_carve(void *base, int64_t n) {
+    char *p = static_cast<char *>(base);
+    const size_t q = align256(static_cast<size_t>(n) * 4);
+    trav_ws w;
+    w.stamp = reinterpret_cast<int32_t *>(p);
+    w.queue[0] = reinterpret_cast<int32_t *>(p + q);
+    w.queue[1] = reinterpret_cast<int32_t *>(p + 2 * q);
+    w.counters = reinterpret_cast<int32_t *>(p + 3 * q);
+    return w;
+}
+bool traversal_group_supported(int g);
+// Synchronize s (the host reads the frontier size once per batch of
+// iterations).  *converged is false when max_iter iterations left a frontier.
+hipError_t sssp(const csr_dev &G, int32_t source, float *dist, const trav_cfg &c, int32_t max_iter,
+                int32_t *iterations, bool *converged, void *ws, hipStream_t s);
+hipError_t bfs(const csr_dev &G, int32_t source, int32_t *depth, const trav_cfg &c, int32_t max_iter,
+               int32_t *iterations, bool *converged, void *ws, hipStream_t s);
+
 // ---- measurement probes -----------------------------------------------------------------
 hipError_t probe_stream_read(const void *buf, size_t bytes, float *out, int grid, hipStream_t s);
 hipError_t probe_gather(const int32_t *idx, int64_t n, const float *x, float *out, int grid, hipStream_t s);

@@ -36,7 +36,7 @@ def test_every_declared_symbol_is_exported():
 def test_version_and_status_strings():
     L = _abi.load()
     assert L.lb_abi_version() == 1
-    for st in range(7):
+    for st in range(8):
         assert L.lb_status_string(st)
     assert L.lb_status_string(99) == b"unknown status"
 
@@ -169,3 +169,40 @@ def test_python_binding_host_only_calls():
     assert lb.resolve_schedule(A, "auto")["schedule"] == "thread_mapped"
     with pytest.raises(lb.LBError):
         lb.resolve_schedule(A, "group_mapped", group_size=5)
+
+
+def test_traversal_host_checks():
+    L = _abi.load()
+    G = csr(1000, 1000, 5000)
+    n = ctypes.c_size_t(0)
+    assert L.lb_traversal_workspace_size(ctypes.byref(G), ctypes.byref(n)) == _abi.OK
+    assert n.value >= 3 * 1000 * 4
+    need = n.value
+    it = ctypes.c_int32(0)
+
+    def sssp(G=G, src=0, out=FAKE, s=None, max_it=0, ws=FAKE, wsb=need):
+        s = s or sched("auto")
+        return L.lb_sssp(ctypes.byref(G), src, out, ctypes.byref(s), max_it, ctypes.byref(it), ws, wsb, None)
+
+    def bfs(G=G, src=0, out=FAKE, s=None, ws=FAKE, wsb=need):
+        s = s or sched("auto")
+        return L.lb_bfs(ctypes.byref(G), src, out, ctypes.byref(s), 0, ctypes.byref(it), ws, wsb, None)
+
+    assert sssp(src=-1) == _abi.ERR_INVALID_ARG
+    assert sssp(src=1000) == _abi.ERR_INVALID_ARG
+    assert sssp(out=0) == _abi.ERR_INVALID_ARG
+    assert sssp(max_it=-1) == _abi.ERR_INVALID_ARG
+    assert sssp(G=csr(1000, 999, 5000)) == _abi.ERR_INVALID_ARG            # not square
+    assert sssp(G=csr(0, 0, 0, ro=0, ci=0, val=0)) == _abi.ERR_INVALID_ARG  # no vertex to start from
+    assert sssp(G=csr(dtype=_abi.BF16)) == _abi.ERR_UNSUPPORTED             # weights are float32
+    assert sssp(s=sched("merge_path")) == _abi.ERR_UNSUPPORTED
+    assert sssp(s=sched("group_mapped", group_size=4)) == _abi.ERR_UNSUPPORTED
+    assert sssp(s=sched("group_mapped", group_size=48)) == _abi.ERR_INVALID_ARG
+    assert sssp(s=sched("group_mapped", group_size=64, tiles_per_group=8)) == _abi.ERR_UNSUPPORTED
+    assert sssp(s=sched("thread_mapped", block_size=100)) == _abi.ERR_INVALID_ARG
+    assert sssp(wsb=need - 1) == _abi.ERR_WORKSPACE_TOO_SMALL
+    assert sssp(ws=0) == _abi.ERR_WORKSPACE_TOO_SMALL
+    # BFS reads no weights: absent values pass the checks (and fail only on the workspace here)
+    assert bfs(G=csr(val=0), wsb=need - 1) == _abi.ERR_WORKSPACE_TOO_SMALL
+    assert bfs(G=csr(val=0, dtype=_abi.BF16), wsb=need - 1) == _abi.ERR_WORKSPACE_TOO_SMALL
+    assert L.lb_status_string(_abi.ERR_NOT_CONVERGED) != b"unknown status"
