@@ -254,8 +254,10 @@ LB_API lb_status_t lb_validate_csr(const lb_csr_t *A, void *stream);
  * for SpMV), LB_GROUP_MAPPED with group_size a power of two in [8, 1024]
  * and tiles_per_group 1 (a group per vertex) or group_size (LDS prefix sum
  * and get_tile over the group's vertices), LB_AUTO = group-mapped with
- * group_size = tiles_per_group = 64 (the paper's SSSP uses a group-level
- * schedule).  LB_MERGE_PATH returns LB_ERR_UNSUPPORTED.  grid_size 0 = the
+ * group_size = tiles_per_group = 1024 (the paper's SSSP uses a group-level
+ * schedule; block-wide groups flatten the atoms of 1024 frontier vertices,
+ * which absorbs power-law hubs best).  LB_MERGE_PATH returns
+ * LB_ERR_UNSUPPORTED.  grid_size 0 = the
  * resident grid (CUs x occupancy).
  * max_iterations 0 = rows + 1 (enough for any graph with weights >= 0); a
  * frontier still non-empty after max_iterations returns

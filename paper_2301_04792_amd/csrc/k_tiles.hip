@@ -107,20 +107,15 @@ hipError_t thread_mapped_spmm(const csr_dev &A, const void *X, int32_t k, int64_
 
 // ------------------------------------------------------------------ group-mapped, one tile per group
 
-// Groups of up to one wavefront are packed 256 lanes to a block; a larger
-// group is exactly one block.
-template <int G>
-struct group_shape {
-    static constexpr int BLOCK = G > kWave ? G : 256;
-    static constexpr int GPB = BLOCK / G;  // groups per block
-};
+// Group shape (lb_schedule.hpp): groups of up to one wavefront are packed
+// 256 lanes to a block; a larger group is exactly one block.
 
 template <int G, typename VT, typename XT>
-__global__ __launch_bounds__(group_shape<G>::BLOCK) void group_mapped_tile_kernel(
+__global__ __launch_bounds__(group_block<G>::BLOCK) void group_mapped_tile_kernel(
     csr_tile_set ts, const int32_t *__restrict__ ci, const VT *__restrict__ val, const XT *__restrict__ x,
     float *__restrict__ y) {
-    constexpr int BLOCK = group_shape<G>::BLOCK;
-    constexpr int GPB = group_shape<G>::GPB;
+    constexpr int BLOCK = group_block<G>::BLOCK;
+    constexpr int GPB = group_block<G>::GPB;
     const int gl = threadIdx.x & (G - 1);
     if constexpr (G <= kWave) {
         const int64_t g0 = static_cast<int64_t>(blockIdx.x) * GPB + threadIdx.x / G;
@@ -156,56 +151,39 @@ __global__ __launch_bounds__(group_shape<G>::BLOCK) void group_mapped_tile_kerne
 
 // ------------------------------------------------------------------ group-mapped, G tiles per group
 
-// Setup shared by the SpMV consumer and the get_tile test hook: for the
-// group's tiles [t0, t0 + G), write the exclusive prefix sums of their atom
-// counts into scan[0..G] (scan[G] = group total).  Returns the group total.
-template <int G, int BLOCK>
-__device__ __forceinline__ int32_t group_tile_scan(const csr_tile_set &ts, int64_t t0, bool active,
-                                                   int32_t *scan, int32_t *s_wave_i) {
-    const int gl = threadIdx.x & (G - 1);
-    const int32_t cnt = (active && t0 + gl < ts.num_tiles) ? ts.atom_count(t0 + gl) : 0;
-    int32_t inc;
-    if constexpr (G <= kWave)
-        inc = group_scan_incl<G>(cnt);
-    else
-        inc = block_scan_incl<BLOCK>(cnt, s_wave_i);
-    scan[gl + 1] = inc;
-    if (gl == 0) scan[0] = 0;
-    __syncthreads();
-    return scan[G];
-}
-
+// The schedule is the public group_mapped_scan (lb_schedule.hpp), the same
+// one the graph traversals run on: per round, the group's G rows are
+// prefix-summed in LDS and its lanes stride the flattened nonzeros, each
+// finding its row with get_tile.  Per-row sums: a segmented scan over the
+// lanes of each step, whose segment tails add into the row's LDS
+// accumulator in step order (deterministic).
 template <int G, typename VT, typename XT>
-__global__ __launch_bounds__(group_shape<G>::BLOCK) void group_mapped_scan_kernel(
+__global__ __launch_bounds__(group_block<G>::BLOCK) void group_mapped_scan_kernel(
     csr_tile_set ts, const int32_t *__restrict__ ci, const VT *__restrict__ val, const XT *__restrict__ x,
     float *__restrict__ y) {
-    constexpr int BLOCK = group_shape<G>::BLOCK;
-    constexpr int GPB = group_shape<G>::GPB;
-    __shared__ int32_t s_scan[GPB][G + 1];
+    using sched = group_mapped_scan<G, csr_tile_set>;
+    constexpr int BLOCK = sched::BLOCK;
+    constexpr int GPB = sched::GPB;
+    __shared__ typename sched::storage s_st[GPB];
     __shared__ float s_acc[GPB][G];
     __shared__ int32_t s_key[G > kWave ? BLOCK : 1];
     __shared__ seg_t s_wave[BLOCK / kWave];
-    __shared__ int32_t s_wave_i[BLOCK / kWave];
 
     const int gl = threadIdx.x & (G - 1);
     const int gi = threadIdx.x / G;
-    const int64_t nchunks = (ts.num_tiles + G - 1) / G;
-    for (int64_t base = static_cast<int64_t>(blockIdx.x) * GPB; base < nchunks;
-         base += static_cast<int64_t>(gridDim.x) * GPB) {  // block-uniform trip count
-        const int64_t chunk = base + gi;
-        const bool active = chunk < nchunks;
-        const int64_t t0 = chunk * G;
+    sched sch(ts, s_st);
+    for (int64_t round : sch.rounds()) {  // uniform across the block
+        const int64_t t0 = (round + gi) * G;
         s_acc[gi][gl] = 0.f;
-        const int32_t total = group_tile_scan<G, BLOCK>(ts, t0, active, s_scan[gi], s_wave_i);
-        const int32_t abase = active ? ts.atoms_begin(t0) : 0;
+        const int32_t total = sch.load(round);  // ends with a barrier: s_acc is clear
         const int32_t steps = (total + G - 1) / G;
         for (int32_t st = 0; st < steps; ++st) {  // uniform within the group
             const int32_t a = st * G + gl;
             int32_t key = G;  // past the last tile: inactive lane
             float p = 0.f;
             if (a < total) {
-                key = get_tile<G>(s_scan[gi], a);
-                const int32_t j = abase + a;
+                key = sch.get_tile(a);
+                const int32_t j = sch.atom(a, key);
                 p = to_f32(ld_stream(val + j)) * to_f32(x[ld_stream(ci + j)]);
             }
             if constexpr (G <= kWave) {
@@ -227,15 +205,15 @@ __global__ __launch_bounds__(group_shape<G>::BLOCK) void group_mapped_scan_kerne
             }
         }
         __syncthreads();
-        if (active && t0 + gl < ts.num_tiles) y[t0 + gl] = s_acc[gi][gl];
-        __syncthreads();
+        if (t0 + gl < ts.num_tiles) y[t0 + gl] = s_acc[gi][gl];
+        sch.done();
     }
 }
 
 template <int G, typename VT>
 static hipError_t launch_group(const csr_dev &A, const void *x, float *y, int K, int grid, hipStream_t s) {
-    constexpr int BLOCK = group_shape<G>::BLOCK;
-    constexpr int GPB = group_shape<G>::GPB;
+    constexpr int BLOCK = group_block<G>::BLOCK;
+    constexpr int GPB = group_block<G>::GPB;
     const csr_tile_set ts{A.ro, A.rows, A.nnz};
     if (K == 1) {
         const dim3 g(static_cast<uint32_t>(blocks_for(A.rows, GPB, grid)));
@@ -268,24 +246,18 @@ hipError_t group_mapped_spmv(const csr_dev &A, const void *x, float *y, int grou
 // ------------------------------------------------------------------ get_tile test hook
 
 template <int G>
-__global__ __launch_bounds__(group_shape<G>::BLOCK) void group_tile_owner_kernel(csr_tile_set ts,
+__global__ __launch_bounds__(group_block<G>::BLOCK) void group_tile_owner_kernel(csr_tile_set ts,
                                                                                  int32_t *__restrict__ owner) {
-    constexpr int BLOCK = group_shape<G>::BLOCK;
-    constexpr int GPB = group_shape<G>::GPB;
-    __shared__ int32_t s_scan[GPB][G + 1];
-    __shared__ int32_t s_wave_i[BLOCK / kWave];
-    const int gl = threadIdx.x & (G - 1);
-    const int gi = threadIdx.x / G;
-    const int64_t nchunks = (ts.num_tiles + G - 1) / G;
-    for (int64_t base = static_cast<int64_t>(blockIdx.x) * GPB; base < nchunks;
-         base += static_cast<int64_t>(gridDim.x) * GPB) {
-        const int64_t chunk = base + gi;
-        const bool active = chunk < nchunks;
-        const int64_t t0 = chunk * G;
-        const int32_t total = group_tile_scan<G, BLOCK>(ts, t0, active, s_scan[gi], s_wave_i);
-        const int32_t abase = active ? ts.atoms_begin(t0) : 0;
-        for (int32_t a = gl; a < total; a += G) owner[abase + a] = get_tile<G>(s_scan[gi], a);
-        __syncthreads();
+    using sched = group_mapped_scan<G, csr_tile_set>;
+    __shared__ typename sched::storage s_st[sched::GPB];
+    sched sch(ts, s_st);
+    for (int64_t round : sch.rounds()) {
+        const int32_t total = sch.load(round);
+        for (int64_t a : sch.atoms(total)) {
+            const int32_t q = sch.get_tile(static_cast<int32_t>(a));
+            owner[sch.atom(static_cast<int32_t>(a), q)] = q;
+        }
+        sch.done();
     }
 }
 
@@ -294,8 +266,8 @@ hipError_t group_tile_owner(const csr_dev &A, int tiles_per_group, int32_t *owne
 #define X(G)                                                                                           \
     if (tiles_per_group == G) {                                                                        \
         const int64_t nchunks = (static_cast<int64_t>(A.rows) + G - 1) / G;                            \
-        const dim3 g(static_cast<uint32_t>(blocks_for(nchunks, group_shape<G>::GPB, 0)));              \
-        hipLaunchKernelGGL((group_tile_owner_kernel<G>), g, dim3(group_shape<G>::BLOCK), 0, s, ts, owner); \
+        const dim3 g(static_cast<uint32_t>(blocks_for(nchunks, group_block<G>::GPB, 0)));              \
+        hipLaunchKernelGGL((group_tile_owner_kernel<G>), g, dim3(group_block<G>::BLOCK), 0, s, ts, owner); \
         return hipGetLastError();                                                                      \
     }
     LB_GROUP_SIZES(X)

@@ -230,10 +230,10 @@ lb_status_t traversal_cfg(const lb_schedule_t *in, lbk::trav_cfg *out) {
     lb_schedule_t s = in ? *in : lb_schedule_t{LB_AUTO, 0, 0, 0, 0, 0};
     if (s.group_size < 0 || s.tiles_per_group < 0 || s.items_per_thread < 0 || s.block_size < 0 || s.grid_size < 0)
         return LB_ERR_INVALID_ARG;
-    if (s.kind == LB_AUTO) {
+    if (s.kind == LB_AUTO) {  // block-wide groups over flattened atoms: measured best on power-law graphs
         s.kind = LB_GROUP_MAPPED;
-        s.group_size = 64;
-        s.tiles_per_group = 64;
+        s.group_size = 1024;
+        s.tiles_per_group = 1024;
     }
     lbk::trav_cfg c{};
     c.kind = s.kind;
