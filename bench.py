@@ -218,7 +218,8 @@ def run_graph(lb, S, dev, no_cpu):
     graph_schedules = (("auto", "auto", {}), ("thread_mapped", "thread_mapped", {}),
                        ("group64", "group_mapped", {"group_size": 64, "tiles_per_group": 1}),
                        ("group1024", "group_mapped", {"group_size": 1024, "tiles_per_group": 1}),
-                       ("group64x64", "group_mapped", {"group_size": 64, "tiles_per_group": 64}))
+                       ("group64x64", "group_mapped", {"group_size": 64, "tiles_per_group": 64}),
+                       ("merge_path", "merge_path", {}))
     for algo, fn in (("sssp", lb.sssp), ("bfs", lb.bfs)):
         per = {}
         for name, sch, p in graph_schedules:

@@ -253,19 +253,23 @@ LB_API lb_status_t lb_validate_csr(const lb_csr_t *A, void *stream);
  * Schedules: LB_THREAD_MAPPED (a thread per frontier vertex, block_size as
  * for SpMV), LB_GROUP_MAPPED with group_size a power of two in [8, 1024]
  * and tiles_per_group 1 (a group per vertex) or group_size (LDS prefix sum
- * and get_tile over the group's vertices), LB_AUTO = group-mapped with
- * group_size = tiles_per_group = 1024 (the paper's SSSP uses a group-level
- * schedule; block-wide groups flatten the atoms of 1024 frontier vertices,
- * which absorbs power-law hubs best).  LB_MERGE_PATH returns
- * LB_ERR_UNSUPPORTED.  grid_size 0 = the
- * resident grid (CUs x occupancy).
+ * and get_tile over the group's vertices), LB_AUTO = the rule of Sec. 6.2
+ * as for SpMV (merge-path unless (rows < 500 or cols < 500) and
+ * nnz < 10000; then thread-mapped, or group-mapped with at least 8 lanes).
+ * LB_MERGE_PATH (256 threads x 8
+ * merge items per unit; other block_size / items_per_thread values return
+ * LB_ERR_UNSUPPORTED): per iteration the frontier's out-degrees are
+ * prefix-summed on the device, the merge of those offsets with the
+ * frontier's edges is split into equal units (Sec. 5.2.1) and a persistent
+ * launch walks them.  grid_size 0 = the resident grid (CUs x occupancy).
  * max_iterations 0 = rows + 1 (enough for any graph with weights >= 0); a
  * frontier still non-empty after max_iterations returns
  * LB_ERR_NOT_CONVERGED (the outputs then hold upper bounds).
  * *iterations (host, may be NULL) receives the number of non-empty
  * frontiers processed.  source in [0, rows). */
 
-/* Workspace bytes for lb_sssp / lb_bfs on G (3 * rows int32 + counters).  Host-only. */
+/* Workspace bytes for lb_sssp / lb_bfs on G (about 4 * rows int32, plus the
+ * merge-path split over at most rows + nnz items).  Host-only. */
 LB_API lb_status_t lb_traversal_workspace_size(const lb_csr_t *G, size_t *bytes);
 
 /* Single-source shortest paths: dist (rows float32, overwritten) receives

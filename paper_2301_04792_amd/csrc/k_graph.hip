@@ -17,8 +17,10 @@
 // Appends are aggregated per wavefront: one atomicAdd reserves the slots of
 // every appending lane and each lane writes at its rank among them.
 //
-// Each advance launch is persistent (the resident grid) and reads the
-// frontier size from device memory, so the host enqueues a batch of
+// Under merge-path an iteration is five launches (degree scan, split,
+// consume; see below); under the other schedules one.  Each advance launch
+// is persistent (the resident grid) and reads the frontier size from device
+// memory, so the host enqueues a batch of
 // iterations without waiting and reads the size once per batch to stop.
 // Three rotating counters: launch i reads counter i % 3, appends to
 // (i + 1) % 3 and zeroes (i + 2) % 3, the one launch i + 1 appends to (and
@@ -151,6 +153,176 @@ __global__ __launch_bounds__(group_block<G>::BLOCK) void advance_scan_kernel(tra
     }
 }
 
+// ---------------------------------------------------------------- merge-path over the frontier
+//
+// The frontier as a tile set for merge-path (Sec. 5.2.1) needs its "row
+// offsets": offs[p] = out-degrees of frontier entries [0, p).  Per
+// iteration: (1) per tile of kScanTile entries, the in-tile exclusive
+// prefix sums and the tile total; (2) one block scans the tile totals and
+// records the frontier's edge count E_f and unit count T_f; (3) the tile
+// prefixes are added in; (4) the split at every unit boundary of the merge
+// of offs[1..nf] with the edges 0..E_f-1 (the SpMV split); (5) a persistent
+// consume: each unit stages its frontier entries in LDS and each thread
+// walks kMergeItems merge items, relaxing the edges it meets.  Every grid
+// is sized for the largest frontier (every vertex); blocks past the
+// frontier's work leave at once.
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+constexpr int kMergeBlock = 256;
+constexpr int kMergeItems = 8;
+constexpr int kMergeW = kMergeBlock * kMergeItems;
+constexpr int kPartGroup = 16;
+
+__global__ __launch_bounds__(kScanThreads) void frontier_scan_tiles(const int32_t *__restrict__ q,
+                                                                    const int32_t *__restrict__ cnt_in,
+                                                                    const int32_t *__restrict__ ro,
+                                                                    int32_t *__restrict__ offs,
+                                                                    int32_t *__restrict__ tile_sum) {
+    __shared__ int32_t s_wave[kScanThreads / kWave];
+    const int32_t nf = *cnt_in;
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanTile;
+    if (base >= nf) return;  // uniform across the block
+    int32_t deg[kScanItems];
+    int32_t sum = 0;
+#pragma unroll
+    for (int u = 0; u < kScanItems; ++u) {
+        const int64_t p = base + threadIdx.x * kScanItems + u;
+        int32_t dg = 0;
+        if (p < nf) {
+            const int32_t v = q[p];
+            dg = ro[v + 1] - ro[v];
+        }
+        deg[u] = dg;
+        sum += dg;
+    }
+    const int32_t incl = block_scan_incl<kScanThreads>(sum, s_wave);
+    int32_t run = incl - sum;
+#pragma unroll
+    for (int u = 0; u < kScanItems; ++u) {
+        const int64_t p = base + threadIdx.x * kScanItems + u;
+        if (p < nf) offs[p] = run;
+        run += deg[u];
+    }
+    if (threadIdx.x == kScanThreads - 1) tile_sum[blockIdx.x] = incl;
+}
+
+// One block: exclusive prefix of the tile totals (in place), then
+// offs[nf] = E_f, meta = {E_f, T_f}.
+__global__ __launch_bounds__(1024) void frontier_scan_totals(const int32_t *__restrict__ cnt_in,
+                                                             int32_t *__restrict__ tile_sum,
+                                                             int32_t *__restrict__ offs,
+                                                             int32_t *__restrict__ meta) {
+    __shared__ int32_t s_wave[1024 / kWave];
+    __shared__ int32_t s_total;
+    const int32_t nf = *cnt_in;
+    const int32_t nb = (nf + kScanTile - 1) / kScanTile;
+    int32_t carry = 0;
+    for (int32_t c = 0; c < nb; c += 1024) {  // uniform across the block
+        const int32_t idx = c + static_cast<int32_t>(threadIdx.x);
+        const int32_t v = idx < nb ? tile_sum[idx] : 0;
+        const int32_t incl = block_scan_incl<1024>(v, s_wave);
+        if (idx < nb) tile_sum[idx] = carry + incl - v;
+        if (threadIdx.x == 1023) s_total = incl;
+        __syncthreads();
+        carry += s_total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        offs[nf] = carry;
+        meta[0] = carry;
+        meta[1] = (nf + carry + kMergeW - 1) / kMergeW;
+    }
+}
+
+__global__ __launch_bounds__(256) void frontier_scan_add(const int32_t *__restrict__ cnt_in,
+                                                         const int32_t *__restrict__ tile_pre,
+                                                         int32_t *__restrict__ offs) {
+    const int32_t nf = *cnt_in;
+    for (int64_t p : grid_stride_range(0, nf)) offs[p] += tile_pre[p / kScanTile];
+}
+
+// Split at boundaries t in [0, T_f]: one group of kPartGroup lanes each.
+__global__ __launch_bounds__(256) void frontier_partition(const int32_t *__restrict__ cnt_in,
+                                                          const int32_t *__restrict__ offs,
+                                                          const int32_t *__restrict__ meta,
+                                                          int32_t *__restrict__ part_i,
+                                                          int32_t *__restrict__ part_j) {
+    const int32_t nf = *cnt_in, ef = meta[0], T = meta[1];
+    const int64_t first = static_cast<int64_t>(blockIdx.x) * (256 / kPartGroup);
+    if (nf == 0 || first > T) return;  // uniform across the block
+    const int64_t t = first + threadIdx.x / kPartGroup;
+    const bool live = t <= T;  // uniform per group; every lane still takes part in the ballots
+    const int64_t total = static_cast<int64_t>(nf) + ef;
+    const int64_t tt = live ? t : T;
+    const int32_t d = static_cast<int32_t>(tt * kMergeW < total ? tt * kMergeW : total);
+    const int32_t i = group_merge_search<kPartGroup>(offs, nf, ef, d);
+    if (live && (threadIdx.x & (kPartGroup - 1)) == 0) {
+        part_i[t] = i;
+        part_j[t] = d - i;
+    }
+}
+
+template <bool BFS>
+__global__ __launch_bounds__(kMergeBlock) void advance_merge_kernel(trav_args t, const int32_t *__restrict__ offs,
+                                                                    const int32_t *__restrict__ meta,
+                                                                    const int32_t *__restrict__ part_i,
+                                                                    const int32_t *__restrict__ part_j) {
+    // frontier entries touched by the unit: row ends relative to j0, the
+    // edge id of atom j of entry k is s_base[k] + j, and the entry's distance
+    __shared__ int32_t s_end[kMergeW + 1];
+    __shared__ int32_t s_base[kMergeW + 1];
+    __shared__ float s_du[BFS ? 1 : kMergeW + 1];
+    const int32_t nf = frontier_size(t);
+    const int32_t T = nf > 0 ? meta[1] : 0;
+    const int tid = threadIdx.x;
+    for (int32_t u = blockIdx.x; u < T; u += gridDim.x) {  // uniform across the block
+        const int32_t i0 = part_i[u], j0 = part_j[u];
+        const int32_t i1 = part_i[u + 1], j1 = part_j[u + 1];
+        const int32_t nrows = i1 - i0, nnzs = j1 - j0;
+        const int32_t last = i1 < nf ? i1 : nf - 1;  // the entry holding the unit's trailing atoms
+        for (int32_t k = tid; k <= last - i0; k += kMergeBlock) {
+            const int32_t p = i0 + k;
+            const int32_t v = t.q_in[p];
+            s_end[k] = offs[p + 1] - j0;
+            s_base[k] = t.ro[v] - offs[p];
+            if constexpr (!BFS) s_du[k] = t.dist[v];
+        }
+        __syncthreads();
+        // this thread's merge items [d, dend) of the unit's nrows + nnzs
+        const int32_t total = nrows + nnzs;
+        const int32_t d = tid * kMergeItems < total ? tid * kMergeItems : total;
+        const int32_t dend = d + kMergeItems < total ? d + kMergeItems : total;
+        int32_t lo = d - nnzs > 0 ? d - nnzs : 0;
+        int32_t hi = d < nrows ? d : nrows;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (s_end[mid] + mid < d)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        int32_t it = lo, jt = d - lo;
+#pragma unroll
+        for (int s = 0; s < kMergeItems; ++s) {  // every lane takes part in each append
+            bool want = false;
+            int32_t v = 0;
+            if (d + s < dend) {
+                if (it < nrows && s_end[it] <= jt) {
+                    ++it;  // entry it's edges are done
+                } else {
+                    const int32_t j = j0 + jt;
+                    want = relax<BFS>(t, BFS ? 0.f : s_du[it], s_base[it] + j, v);
+                    ++jt;
+                }
+            }
+            frontier_push(want, v, t.q_out, t.cnt_out);
+        }
+        __syncthreads();
+    }
+}
+
 template <bool BFS>
 __global__ __launch_bounds__(256) void traversal_init_kernel(int32_t n, int32_t source, float *dist,
                                                              int32_t *depth, int32_t *stamp, int32_t *q0,
@@ -190,8 +362,29 @@ hipError_t launch_advance(K kernel, int block, int grid, const trav_args &t, hip
 }
 
 template <bool BFS>
-hipError_t advance(const trav_cfg &c, const trav_args &t, hipStream_t s) {
+hipError_t advance_merge(const csr_dev &G, const trav_cfg &c, const trav_ws &w, const trav_args &t, hipStream_t s) {
+    const int64_t n = G.rows;
+    const int64_t scan_blocks = (n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(frontier_scan_tiles, dim3(static_cast<uint32_t>(scan_blocks)), dim3(kScanThreads), 0, s,
+                       t.q_in, t.cnt_in, G.ro, w.offs, w.tile_sum);
+    hipLaunchKernelGGL(frontier_scan_totals, dim3(1), dim3(1024), 0, s, t.cnt_in, w.tile_sum, w.offs, w.meta);
+    const int64_t add_blocks = (n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048;
+    hipLaunchKernelGGL(frontier_scan_add, dim3(static_cast<uint32_t>(add_blocks)), dim3(256), 0, s, t.cnt_in,
+                       w.tile_sum, w.offs);
+    const int64_t tmax = trav_merge_units(n, G.nnz);
+    const int64_t part_blocks = ((tmax + 1) * kPartGroup + 255) / 256;
+    hipLaunchKernelGGL(frontier_partition, dim3(static_cast<uint32_t>(part_blocks)), dim3(256), 0, s, t.cnt_in,
+                       w.offs, w.meta, w.part_i, w.part_j);
+    const int grid = c.grid > 0 ? c.grid : resident_blocks(advance_merge_kernel<BFS>, kMergeBlock);
+    hipLaunchKernelGGL(advance_merge_kernel<BFS>, dim3(static_cast<uint32_t>(grid)), dim3(kMergeBlock), 0, s, t,
+                       w.offs, w.meta, w.part_i, w.part_j);
+    return hipGetLastError();
+}
+
+template <bool BFS>
+hipError_t advance(const csr_dev &G, const trav_cfg &c, const trav_ws &w, const trav_args &t, hipStream_t s) {
     prof_scope p(s, BFS ? "bfs_advance" : "sssp_advance");
+    if (c.kind == LB_MERGE_PATH) return advance_merge<BFS>(G, c, w, t, s);
     if (c.kind == LB_THREAD_MAPPED) return launch_advance(advance_thread_kernel<BFS>, c.block, c.grid, t, s);
 #define LB_G(G)                                                                                               \
     if (c.group == G) {                                                                                       \
@@ -207,7 +400,7 @@ hipError_t advance(const trav_cfg &c, const trav_args &t, hipStream_t s) {
 template <bool BFS>
 hipError_t run_traversal(const csr_dev &G, int32_t source, float *dist, int32_t *depth, const trav_cfg &c,
                          int32_t max_iter, int32_t *iterations, bool *converged, void *ws, hipStream_t s) {
-    const trav_ws w = trav_ws_carve(ws, G.rows);
+    const trav_ws w = trav_ws_carve(ws, G.rows, G.nnz);
     {
         prof_scope p(s, "traversal_init");
         const int64_t blocks = (static_cast<int64_t>(G.rows) + 255) / 256;
@@ -229,7 +422,7 @@ hipError_t run_traversal(const csr_dev &G, int32_t source, float *dist, int32_t 
             t.cnt_in = w.counters + launched % 3;
             t.cnt_out = w.counters + (launched + 1) % 3;
             t.cnt_clear = w.counters + (launched + 2) % 3;
-            const hipError_t e = advance<BFS>(c, t, s);
+            const hipError_t e = advance<BFS>(G, c, w, t, s);
             if (e != hipSuccess) return e;
         }
         hipError_t e = hipMemcpyAsync(host, w.counters, sizeof host, hipMemcpyDeviceToHost, s);

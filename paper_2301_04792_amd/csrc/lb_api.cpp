@@ -226,14 +226,15 @@ lb_status_t check_graph(const lb_csr_t *G, bool need_values) {
     return LB_OK;
 }
 
-lb_status_t traversal_cfg(const lb_schedule_t *in, lbk::trav_cfg *out) {
+lb_status_t traversal_cfg(const lb_csr_t *G, const lb_schedule_t *in, lbk::trav_cfg *out) {
     lb_schedule_t s = in ? *in : lb_schedule_t{LB_AUTO, 0, 0, 0, 0, 0};
     if (s.group_size < 0 || s.tiles_per_group < 0 || s.items_per_thread < 0 || s.block_size < 0 || s.grid_size < 0)
         return LB_ERR_INVALID_ARG;
-    if (s.kind == LB_AUTO) {  // block-wide groups over flattened atoms: measured best on power-law graphs
-        s.kind = LB_GROUP_MAPPED;
-        s.group_size = 1024;
-        s.tiles_per_group = 1024;
+    if (s.kind == LB_AUTO) {  // the Sec. 6.2 rule, as for SpMV; groups of at least 8 lanes
+        const lb_schedule_t h = heuristic(G);
+        s.kind = h.kind;
+        s.group_size = h.group_size < 8 ? 8 : h.group_size;
+        s.tiles_per_group = 1;
     }
     lbk::trav_cfg c{};
     c.kind = s.kind;
@@ -250,7 +251,10 @@ lb_status_t traversal_cfg(const lb_schedule_t *in, lbk::trav_cfg *out) {
             c.tiles_per_group = s.tiles_per_group ? s.tiles_per_group : 1;
             if (c.tiles_per_group != 1 && c.tiles_per_group != c.group) return LB_ERR_UNSUPPORTED;
             break;
-        case LB_MERGE_PATH: return LB_ERR_UNSUPPORTED;
+        case LB_MERGE_PATH:  // one configuration: 256 threads x 8 merge items per unit
+            if ((s.block_size && s.block_size != 256) || (s.items_per_thread && s.items_per_thread != 8))
+                return LB_ERR_UNSUPPORTED;
+            break;
         default: return LB_ERR_INVALID_ARG;
     }
     *out = c;
@@ -264,9 +268,9 @@ lb_status_t traversal(const lb_csr_t *G, int64_t source, void *out, const lb_sch
     if (st != LB_OK) return st;
     if (!out || source < 0 || source >= G->rows || max_iterations < 0) return LB_ERR_INVALID_ARG;
     lbk::trav_cfg c;
-    st = traversal_cfg(s, &c);
+    st = traversal_cfg(G, s, &c);
     if (st != LB_OK) return st;
-    if (!workspace || workspace_bytes < lbk::trav_ws_bytes(G->rows)) return LB_ERR_WORKSPACE_TOO_SMALL;
+    if (!workspace || workspace_bytes < lbk::trav_ws_bytes(G->rows, G->nnz)) return LB_ERR_WORKSPACE_TOO_SMALL;
     const int64_t cap = G->rows + 1;
     const int32_t max_iter = static_cast<int32_t>(max_iterations == 0 || max_iterations > cap ? cap : max_iterations);
     lbk::csr_dev d = to_dev(G);
@@ -445,7 +449,7 @@ LB_API lb_status_t lb_traversal_workspace_size(const lb_csr_t *G, size_t *bytes)
     if (!bytes) return LB_ERR_INVALID_ARG;
     const lb_status_t st = check_graph(G, false);
     if (st != LB_OK) return st;
-    *bytes = lbk::trav_ws_bytes(G->rows);
+    *bytes = lbk::trav_ws_bytes(G->rows, G->nnz);
     return LB_OK;
 }
 

@@ -118,29 +118,55 @@ hipError_t group_tile_owner(const csr_dev &A, int tiles_per_group, int32_t *owne
 #define LB_TRAVERSAL_GROUPS(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024)
 
 struct trav_cfg {
-    lb_sched_kind_t kind;  // LB_THREAD_MAPPED or LB_GROUP_MAPPED
+    lb_sched_kind_t kind;  // LB_THREAD_MAPPED, LB_GROUP_MAPPED or LB_MERGE_PATH
     int group;             // group-mapped: lanes per group
     int tiles_per_group;   // group-mapped: 1 or group
     int block;             // thread-mapped: threads per block
     int grid;              // 0 = resident grid
 };
 
+// Merge-path units of a frontier: at most (n + nnz) merge items of 2048.
+inline int64_t trav_merge_units(int64_t n, int64_t nnz) { return (n + nnz + 2047) / 2048; }
+
 // Workspace: stamp[n], two frontier queues of n vertex ids, 4 counters
-// (three rotating frontier sizes and the count of non-empty frontiers).
+// (three rotating frontier sizes and the count of non-empty frontiers);
+// for merge-path also the frontier's offsets[n + 1], per-tile degree sums,
+// {E_f, T_f} and the split at every unit boundary.
 struct trav_ws {
     int32_t *stamp;
     int32_t *queue[2];
     int32_t *counters;
+    int32_t *offs;
+    int32_t *tile_sum;
+    int32_t *meta;
+    int32_t *part_i;
+    int32_t *part_j;
 };
-inline size_t trav_ws_bytes(int64_t n) { return 3 * align256(static_cast<size_t>(n) * 4) + 256; }
-inline trav_ws trav_ws_carve(void *base, int64_t n) {
+inline size_t trav_ws_bytes(int64_t n, int64_t nnz) {
+    const size_t q = align256(static_cast<size_t>(n) * 4);
+    const size_t units = static_cast<size_t>(trav_merge_units(n, nnz)) + 1;
+    return 3 * q + 256 + align256(static_cast<size_t>(n + 1) * 4) + align256(static_cast<size_t>(n / 2048 + 2) * 4) +
+           256 + 2 * align256(units * 4);
+}
+inline trav_ws trav_ws_carve(void *base, int64_t n, int64_t nnz) {
     char *p = static_cast<char *>(base);
     const size_t q = align256(static_cast<size_t>(n) * 4);
+    const size_t units = static_cast<size_t>(trav_merge_units(n, nnz)) + 1;
     trav_ws w;
     w.stamp = reinterpret_cast<int32_t *>(p);
     w.queue[0] = reinterpret_cast<int32_t *>(p + q);
     w.queue[1] = reinterpret_cast<int32_t *>(p + 2 * q);
     w.counters = reinterpret_cast<int32_t *>(p + 3 * q);
+    p += 3 * q + 256;
+    w.offs = reinterpret_cast<int32_t *>(p);
+    p += align256(static_cast<size_t>(n + 1) * 4);
+    w.tile_sum = reinterpret_cast<int32_t *>(p);
+    p += align256(static_cast<size_t>(n / 2048 + 2) * 4);
+    w.meta = reinterpret_cast<int32_t *>(p);
+    p += 256;
+    w.part_i = reinterpret_cast<int32_t *>(p);
+    p += align256(units * 4);
+    w.part_j = reinterpret_cast<int32_t *>(p);
     return w;
 }
 bool traversal_group_supported(int g);

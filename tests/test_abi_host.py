@@ -195,7 +195,9 @@ def test_traversal_host_checks():
     assert sssp(G=csr(1000, 999, 5000)) == _abi.ERR_INVALID_ARG            # not square
     assert sssp(G=csr(0, 0, 0, ro=0, ci=0, val=0)) == _abi.ERR_INVALID_ARG  # no vertex to start from
     assert sssp(G=csr(dtype=_abi.BF16)) == _abi.ERR_UNSUPPORTED             # weights are float32
-    assert sssp(s=sched("merge_path")) == _abi.ERR_UNSUPPORTED
+    assert sssp(s=sched("merge_path", block_size=512)) == _abi.ERR_UNSUPPORTED  # one configuration: 256 x 8
+    assert sssp(s=sched("merge_path", items_per_thread=4)) == _abi.ERR_UNSUPPORTED
+    assert sssp(s=sched("merge_path"), wsb=need - 1) == _abi.ERR_WORKSPACE_TOO_SMALL
     assert sssp(s=sched("group_mapped", group_size=4)) == _abi.ERR_UNSUPPORTED
     assert sssp(s=sched("group_mapped", group_size=48)) == _abi.ERR_INVALID_ARG
     assert sssp(s=sched("group_mapped", group_size=64, tiles_per_group=8)) == _abi.ERR_UNSUPPORTED

@@ -29,6 +29,8 @@ SCHEDULES = [
     ("group_mapped", {"group_size": 128, "tiles_per_group": 128}),
     ("group_mapped", {"group_size": 1024, "tiles_per_group": 1024}),
     ("group_mapped", {"group_size": 64, "tiles_per_group": 64, "grid_size": 3}),
+    ("merge_path", {}),
+    ("merge_path", {"grid_size": 5}),
 ]
 IDS = [f"{k}-{'-'.join(f'{a}{b}' for a, b in p.items()) or 'default'}" for k, p in SCHEDULES]
 
@@ -76,7 +78,8 @@ def test_random_and_powerlaw(schedule, params):
             check(G, src, schedule, params, f"{G.shape} src {src}")
 
 
-@pytest.mark.parametrize("schedule,params", SCHEDULES[:2] + SCHEDULES[7:9], ids=IDS[:2] + IDS[7:9])
+@pytest.mark.parametrize("schedule,params", SCHEDULES[:2] + SCHEDULES[7:9] + SCHEDULES[12:],
+                         ids=IDS[:2] + IDS[7:9] + IDS[12:])
 def test_grid_path_and_edge_cases(schedule, params):
     N = 64
     G = S.grid_graph(N, kind="uniform")
@@ -112,11 +115,13 @@ def test_fullsize_powerlaw1M():
     G, src = S.config_c4_graph()
     Gd = to_dev(G)
     ref = oracle.sssp(G.row_offsets, G.col_idx, G.values, src)
-    for schedule, params in (("auto", {}), ("group_mapped", {"group_size": 256, "tiles_per_group": 1})):
+    for schedule, params in (("auto", {}), ("group_mapped", {"group_size": 256, "tiles_per_group": 1}),
+                             ("merge_path", {})):
         d, it = lb.sssp(Gd, src, schedule, **params)
         got = d.cpu().numpy()
         assert np.array_equal(got.view(np.int32), ref.view(np.int32)), schedule
         assert it > 1
     dref = oracle.bfs(G.row_offsets, G.col_idx, src)
-    h, levels = lb.bfs(Gd.pattern, src)
-    assert np.array_equal(h.cpu().numpy(), dref) and levels == int(dref.max()) + 1
+    for schedule in ("auto", "merge_path"):
+        h, levels = lb.bfs(Gd.pattern, src, schedule)
+        assert np.array_equal(h.cpu().numpy(), dref) and levels == int(dref.max()) + 1, schedule
