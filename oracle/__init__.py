@@ -18,6 +18,8 @@ Functions and the passages they follow (Osama, Porumbescu, Owens, PPoPP'23):
   get_tile_brute  -- Sec. 5.2.3, group-mapped: the tile that owns an atom,
                      by enumeration of the group's prefix-summed tile sizes
   batched_spmm    -- one spmm per matrix of a batch
+  spmv_coo        -- y = A x with A given as row-sorted (row, col, value) triples
+  spmv_csc        -- y = A x with A given column by column (Sec. 3.1 formats)
   sssp            -- Sec. 5.3, the SSSP example on the same tile sets: float32
                      distances, least fixed point of
                      dist[v] = min over edges of fl(dist[u] + w)  (Dijkstra)
@@ -76,9 +78,11 @@ def _bind(lib):
     lib.orc_merge_walk.argtypes = [I64, I64, P, I64, I64, P, P]
     lib.orc_num_threads.argtypes = []
     lib.orc_sssp.argtypes = [I64, P, P, P, I64, P]
+    lib.orc_spmv_coo.argtypes = [I64, I64, P, P, P, INT, P, INT, INT, P]
+    lib.orc_spmv_csc.argtypes = [I64, I64, P, P, P, INT, P, INT, INT, P]
     lib.orc_bfs.argtypes = [I64, P, P, I64, P]
     for f in ("orc_spmv", "orc_spmm", "orc_spmv_transpose", "orc_dvalues", "orc_merge_walk", "orc_num_threads",
-              "orc_sssp", "orc_bfs"):
+              "orc_sssp", "orc_bfs", "orc_spmv_coo", "orc_spmv_csc"):
         getattr(lib, f).restype = INT
     return lib
 
@@ -161,6 +165,24 @@ class Oracle:
             raise ValueError("orc_merge_walk rejected its arguments")
         return oi, oj
 
+    def spmv_coo(self, m, row_idx, col_idx, values, x, abs_terms=False):
+        ri, ci, v, xx = _c(row_idx, np.int32), _c(col_idx, np.int32), _c(values), _c(x)
+        y = np.empty(int(m), dtype=np.float64)
+        rc = self.lib.orc_spmv_coo(int(m), ci.shape[0], _ptr(ri), _ptr(ci), _ptr(v), _dtype_code(v), _ptr(xx),
+                                   _dtype_code(xx), int(bool(abs_terms)), _ptr(y))
+        if rc:
+            raise ValueError("orc_spmv_coo rejected its arguments")
+        return y
+
+    def spmv_csc(self, m, col_offsets, row_idx, values, x, abs_terms=False):
+        co, ri, v, xx = _c(col_offsets, np.int32), _c(row_idx, np.int32), _c(values), _c(x)
+        y = np.empty(int(m), dtype=np.float64)
+        rc = self.lib.orc_spmv_csc(int(m), co.shape[0] - 1, _ptr(co), _ptr(ri), _ptr(v), _dtype_code(v), _ptr(xx),
+                                   _dtype_code(xx), int(bool(abs_terms)), _ptr(y))
+        if rc:
+            raise ValueError("orc_spmv_csc rejected its arguments")
+        return y
+
     def sssp(self, row_offsets, col_idx, weights, source):
         """float32 distances from ``source`` (+inf where unreachable)."""
         ro, ci, w = _c(row_offsets, np.int32), _c(col_idx, np.int32), _c(weights, np.float32)
@@ -231,6 +253,14 @@ def merge_walk(row_offsets, nnz, W, T):
 
 def batched_spmm(batch, X):
     return default().batched_spmm(batch, X)
+
+
+def spmv_coo(m, row_idx, col_idx, values, x, abs_terms=False):
+    return default().spmv_coo(m, row_idx, col_idx, values, x, abs_terms)
+
+
+def spmv_csc(m, col_offsets, row_idx, values, x, abs_terms=False):
+    return default().spmv_csc(m, col_offsets, row_idx, values, x, abs_terms)
 
 
 def sssp(row_offsets, col_idx, weights, source):

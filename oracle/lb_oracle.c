@@ -19,6 +19,8 @@
  *     nonzero j.  Recorded at diagonals d_t = min(t*W, m + nnz).
  *   - Backward of y = A x (not in the paper): dx = A^T dy,
  *     dvalues[j] = dy[row(j)] * x[col_idx[j]].
+ *   - COO and CSC SpMV (Sec. 3.1 names both among the library's formats):
+ *     the same y = A x, the matrix given per entry (COO) or per column (CSC).
  *   - SSSP (Sec. 5.3, the graph example) and BFS (named in Sec. 6) on the
  *     same tile sets: vertices are tiles, out-edges are atoms.  Distances
  *     are float32 as in the paper's example; see orc_sssp.
@@ -281,5 +283,43 @@ int orc_bfs(int64_t n, const int32_t *row_offsets, const int32_t *col_idx,
         }
     }
     free(queue);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Other tile sets (Sec. 3.1 lists COO and CSC among the library's formats;
+ * Sec. 5.2.1: merge-path needs only an iterator counting atoms per tile).
+ * ------------------------------------------------------------------------ */
+
+/* COO sorted by row: nonzero j is (row_idx[j], col_idx[j], values[j]).
+ * y[r] = sum over j with row_idx[j] == r of values[j] * x[col_idx[j]], in
+ * ascending j (the CSR sum of the same matrix); rows without entries are 0. */
+int orc_spmv_coo(int64_t m, int64_t nnz, const int32_t *row_idx, const int32_t *col_idx,
+                 const void *values, int vdt, const void *x, int xdt, int abs_terms, double *y)
+{
+    if (m < 0 || nnz < 0 || !orc_dtype_ok(vdt) || !orc_dtype_ok(xdt)) return 1;
+    for (int64_t r = 0; r < m; ++r) y[r] = 0.0;
+    for (int64_t j = 0; j < nnz; ++j) {
+        double t = orc_load(values, vdt, j) * orc_load(x, xdt, col_idx[j]);
+        y[row_idx[j]] += abs_terms ? (t < 0 ? -t : t) : t;
+    }
+    return 0;
+}
+
+/* CSC: column c's nonzeros are [col_offsets[c], col_offsets[c+1]), with rows
+ * row_idx[j].  y[r] = sum over the nonzeros of row r of values[j] * x[c],
+ * visiting columns in ascending order. */
+int orc_spmv_csc(int64_t m, int64_t n, const int32_t *col_offsets, const int32_t *row_idx,
+                 const void *values, int vdt, const void *x, int xdt, int abs_terms, double *y)
+{
+    if (m < 0 || n < 0 || !orc_dtype_ok(vdt) || !orc_dtype_ok(xdt)) return 1;
+    for (int64_t r = 0; r < m; ++r) y[r] = 0.0;
+    for (int64_t c = 0; c < n; ++c) {
+        double xc = orc_load(x, xdt, c);
+        for (int64_t j = col_offsets[c]; j < col_offsets[c + 1]; ++j) {
+            double t = orc_load(values, vdt, j) * xc;
+            y[row_idx[j]] += abs_terms ? (t < 0 ? -t : t) : t;
+        }
+    }
     return 0;
 }

@@ -32,3 +32,4 @@ from .graph import (  # noqa: F401
     max_degree_vertex,
     config_c4_graph,
 )
+from .formats import COOHost, CSCHost, to_coo, to_csc, coo_with_duplicates  # noqa: F401

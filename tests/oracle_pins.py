@@ -548,4 +548,69 @@ def pin_sssp_rejects_negative_weights(orc):
         raise AssertionError(f"weight {bad} accepted")
 
 
+# --------------------------------------------------------------------------- COO and CSC
+
+def _format_cases():
+    from synthetic import coo_with_duplicates, special_matrices
+
+    cases = [A for A, _ in _tiny_cases()]
+    sp = special_matrices()
+    cases += [sp[k][0] for k in ("all_empty", "n1", "leading_empty", "trailing_empty", "ragged")]
+    return cases, coo_with_duplicates
+
+
+def pin_coo_csc_scipy(orc):
+    """COO and CSC products equal scipy's coo_matrix / csc_matrix products
+    (library routines, duplicates summed), and a dense product on tiny ones."""
+    import scipy.sparse as sp
+
+    from synthetic import to_coo, to_csc
+
+    cases, dups = _format_cases()
+    rng = np.random.default_rng(77)
+    for A in cases:
+        x = rng.uniform(-1, 1, A.n).astype(np.float32)
+        C, K, Dp = to_coo(A), to_csc(A), dups(A, 5)
+        for coo in (C, Dp):
+            M = sp.coo_matrix((coo.values.astype(np.float64), (coo.row_idx, coo.col_idx)), shape=A.shape)
+            ref = M @ x.astype(np.float64)
+            scale = abs(M) @ np.abs(x.astype(np.float64))
+            _close(orc.spmv_coo(A.m, coo.row_idx, coo.col_idx, coo.values, x), ref, scale, what="coo vs scipy")
+        M = sp.csc_matrix((K.values.astype(np.float64), K.row_idx, K.col_offsets), shape=A.shape)
+        ref = M @ x.astype(np.float64)
+        scale = abs(M) @ np.abs(x.astype(np.float64))
+        _close(orc.spmv_csc(A.m, K.col_offsets, K.row_idx, K.values, x), ref, scale, what="csc vs scipy")
+        if A.m * A.n <= 4096:
+            D = _dense(A)
+            _close(orc.spmv_csc(A.m, K.col_offsets, K.row_idx, K.values, x), D @ x.astype(np.float64),
+                   np.abs(D) @ np.abs(x.astype(np.float64)), what="csc vs dense")
+
+
+def pin_coo_equals_csr_sum(orc):
+    """A row-sorted COO visits each row's entries in the CSR order, so its
+    double sums equal the CSR oracle's bit for bit."""
+    from synthetic import to_coo
+
+    cases, _ = _format_cases()
+    A, x = config_c1()
+    for M in cases + [A]:
+        xm = x[:M.n] if M.n <= x.shape[0] else np.resize(x, M.n)
+        C = to_coo(M)
+        assert np.array_equal(orc.spmv_coo(M.m, C.row_idx, C.col_idx, C.values, xm),
+                              orc.spmv(M.row_offsets, M.col_idx, M.values, xm))
+
+
+def pin_coo_csc_integer_exact(orc):
+    """Integer values and x: every format gives the exact integer sums."""
+    from synthetic import to_coo, to_csc
+
+    A, _ = powerlaw_csr(21, 3000, 2500, 1.5, 400, 0.2)
+    Ai, xi = integer_valued(A, 4)
+    D = _dense(Ai)
+    exact = D @ xi.astype(np.float64)
+    C, K = to_coo(Ai), to_csc(Ai)
+    assert np.array_equal(orc.spmv_coo(Ai.m, C.row_idx, C.col_idx, C.values, xi), exact)
+    assert np.array_equal(orc.spmv_csc(Ai.m, K.col_offsets, K.row_idx, K.values, xi), exact)
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

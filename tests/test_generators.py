@@ -107,3 +107,19 @@ def test_graph_generators():
     assert np.diff(G.row_offsets)[s] == np.diff(G.row_offsets).max()
     R = random_graph(3, 100, 7)
     assert R.m == R.n == 100 and np.diff(R.row_offsets).max() <= 7
+
+
+def test_format_conversions():
+    import scipy.sparse as sp
+
+    from synthetic import coo_with_duplicates, powerlaw_csr, to_coo, to_csc
+
+    A, _ = powerlaw_csr(9, 400, 300, 1.5, 200, 0.2)
+    M = sp.csr_matrix((A.values, A.col_idx, A.row_offsets), shape=A.shape)
+    C = to_coo(A)
+    assert np.all(np.diff(C.row_idx) >= 0)
+    assert (sp.coo_matrix((C.values, (C.row_idx, C.col_idx)), shape=A.shape) != M).nnz == 0
+    K = to_csc(A)
+    assert (sp.csc_matrix((K.values, K.row_idx, K.col_offsets), shape=A.shape) != M).nnz == 0
+    D = coo_with_duplicates(A, 3)
+    assert D.nnz > C.nnz and np.all(np.diff(D.row_idx) >= 0)

@@ -31,6 +31,9 @@ MUTANTS = [
     ("sssp_stop_early", "while (size > 0) {", "while (size > 1) {"),
     ("bfs_dropped_increment", "depth[v] = depth[u] + 1;", "depth[v] = depth[u] + (u != source);"),
     ("bfs_stack_not_queue", "int32_t u = queue[head++];", "int32_t u = queue[--tail];"),
+    ("coo_wrong_row", "        y[row_idx[j]] += abs_terms ? (t < 0 ? -t : t) : t;\n    }\n    return 0;\n}\n\n/* CSC",
+     "        y[row_idx[j] > 0 && (j & 1) ? row_idx[j] - 1 : row_idx[j]] += abs_terms ? (t < 0 ? -t : t) : t;\n    }\n    return 0;\n}\n\n/* CSC"),
+    ("csc_wrong_x", "double xc = orc_load(x, xdt, c);", "double xc = orc_load(x, xdt, c > 0 && (c & 1) ? c - 1 : c);"),
     ("bf16_shift", "uint32_t bits = (uint32_t)((const uint16_t *)p)[i] << 16;", "uint32_t bits = (uint32_t)((const uint16_t *)p)[i] << 15;"),
 ]
 
