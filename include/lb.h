@@ -128,6 +128,32 @@ typedef struct lb_batch_t {
     const int64_t *mat_col_base;
 } lb_batch_t;
 
+/* A row-sorted COO matrix in device memory: entry j is (row_idx[j],
+ * col_idx[j], values[j]); row_idx is non-decreasing (a device-only
+ * precondition), entries of one row in any column order, repeated
+ * (row, col) pairs are summed.  Pointers may be NULL only when nnz == 0. */
+typedef struct lb_coo_t {
+    int64_t rows;
+    int64_t cols;
+    int64_t nnz;
+    const int32_t *row_idx;
+    const int32_t *col_idx;
+    const void *values;
+    lb_dtype_t value_dtype;
+} lb_coo_t;
+
+/* A CSC matrix in device memory: column c's entries are
+ * [col_offsets[c], col_offsets[c+1]) with rows row_idx[j] and values[j]. */
+typedef struct lb_csc_t {
+    int64_t rows;
+    int64_t cols;
+    int64_t nnz;
+    const int32_t *col_offsets;
+    const int32_t *row_idx;
+    const void *values;
+    lb_dtype_t value_dtype;
+} lb_csc_t;
+
 /* Version of this header the library was built from (LB_ABI_VERSION). */
 LB_API int lb_abi_version(void);
 
@@ -238,6 +264,40 @@ LB_API void lb_autotune_clear(void);
  * Returns LB_OK or LB_ERR_INVALID_CSR. */
 LB_API lb_status_t lb_validate_csr(const lb_csr_t *A, void *stream);
 
+/* ---- Other tile sets (Sec. 3.1 names CSR, CSC and COO; Sec. 5.2.1: a
+ * format needs only an iterator counting atoms per tile).
+ *
+ * COO: y = A x (rows float32, overwritten; rows without entries get 0),
+ * x of A->value_dtype.  LB_MERGE_PATH (as for CSR: block_size 128/256/512,
+ * items_per_thread 4/8/12/16): entry j is the (j + row_idx[j])-th item of
+ * the merge of row ends and entries, so the split is one search over the
+ * entries and equals the CSR split of the same matrix; consume and carry
+ * fix-up as for CSR, bit-reproducible.  LB_THREAD_MAPPED and LB_GROUP_MAPPED
+ * (tiles_per_group 1, group_size a power of two in [8, 1024]) find each
+ * row's entries by binary search of row_idx.  LB_AUTO = the Sec. 6.2 rule.
+ * rows + nnz < 2^31 - 1.  Workspace from lb_coo_workspace_size. */
+LB_API lb_status_t lb_coo_workspace_size(const lb_coo_t *A, const lb_schedule_t *s, size_t *bytes);
+LB_API lb_status_t lb_spmv_coo(const lb_coo_t *A, const void *x, lb_dtype_t x_dtype, float *y,
+                               const lb_schedule_t *s, void *workspace, size_t workspace_bytes,
+                               void *stream);
+
+/* The COO merge-path split (test hook): out_row[t], out_nz[t] for t in
+ * [0, num_units] at diagonals min(t * items_per_unit, rows + nnz). */
+LB_API lb_status_t lb_coo_merge_path_partition(const int32_t *row_idx, int64_t rows, int64_t nnz,
+                                               int64_t items_per_unit, int64_t num_units,
+                                               int32_t *out_row, int32_t *out_nz, void *stream);
+
+/* CSC: y = A x with columns as tiles: entry j adds values[j] * x[c] into
+ * y[row_idx[j]].  x is float32 (values float32 or BF16); y (rows float32)
+ * is zeroed by the call and accumulated with float atomics, so it is not
+ * bit-reproducible run to run.  LB_MERGE_PATH or LB_AUTO (the merge-path
+ * split of the columns; block_size/items_per_thread as for CSR).
+ * cols + nnz < 2^31 - 1.  Workspace from lb_csc_workspace_size. */
+LB_API lb_status_t lb_csc_workspace_size(const lb_csc_t *A, const lb_schedule_t *s, size_t *bytes);
+LB_API lb_status_t lb_spmv_csc(const lb_csc_t *A, const void *x, lb_dtype_t x_dtype, float *y,
+                               const lb_schedule_t *s, void *workspace, size_t workspace_bytes,
+                               void *stream);
+
 /* ---- Graph traversal on the same schedules (Sec. 5.3 SSSP example; BFS,
  * named in Sec. 6).
  * The graph G is a square CSR read as adjacency: vertex u's out-edges are
@@ -309,7 +369,8 @@ LB_API int32_t lb_probe_default_grid(void);
  * pair of HIP events on its stream.  lb_profile_read synchronizes those
  * events and returns, for the kernel family `name` ("merge_partition",
  * "merge_consume", "merge_fixup", "thread_mapped", "group_mapped",
- * "backward", "batched_consume", "batched_fixup", "fill", "traversal_init",
+ * "backward", "batched_consume", "batched_fixup", "fill", "coo_partition",
+ * "coo_consume", "coo_fixup", "coo_tiles", "traversal_init",
  * "sssp_advance", "bfs_advance"), the summed
  * duration in milliseconds and the launch count since the last reset. */
 LB_API void lb_profile_enable(int on);

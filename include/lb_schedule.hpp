@@ -7,9 +7,12 @@
 //
 // Tile sets (Sec. 3.1 and 4.1): tiles own contiguous ranges of atoms.
 //   csr_tile_set      tile p is row p; its atoms are [offsets[p], offsets[p+1]).
+//   coo_tile_set      tile p is row p of a row-sorted COO; its atoms are
+//                     found by binary search of the row indices.
 //   indexed_tile_set  tile position p names row ids[p] (a graph frontier,
 //                     a list of selected rows); its atoms are that row's.
-//   Both give tile(p) -> {id, begin, end} with one read of ids[p].
+//   Each gives tile(p) -> {id, begin, end} (one read of ids[p] for the
+//   indexed set).
 //
 // Schedules (Sec. 4.2, 5.1, 5.2.3):
 //   thread_mapped<TS>          each thread takes whole tiles (grid stride) and
@@ -136,6 +139,29 @@ struct csr_tile_set {
     __device__ int32_t atom_count(int64_t p) const { return row_offsets[p + 1] - row_offsets[p]; }
     __device__ tile_ref tile(int64_t p) const {
         return {static_cast<int32_t>(p), row_offsets[p], row_offsets[p + 1]};
+    }
+};
+
+// A row-sorted COO as tiles: tile p is row p and its atoms are the entries
+// with row_idx == p.  With no offsets array, the atoms-per-tile iterator is
+// a binary search of row_idx for the first entry of row p and of row p + 1.
+struct coo_tile_set {
+    const int32_t *row_idx;
+    int64_t num_tiles;
+    int64_t num_atoms;
+    __device__ int32_t first_entry(int64_t r) const {  // lower_bound(row_idx, r)
+        int64_t lo = 0, hi = num_atoms;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (row_idx[mid] < r)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        return static_cast<int32_t>(lo);
+    }
+    __device__ tile_ref tile(int64_t p) const {
+        return {static_cast<int32_t>(p), first_entry(p), first_entry(p + 1)};
     }
 };
 

@@ -10,6 +10,8 @@ library and fails if it is missing.
     Y = spmm(A, X)                                   # X: cols x k, row-major
     y = SpMV.apply(values, x, pattern, "merge_path") # differentiable in values and x
     Y = batched_spmm(batch, X)                       # one persistent launch
+    y = spmv_coo(COO.from_host(coo), x)              # other tile sets: COO (merge-path on the entries)
+    y = spmv_csc(CSC.from_host(csc), x)              # and CSC (columns as tiles)
     dist, iters = sssp(G, source)                    # graph consumer on the same schedules
     depth, iters = bfs(G, source)
 """
@@ -27,7 +29,8 @@ _lib = _abi.load()
 
 __all__ = ["CSR", "Pattern", "Batch", "spmv", "spmm", "spmv_backward", "SpMV", "spmv_diff",
            "batched_spmm", "tune", "tune_batched", "merge_path_partition", "group_tile_owner",
-           "sssp", "bfs", "traversal_workspace_size",
+           "sssp", "bfs", "traversal_workspace_size", "COO", "CSC", "spmv_coo", "spmv_csc",
+           "coo_merge_path_partition",
            "validate", "resolve_schedule", "profile_enable", "profile_reset", "profile_read", "LBError"]
 
 _DT = {torch.float32: _abi.F32, torch.bfloat16: _abi.BF16, torch.float64: _abi.F64}
@@ -331,6 +334,16 @@ def merge_path_partition(row_offsets: torch.Tensor, nnz: int, items_per_unit: in
     return oi, oj
 
 
+def coo_merge_path_partition(row_idx: torch.Tensor, rows: int, items_per_unit: int, num_units: int):
+    """The COO merge-path split: (row, nz) at diagonals min(t * items_per_unit, rows + nnz)."""
+    oi = torch.empty(num_units + 1, dtype=torch.int32, device=row_idx.device)
+    oj = torch.empty(num_units + 1, dtype=torch.int32, device=row_idx.device)
+    _abi.check(_lib.lb_coo_merge_path_partition(_ptr(row_idx), int(rows), row_idx.numel(), int(items_per_unit),
+                                                int(num_units), _ptr(oi), _ptr(oj), _stream(row_idx.device)),
+               "lb_coo_merge_path_partition")
+    return oi, oj
+
+
 def group_tile_owner(A: CSR, tiles_per_group: int) -> torch.Tensor:
     owner = torch.empty(A.nnz, dtype=torch.int32, device=A.device)
     _abi.check(_lib.lb_group_tile_owner(ctypes.byref(A.c_struct()), int(tiles_per_group), _ptr(owner),
@@ -423,3 +436,99 @@ def bfs(G: Pattern, source: int, schedule="auto", depth: torch.Tensor | None = N
     if depth is None:
         depth = torch.empty(G.shape[0], dtype=torch.int32, device=G.device)
     return _traverse(_lib.lb_bfs, "lb_bfs", G, source, depth, schedule, max_iterations, workspace, params)
+
+
+# ---------------------------------------------------------------------------- COO and CSC
+
+def _values_from_host(vals, dtype):
+    if vals.dtype == np.uint16:  # BF16 bit patterns
+        return torch.from_numpy(vals.view(np.int16).copy()).view(torch.bfloat16)
+    return torch.from_numpy(np.ascontiguousarray(vals)).to(dtype)
+
+
+class COO:
+    """Row-sorted COO in device memory: int32 row_idx, col_idx; values float32 or bfloat16."""
+
+    def __init__(self, row_idx, col_idx, values, shape):
+        if row_idx.dtype != torch.int32 or col_idx.dtype != torch.int32:
+            raise TypeError("row_idx and col_idx must be int32")
+        if not (row_idx.numel() == col_idx.numel() == values.numel()):
+            raise ValueError("row_idx, col_idx and values differ in length")
+        self.row_idx, self.col_idx, self.values = row_idx.contiguous(), col_idx.contiguous(), values.contiguous()
+        self.shape = (int(shape[0]), int(shape[1]))
+
+    @classmethod
+    def from_host(cls, host, device="cuda", dtype=torch.float32) -> "COO":
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
+        return cls(t(host.row_idx), t(host.col_idx), _values_from_host(host.values, dtype).to(device), host.shape)
+
+    @property
+    def nnz(self):
+        return int(self.col_idx.numel())
+
+    @property
+    def device(self):
+        return self.col_idx.device
+
+    def c_struct(self):
+        return _abi.COO(self.shape[0], self.shape[1], self.nnz, self.row_idx.data_ptr(), self.col_idx.data_ptr(),
+                        self.values.data_ptr(), _dtype_code(self.values))
+
+
+class CSC:
+    """CSC in device memory: int32 col_offsets[cols + 1], row_idx; values float32 or bfloat16."""
+
+    def __init__(self, col_offsets, row_idx, values, shape):
+        if col_offsets.dtype != torch.int32 or row_idx.dtype != torch.int32:
+            raise TypeError("col_offsets and row_idx must be int32")
+        self.col_offsets, self.row_idx, self.values = col_offsets.contiguous(), row_idx.contiguous(), values.contiguous()
+        self.shape = (int(shape[0]), int(shape[1]))
+        if self.col_offsets.numel() != self.shape[1] + 1:
+            raise ValueError("col_offsets must hold cols + 1 entries")
+
+    @classmethod
+    def from_host(cls, host, device="cuda", dtype=torch.float32) -> "CSC":
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
+        return cls(t(host.col_offsets), t(host.row_idx), _values_from_host(host.values, dtype).to(device), host.shape)
+
+    @property
+    def nnz(self):
+        return int(self.row_idx.numel())
+
+    @property
+    def device(self):
+        return self.row_idx.device
+
+    def c_struct(self):
+        return _abi.CSC(self.shape[0], self.shape[1], self.nnz, self.col_offsets.data_ptr(), self.row_idx.data_ptr(),
+                        self.values.data_ptr(), _dtype_code(self.values))
+
+
+def _format_spmv(fn_size, fn, what, A, x, schedule, y, workspace, params):
+    if x.dim() != 1 or x.numel() != A.shape[1]:
+        raise ValueError("x must be a vector of length cols")
+    x = x.contiguous()
+    s = make_schedule(schedule, **params)
+    n = ctypes.c_size_t(0)
+    a = A.c_struct()
+    _abi.check(fn_size(ctypes.byref(a), ctypes.byref(s), ctypes.byref(n)), what + " workspace size")
+    ws = _workspace(n.value, A.device, workspace)
+    if y is None:
+        y = torch.empty(A.shape[0], dtype=torch.float32, device=A.device)
+    _abi.check(fn(ctypes.byref(a), _ptr(x), _dtype_code(x), _ptr(y), ctypes.byref(s), _ptr(ws),
+                  0 if ws is None else ws.numel(), _stream(A.device)), what)
+    return y
+
+
+def spmv_coo(A: COO, x: torch.Tensor, schedule="merge_path", y: torch.Tensor | None = None,
+             workspace: torch.Tensor | None = None, **params) -> torch.Tensor:
+    """y = A x for a row-sorted COO (float32 y)."""
+    return _format_spmv(_lib.lb_coo_workspace_size, _lib.lb_spmv_coo, "lb_spmv_coo", A, x, schedule, y, workspace,
+                        params)
+
+
+def spmv_csc(A: CSC, x: torch.Tensor, schedule="merge_path", y: torch.Tensor | None = None,
+             workspace: torch.Tensor | None = None, **params) -> torch.Tensor:
+    """y = A x for a CSC matrix (float32 x and y; float atomics: not bit-reproducible)."""
+    return _format_spmv(_lib.lb_csc_workspace_size, _lib.lb_spmv_csc, "lb_spmv_csc", A, x, schedule, y, workspace,
+                        params)

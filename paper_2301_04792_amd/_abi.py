@@ -50,6 +50,18 @@ class Batch(ctypes.Structure):
                 ("mat_col_base", ctypes.c_void_p)]
 
 
+class COO(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int64), ("cols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_idx", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
+                ("values", ctypes.c_void_p), ("value_dtype", ctypes.c_int)]
+
+
+class CSC(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int64), ("cols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("col_offsets", ctypes.c_void_p), ("row_idx", ctypes.c_void_p),
+                ("values", ctypes.c_void_p), ("value_dtype", ctypes.c_int)]
+
+
 class LBError(RuntimeError):
     def __init__(self, status: int, what: str, detail: str = ""):
         self.status = status
@@ -65,6 +77,8 @@ P = ctypes.c_void_p
 PCSR = ctypes.POINTER(CSR)
 PSCHED = ctypes.POINTER(Schedule)
 PBATCH = ctypes.POINTER(Batch)
+PCOO = ctypes.POINTER(COO)
+PCSC = ctypes.POINTER(CSC)
 I32, I64, SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
 ST = ctypes.c_int
 
@@ -87,6 +101,11 @@ SIGNATURES = {
     "lb_batched_autotune": (ST, [PBATCH, P, ST, I32, P, P, SZ, PSCHED, P]),
     "lb_autotune_clear": (None, []),
     "lb_validate_csr": (ST, [PCSR, P]),
+    "lb_coo_workspace_size": (ST, [PCOO, PSCHED, ctypes.POINTER(SZ)]),
+    "lb_spmv_coo": (ST, [PCOO, P, ST, P, PSCHED, P, SZ, P]),
+    "lb_coo_merge_path_partition": (ST, [P, I64, I64, I64, I64, P, P, P]),
+    "lb_csc_workspace_size": (ST, [PCSC, PSCHED, ctypes.POINTER(SZ)]),
+    "lb_spmv_csc": (ST, [PCSC, P, ST, P, PSCHED, P, SZ, P]),
     "lb_traversal_workspace_size": (ST, [PCSR, ctypes.POINTER(SZ)]),
     "lb_sssp": (ST, [PCSR, I64, P, PSCHED, I32, ctypes.POINTER(I32), P, SZ, P]),
     "lb_bfs": (ST, [PCSR, I64, P, PSCHED, I32, ctypes.POINTER(I32), P, SZ, P]),

@@ -119,11 +119,6 @@ static hipError_t run_backward(const csr_dev &A, const void *x, const float *dy,
     return hipGetLastError();
 }
 
-#define LB_MERGE_CONFIGS(X) \
-    X(128, 4) X(128, 8) X(128, 12) X(128, 16) \
-    X(256, 4) X(256, 8) X(256, 12) X(256, 16) \
-    X(512, 4) X(512, 8) X(512, 12) X(512, 16)
-
 hipError_t merge_backward(const csr_dev &A, const void *x, const float *dy, float *dx, float *dvalues, int block,
                           int items, void *ws, hipStream_t s) {
 #define X_(B, I)                                                                                 \

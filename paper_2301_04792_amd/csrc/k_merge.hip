@@ -253,11 +253,6 @@ static hipError_t run_merge_spmv(const csr_dev &A, const void *x, float *y, void
     return launch_fixup(T, A.rows, 1, w.carry_row, w.carry_val, y, 1, s, "merge_fixup");
 }
 
-#define LB_MERGE_CONFIGS(X) \
-    X(128, 4) X(128, 8) X(128, 12) X(128, 16) \
-    X(256, 4) X(256, 8) X(256, 12) X(256, 16) \
-    X(512, 4) X(512, 8) X(512, 12) X(512, 16)
-
 bool merge_config_supported(int block, int items) {
 #define X(B, I) if (block == B && items == I) return true;
     LB_MERGE_CONFIGS(X)

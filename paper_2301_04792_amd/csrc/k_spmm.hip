@@ -496,11 +496,6 @@ static hipError_t run_spmm(const spmm_problem &P, const VT *X, int32_t k, int64_
     return e;
 }
 
-#define LB_MERGE_CONFIGS(X) \
-    X(128, 4) X(128, 8) X(128, 12) X(128, 16) \
-    X(256, 4) X(256, 8) X(256, 12) X(256, 16) \
-    X(512, 4) X(512, 8) X(512, 12) X(512, 16)
-
 template <bool BATCHED>
 static hipError_t dispatch(const spmm_problem &P, lb_dtype_t dt, const void *X, int32_t k, int64_t ldx, float *Y,
                            int64_t ldy, int block, int items, void *ws, hipStream_t s) {

@@ -209,6 +209,52 @@ size_t ws_bytes_for(const lb_csr_t *A, const lb_schedule_t &s, int32_t k) {
     return lbk::merge_ws_bytes(T, k <= 0 ? 1 : spmm_pass_cols(k));
 }
 
+// ------------------------------------------------------------------ COO and CSC
+
+lb_status_t check_coo(const lb_coo_t *A) {
+    if (!A) return LB_ERR_INVALID_ARG;
+    if (A->nnz > 0 && !A->row_idx) return LB_ERR_INVALID_ARG;
+    // the CSR checks on the sizes, dtype and entry arrays; a COO has no offsets array
+    static const int32_t no_offsets = 0;
+    const lb_csr_t c{A->rows, A->cols, A->nnz, &no_offsets, A->col_idx, A->values, A->value_dtype};
+    return check_csr(&c);
+}
+
+// The CSC checked as the CSR of its transpose (tiles are columns).
+lb_status_t check_csc(const lb_csc_t *A, lb_csr_t *as_csr) {
+    if (!A) return LB_ERR_INVALID_ARG;
+    const lb_csr_t c{A->cols, A->rows, A->nnz, A->col_offsets, A->row_idx, A->values, A->value_dtype};
+    lb_status_t st = check_csr(&c);
+    if (st != LB_OK) return st;
+    *as_csr = c;
+    return LB_OK;
+}
+
+// Schedule of a COO product: LB_AUTO takes the Sec. 6.2 rule (groups of at least 8 lanes).
+lb_status_t coo_schedule(const lb_coo_t *A, const lb_schedule_t *in, lb_schedule_t *out) {
+    if (!in || !out) return LB_ERR_INVALID_ARG;
+    lb_schedule_t s = *in;
+    if (s.kind == LB_AUTO) {
+        const lb_csr_t c{A->rows, A->cols, A->nnz, nullptr, nullptr, nullptr, A->value_dtype};
+        s = heuristic(&c);
+        if (s.kind == LB_GROUP_MAPPED && s.group_size < 8) s.group_size = 8;
+    }
+    lb_status_t st = fill_defaults(&s, out);
+    if (st != LB_OK) return st;
+    if (out->kind == LB_GROUP_MAPPED) {
+        if (out->tiles_per_group != 1) return LB_ERR_UNSUPPORTED;
+        if (!lbk::traversal_group_supported(out->group_size)) return LB_ERR_UNSUPPORTED;
+    }
+    return LB_OK;
+}
+
+lb_status_t csc_schedule(const lb_schedule_t *in, lb_schedule_t *out) {
+    lb_schedule_t s = in ? *in : lb_schedule_t{LB_MERGE_PATH, 0, 0, 0, 0, 0};
+    if (s.kind == LB_AUTO) s.kind = LB_MERGE_PATH;
+    if (s.kind != LB_MERGE_PATH) return LB_ERR_UNSUPPORTED;
+    return fill_defaults(&s, out);
+}
+
 // ------------------------------------------------------------------ graph traversal checks
 
 // A graph is a square CSR; BFS reads no values, so they may be absent.
@@ -443,6 +489,88 @@ LB_API lb_status_t lb_spmv(const lb_csr_t *A, const void *x, lb_dtype_t x_dtype,
             return hip_status(lbk::merge_spmv(d, x, y, r.block_size, r.items_per_thread, workspace, hs));
         default: return LB_ERR_INVALID_ARG;
     }
+}
+
+LB_API lb_status_t lb_coo_workspace_size(const lb_coo_t *A, const lb_schedule_t *s, size_t *bytes) {
+    if (!bytes) return LB_ERR_INVALID_ARG;
+    lb_status_t st = check_coo(A);
+    if (st != LB_OK) return st;
+    lb_schedule_t r;
+    st = coo_schedule(A, s, &r);
+    if (st != LB_OK) return st;
+    *bytes = 0;
+    if (r.kind == LB_MERGE_PATH) {
+        const int64_t W = static_cast<int64_t>(r.block_size) * r.items_per_thread;
+        *bytes = lbk::merge_ws_bytes(lbk::merge_units(A->rows, A->nnz, W), 1);
+    }
+    return LB_OK;
+}
+
+LB_API lb_status_t lb_spmv_coo(const lb_coo_t *A, const void *x, lb_dtype_t x_dtype, float *y, const lb_schedule_t *s,
+                               void *workspace, size_t workspace_bytes, void *stream) {
+    lb_status_t st = check_coo(A);
+    if (st != LB_OK) return st;
+    if (A->rows > 0 && !y) return LB_ERR_INVALID_ARG;
+    if (A->nnz > 0 && !x) return LB_ERR_INVALID_ARG;
+    if (x_dtype != A->value_dtype) return LB_ERR_UNSUPPORTED;
+    lb_schedule_t r;
+    st = coo_schedule(A, s, &r);
+    if (st != LB_OK) return st;
+    size_t need = 0;
+    (void)lb_coo_workspace_size(A, &r, &need);
+    if (need > 0 && (workspace_bytes < need || !workspace)) return LB_ERR_WORKSPACE_TOO_SMALL;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    if (A->rows == 0) return LB_OK;
+    if (A->nnz == 0) return hip_status(lbk::fill_f32(y, A->rows, 0.f, hs));
+    const lbk::coo_dev d{static_cast<int32_t>(A->rows), static_cast<int32_t>(A->cols), static_cast<int32_t>(A->nnz),
+                         A->row_idx, A->col_idx, A->values, A->value_dtype};
+    return hip_status(lbk::coo_spmv(d, x, y, r.kind, r.group_size, r.block_size, r.items_per_thread, r.grid_size,
+                                    workspace, hs));
+}
+
+LB_API lb_status_t lb_coo_merge_path_partition(const int32_t *row_idx, int64_t rows, int64_t nnz,
+                                               int64_t items_per_unit, int64_t num_units, int32_t *out_row,
+                                               int32_t *out_nz, void *stream) {
+    if (rows < 0 || nnz < 0 || items_per_unit <= 0 || num_units < 0) return LB_ERR_INVALID_ARG;
+    if (rows + nnz > kMaxCoord || items_per_unit > kMaxCoord || num_units > kMaxCoord) return LB_ERR_OVERFLOW;
+    if (!out_row || !out_nz || (nnz > 0 && !row_idx)) return LB_ERR_INVALID_ARG;
+    return hip_status(lbk::coo_partition(row_idx, static_cast<int32_t>(rows), static_cast<int32_t>(nnz),
+                                         static_cast<int32_t>(items_per_unit), static_cast<int32_t>(num_units),
+                                         out_row, out_nz, static_cast<hipStream_t>(stream)));
+}
+
+LB_API lb_status_t lb_csc_workspace_size(const lb_csc_t *A, const lb_schedule_t *s, size_t *bytes) {
+    if (!bytes) return LB_ERR_INVALID_ARG;
+    lb_csr_t c;
+    lb_status_t st = check_csc(A, &c);
+    if (st != LB_OK) return st;
+    lb_schedule_t r;
+    st = csc_schedule(s, &r);
+    if (st != LB_OK) return st;
+    *bytes = ws_bytes_for(&c, r, 0);
+    return LB_OK;
+}
+
+LB_API lb_status_t lb_spmv_csc(const lb_csc_t *A, const void *x, lb_dtype_t x_dtype, float *y, const lb_schedule_t *s,
+                               void *workspace, size_t workspace_bytes, void *stream) {
+    lb_csr_t c;
+    lb_status_t st = check_csc(A, &c);
+    if (st != LB_OK) return st;
+    if (A->rows > 0 && !y) return LB_ERR_INVALID_ARG;
+    if (A->nnz > 0 && !x) return LB_ERR_INVALID_ARG;
+    if (x_dtype != LB_F32) return LB_ERR_UNSUPPORTED;
+    lb_schedule_t r;
+    st = csc_schedule(s, &r);
+    if (st != LB_OK) return st;
+    const size_t need = ws_bytes_for(&c, r, 0);
+    if (workspace_bytes < need || !workspace) return LB_ERR_WORKSPACE_TOO_SMALL;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    if (A->rows == 0) return LB_OK;
+    hipError_t e = lbk::fill_f32(y, A->rows, 0.f, hs);
+    if (e != hipSuccess || A->nnz == 0) return hip_status(e);
+    // the scatter of the backward pass: columns are its tiles, x its per-tile value
+    return hip_status(lbk::merge_backward(to_dev(&c), nullptr, static_cast<const float *>(x), y, nullptr,
+                                          r.block_size, r.items_per_thread, workspace, hs));
 }
 
 LB_API lb_status_t lb_traversal_workspace_size(const lb_csr_t *G, size_t *bytes) {

@@ -34,28 +34,23 @@ __device__ __forceinline__ T ld_stream(const T *p) {
 
 // ---------------------------------------------------------------- merge-path split (Sec. 5.2.1)
 
-// Number of row ends of the merge of row_offsets[1..rows] with the nonzero
-// indices 0..nnz-1 that precede diagonal d (row end r is the
-// (r + row_offsets[r + 1])-th merge item), found by an aligned group of G
-// lanes (G a power of two <= 64) with a G-ary search: each step the G lanes
-// probe G evenly spaced rows and a ballot narrows the range G-fold.  All
-// lanes of the wavefront must execute it (the ballot spans the wavefront);
-// every lane of a group returns the same value.
-template <int G>
-__device__ __forceinline__ int32_t group_merge_search(const int32_t *__restrict__ ro, int32_t rows, int32_t nnz,
-                                                      int32_t d) {
+// Count of the positions r in [lo, hi) with key(r) < d, where key is
+// increasing, every r < lo counts and no r >= hi does; found by an aligned
+// group of G lanes (G a power of two <= 64) with a G-ary search: each step
+// the G lanes probe G evenly spaced positions and a ballot narrows the range
+// G-fold.  All lanes of the wavefront must execute it (the ballot spans the
+// wavefront); every lane of a group returns the same value.
+template <int G, typename Key>
+__device__ __forceinline__ int32_t group_count_below(int32_t lo, int32_t hi, int32_t d, Key key) {
     const int gl = threadIdx.x & (G - 1);
     const int shift = (threadIdx.x & (kWave - 1)) & ~(G - 1);
     const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1);
-    // p(r) < d for r < lo, p(r) >= d for r >= hi; the answer lies in [lo, hi]
-    int32_t lo = d - nnz > 0 ? d - nnz : 0;
-    int32_t hi = d < rows ? d : rows;
     for (;;) {
         const bool wide = hi - lo > G;
         if (__ballot(wide) == 0) break;  // every group of the wavefront has narrowed down
         const int32_t step = wide ? (hi - lo + G - 1) / G : 1;
         const int32_t r = lo + (gl + 1) * step - 1;
-        const bool below = wide && r < hi && ro[r + 1] + r < d;  // true on a prefix of the group
+        const bool below = wide && r < hi && key(r) < d;  // true on a prefix of the group
         const int32_t c = __popcll((__ballot(below) >> shift) & gmask);
         if (wide) {
             const int32_t rc = lo + (c + 1) * step - 1;  // first probe not below d
@@ -64,12 +59,34 @@ __device__ __forceinline__ int32_t group_merge_search(const int32_t *__restrict_
         }
     }
     const int32_t r = lo + gl;
-    const bool below = r < hi && ro[r + 1] + r < d;
+    const bool below = r < hi && key(r) < d;
     return lo + __popcll((__ballot(below) >> shift) & gmask);
 }
 
-// Number of entries of the sorted int64 array a[0..n) that are <= key, by an
-// aligned group of G lanes (G-ary search, same ballot rules as above).
+// Number of row ends of the merge of row_offsets[1..rows] with the nonzero
+// indices 0..nnz-1 that precede diagonal d: row end r is the
+// (r + row_offsets[r + 1])-th merge item.  Rows below d - nnz end before d
+// and rows at or past d cannot.
+template <int G>
+__device__ __forceinline__ int32_t group_merge_search(const int32_t *__restrict__ ro, int32_t rows, int32_t nnz,
+                                                      int32_t d) {
+    const int32_t lo = d - nnz > 0 ? d - nnz : 0;
+    const int32_t hi = d < rows ? d : rows;
+    return group_count_below<G>(lo, hi, d, [ro](int32_t r) { return ro[r + 1] + r; });
+}
+
+// The same split for a row-sorted COO: nonzero j is the (j + row_idx[j])-th
+// merge item (the rows before it have ended, its own row has not), so the
+// nonzeros preceding d are counted directly; the row ends are d minus that.
+// Nonzeros below d - rows precede d and those at or past d cannot.
+template <int G>
+__device__ __forceinline__ int32_t group_coo_search(const int32_t *__restrict__ row_idx, int32_t rows, int32_t nnz,
+                                                    int32_t d) {
+    const int32_t lo = d - rows > 0 ? d - rows : 0;
+    const int32_t hi = d < nnz ? d : nnz;
+    return group_count_below<G>(lo, hi, d, [row_idx](int32_t j) { return row_idx[j] + j; });
+}
+
 template <int G>
 __device__ __forceinline__ int32_t group_count_le(const int64_t *__restrict__ a, int32_t n, int64_t key) {
     const int gl = threadIdx.x & (G - 1);

@@ -37,6 +37,12 @@ struct prof_scope {
 
 inline size_t align256(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
 
+// Instantiated merge-path configurations (block_size, items_per_thread).
+#define LB_MERGE_CONFIGS(X) \
+    X(128, 4) X(128, 8) X(128, 12) X(128, 16) \
+    X(256, 4) X(256, 8) X(256, 12) X(256, 16) \
+    X(512, 4) X(512, 8) X(512, 12) X(512, 16)
+
 // ---- merge-path split ---------------------------------------------------------------
 // Work units of W merge items; T = ceil((rows + nnz) / W) units.
 inline int64_t merge_units(int64_t rows, int64_t nnz, int64_t W) { return (rows + nnz + W - 1) / W; }
@@ -113,6 +119,23 @@ hipError_t thread_mapped_spmm(const csr_dev &A, const void *X, int32_t k, int64_
 hipError_t group_mapped_spmv(const csr_dev &A, const void *x, float *y, int group_size,
                              int tiles_per_group, int grid, hipStream_t s);
 hipError_t group_tile_owner(const csr_dev &A, int tiles_per_group, int32_t *owner, hipStream_t s);
+
+// ---- COO and CSC ---------------------------------------------------------------------------
+// A row-sorted COO matrix: row_idx[nnz] non-decreasing, col_idx[nnz], values[nnz].
+struct coo_dev {
+    int32_t rows, cols, nnz;
+    const int32_t *ri;
+    const int32_t *ci;
+    const void *val;
+    lb_dtype_t dt;
+};
+// The merge-path split of a COO (bit-equal to the CSR split of the same matrix).
+hipError_t coo_partition(const int32_t *row_idx, int32_t rows, int32_t nnz, int32_t W, int32_t T, int32_t *part_i,
+                         int32_t *part_j, hipStream_t s);
+// kind: LB_MERGE_PATH (block/items a LB_MERGE_CONFIGS pair, workspace merge_ws_bytes(T, 1)),
+// LB_THREAD_MAPPED (block threads) or LB_GROUP_MAPPED (group lanes, one row per group).
+hipError_t coo_spmv(const coo_dev &A, const void *x, float *y, lb_sched_kind_t kind, int group, int block, int items,
+                    int grid, void *ws, hipStream_t s);
 
 // ---- graph traversal (SSSP, BFS) ---------------------------------------------------------
 #define LB_TRAVERSAL_GROUPS(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024)

@@ -208,3 +208,49 @@ def test_traversal_host_checks():
     assert bfs(G=csr(val=0), wsb=need - 1) == _abi.ERR_WORKSPACE_TOO_SMALL
     assert bfs(G=csr(val=0, dtype=_abi.BF16), wsb=need - 1) == _abi.ERR_WORKSPACE_TOO_SMALL
     assert L.lb_status_string(_abi.ERR_NOT_CONVERGED) != b"unknown status"
+
+
+def test_coo_csc_host_checks():
+    L = _abi.load()
+    n = ctypes.c_size_t(0)
+    coo = _abi.COO(1000, 800, 5000, FAKE, FAKE, FAKE, _abi.F32)
+    csc = _abi.CSC(1000, 800, 5000, FAKE, FAKE, FAKE, _abi.F32)
+
+    def cws(A, s):
+        return L.lb_coo_workspace_size(ctypes.byref(A), ctypes.byref(s), ctypes.byref(n))
+
+    assert cws(coo, sched("merge_path")) == _abi.OK and n.value > 0
+    need = n.value
+    assert cws(coo, sched("thread_mapped")) == _abi.OK and n.value == 0
+    assert cws(coo, sched("group_mapped", group_size=4)) == _abi.ERR_UNSUPPORTED
+    assert cws(coo, sched("group_mapped", group_size=64, tiles_per_group=64)) == _abi.ERR_UNSUPPORTED
+    assert cws(coo, sched("merge_path", items_per_thread=5)) == _abi.ERR_UNSUPPORTED
+    assert cws(_abi.COO(2**31, 1, 2**31, FAKE, FAKE, FAKE, _abi.F32), sched()) == _abi.ERR_OVERFLOW
+    assert cws(_abi.COO(10, 10, 5, 0, FAKE, FAKE, _abi.F32), sched()) == _abi.ERR_INVALID_ARG  # entries, no rows
+    assert cws(_abi.COO(10, 10, 0, 0, 0, 0, _abi.F32), sched()) == _abi.OK  # empty: no arrays needed
+
+    def spmv_coo(A=coo, x=FAKE, dt=_abi.F32, y=FAKE, s=None, ws=FAKE, wsb=need):
+        s = s or sched("merge_path")
+        return L.lb_spmv_coo(ctypes.byref(A), x, dt, y, ctypes.byref(s), ws, wsb, None)
+
+    assert spmv_coo(y=0) == _abi.ERR_INVALID_ARG
+    assert spmv_coo(x=0) == _abi.ERR_INVALID_ARG
+    assert spmv_coo(dt=_abi.BF16) == _abi.ERR_UNSUPPORTED
+    assert spmv_coo(wsb=need - 1) == _abi.ERR_WORKSPACE_TOO_SMALL
+    assert L.lb_coo_merge_path_partition(FAKE, -1, 5, 8, 3, FAKE, FAKE, None) == _abi.ERR_INVALID_ARG
+    assert L.lb_coo_merge_path_partition(FAKE, 5, 5, 0, 3, FAKE, FAKE, None) == _abi.ERR_INVALID_ARG
+    assert L.lb_coo_merge_path_partition(FAKE, 5, 5, 8, 3, 0, FAKE, None) == _abi.ERR_INVALID_ARG
+
+    assert L.lb_csc_workspace_size(ctypes.byref(csc), ctypes.byref(sched("auto")), ctypes.byref(n)) == _abi.OK
+    need_c = n.value
+    assert need_c > 0
+    assert L.lb_csc_workspace_size(ctypes.byref(csc), ctypes.byref(sched("thread_mapped")),
+                                   ctypes.byref(n)) == _abi.ERR_UNSUPPORTED
+
+    def spmv_csc(A=csc, x=FAKE, dt=_abi.F32, y=FAKE, ws=FAKE, wsb=need_c):
+        return L.lb_spmv_csc(ctypes.byref(A), x, dt, y, ctypes.byref(sched("merge_path")), ws, wsb, None)
+
+    assert spmv_csc(dt=_abi.BF16) == _abi.ERR_UNSUPPORTED  # x is float32
+    assert spmv_csc(wsb=need_c - 1) == _abi.ERR_WORKSPACE_TOO_SMALL
+    assert spmv_csc(A=_abi.CSC(1000, 2**31 - 10, 50, FAKE, FAKE, FAKE, _abi.F32)) == _abi.ERR_OVERFLOW
+    assert spmv_csc(y=0) == _abi.ERR_INVALID_ARG
