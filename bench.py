@@ -11,7 +11,7 @@ back-to-back steps with the inputs already in HBM.
 The same JSON line carries the roofline of the dominant kernel (merge-path
 consume, timed by the library's HIP events on the launch stream), the FP64
 oracle timed on the host cores, and per-schedule, BF16, forward+backward,
-batched and graph-traversal (SSSP, BFS) figures on the other workloads
+COO/CSC, batched and graph-traversal (SSSP, BFS) figures on the other workloads
 (skip them with --quick).  Accuracy is asserted by the GPU tests, not here:
 the oracle runs in this script only as the timed CPU baseline.
 
@@ -519,6 +519,26 @@ def main():
                                     "bwd_kernel_ms": round(bw_ms, 4),
                                     "fwd_bwd_gbs": round((Bf4 + Bb4) / ((tf + tb) * 1e-3) / 1e9, 2)}
     log(f"[bench] fwd+bwd: {result['fwd_bwd_powerlaw1M']}")
+
+    # ------------------------------------------------------------ other tile sets (1M): COO and CSC
+    fm = {"nnz": C4.nnz, "note": "bytes: CSR nnz*8+(m+1)*4+n*4+m*4; COO nnz*12+n*4+m*4; CSC nnz*8+(n+1)*4+n*4+m*4"}
+    Bcoo = C4.nnz * 12 + C4.n * 4 + C4.m * 4
+    Bcsc = C4.nnz * 8 + (C4.n + 1) * 4 + C4.n * 4 + C4.m * 4
+    fm["csr_merge_path"] = {"ms": round(tf, 4), "gbs": round(Bf4 / (tf * 1e-3) / 1e9, 2)}
+    coo4 = lb.COO.from_host(S.to_coo(C4), dev)
+    for name, p in (("coo_merge_path", {}), ("coo_thread_mapped", {}), ("coo_group_mapped64", {"group_size": 64})):
+        sch = name[4:].replace("64", "")
+        wsz = torch.empty(max(1, lb.coo_workspace_size(coo4, sch, **p)), dtype=torch.uint8, device=dev)
+        t = timed(lambda: lb.spmv_coo(coo4, x4d, sch, y=y4, workspace=wsz, **p),
+                  3 if sch != "merge_path" else extra_steps, 1)
+        fm[name] = {"ms": round(t, 4), "gbs": round(Bcoo / (t * 1e-3) / 1e9, 2)}
+    del coo4
+    csc4 = lb.CSC.from_host(S.to_csc(C4), dev)
+    t = timed(lambda: lb.spmv_csc(csc4, x4d, "merge_path", y=y4), extra_steps, 1)
+    fm["csc_merge_path"] = {"ms": round(t, 4), "gbs": round(Bcsc / (t * 1e-3) / 1e9, 2)}
+    del csc4
+    result["formats_powerlaw1M"] = fm
+    log(f"[bench] formats: {fm}")
     del C4d, x4d, dy4, y4, ws4
 
     # ------------------------------------------------------------ batched (512 matrices)

@@ -30,7 +30,7 @@ _lib = _abi.load()
 __all__ = ["CSR", "Pattern", "Batch", "spmv", "spmm", "spmv_backward", "SpMV", "spmv_diff",
            "batched_spmm", "tune", "tune_batched", "merge_path_partition", "group_tile_owner",
            "sssp", "bfs", "traversal_workspace_size", "COO", "CSC", "spmv_coo", "spmv_csc",
-           "coo_merge_path_partition",
+           "coo_merge_path_partition", "coo_workspace_size", "csc_workspace_size",
            "validate", "resolve_schedule", "profile_enable", "profile_reset", "profile_read", "LBError"]
 
 _DT = {torch.float32: _abi.F32, torch.bfloat16: _abi.BF16, torch.float64: _abi.F64}
@@ -502,6 +502,22 @@ class CSC:
     def c_struct(self):
         return _abi.CSC(self.shape[0], self.shape[1], self.nnz, self.col_offsets.data_ptr(), self.row_idx.data_ptr(),
                         self.values.data_ptr(), _dtype_code(self.values))
+
+
+def coo_workspace_size(A: COO, schedule="merge_path", **params) -> int:
+    s = make_schedule(schedule, **params)
+    n = ctypes.c_size_t(0)
+    _abi.check(_lib.lb_coo_workspace_size(ctypes.byref(A.c_struct()), ctypes.byref(s), ctypes.byref(n)),
+               "lb_coo_workspace_size")
+    return int(n.value)
+
+
+def csc_workspace_size(A: CSC, schedule="merge_path", **params) -> int:
+    s = make_schedule(schedule, **params)
+    n = ctypes.c_size_t(0)
+    _abi.check(_lib.lb_csc_workspace_size(ctypes.byref(A.c_struct()), ctypes.byref(s), ctypes.byref(n)),
+               "lb_csc_workspace_size")
+    return int(n.value)
 
 
 def _format_spmv(fn_size, fn, what, A, x, schedule, y, workspace, params):
