@@ -63,7 +63,9 @@ typedef enum lb_sched_kind_t {
     LB_THREAD_MAPPED = 0,  /* tile r -> one thread, grid-stride over tiles (Sec. 4.2 listing) */
     LB_GROUP_MAPPED = 1,   /* tiles -> groups of G lanes (Sec. 5.2.2, Sec. 5.2.3) */
     LB_MERGE_PATH = 2,     /* rows + nnz split evenly over threads (Sec. 5.2.1) */
-    LB_AUTO = 3            /* heuristic of Sec. 6.2 (alpha = 500, beta = 10000), or a tuned pick */
+    LB_AUTO = 3,           /* heuristic of Sec. 6.2 (alpha = 500, beta = 10000), or a tuned pick */
+    LB_WORK_QUEUE = 4      /* group-mapped, G tiles per group, rounds handed to a persistent grid by
+                              a device work queue (Sec. 5.1 persistent mode, infinite_range) */
 } lb_sched_kind_t;
 
 /* A CSR matrix in device memory (Sec. 4.1): row_offsets[rows + 1],
@@ -82,6 +84,11 @@ typedef struct lb_csr_t {
 /* Schedule parameters.  A zero field takes the default noted.
  *  group_size        LB_GROUP_MAPPED: lanes per group, a power of two in
  *                    [1, 1024] (default 64, one wavefront).
+ *                    LB_WORK_QUEUE: as group-mapped with tiles_per_group =
+ *                    group_size (default 64); a persistent grid (grid_size, 0 =
+ *                    resident blocks) claims rounds of G-tile chunks from a
+ *                    counter in the workspace (256 bytes), so blocks that meet
+ *                    short rows take more work.  lb_spmv, lb_sssp and lb_bfs.
  *  tiles_per_group   LB_GROUP_MAPPED: 1 = one tile per group at a time, lanes
  *                    stride its atoms (Sec. 5.2.2); equal to group_size = the
  *                    group takes that many tiles, prefix-sums their sizes in
@@ -311,7 +318,8 @@ LB_API lb_status_t lb_spmv_csc(const lb_csc_t *A, const void *x, lb_dtype_t x_dt
  * the frontier size from the device once per batch of iterations, so these
  * calls synchronize `stream`.
  * Schedules: LB_THREAD_MAPPED (a thread per frontier vertex, block_size as
- * for SpMV), LB_GROUP_MAPPED with group_size a power of two in [8, 1024]
+ * for SpMV), LB_WORK_QUEUE (group_size in [8, 1024]: frontier chunks handed
+ * out by a device work queue), LB_GROUP_MAPPED with group_size a power of two in [8, 1024]
  * and tiles_per_group 1 (a group per vertex) or group_size (LDS prefix sum
  * and get_tile over the group's vertices), LB_AUTO = the rule of Sec. 6.2
  * as for SpMV (merge-path unless (rows < 500 or cols < 500) and

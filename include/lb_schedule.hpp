@@ -14,6 +14,9 @@
 //   Each gives tile(p) -> {id, begin, end} (one read of ids[p] for the
 //   indexed set).
 //
+// Ranges (Sec. 5.1): step_range, grid_stride_range, infinite_range, and
+// queue_rounds, a work queue that hands rounds to persistent blocks.
+//
 // Schedules (Sec. 4.2, 5.1, 5.2.3):
 //   thread_mapped<TS>          each thread takes whole tiles (grid stride) and
 //                              walks their atoms one by one.
@@ -23,7 +26,9 @@
 //                              their atom counts in LDS and strides the
 //                              flattened atoms; get_tile(a) is the last tile
 //                              whose prefix sum is <= a (upper_bound - 1), so
-//                              empty tiles own no atom (K = G).
+//                              empty tiles own no atom (K = G); its rounds
+//                              come from a grid stride (rounds()) or from a
+//                              work queue (queued_rounds()).
 //
 // Group shape: groups of up to one wavefront are packed 256 lanes to a
 // block; a group of more than 64 lanes is one block.  Launch group
@@ -77,6 +82,52 @@ __device__ __forceinline__ step_range grid_stride_range(int64_t begin, int64_t e
     return {static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x + begin, end,
             static_cast<int64_t>(gridDim.x) * blockDim.x};
 }
+
+// begin, begin + step, ... with no end (Sec. 5.1, persistent kernels): the
+// loop body decides when to stop.
+struct infinite_range {
+    int64_t b, s;
+    struct iterator {
+        int64_t v, s;
+        __device__ int64_t operator*() const { return v; }
+        __device__ iterator &operator++() {
+            v += s;
+            return *this;
+        }
+        __device__ bool operator!=(const iterator &) const { return true; }
+    };
+    __device__ iterator begin() const { return {b, s}; }
+    __device__ iterator end() const { return {b, s}; }
+};
+
+// A work queue for persistent blocks: rounds [0, count) are handed out at run
+// time, `step` at a time, by one atomicAdd on a device counter (thread 0
+// claims, LDS broadcasts), so a block that finishes early takes more work.
+// Uniform across the block: every thread of the block iterates it.  The
+// counter must hold 0 when the launch starts; s_slot is one int of LDS.
+struct queue_rounds {
+    int32_t *ticket;
+    int32_t *s_slot;
+    int64_t step, count;  // rounds claimed per claim; rounds in all
+    __device__ int64_t claim() const {
+        __syncthreads();  // every thread has read the previous claim
+        if (threadIdx.x == 0) *s_slot = atomicAdd(ticket, static_cast<int32_t>(step));
+        __syncthreads();
+        return *s_slot;
+    }
+    struct iterator {
+        const queue_rounds *q;
+        int64_t v;
+        __device__ int64_t operator*() const { return v; }
+        __device__ iterator &operator++() {
+            v = q->claim();
+            return *this;
+        }
+        __device__ bool operator!=(const iterator &o) const { return v < o.v; }
+    };
+    __device__ iterator begin() const { return {this, claim()}; }
+    __device__ iterator end() const { return {this, count}; }
+};
 
 // ---------------------------------------------------------------- collectives used by the schedules
 
@@ -238,6 +289,12 @@ struct group_mapped_scan {
     __device__ step_range rounds() const {
         const int64_t chunks = (ts.num_tiles + G - 1) / G;
         return {static_cast<int64_t>(blockIdx.x) * GPB, chunks, static_cast<int64_t>(gridDim.x) * GPB};
+    }
+
+    // The same rounds handed out by a work queue (a persistent grid claims
+    // them at run time; `ticket` must be 0 at launch, s_slot one int of LDS).
+    __device__ queue_rounds queued_rounds(int32_t *ticket, int32_t *s_slot) const {
+        return {ticket, s_slot, GPB, (ts.num_tiles + G - 1) / G};
     }
 
     // Loads the group's chunk for this round and returns its atom count.

@@ -17,10 +17,10 @@ LIB_PATH = os.environ.get("LB_LIBRARY", os.path.join(_PKG, "liblb.so"))
 # lb_dtype_t
 F32, BF16, F64 = 0, 1, 2
 # lb_sched_kind_t
-THREAD_MAPPED, GROUP_MAPPED, MERGE_PATH, AUTO = 0, 1, 2, 3
+THREAD_MAPPED, GROUP_MAPPED, MERGE_PATH, AUTO, WORK_QUEUE = 0, 1, 2, 3, 4
 
 KIND_BY_NAME = {"thread_mapped": THREAD_MAPPED, "group_mapped": GROUP_MAPPED,
-                "merge_path": MERGE_PATH, "auto": AUTO}
+                "merge_path": MERGE_PATH, "auto": AUTO, "work_queue": WORK_QUEUE}
 NAME_BY_KIND = {v: k for k, v in KIND_BY_NAME.items()}
 
 

@@ -51,6 +51,8 @@ struct trav_args {
     int32_t *cnt_out;
     int32_t *cnt_clear;
     int32_t *rounds;    // non-empty frontiers processed
+    int32_t *ticket;        // work queue of this launch (LB_WORK_QUEUE)
+    int32_t *ticket_clear;  // the next launch's work queue, zeroed here
     int32_t iter;
 };
 
@@ -90,6 +92,7 @@ __device__ __forceinline__ int32_t frontier_size(const trav_args &t) {
     const int32_t nf = *t.cnt_in;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         *t.cnt_clear = 0;
+        *t.ticket_clear = 0;
         if (nf > 0) *t.rounds += 1;
     }
     return nf;
@@ -133,13 +136,14 @@ __global__ __launch_bounds__(group_block<G>::BLOCK) void advance_group_kernel(tr
     }
 }
 
-template <int G, bool BFS>
+template <int G, bool BFS, bool QUEUE>
 __global__ __launch_bounds__(group_block<G>::BLOCK) void advance_scan_kernel(trav_args t) {
     using sched = group_mapped_scan<G, indexed_tile_set>;
     __shared__ typename sched::storage st[sched::GPB];
+    __shared__ int32_t s_slot;
     const int32_t nf = frontier_size(t);
     sched sch(indexed_tile_set{t.q_in, t.ro, nf}, st);
-    for (int64_t round : sch.rounds()) {  // uniform across the block
+    auto round_body = [&](int64_t round) {  // called by every thread of the block
         const int32_t total = sch.load(round);
         for (int64_t a : sch.atoms(total)) {
             const int32_t q = sch.get_tile(static_cast<int32_t>(a));
@@ -150,6 +154,11 @@ __global__ __launch_bounds__(group_block<G>::BLOCK) void advance_scan_kernel(tra
             frontier_push(want, v, t.q_out, t.cnt_out);
         }
         sch.done();
+    };
+    if constexpr (QUEUE) {
+        for (int64_t round : sch.queued_rounds(t.ticket, &s_slot)) round_body(round);
+    } else {
+        for (int64_t round : sch.rounds()) round_body(round);  // uniform across the block
     }
 }
 
@@ -341,6 +350,8 @@ __global__ __launch_bounds__(256) void traversal_init_kernel(int32_t n, int32_t 
         counters[1] = 0;
         counters[2] = 0;
         counters[3] = 0;  // rounds
+        counters[4] = 0;  // work-queue tickets of the first two launches
+        counters[5] = 0;
     }
 }
 
@@ -388,9 +399,11 @@ hipError_t advance(const csr_dev &G, const trav_cfg &c, const trav_ws &w, const 
     if (c.kind == LB_THREAD_MAPPED) return launch_advance(advance_thread_kernel<BFS>, c.block, c.grid, t, s);
 #define LB_G(G)                                                                                               \
     if (c.group == G) {                                                                                       \
+        if (c.kind == LB_WORK_QUEUE)                                                                          \
+            return launch_advance(advance_scan_kernel<G, BFS, true>, group_block<G>::BLOCK, c.grid, t, s);     \
         if (c.tiles_per_group == 1)                                                                           \
             return launch_advance(advance_group_kernel<G, BFS>, group_block<G>::BLOCK, c.grid, t, s);          \
-        return launch_advance(advance_scan_kernel<G, BFS>, group_block<G>::BLOCK, c.grid, t, s);               \
+        return launch_advance(advance_scan_kernel<G, BFS, false>, group_block<G>::BLOCK, c.grid, t, s);        \
     }
     LB_TRAVERSAL_GROUPS(LB_G)
 #undef LB_G
@@ -410,7 +423,7 @@ hipError_t run_traversal(const csr_dev &G, int32_t source, float *dist, int32_t 
         if (e != hipSuccess) return e;
     }
     trav_args t{G.ro, G.ci, static_cast<const float *>(G.val), dist, depth, w.stamp,
-                nullptr, nullptr, nullptr, nullptr, nullptr, w.counters + 3, 0};
+                nullptr, nullptr, nullptr, nullptr, nullptr, w.counters + 3, nullptr, nullptr, 0};
     int32_t launched = 0, batch = 4;
     int32_t host[4] = {0, 0, 0, 0};
     *converged = false;
@@ -422,6 +435,8 @@ hipError_t run_traversal(const csr_dev &G, int32_t source, float *dist, int32_t 
             t.cnt_in = w.counters + launched % 3;
             t.cnt_out = w.counters + (launched + 1) % 3;
             t.cnt_clear = w.counters + (launched + 2) % 3;
+            t.ticket = w.counters + 4 + (launched & 1);
+            t.ticket_clear = w.counters + 4 + ((launched + 1) & 1);
             const hipError_t e = advance<BFS>(G, c, w, t, s);
             if (e != hipSuccess) return e;
         }

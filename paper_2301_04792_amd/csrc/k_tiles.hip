@@ -157,10 +157,10 @@ __global__ __launch_bounds__(group_block<G>::BLOCK) void group_mapped_tile_kerne
 // finding its row with get_tile.  Per-row sums: a segmented scan over the
 // lanes of each step, whose segment tails add into the row's LDS
 // accumulator in step order (deterministic).
-template <int G, typename VT, typename XT>
+template <int G, bool QUEUE, typename VT, typename XT>
 __global__ __launch_bounds__(group_block<G>::BLOCK) void group_mapped_scan_kernel(
     csr_tile_set ts, const int32_t *__restrict__ ci, const VT *__restrict__ val, const XT *__restrict__ x,
-    float *__restrict__ y) {
+    float *__restrict__ y, int32_t *__restrict__ ticket) {
     using sched = group_mapped_scan<G, csr_tile_set>;
     constexpr int BLOCK = sched::BLOCK;
     constexpr int GPB = sched::GPB;
@@ -169,10 +169,12 @@ __global__ __launch_bounds__(group_block<G>::BLOCK) void group_mapped_scan_kerne
     __shared__ int32_t s_key[G > kWave ? BLOCK : 1];
     __shared__ seg_t s_wave[BLOCK / kWave];
 
+    __shared__ int32_t s_slot;
+
     const int gl = threadIdx.x & (G - 1);
     const int gi = threadIdx.x / G;
     sched sch(ts, s_st);
-    for (int64_t round : sch.rounds()) {  // uniform across the block
+    auto round_body = [&](int64_t round) {  // called by every thread of the block
         const int64_t t0 = (round + gi) * G;
         s_acc[gi][gl] = 0.f;
         const int32_t total = sch.load(round);  // ends with a barrier: s_acc is clear
@@ -207,11 +209,27 @@ __global__ __launch_bounds__(group_block<G>::BLOCK) void group_mapped_scan_kerne
         __syncthreads();
         if (t0 + gl < ts.num_tiles) y[t0 + gl] = s_acc[gi][gl];
         sch.done();
+    };
+    if constexpr (QUEUE) {  // persistent grid, rounds claimed from the work queue
+        for (int64_t round : sch.queued_rounds(ticket, &s_slot)) round_body(round);
+    } else {
+        for (int64_t round : sch.rounds()) round_body(round);  // uniform across the block
     }
 }
 
+template <typename K>
+static int resident_blocks(K kernel, int block) {
+    int dev = 0, cus = 256, per_cu = 1;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0);
+    }
+    return cus * (per_cu > 0 ? per_cu : 1);
+}
+
 template <int G, typename VT>
-static hipError_t launch_group(const csr_dev &A, const void *x, float *y, int K, int grid, hipStream_t s) {
+static hipError_t launch_group(const csr_dev &A, const void *x, float *y, int K, int grid, int32_t *ticket,
+                               hipStream_t s) {
     constexpr int BLOCK = group_block<G>::BLOCK;
     constexpr int GPB = group_block<G>::GPB;
     const csr_tile_set ts{A.ro, A.rows, A.nnz};
@@ -219,11 +237,20 @@ static hipError_t launch_group(const csr_dev &A, const void *x, float *y, int K,
         const dim3 g(static_cast<uint32_t>(blocks_for(A.rows, GPB, grid)));
         hipLaunchKernelGGL((group_mapped_tile_kernel<G, VT, VT>), g, dim3(BLOCK), 0, s, ts, A.ci,
                            static_cast<const VT *>(A.val), static_cast<const VT *>(x), y);
+    } else if (ticket) {  // work queue: zero the counter, then a persistent grid
+        const hipError_t e = fill_f32(reinterpret_cast<float *>(ticket), 1, 0.f, s);  // +0.0f is all zero bits
+        if (e != hipSuccess) return e;
+        const auto kern = group_mapped_scan_kernel<G, true, VT, VT>;
+        const int64_t nchunks = (static_cast<int64_t>(A.rows) + G - 1) / G;
+        const int64_t g = grid > 0 ? grid : resident_blocks(kern, BLOCK);
+        const int64_t need = (nchunks + GPB - 1) / GPB;
+        hipLaunchKernelGGL(kern, dim3(static_cast<uint32_t>(g < need ? g : (need > 0 ? need : 1))), dim3(BLOCK), 0,
+                           s, ts, A.ci, static_cast<const VT *>(A.val), static_cast<const VT *>(x), y, ticket);
     } else {
         const int64_t nchunks = (static_cast<int64_t>(A.rows) + G - 1) / G;
         const dim3 g(static_cast<uint32_t>(blocks_for(nchunks, GPB, grid)));
-        hipLaunchKernelGGL((group_mapped_scan_kernel<G, VT, VT>), g, dim3(BLOCK), 0, s, ts, A.ci,
-                           static_cast<const VT *>(A.val), static_cast<const VT *>(x), y);
+        hipLaunchKernelGGL((group_mapped_scan_kernel<G, false, VT, VT>), g, dim3(BLOCK), 0, s, ts, A.ci,
+                           static_cast<const VT *>(A.val), static_cast<const VT *>(x), y, nullptr);
     }
     return hipGetLastError();
 }
@@ -231,12 +258,12 @@ static hipError_t launch_group(const csr_dev &A, const void *x, float *y, int K,
 #define LB_GROUP_SIZES(X) X(1) X(2) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024)
 
 hipError_t group_mapped_spmv(const csr_dev &A, const void *x, float *y, int group_size, int tiles_per_group,
-                             int grid, hipStream_t s) {
-    prof_scope p(s, "group_mapped");
-#define X(G)                                                                                  \
-    if (group_size == G) {                                                                    \
-        if (A.dt == LB_BF16) return launch_group<G, bf16_bits>(A, x, y, tiles_per_group, grid, s); \
-        return launch_group<G, float>(A, x, y, tiles_per_group, grid, s);                     \
+                             int grid, int32_t *ticket, hipStream_t s) {
+    prof_scope p(s, ticket ? "work_queue" : "group_mapped");
+#define X(G)                                                                                           \
+    if (group_size == G) {                                                                             \
+        if (A.dt == LB_BF16) return launch_group<G, bf16_bits>(A, x, y, tiles_per_group, grid, ticket, s); \
+        return launch_group<G, float>(A, x, y, tiles_per_group, grid, ticket, s);                      \
     }
     LB_GROUP_SIZES(X)
 #undef X

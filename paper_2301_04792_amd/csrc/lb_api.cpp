@@ -158,6 +158,13 @@ lb_status_t fill_defaults(const lb_schedule_t *in, lb_schedule_t *out) {
             if (s.items_per_thread == 0) s.items_per_thread = kDefaultItems;
             if (!lbk::merge_config_supported(s.block_size, s.items_per_thread)) return LB_ERR_UNSUPPORTED;
             break;
+        case LB_WORK_QUEUE:
+            if (s.group_size == 0) s.group_size = kDefaultGroup;
+            if (!is_pow2(s.group_size) || s.group_size > 1024) return LB_ERR_INVALID_ARG;
+            if (s.tiles_per_group == 0) s.tiles_per_group = s.group_size;
+            if (s.tiles_per_group != s.group_size) return LB_ERR_UNSUPPORTED;
+            s.block_size = s.group_size > 64 ? s.group_size : 256;
+            break;
         default:
             return LB_ERR_INVALID_ARG;
     }
@@ -203,6 +210,7 @@ lb_status_t resolve(const lb_csr_t *A, int32_t k, const lb_schedule_t *in, lb_sc
 int spmm_pass_cols(int32_t k) { return k >= 8 ? 8 : (k >= 4 ? 4 : (k >= 2 ? 2 : 1)); }
 
 size_t ws_bytes_for(const lb_csr_t *A, const lb_schedule_t &s, int32_t k) {
+    if (s.kind == LB_WORK_QUEUE) return 256;  // the queue's counter
     if (s.kind != LB_MERGE_PATH) return 0;
     const int64_t W = static_cast<int64_t>(s.block_size) * s.items_per_thread;
     const int64_t T = lbk::merge_units(A->rows, A->nnz, W);
@@ -241,6 +249,7 @@ lb_status_t coo_schedule(const lb_coo_t *A, const lb_schedule_t *in, lb_schedule
     }
     lb_status_t st = fill_defaults(&s, out);
     if (st != LB_OK) return st;
+    if (out->kind == LB_WORK_QUEUE) return LB_ERR_UNSUPPORTED;
     if (out->kind == LB_GROUP_MAPPED) {
         if (out->tiles_per_group != 1) return LB_ERR_UNSUPPORTED;
         if (!lbk::traversal_group_supported(out->group_size)) return LB_ERR_UNSUPPORTED;
@@ -291,11 +300,13 @@ lb_status_t traversal_cfg(const lb_csr_t *G, const lb_schedule_t *in, lbk::trav_
             if (c.block % 64 != 0 || c.block > 1024) return LB_ERR_INVALID_ARG;
             break;
         case LB_GROUP_MAPPED:
+        case LB_WORK_QUEUE:
             c.group = s.group_size ? s.group_size : kDefaultGroup;
             if (!is_pow2(c.group) || c.group > 1024) return LB_ERR_INVALID_ARG;
             if (!lbk::traversal_group_supported(c.group)) return LB_ERR_UNSUPPORTED;
-            c.tiles_per_group = s.tiles_per_group ? s.tiles_per_group : 1;
+            c.tiles_per_group = s.tiles_per_group ? s.tiles_per_group : (s.kind == LB_WORK_QUEUE ? c.group : 1);
             if (c.tiles_per_group != 1 && c.tiles_per_group != c.group) return LB_ERR_UNSUPPORTED;
+            if (s.kind == LB_WORK_QUEUE && c.tiles_per_group != c.group) return LB_ERR_UNSUPPORTED;
             break;
         case LB_MERGE_PATH:  // one configuration: 256 threads x 8 merge items per unit
             if ((s.block_size && s.block_size != 256) || (s.items_per_thread && s.items_per_thread != 8))
@@ -385,6 +396,7 @@ std::vector<lb_schedule_t> candidates(const lb_csr_t *A, int32_t k) {
             c.push_back({LB_GROUP_MAPPED, g, 1, 0, 0, 0});
             c.push_back({LB_GROUP_MAPPED, g, g, 0, 0, 0});
         }
+        for (int g : {64, 256}) c.push_back({LB_WORK_QUEUE, g, g, 0, 0, 0});
     }
     (void)A;
     return c;
@@ -484,7 +496,11 @@ LB_API lb_status_t lb_spmv(const lb_csr_t *A, const void *x, lb_dtype_t x_dtype,
     switch (r.kind) {
         case LB_THREAD_MAPPED: return hip_status(lbk::thread_mapped_spmv(d, x, y, r.block_size, r.grid_size, hs));
         case LB_GROUP_MAPPED:
-            return hip_status(lbk::group_mapped_spmv(d, x, y, r.group_size, r.tiles_per_group, r.grid_size, hs));
+            return hip_status(
+                lbk::group_mapped_spmv(d, x, y, r.group_size, r.tiles_per_group, r.grid_size, nullptr, hs));
+        case LB_WORK_QUEUE:
+            return hip_status(lbk::group_mapped_spmv(d, x, y, r.group_size, r.group_size, r.grid_size,
+                                                     static_cast<int32_t *>(workspace), hs));
         case LB_MERGE_PATH:
             return hip_status(lbk::merge_spmv(d, x, y, r.block_size, r.items_per_thread, workspace, hs));
         default: return LB_ERR_INVALID_ARG;
@@ -606,7 +622,7 @@ LB_API lb_status_t lb_spmm(const lb_csr_t *A, const void *X, lb_dtype_t x_dtype,
     lb_schedule_t r;
     st = resolve(A, k, s, &r);
     if (st != LB_OK) return st;
-    if (r.kind == LB_GROUP_MAPPED) return LB_ERR_UNSUPPORTED;
+    if (r.kind == LB_GROUP_MAPPED || r.kind == LB_WORK_QUEUE) return LB_ERR_UNSUPPORTED;
     const size_t need = ws_bytes_for(A, r, k);
     if (need > 0 && (workspace_bytes < need || !workspace)) return LB_ERR_WORKSPACE_TOO_SMALL;
     hipStream_t hs = static_cast<hipStream_t>(stream);

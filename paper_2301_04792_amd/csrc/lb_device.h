@@ -44,7 +44,7 @@ template <int G, typename Key>
 __device__ __forceinline__ int32_t group_count_below(int32_t lo, int32_t hi, int32_t d, Key key) {
     const int gl = threadIdx.x & (G - 1);
     const int shift = (threadIdx.x & (kWave - 1)) & ~(G - 1);
-    const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1);
+    const uint64_t gmask = G >= 64 ? ~0ull : ((1ull << (G & 63)) - 1);
     for (;;) {
         const bool wide = hi - lo > G;
         if (__ballot(wide) == 0) break;  // every group of the wavefront has narrowed down
@@ -91,7 +91,7 @@ template <int G>
 __device__ __forceinline__ int32_t group_count_le(const int64_t *__restrict__ a, int32_t n, int64_t key) {
     const int gl = threadIdx.x & (G - 1);
     const int shift = (threadIdx.x & (kWave - 1)) & ~(G - 1);
-    const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1);
+    const uint64_t gmask = G >= 64 ? ~0ull : ((1ull << (G & 63)) - 1);
     int32_t lo = 0, hi = n;  // a[r] <= key for r < lo, a[r] > key for r >= hi
     for (;;) {
         const bool wide = hi - lo > G;

@@ -116,8 +116,10 @@ hipError_t thread_mapped_spmv(const csr_dev &A, const void *x, float *y, int blo
                               hipStream_t s);
 hipError_t thread_mapped_spmm(const csr_dev &A, const void *X, int32_t k, int64_t ldx, float *Y,
                               int64_t ldy, int block, int grid, hipStream_t s);
+// ticket non-null: the work-queue form (tiles_per_group == group_size, a
+// persistent grid claiming rounds from *ticket, which the call zeroes first).
 hipError_t group_mapped_spmv(const csr_dev &A, const void *x, float *y, int group_size,
-                             int tiles_per_group, int grid, hipStream_t s);
+                             int tiles_per_group, int grid, int32_t *ticket, hipStream_t s);
 hipError_t group_tile_owner(const csr_dev &A, int tiles_per_group, int32_t *owner, hipStream_t s);
 
 // ---- COO and CSC ---------------------------------------------------------------------------
@@ -141,7 +143,7 @@ hipError_t coo_spmv(const coo_dev &A, const void *x, float *y, lb_sched_kind_t k
 #define LB_TRAVERSAL_GROUPS(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024)
 
 struct trav_cfg {
-    lb_sched_kind_t kind;  // LB_THREAD_MAPPED, LB_GROUP_MAPPED or LB_MERGE_PATH
+    lb_sched_kind_t kind;  // LB_THREAD_MAPPED, LB_GROUP_MAPPED, LB_MERGE_PATH or LB_WORK_QUEUE
     int group;             // group-mapped: lanes per group
     int tiles_per_group;   // group-mapped: 1 or group
     int block;             // thread-mapped: threads per block
@@ -151,8 +153,9 @@ struct trav_cfg {
 // Merge-path units of a frontier: at most (n + nnz) merge items of 2048.
 inline int64_t trav_merge_units(int64_t n, int64_t nnz) { return (n + nnz + 2047) / 2048; }
 
-// Workspace: stamp[n], two frontier queues of n vertex ids, 4 counters
-// (three rotating frontier sizes and the count of non-empty frontiers);
+// Workspace: stamp[n], two frontier queues of n vertex ids, counters (three
+// rotating frontier sizes, the count of non-empty frontiers, two rotating
+// work-queue tickets);
 // for merge-path also the frontier's offsets[n + 1], per-tile degree sums,
 // {E_f, T_f} and the split at every unit boundary.
 struct trav_ws {

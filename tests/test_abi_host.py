@@ -254,3 +254,24 @@ def test_coo_csc_host_checks():
     assert spmv_csc(wsb=need_c - 1) == _abi.ERR_WORKSPACE_TOO_SMALL
     assert spmv_csc(A=_abi.CSC(1000, 2**31 - 10, 50, FAKE, FAKE, FAKE, _abi.F32)) == _abi.ERR_OVERFLOW
     assert spmv_csc(y=0) == _abi.ERR_INVALID_ARG
+
+
+def test_work_queue_host_checks():
+    L = _abi.load()
+    A = csr(100000, 100000, 10**6)
+    n = ctypes.c_size_t(0)
+    s = sched("work_queue")
+    assert L.lb_workspace_size(ctypes.byref(A), ctypes.byref(s), 1, ctypes.byref(n)) == _abi.OK and n.value == 256
+    st, out = resolve(A, sched("work_queue", group_size=128))
+    assert st == _abi.OK and out.tiles_per_group == 128 and out.block_size == 128
+    st, out = resolve(A, sched("work_queue"))
+    assert st == _abi.OK and out.group_size == 64 and out.tiles_per_group == 64 and out.block_size == 256
+    assert resolve(A, sched("work_queue", group_size=64, tiles_per_group=1))[0] == _abi.ERR_UNSUPPORTED
+    assert resolve(A, sched("work_queue", group_size=48))[0] == _abi.ERR_INVALID_ARG
+    # the work queue serves lb_spmv and the traversals only
+    spmm = L.lb_spmm(ctypes.byref(A), FAKE, _abi.F32, 4, 4, FAKE, 4, ctypes.byref(s), FAKE, 1 << 20, None)
+    assert spmm == _abi.ERR_UNSUPPORTED
+    coo = _abi.COO(1000, 800, 5000, FAKE, FAKE, FAKE, _abi.F32)
+    assert L.lb_coo_workspace_size(ctypes.byref(coo), ctypes.byref(s), ctypes.byref(n)) == _abi.ERR_UNSUPPORTED
+    assert L.lb_spmv(ctypes.byref(A), FAKE, _abi.F32, FAKE, ctypes.byref(s), FAKE, 255, None) \
+        == _abi.ERR_WORKSPACE_TOO_SMALL

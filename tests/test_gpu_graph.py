@@ -31,6 +31,8 @@ SCHEDULES = [
     ("group_mapped", {"group_size": 64, "tiles_per_group": 64, "grid_size": 3}),
     ("merge_path", {}),
     ("merge_path", {"grid_size": 5}),
+    ("work_queue", {}),
+    ("work_queue", {"group_size": 256, "grid_size": 2}),
 ]
 IDS = [f"{k}-{'-'.join(f'{a}{b}' for a, b in p.items()) or 'default'}" for k, p in SCHEDULES]
 

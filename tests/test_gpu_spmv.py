@@ -23,7 +23,9 @@ GROUP_CONFIGS = [(g, k) for g in (1, 2, 8, 32, 64, 128, 256, 1024) for k in (1, 
 
 SCHEDULES = ([("thread_mapped", {}), ("thread_mapped", {"block_size": 64}), ("auto", {})]
              + [("group_mapped", {"group_size": g, "tiles_per_group": k}) for g, k in GROUP_CONFIGS]
-             + [("merge_path", {"block_size": b, "items_per_thread": i}) for b, i in MERGE_CONFIGS])
+             + [("merge_path", {"block_size": b, "items_per_thread": i}) for b, i in MERGE_CONFIGS]
+             + [("work_queue", {"group_size": g}) for g in (8, 64, 256, 1024)]
+             + [("work_queue", {"group_size": 64, "grid_size": 1}), ("work_queue", {"group_size": 32, "grid_size": 7})])
 SCHED_IDS = [f"{n}-{'-'.join(f'{k}{v}' for k, v in p.items())}" for n, p in SCHEDULES]
 
 
@@ -306,3 +308,17 @@ def test_validate_csr():
     ro[10], ro[11] = ro[11], ro[10] - 1
     Ar = lb.CSR(torch.from_numpy(ro).to(DEV), Ad.col_idx, Ad.values, A.shape)
     assert not lb.validate(Ar)
+
+
+@pytest.mark.parametrize("g,grid", [(8, 0), (64, 0), (64, 1), (256, 3), (1024, 0)])
+def test_work_queue_equals_static_rounds(g, grid):
+    # the queue only changes which block runs a chunk, not the chunk's arithmetic
+    mats = {"c1": S.config_c1(), "powerlaw": S.powerlaw_csr(36, 40_000, 40_000, 1.6, 20_000, 0.2)}
+    mats.update({k: v for k, v in S.special_matrices().items() if k != "m0"})
+    for name, (A, x) in mats.items():
+        Ad, xd = upload(A, x)
+        yq = lb.spmv(Ad, xd, "work_queue", group_size=g, grid_size=grid)
+        ys = lb.spmv(Ad, xd, "group_mapped", group_size=g, tiles_per_group=g)
+        assert torch.equal(yq, ys), (name, g, grid)
+        yq2 = lb.spmv(Ad, xd, "work_queue", group_size=g, grid_size=grid)  # reused workspace: counter re-zeroed
+        assert torch.equal(yq, yq2), (name, g, grid)
