@@ -219,7 +219,8 @@ def run_graph(lb, S, dev, no_cpu):
                        ("group64", "group_mapped", {"group_size": 64, "tiles_per_group": 1}),
                        ("group1024", "group_mapped", {"group_size": 1024, "tiles_per_group": 1}),
                        ("group64x64", "group_mapped", {"group_size": 64, "tiles_per_group": 64}),
-                       ("merge_path", "merge_path", {}))
+                       ("merge_path", "merge_path", {}),
+                       ("work_queue1024", "work_queue", {"group_size": 1024}))
     for algo, fn in (("sssp", lb.sssp), ("bfs", lb.bfs)):
         per = {}
         for name, sch, p in graph_schedules:
@@ -458,7 +459,9 @@ def main():
     per = {}
     for name, p in (("merge_path", {}), ("merge_path", {"block_size": 512, "items_per_thread": 8}),
                     ("thread_mapped", {}), ("group_mapped", {"group_size": 64}),
-                    ("group_mapped", {"group_size": 256}), ("group_mapped", {"group_size": 32, "tiles_per_group": 32})):
+                    ("group_mapped", {"group_size": 256}), ("group_mapped", {"group_size": 32, "tiles_per_group": 32}),
+                    ("group_mapped", {"group_size": 1024, "tiles_per_group": 1024}),
+                    ("work_queue", {"group_size": 1024})):
         wsz = lb.workspace_size(Ad, name, **p)
         w2 = torch.empty(max(wsz, 1), dtype=torch.uint8, device=dev)
         f = (lambda name=name, p=p, w2=w2: lb.spmv(Ad, xd, name, y=y, workspace=w2, **p))
