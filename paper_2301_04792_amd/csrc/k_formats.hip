@@ -191,10 +191,12 @@ hipError_t run_coo_merge(const coo_dev &A, const void *x, float *y, void *ws, hi
     return launch_fixup(T, A.rows, 1, w.carry_row, w.carry_val, y, 1, s, "coo_fixup");
 }
 
+// Blocks for `work` items at `per_block` per block, capped by a caller grid
+// and at 2^20 blocks (grid-stride kernels; blocks x threads stays below 2^32).
 int64_t grid_for(int64_t work, int64_t per_block, int grid) {
     int64_t g = (work + per_block - 1) / per_block;
     if (grid > 0 && g > grid) g = grid;
-    if (g > 0x7fffffff) g = 0x7fffffff;
+    if (g > (int64_t(1) << 20)) g = int64_t(1) << 20;
     return g < 1 ? 1 : g;
 }
 

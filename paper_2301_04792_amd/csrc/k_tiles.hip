@@ -47,10 +47,15 @@ __global__ __launch_bounds__(1024) void thread_mapped_spmv_kernel(csr_tile_set t
     }
 }
 
+// Blocks for `work` items at `per_block` per block, capped by a caller grid
+// and at kMaxBlocks: the kernels loop with a grid stride, and a launch must
+// keep blocks x threads below 2^32 (a group per row with 1024 lanes reaches
+// that at 4M rows).
+constexpr int64_t kMaxBlocks = int64_t(1) << 20;
 static int64_t blocks_for(int64_t work, int64_t per_block, int grid) {
     int64_t g = (work + per_block - 1) / per_block;
     if (grid > 0 && g > grid) g = grid;
-    if (g > 0x7fffffff) g = 0x7fffffff;
+    if (g > kMaxBlocks) g = kMaxBlocks;
     return g < 1 ? 1 : g;
 }
 

@@ -78,10 +78,19 @@ def test_laplacian2048(dtype):
         xh = x
         xd = torch.from_numpy(x).to(DEV)
     Ld = lb.CSR.from_host(L, DEV)
+    ref, scale = oracle_spmv(L, xh)
     for params in ({}, {"block_size": 256, "items_per_thread": 12}):
         y = lb.spmv(Ld, xd, "merge_path", **params).cpu().numpy()
-        ref, scale = oracle_spmv(L, xh)
         assert_rows_close(y, ref, scale, what=f"laplacian {dtype} {params}")
+    # 2^22 rows x 1024-lane groups: 2^32 threads unless the launch is capped
+    for name, params in (("group_mapped", {"group_size": 1024}), ("thread_mapped", {}),
+                         ("work_queue", {"group_size": 256})):
+        y = lb.spmv(Ld, xd, name, **params).cpu().numpy()
+        assert_rows_close(y, ref, scale, what=f"laplacian {dtype} {name} {params}")
+    tuned = lb.tune(Ld)  # every candidate launches on 4M rows
+    y = lb.spmv(Ld, xd, "auto").cpu().numpy()
+    lb.autotune_clear()
+    assert_rows_close(y, ref, scale, what=f"laplacian {dtype} tuned {tuned}")
 
 
 def test_powerlaw1m_forward_backward():
