@@ -515,11 +515,21 @@ def main():
     tf = timed(lambda: lb.spmv(C4d, x4d, "merge_path", y=y4, workspace=ws4), extra_steps, 2)
     tb = timed(lambda: lb.spmv_backward(C4d, x4d, dy4), extra_steps, 2)
     bw_ms, _ = kernel_avg_ms(lambda: lb.spmv_backward(C4d, x4d, dy4), extra_steps, "backward")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tr4 = lb.transpose_pattern(C4d.pattern)  # once per pattern
+    torch.cuda.synchronize()
+    tbuild = (time.perf_counter() - t0) * 1e3
+    tbt = timed(lambda: lb.spmv_backward(C4d, x4d, dy4, transposed=tr4), extra_steps, 2)
     Bf4, Bb4 = spmv_bytes(C4.m, C4.n, C4.nnz), backward_bytes(C4.m, C4.n, C4.nnz)
     result["fwd_bwd_powerlaw1M"] = {"nnz": C4.nnz, "fwd_ms": round(tf, 4), "bwd_ms": round(tb, 4),
                                     "fwd_gbs": round(Bf4 / (tf * 1e-3) / 1e9, 2),
                                     "bwd_gbs": round(Bb4 / (tb * 1e-3) / 1e9, 2),
                                     "bwd_kernel_ms": round(bw_ms, 4),
+                                    "bwd_transposed_ms": round(tbt, 4),
+                                    "bwd_transposed_gbs": round(Bb4 / (tbt * 1e-3) / 1e9, 2),
+                                    "transpose_build_ms": round(tbuild, 3),
+                                    "fwd_bwd_transposed_gbs": round((Bf4 + Bb4) / ((tf + tbt) * 1e-3) / 1e9, 2),
                                     "fwd_bwd_gbs": round((Bf4 + Bb4) / ((tf + tb) * 1e-3) / 1e9, 2)}
     log(f"[bench] fwd+bwd: {result['fwd_bwd_powerlaw1M']}")
 

@@ -215,6 +215,29 @@ LB_API lb_status_t lb_spmv_backward(const lb_csr_t *A, const void *x, lb_dtype_t
                                     const lb_schedule_t *s, void *workspace,
                                     size_t workspace_bytes, void *stream);
 
+/* Backward without atomics, for a pattern reused across calls (a training
+ * loop): lb_transpose_pattern builds A^T's pattern once --
+ * at_row_offsets[cols + 1], at_col_idx[nnz] (the rows of A) and perm[nnz]
+ * (entry p of A^T is entry perm[p] of A); the order inside a row of A^T
+ * comes from atomics and varies from build to build.  Workspace from
+ * lb_transpose_workspace_size.  cols + nnz < 2^31 - 1.
+ * lb_spmv_backward_transposed then computes dvalues as lb_spmv_backward
+ * does (bit-exact) and dx = A^T dy by permuting the current values into
+ * A^T's order (float32) and running the merge-path SpMV on A^T: a gather,
+ * no atomics; for a fixed pattern build dx is bit-reproducible.  s as for
+ * lb_spmv_backward (merge-path block_size / items_per_thread); workspace
+ * from lb_backward_transposed_workspace_size. */
+LB_API lb_status_t lb_transpose_workspace_size(const lb_csr_t *A, size_t *bytes);
+LB_API lb_status_t lb_transpose_pattern(const lb_csr_t *A, int32_t *at_row_offsets, int32_t *at_col_idx,
+                                        int32_t *perm, void *workspace, size_t workspace_bytes, void *stream);
+LB_API lb_status_t lb_backward_transposed_workspace_size(const lb_csr_t *A, const lb_schedule_t *s,
+                                                         size_t *bytes);
+LB_API lb_status_t lb_spmv_backward_transposed(const lb_csr_t *A, const int32_t *at_row_offsets,
+                                               const int32_t *at_col_idx, const int32_t *perm, const void *x,
+                                               lb_dtype_t x_dtype, const float *dy, float *dx, float *dvalues,
+                                               const lb_schedule_t *s, void *workspace, size_t workspace_bytes,
+                                               void *stream);
+
 /* Workspace bytes for lb_batched_spmm with k right-hand sides.  Host-only. */
 LB_API lb_status_t lb_batched_workspace_size(const lb_batch_t *B, const lb_schedule_t *s,
                                              int32_t k, size_t *bytes);
@@ -378,7 +401,8 @@ LB_API int32_t lb_probe_default_grid(void);
  * events and returns, for the kernel family `name` ("merge_partition",
  * "merge_consume", "merge_fixup", "thread_mapped", "group_mapped",
  * "backward", "batched_consume", "batched_fixup", "fill", "coo_partition",
- * "coo_consume", "coo_fixup", "coo_tiles", "traversal_init",
+ * "coo_consume", "coo_fixup", "coo_tiles", "transpose", "permute_values",
+ * "work_queue", "traversal_init",
  * "sssp_advance", "bfs_advance"), the summed
  * duration in milliseconds and the launch count since the last reset. */
 LB_API void lb_profile_enable(int on);

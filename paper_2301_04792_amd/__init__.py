@@ -30,7 +30,7 @@ _lib = _abi.load()
 __all__ = ["CSR", "Pattern", "Batch", "spmv", "spmm", "spmv_backward", "SpMV", "spmv_diff",
            "batched_spmm", "tune", "tune_batched", "merge_path_partition", "group_tile_owner",
            "sssp", "bfs", "traversal_workspace_size", "COO", "CSC", "spmv_coo", "spmv_csc",
-           "coo_merge_path_partition", "coo_workspace_size", "csc_workspace_size",
+           "coo_merge_path_partition", "coo_workspace_size", "csc_workspace_size", "transpose_pattern",
            "validate", "resolve_schedule", "profile_enable", "profile_reset", "profile_read", "LBError"]
 
 _DT = {torch.float32: _abi.F32, torch.bfloat16: _abi.BF16, torch.float64: _abi.F64}
@@ -177,13 +177,49 @@ def spmm(A: CSR, X: torch.Tensor, schedule="merge_path", Y: torch.Tensor | None 
     return Y
 
 
+def transpose_pattern(P: Pattern):
+    """A^T's pattern for the transposed backward: (at_row_offsets, at_col_idx, perm),
+    entry p of A^T being entry perm[p] of A.  Built once per pattern and cached on it."""
+    cached = getattr(P, "_transposed", None)
+    if cached is not None:
+        return cached
+    c = _abi.CSR(P.shape[0], P.shape[1], P.nnz, P.row_offsets.data_ptr(), P.col_idx.data_ptr(),
+                 P.col_idx.data_ptr(), _abi.F32)  # the values are not read
+    n = ctypes.c_size_t(0)
+    _abi.check(_lib.lb_transpose_workspace_size(ctypes.byref(c), ctypes.byref(n)), "lb_transpose_workspace_size")
+    at_ro = torch.empty(P.shape[1] + 1, dtype=torch.int32, device=P.device)
+    at_ci = torch.empty(max(P.nnz, 1), dtype=torch.int32, device=P.device)
+    perm = torch.empty(max(P.nnz, 1), dtype=torch.int32, device=P.device)
+    ws = _workspace(max(n.value, 1), P.device)
+    _abi.check(_lib.lb_transpose_pattern(ctypes.byref(c), _ptr(at_ro), _ptr(at_ci), _ptr(perm), _ptr(ws),
+                                         max(n.value, 1), _stream(P.device)), "lb_transpose_pattern")
+    P._transposed = (at_ro, at_ci, perm)
+    return P._transposed
+
+
 def spmv_backward(A: CSR, x: torch.Tensor, dy: torch.Tensor, need_dx: bool = True, need_dvalues: bool = True,
-                  schedule="merge_path", **params):
-    """(dx, dvalues) of y = A x: dx = A^T dy, dvalues[j] = dy[row(j)] x[col(j)] (float32)."""
+                  schedule="merge_path", transposed=None, **params):
+    """(dx, dvalues) of y = A x: dx = A^T dy, dvalues[j] = dy[row(j)] x[col(j)] (float32).
+
+    transposed: None (dx by atomic scatter) or the (at_row_offsets, at_col_idx, perm)
+    of transpose_pattern (dx by a merge-path SpMV over A^T, no atomics)."""
     dy = dy.contiguous().to(torch.float32)
     x = x.contiguous()
     s = make_schedule(schedule, **params)
     c = A.c_struct()
+    if transposed is not None:
+        at_ro, at_ci, perm = transposed
+        n = ctypes.c_size_t(0)
+        _abi.check(_lib.lb_backward_transposed_workspace_size(ctypes.byref(c), ctypes.byref(s), ctypes.byref(n)),
+                   "lb_backward_transposed_workspace_size")
+        dx = torch.empty(A.shape[1], dtype=torch.float32, device=A.device) if need_dx else None
+        dv = torch.empty(A.nnz, dtype=torch.float32, device=A.device) if need_dvalues else None
+        ws = _workspace(max(n.value, 1), A.device)
+        _abi.check(_lib.lb_spmv_backward_transposed(ctypes.byref(c), _ptr(at_ro), _ptr(at_ci), _ptr(perm), _ptr(x),
+                                                    _dtype_code(x), _ptr(dy), _ptr(dx), _ptr(dv), ctypes.byref(s),
+                                                    _ptr(ws), max(n.value, 1), _stream(A.device)),
+                   "lb_spmv_backward_transposed")
+        return dx, dv
     n = ctypes.c_size_t(0)
     _abi.check(_lib.lb_workspace_size(ctypes.byref(c), ctypes.byref(s), 0, ctypes.byref(n)), "lb_workspace_size")
     dx = torch.empty(A.shape[1], dtype=torch.float32, device=A.device) if need_dx else None
@@ -198,15 +234,19 @@ def spmv_backward(A: CSR, x: torch.Tensor, dy: torch.Tensor, need_dx: bool = Tru
 class SpMV(torch.autograd.Function):
     """y = A(values) x, differentiable in values and x.
 
-    forward: lb_spmv with the given schedule; backward: lb_spmv_backward
-    (dx = A^T dy by merge-path scatter, dvalues = dy[row] * x[col])."""
+    forward: lb_spmv with the given schedule; backward: dvalues = dy[row] * x[col]
+    and dx = A^T dy, by merge-path scatter (backward="scatter") or by a
+    merge-path SpMV over A^T built once per pattern (backward="transposed")."""
 
     @staticmethod
-    def forward(ctx, values, x, pattern: Pattern, schedule="merge_path"):
+    def forward(ctx, values, x, pattern: Pattern, schedule="merge_path", backward="scatter"):
+        if backward not in ("scatter", "transposed"):
+            raise ValueError("backward must be 'scatter' or 'transposed'")
         A = pattern.with_values(values)
         y = spmv(A, x, schedule)
         ctx.save_for_backward(values, x)
         ctx.pattern = pattern
+        ctx.backward_kind = backward
         return y
 
     @staticmethod
@@ -214,16 +254,18 @@ class SpMV(torch.autograd.Function):
         values, x = ctx.saved_tensors
         A = ctx.pattern.with_values(values)
         need_dv, need_dx = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
-        dx, dv = spmv_backward(A, x, dy, need_dx=need_dx, need_dvalues=need_dv)
+        tr = transpose_pattern(ctx.pattern) if ctx.backward_kind == "transposed" and need_dx else None
+        dx, dv = spmv_backward(A, x, dy, need_dx=need_dx, need_dvalues=need_dv, transposed=tr)
         if dv is not None and dv.dtype != values.dtype:
             dv = dv.to(values.dtype)
         if dx is not None and dx.dtype != x.dtype:
             dx = dx.to(x.dtype)
-        return dv, dx, None, None
+        return dv, dx, None, None, None
 
 
-def spmv_diff(pattern: Pattern, values: torch.Tensor, x: torch.Tensor, schedule="merge_path") -> torch.Tensor:
-    return SpMV.apply(values, x, pattern, schedule)
+def spmv_diff(pattern: Pattern, values: torch.Tensor, x: torch.Tensor, schedule="merge_path",
+              backward="scatter") -> torch.Tensor:
+    return SpMV.apply(values, x, pattern, schedule, backward)
 
 
 class Batch:

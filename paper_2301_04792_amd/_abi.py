@@ -101,6 +101,10 @@ SIGNATURES = {
     "lb_batched_autotune": (ST, [PBATCH, P, ST, I32, P, P, SZ, PSCHED, P]),
     "lb_autotune_clear": (None, []),
     "lb_validate_csr": (ST, [PCSR, P]),
+    "lb_transpose_workspace_size": (ST, [PCSR, ctypes.POINTER(SZ)]),
+    "lb_transpose_pattern": (ST, [PCSR, P, P, P, P, SZ, P]),
+    "lb_backward_transposed_workspace_size": (ST, [PCSR, PSCHED, ctypes.POINTER(SZ)]),
+    "lb_spmv_backward_transposed": (ST, [PCSR, P, P, P, P, ST, P, P, P, PSCHED, P, SZ, P]),
     "lb_coo_workspace_size": (ST, [PCOO, PSCHED, ctypes.POINTER(SZ)]),
     "lb_spmv_coo": (ST, [PCOO, P, ST, P, PSCHED, P, SZ, P]),
     "lb_coo_merge_path_partition": (ST, [P, I64, I64, I64, I64, P, P, P]),

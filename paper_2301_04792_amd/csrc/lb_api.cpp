@@ -507,6 +507,69 @@ LB_API lb_status_t lb_spmv(const lb_csr_t *A, const void *x, lb_dtype_t x_dtype,
     }
 }
 
+LB_API lb_status_t lb_transpose_workspace_size(const lb_csr_t *A, size_t *bytes) {
+    if (!bytes) return LB_ERR_INVALID_ARG;
+    const lb_status_t st = check_csr(A);
+    if (st != LB_OK) return st;
+    if (A->cols + A->nnz > kMaxCoord) return LB_ERR_OVERFLOW;
+    *bytes = lbk::transpose_ws_bytes(A->cols, A->nnz);
+    return LB_OK;
+}
+
+LB_API lb_status_t lb_transpose_pattern(const lb_csr_t *A, int32_t *at_row_offsets, int32_t *at_col_idx,
+                                        int32_t *perm, void *workspace, size_t workspace_bytes, void *stream) {
+    size_t need = 0;
+    const lb_status_t st = lb_transpose_workspace_size(A, &need);
+    if (st != LB_OK) return st;
+    if (!at_row_offsets || (A->nnz > 0 && (!at_col_idx || !perm))) return LB_ERR_INVALID_ARG;
+    if (!workspace || workspace_bytes < need) return LB_ERR_WORKSPACE_TOO_SMALL;
+    return hip_status(lbk::transpose_pattern(to_dev(A), at_row_offsets, at_col_idx, perm, workspace,
+                                             static_cast<hipStream_t>(stream)));
+}
+
+lb_status_t backward_transposed_schedule(const lb_schedule_t *s, lb_schedule_t *out) {
+    lb_schedule_t in = s ? *s : lb_schedule_t{LB_MERGE_PATH, 0, 0, 0, 0, 0};
+    if (in.kind == LB_AUTO) in.kind = LB_MERGE_PATH;
+    if (in.kind != LB_MERGE_PATH) return LB_ERR_UNSUPPORTED;
+    return fill_defaults(&in, out);
+}
+
+LB_API lb_status_t lb_backward_transposed_workspace_size(const lb_csr_t *A, const lb_schedule_t *s, size_t *bytes) {
+    if (!bytes) return LB_ERR_INVALID_ARG;
+    lb_status_t st = check_csr(A);
+    if (st != LB_OK) return st;
+    if (A->cols + A->nnz > kMaxCoord) return LB_ERR_OVERFLOW;
+    lb_schedule_t r;
+    st = backward_transposed_schedule(s, &r);
+    if (st != LB_OK) return st;
+    *bytes = lbk::backward_transposed_ws_bytes(A->rows, A->cols, A->nnz, r.block_size, r.items_per_thread);
+    return LB_OK;
+}
+
+LB_API lb_status_t lb_spmv_backward_transposed(const lb_csr_t *A, const int32_t *at_row_offsets,
+                                               const int32_t *at_col_idx, const int32_t *perm, const void *x,
+                                               lb_dtype_t x_dtype, const float *dy, float *dx, float *dvalues,
+                                               const lb_schedule_t *s, void *workspace, size_t workspace_bytes,
+                                               void *stream) {
+    size_t need = 0;
+    lb_status_t st = lb_backward_transposed_workspace_size(A, s, &need);
+    if (st != LB_OK) return st;
+    if (x_dtype != A->value_dtype) return LB_ERR_UNSUPPORTED;
+    if (A->rows > 0 && A->nnz > 0 && !dy && (dx || dvalues)) return LB_ERR_INVALID_ARG;
+    if (dvalues && A->nnz > 0 && !x) return LB_ERR_INVALID_ARG;
+    if (dx && (!at_row_offsets || (A->nnz > 0 && (!at_col_idx || !perm)))) return LB_ERR_INVALID_ARG;
+    if (!workspace || workspace_bytes < need) return LB_ERR_WORKSPACE_TOO_SMALL;
+    lb_schedule_t r;
+    (void)backward_transposed_schedule(s, &r);
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    if (A->nnz == 0 || A->rows == 0) {  // no entries: dx = 0, no dvalues
+        if (dx && A->cols > 0) return hip_status(lbk::fill_f32(dx, A->cols, 0.f, hs));
+        return LB_OK;
+    }
+    return hip_status(lbk::backward_transposed(to_dev(A), at_row_offsets, at_col_idx, perm, x, dy, dx, dvalues,
+                                               r.block_size, r.items_per_thread, workspace, hs));
+}
+
 LB_API lb_status_t lb_coo_workspace_size(const lb_coo_t *A, const lb_schedule_t *s, size_t *bytes) {
     if (!bytes) return LB_ERR_INVALID_ARG;
     lb_status_t st = check_coo(A);

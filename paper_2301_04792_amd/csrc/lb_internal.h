@@ -122,6 +122,18 @@ hipError_t group_mapped_spmv(const csr_dev &A, const void *x, float *y, int grou
                              int tiles_per_group, int grid, int32_t *ticket, hipStream_t s);
 hipError_t group_tile_owner(const csr_dev &A, int tiles_per_group, int32_t *owner, hipStream_t s);
 
+// ---- transposed backward (k_transpose.hip) ------------------------------------------------
+// Workspace of transpose_pattern (ranks and scan tile sums).
+size_t transpose_ws_bytes(int64_t cols, int64_t nnz);
+// A^T's offsets (cols + 1), column indices (= rows of A) and the A entry of each A^T entry.
+hipError_t transpose_pattern(const csr_dev &A, int32_t *at_ro, int32_t *at_ci, int32_t *perm, void *ws,
+                             hipStream_t s);
+size_t backward_transposed_ws_bytes(int64_t rows, int64_t cols, int64_t nnz, int block, int items);
+// dvalues (dvalues-only merge pass over A) and dx = A^T dy (values permuted to float32, merge-path SpMV on A^T).
+hipError_t backward_transposed(const csr_dev &A, const int32_t *at_ro, const int32_t *at_ci, const int32_t *perm,
+                               const void *x, const float *dy, float *dx, float *dvalues, int block, int items,
+                               void *ws, hipStream_t s);
+
 // ---- COO and CSC ---------------------------------------------------------------------------
 // A row-sorted COO matrix: row_idx[nnz] non-decreasing, col_idx[nnz], values[nnz].
 struct coo_dev {

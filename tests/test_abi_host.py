@@ -275,3 +275,28 @@ def test_work_queue_host_checks():
     assert L.lb_coo_workspace_size(ctypes.byref(coo), ctypes.byref(s), ctypes.byref(n)) == _abi.ERR_UNSUPPORTED
     assert L.lb_spmv(ctypes.byref(A), FAKE, _abi.F32, FAKE, ctypes.byref(s), FAKE, 255, None) \
         == _abi.ERR_WORKSPACE_TOO_SMALL
+
+
+def test_transposed_backward_host_checks():
+    L = _abi.load()
+    A = csr(1000, 800, 5000)
+    n = ctypes.c_size_t(0)
+    assert L.lb_transpose_workspace_size(ctypes.byref(A), ctypes.byref(n)) == _abi.OK and n.value >= 5000 * 4
+    tneed = n.value
+    assert L.lb_transpose_workspace_size(ctypes.byref(csr(10, 2**31 - 100, 200)), ctypes.byref(n)) == _abi.ERR_OVERFLOW
+    assert L.lb_transpose_pattern(ctypes.byref(A), FAKE, FAKE, FAKE, FAKE, tneed - 1, None) \
+        == _abi.ERR_WORKSPACE_TOO_SMALL
+    assert L.lb_transpose_pattern(ctypes.byref(A), 0, FAKE, FAKE, FAKE, tneed, None) == _abi.ERR_INVALID_ARG
+    s = sched("merge_path")
+    assert L.lb_backward_transposed_workspace_size(ctypes.byref(A), ctypes.byref(s), ctypes.byref(n)) == _abi.OK
+    need = n.value
+    assert L.lb_backward_transposed_workspace_size(ctypes.byref(A), ctypes.byref(sched("thread_mapped")),
+                                                   ctypes.byref(n)) == _abi.ERR_UNSUPPORTED
+
+    def bwd(dx=FAKE, at=FAKE, wsb=need, dt=_abi.F32):
+        return L.lb_spmv_backward_transposed(ctypes.byref(A), at, FAKE, FAKE, FAKE, dt, FAKE, dx, FAKE,
+                                             ctypes.byref(s), FAKE, wsb, None)
+
+    assert bwd(wsb=need - 1) == _abi.ERR_WORKSPACE_TOO_SMALL
+    assert bwd(at=0) == _abi.ERR_INVALID_ARG  # dx needs the transposed pattern
+    assert bwd(dt=_abi.BF16) == _abi.ERR_UNSUPPORTED

@@ -322,3 +322,73 @@ def test_work_queue_equals_static_rounds(g, grid):
         assert torch.equal(yq, ys), (name, g, grid)
         yq2 = lb.spmv(Ad, xd, "work_queue", group_size=g, grid_size=grid)  # reused workspace: counter re-zeroed
         assert torch.equal(yq, yq2), (name, g, grid)
+
+
+def _transpose_cases():
+    out = {"c1": S.config_c1()[0], "powerlaw": S.powerlaw_csr(37, 30_000, 20_000, 1.5, 8000, 0.2)[0]}
+    out.update({k: v[0] for k, v in S.special_matrices().items() if k != "m0"})
+    return out
+
+
+@pytest.mark.parametrize("name", sorted(_transpose_cases().keys()))
+def test_transpose_pattern(name):
+    A = _transpose_cases()[name]
+    Ad = lb.CSR.from_host(A, DEV)
+    at_ro, at_ci, perm = [t.cpu().numpy() for t in lb.transpose_pattern(Ad.pattern)]
+    nnz = A.nnz
+    at_ci, perm = at_ci[:nnz], perm[:nnz]
+    counts = np.bincount(A.col_idx, minlength=A.n)
+    assert np.array_equal(np.diff(at_ro.astype(np.int64)), counts) and at_ro[0] == 0
+    assert np.array_equal(np.sort(perm), np.arange(nnz))  # a permutation of A's entries
+    rows = np.repeat(np.arange(A.m), np.diff(A.row_offsets.astype(np.int64)))
+    at_row = np.repeat(np.arange(A.n), counts)
+    assert np.array_equal(A.col_idx[perm], at_row)  # entry p of A^T lies in A^T row col(perm[p])
+    assert np.array_equal(rows[perm], at_ci)  # and its column is the row of that A entry
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_backward_transposed(dtype):
+    for name, (A, x) in {"c1": S.config_c1(), "powerlaw": S.powerlaw_csr(38, 20_000, 15_000, 1.5, 6000, 0.2),
+                         **{k: v for k, v in S.special_matrices().items() if k != "m0"}}.items():
+        if dtype == "bf16":
+            A = A.with_values(S.to_bf16_bits(A.values))
+            x = S.to_bf16_bits(x)
+        Ad, xd = upload(A, x)
+        dy = S.random_vector(39, A.m)
+        dyd = torch.from_numpy(dy).to(DEV)
+        tr = lb.transpose_pattern(Ad.pattern)
+        for params in ({}, {"block_size": 512, "items_per_thread": 16}):
+            dx, dv = lb.spmv_backward(Ad, xd, dyd, transposed=tr, **params)
+            ref = oracle.spmv_transpose(A.row_offsets, A.col_idx, A.values, dy, A.n)
+            scale = oracle.spmv_transpose(A.row_offsets, A.col_idx, A.values, dy, A.n, abs_terms=True)
+            assert_rows_close(dx.cpu().numpy(), ref, scale, what=f"transposed dx {name} {dtype} {params}")
+            dref = oracle.dvalues(A.row_offsets, A.col_idx, dy.astype(np.float64), x)
+            assert np.array_equal(dv.cpu().numpy(), dref.astype(np.float32)), (name, dtype)
+            dx2, _ = lb.spmv_backward(Ad, xd, dyd, transposed=tr, need_dvalues=False, **params)
+            assert torch.equal(dx, dx2), name  # no atomics: reproducible for one transpose build
+
+
+def test_backward_transposed_integer_and_autograd():
+    A, _ = S.powerlaw_csr(40, 30_000, 30_000, 1.4, 20_000, 0.2)
+    Ai, xi = S.integer_valued(A, 8)
+    dy = S.integer_valued(A, 9)[1].astype(np.float32)  # square: one entry per row
+    Ad, xd = upload(Ai, xi)
+    tr = lb.transpose_pattern(Ad.pattern)
+    dx, _ = lb.spmv_backward(Ad, xd, torch.from_numpy(dy).to(DEV), transposed=tr)
+    exact = oracle.spmv_transpose(Ai.row_offsets, Ai.col_idx, Ai.values, dy.astype(np.float64), Ai.n)
+    assert np.array_equal(dx.cpu().numpy().astype(np.float64), exact)
+    B, x = S.config_c1()
+    Bd, xbd = upload(B, x)
+    vals = Bd.values.clone().requires_grad_(True)
+    xg = xbd.clone().requires_grad_(True)
+    w = torch.from_numpy(S.random_vector(41, B.m)).to(DEV)
+    (lb.spmv_diff(Bd.pattern, vals, xg, "merge_path", "transposed") * w).sum().backward()
+    gv_t, gx_t = vals.grad.clone(), xg.grad.clone()
+    vals.grad = None
+    xg.grad = None
+    (lb.spmv_diff(Bd.pattern, vals, xg, "merge_path", "scatter") * w).sum().backward()
+    assert torch.equal(vals.grad, gv_t)  # dvalues: one product each, identical
+    ref = oracle.spmv_transpose(B.row_offsets, B.col_idx, B.values, w.cpu().numpy().astype(np.float64), B.n)
+    scale = oracle.spmv_transpose(B.row_offsets, B.col_idx, B.values, w.cpu().numpy().astype(np.float64), B.n,
+                                  abs_terms=True)
+    assert_rows_close(gx_t.cpu().numpy(), ref, scale, what="autograd transposed dx")
