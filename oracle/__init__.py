@@ -20,6 +20,8 @@ Functions and the passages they follow (Osama, Porumbescu, Owens, PPoPP'23):
   batched_spmm    -- one spmm per matrix of a batch
   spmv_coo        -- y = A x with A given as row-sorted (row, col, value) triples
   spmv_csc        -- y = A x with A given column by column (Sec. 3.1 formats)
+  spgemm          -- C = A B (Gustavson, Sec. 5.3 extension): every column a
+                     product reaches, ascending, values summed in double
   sssp            -- Sec. 5.3, the SSSP example on the same tile sets: float32
                      distances, least fixed point of
                      dist[v] = min over edges of fl(dist[u] + w)  (Dijkstra)
@@ -79,10 +81,12 @@ def _bind(lib):
     lib.orc_num_threads.argtypes = []
     lib.orc_sssp.argtypes = [I64, P, P, P, I64, P]
     lib.orc_spmv_coo.argtypes = [I64, I64, P, P, P, INT, P, INT, INT, P]
+    lib.orc_spgemm_count.argtypes = [I64, I64, P, P, P, P, P]
+    lib.orc_spgemm_compute.argtypes = [I64, I64, P, P, P, INT, P, P, P, INT, P, INT, P, P]
     lib.orc_spmv_csc.argtypes = [I64, I64, P, P, P, INT, P, INT, INT, P]
     lib.orc_bfs.argtypes = [I64, P, P, I64, P]
     for f in ("orc_spmv", "orc_spmm", "orc_spmv_transpose", "orc_dvalues", "orc_merge_walk", "orc_num_threads",
-              "orc_sssp", "orc_bfs", "orc_spmv_coo", "orc_spmv_csc"):
+              "orc_sssp", "orc_bfs", "orc_spmv_coo", "orc_spmv_csc", "orc_spgemm_count", "orc_spgemm_compute"):
         getattr(lib, f).restype = INT
     return lib
 
@@ -183,6 +187,25 @@ class Oracle:
             raise ValueError("orc_spmv_csc rejected its arguments")
         return y
 
+    def spgemm(self, A, B, abs_terms=False):
+        """C = A B for host CSRs A (m x k) and B (k x n): (row_offsets int64,
+        col_idx int32, values float64)."""
+        ar, ac, av = _c(A.row_offsets, np.int32), _c(A.col_idx, np.int32), _c(A.values)
+        br, bc, bv = _c(B.row_offsets, np.int32), _c(B.col_idx, np.int32), _c(B.values)
+        m, n = A.shape[0], B.shape[1]
+        cro = np.empty(m + 1, dtype=np.int64)
+        if self.lib.orc_spgemm_count(m, n, _ptr(ar), _ptr(ac), _ptr(br), _ptr(bc), _ptr(cro)):
+            raise ValueError("orc_spgemm_count rejected its arguments")
+        cci = np.empty(max(int(cro[-1]), 1), dtype=np.int32)
+        cv = np.empty(max(int(cro[-1]), 1), dtype=np.float64)
+        rc = self.lib.orc_spgemm_compute(m, n, _ptr(ar), _ptr(ac), _ptr(av), _dtype_code(av), _ptr(br), _ptr(bc),
+                                         _ptr(bv), _dtype_code(bv), _ptr(cro), int(bool(abs_terms)), _ptr(cci),
+                                         _ptr(cv))
+        if rc:
+            raise ValueError(f"orc_spgemm_compute rejected its arguments ({rc})")
+        nnz = int(cro[-1])
+        return cro, cci[:nnz], cv[:nnz]
+
     def sssp(self, row_offsets, col_idx, weights, source):
         """float32 distances from ``source`` (+inf where unreachable)."""
         ro, ci, w = _c(row_offsets, np.int32), _c(col_idx, np.int32), _c(weights, np.float32)
@@ -261,6 +284,10 @@ def spmv_coo(m, row_idx, col_idx, values, x, abs_terms=False):
 
 def spmv_csc(m, col_offsets, row_idx, values, x, abs_terms=False):
     return default().spmv_csc(m, col_offsets, row_idx, values, x, abs_terms)
+
+
+def spgemm(A, B, abs_terms=False):
+    return default().spgemm(A, B, abs_terms)
 
 
 def sssp(row_offsets, col_idx, weights, source):

@@ -21,6 +21,9 @@
  *     dvalues[j] = dy[row(j)] * x[col_idx[j]].
  *   - COO and CSC SpMV (Sec. 3.1 names both among the library's formats):
  *     the same y = A x, the matrix given per entry (COO) or per column (CSC).
+ *   - SpGEMM C = A B (Gustavson; Sec. 5.3 names it as an extension):
+ *     structural union of each row's products, columns ascending, values in
+ *     double.
  *   - SSSP (Sec. 5.3, the graph example) and BFS (named in Sec. 6) on the
  *     same tile sets: vertices are tiles, out-edges are atoms.  Distances
  *     are float32 as in the paper's example; see orc_sssp.
@@ -321,5 +324,107 @@ int orc_spmv_csc(int64_t m, int64_t n, const int32_t *col_offsets, const int32_t
             y[row_idx[j]] += abs_terms ? (t < 0 ? -t : t) : t;
         }
     }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Sparse matrix-matrix product C = A B (Gustavson; Sec. 5.3 names it as an
+ * extension: size each output row, allocate, multiply).  A is m x k, B is
+ * k x n, both CSR.  Row i of C holds every column c reached by a product
+ * A[i, j] * B[j, c] (structurally, even when the sum is 0), in ascending
+ * order, with value sum over j of A[i, j] * B[j, c] in double (products in
+ * ascending A entry, then ascending B entry).  Dense accumulator per row.
+ * ------------------------------------------------------------------------ */
+
+static int orc_cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* Pass 1: c_row_offsets[m + 1] (entries per row, prefix-summed). */
+int orc_spgemm_count(int64_t m, int64_t n, const int32_t *a_ro, const int32_t *a_ci,
+                     const int32_t *b_ro, const int32_t *b_ci, int64_t *c_ro)
+{
+    if (m < 0 || n < 0) return 1;
+    unsigned char *seen = (unsigned char *)calloc((size_t)(n > 0 ? n : 1), 1);
+    int32_t *list = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof *list);
+    if (!seen || !list) {
+        free(seen);
+        free(list);
+        return 3;
+    }
+    c_ro[0] = 0;
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t cnt = 0;
+        for (int64_t e = a_ro[i]; e < a_ro[i + 1]; ++e) {
+            int32_t j = a_ci[e];
+            for (int64_t f = b_ro[j]; f < b_ro[j + 1]; ++f) {
+                int32_t c = b_ci[f];
+                if (!seen[c]) {
+                    seen[c] = 1;
+                    list[cnt++] = c;
+                }
+            }
+        }
+        for (int64_t t = 0; t < cnt; ++t) seen[list[t]] = 0;
+        c_ro[i + 1] = c_ro[i] + cnt;
+    }
+    free(seen);
+    free(list);
+    return 0;
+}
+
+/* Pass 2: columns (ascending) and values of every row; c_ro from pass 1.
+ * With abs_terms, the values are sums of |A[i, j] * B[j, c]| (the scale of
+ * the tolerance). */
+int orc_spgemm_compute(int64_t m, int64_t n, const int32_t *a_ro, const int32_t *a_ci,
+                       const void *a_val, int adt, const int32_t *b_ro, const int32_t *b_ci,
+                       const void *b_val, int bdt, const int64_t *c_ro, int abs_terms,
+                       int32_t *c_ci, double *c_val)
+{
+    if (m < 0 || n < 0 || !orc_dtype_ok(adt) || !orc_dtype_ok(bdt)) return 1;
+    double *acc = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof *acc);
+    unsigned char *seen = (unsigned char *)calloc((size_t)(n > 0 ? n : 1), 1);
+    if (!acc || !seen) {
+        free(acc);
+        free(seen);
+        return 3;
+    }
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t cnt = 0;
+        int32_t *cols = c_ci + c_ro[i];
+        for (int64_t e = a_ro[i]; e < a_ro[i + 1]; ++e) {
+            int32_t j = a_ci[e];
+            double a = orc_load(a_val, adt, e);
+            for (int64_t f = b_ro[j]; f < b_ro[j + 1]; ++f) {
+                int32_t c = b_ci[f];
+                double t = a * orc_load(b_val, bdt, f);
+                acc[c] += abs_terms ? (t < 0 ? -t : t) : t;
+                if (!seen[c]) {
+                    seen[c] = 1;
+                    if (c_ro[i] + cnt >= c_ro[i + 1]) {
+                        free(acc);
+                        free(seen);
+                        return 4; /* c_ro does not match the product */
+                    }
+                    cols[cnt++] = c;
+                }
+            }
+        }
+        if (c_ro[i] + cnt != c_ro[i + 1]) {
+            free(acc);
+            free(seen);
+            return 4;
+        }
+        qsort(cols, (size_t)cnt, sizeof *cols, orc_cmp_i32);
+        for (int64_t t = 0; t < cnt; ++t) {
+            c_val[c_ro[i] + t] = acc[cols[t]];
+            acc[cols[t]] = 0.0;
+            seen[cols[t]] = 0;
+        }
+    }
+    free(acc);
+    free(seen);
     return 0;
 }

@@ -613,4 +613,108 @@ def pin_coo_csc_integer_exact(orc):
     assert np.array_equal(orc.spmv_csc(Ai.m, K.col_offsets, K.row_idx, K.values, xi), exact)
 
 
+# --------------------------------------------------------------------------- SpGEMM
+
+def _spgemm_cases():
+    from synthetic import CSRHost, special_matrices
+
+    out = []
+    for seed, (m, k, n, la, lb) in enumerate([(30, 20, 25, 5, 6), (64, 64, 64, 12, 12), (7, 90, 3, 40, 2),
+                                              (200, 150, 300, 8, 10), (1, 40, 40, 40, 40)]):
+        A, _ = uniform_csr(500 + seed, m, k, la)
+        B, _ = uniform_csr(600 + seed, k, n, lb)
+        out.append((A, B))
+    P, _ = powerlaw_csr(610, 800, 800, 1.6, 400, 0.3)
+    out.append((P, P))
+    E = special_matrices()["leading_empty"][0]  # 7 x 12
+    out.append((E, uniform_csr(611, 12, 9, 4)[0]))
+    Z = CSRHost(np.zeros(6, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32), (5, 8))
+    out.append((Z, uniform_csr(612, 8, 8, 3)[0]))
+    return out
+
+
+def _sp(A, ones=False):
+    import scipy.sparse as sp
+
+    data = np.ones(A.nnz, np.int64) if ones else A.values.astype(np.float64)
+    return sp.csr_matrix((data, A.col_idx, A.row_offsets), shape=A.shape)
+
+
+def pin_spgemm_structure_and_values_vs_scipy(orc):
+    """Structure = scipy's product of the 0/1 patterns (an entry wherever a
+    product exists); values = scipy's float64 product (which drops exact
+    zeros: those entries must be 0 here)."""
+    for A, B in _spgemm_cases():
+        cro, cci, cv = orc.spgemm(A, B)
+        S = (_sp(A, True) @ _sp(B, True)).tocsr()
+        S.sort_indices()
+        assert np.array_equal(cro, S.indptr.astype(np.int64)) and np.array_equal(cci, S.indices), A.shape
+        V = (_sp(A) @ _sp(B)).tocsr()
+        if cro[-1] == 0:
+            assert V.nnz == 0
+            continue
+        dense_rows = np.repeat(np.arange(A.shape[0]), np.diff(cro))
+        ref = np.asarray(V[dense_rows, cci]).ravel()
+        scale = orc.spgemm(A, B, abs_terms=True)[2]
+        _close(cv, ref, scale, what="spgemm vs scipy")
+
+
+def pin_spgemm_dense_tiny(orc):
+    """Scattered into a dense matrix, C equals the dense float64 product."""
+    for A, B in _spgemm_cases():
+        if A.shape[0] * B.shape[1] > 40_000:
+            continue
+        cro, cci, cv = orc.spgemm(A, B)
+        C = np.zeros((A.shape[0], B.shape[1]))
+        rows = np.repeat(np.arange(A.shape[0]), np.diff(cro))
+        C[rows, cci] = cv
+        D = _dense(A) @ _dense(B)
+        _close(C, D, np.abs(_dense(A)) @ np.abs(_dense(B)), what="spgemm vs dense")
+
+
+def pin_spgemm_identity(orc):
+    """A I = A and I A = A exactly (one product per entry)."""
+    from synthetic import CSRHost
+
+    for A, _ in _spgemm_cases()[:4]:
+        for side in ("right", "left"):
+            k = A.shape[1] if side == "right" else A.shape[0]
+            I = CSRHost(np.arange(k + 1, dtype=np.int32), np.arange(k, dtype=np.int32), np.ones(k, np.float32),
+                        (k, k))
+            cro, cci, cv = orc.spgemm(A, I) if side == "right" else orc.spgemm(I, A)
+            assert np.array_equal(cro, A.row_offsets.astype(np.int64)) and np.array_equal(cci, A.col_idx)
+            assert np.array_equal(cv, A.values.astype(np.float64))
+
+
+def pin_spgemm_associates_with_spmv(orc):
+    """(A B) x = A (B x), each side through the (separately pinned) SpMV oracle."""
+    from synthetic import CSRHost
+
+    rng = np.random.default_rng(613)
+    for A, B in _spgemm_cases():
+        cro, cci, cv = orc.spgemm(A, B)
+        x = rng.uniform(-1, 1, B.shape[1])
+        C = CSRHost(cro.astype(np.int32), cci, cv, (A.shape[0], B.shape[1]))
+        lhs = orc.spmv(C.row_offsets, C.col_idx, C.values, x)
+        bx = orc.spmv(B.row_offsets, B.col_idx, B.values, x)
+        rhs = orc.spmv(A.row_offsets, A.col_idx, A.values, bx)
+        scale = np.abs(_dense(A)) @ (np.abs(_dense(B)) @ np.abs(x)) if A.shape[0] * B.shape[1] <= 40_000 else None
+        if scale is not None:
+            _close(lhs, rhs, scale, rtol=1e-12, what="spgemm associativity")
+
+
+def pin_spgemm_integer_exact(orc):
+    """Integer values: the sums are exact, equal to the dense integer product."""
+    A, _ = powerlaw_csr(614, 300, 300, 1.5, 120, 0.2)
+    Ai, _ = integer_valued(A, 15)
+    Bi, _ = integer_valued(A, 16)
+    cro, cci, cv = orc.spgemm(Ai, Bi)
+    D = _dense(Ai) @ _dense(Bi)
+    rows = np.repeat(np.arange(300), np.diff(cro))
+    assert np.array_equal(cv, D[rows, cci])
+    C = np.zeros_like(D)
+    C[rows, cci] = cv
+    assert np.array_equal(C, D)
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

@@ -34,6 +34,10 @@ MUTANTS = [
     ("coo_wrong_row", "        y[row_idx[j]] += abs_terms ? (t < 0 ? -t : t) : t;\n    }\n    return 0;\n}\n\n/* CSC",
      "        y[row_idx[j] > 0 && (j & 1) ? row_idx[j] - 1 : row_idx[j]] += abs_terms ? (t < 0 ? -t : t) : t;\n    }\n    return 0;\n}\n\n/* CSC"),
     ("csc_wrong_x", "double xc = orc_load(x, xdt, c);", "double xc = orc_load(x, xdt, c > 0 && (c & 1) ? c - 1 : c);"),
+    ("spgemm_wrong_b_entry", "double t = a * orc_load(b_val, bdt, f);", "double t = a * orc_load(b_val, bdt, f > b_ro[j] ? f - 1 : f);"),
+    ("spgemm_skips_first_column", "                int32_t c = b_ci[f];\n                if (!seen[c]) {\n                    seen[c] = 1;\n                    list[cnt++] = c;",
+     "                int32_t c = b_ci[f];\n                if (f == b_ro[j] && j == 0) continue;\n                if (!seen[c]) {\n                    seen[c] = 1;\n                    list[cnt++] = c;"),
+    ("spgemm_unsorted", "        qsort(cols, (size_t)cnt, sizeof *cols, orc_cmp_i32);", "        (void)orc_cmp_i32;"),
     ("bf16_shift", "uint32_t bits = (uint32_t)((const uint16_t *)p)[i] << 16;", "uint32_t bits = (uint32_t)((const uint16_t *)p)[i] << 15;"),
 ]
 
