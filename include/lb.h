@@ -328,6 +328,28 @@ LB_API lb_status_t lb_spmv_csc(const lb_csc_t *A, const void *x, lb_dtype_t x_dt
                                const lb_schedule_t *s, void *workspace, size_t workspace_bytes,
                                void *stream);
 
+/* ---- Sparse matrix-matrix product C = A B (Gustavson; Sec. 5.3 names it as
+ * the extension of SpMM: a kernel sizing each output row, an allocation, a
+ * multiply kernel).  A is rows x cols, B is A->cols x n (B->rows must equal
+ * A->cols), both float32.  Row i of C holds every column reached by a
+ * product A[i, j] * B[j, c], ascending (structural: kept even if the sum is
+ * 0), with value sum_j A[i, j] * B[j, c] in float32.  Rows are accumulated
+ * by product count: up to 256 products one wavefront, up to 4096 one block
+ * (both sort (column, product index) in LDS and sum in product order:
+ * deterministic), beyond that a dense slot per block of a work queue (float
+ * atomics: summation order varies run to run).
+ * lb_spgemm_count (synchronizing) writes C's row offsets (A->rows + 1,
+ * device) and *c_nnz (host); the caller allocates col_idx and values of
+ * *c_nnz entries; lb_spgemm_compute fills them.  Both take the workspace of
+ * lb_spgemm_workspace_size (contents on entry irrelevant).  nnz(C) must fit
+ * int32 (else LB_ERR_OVERFLOW from the count). */
+LB_API lb_status_t lb_spgemm_workspace_size(const lb_csr_t *A, const lb_csr_t *B, size_t *bytes);
+LB_API lb_status_t lb_spgemm_count(const lb_csr_t *A, const lb_csr_t *B, int32_t *c_row_offsets, int64_t *c_nnz,
+                                   void *workspace, size_t workspace_bytes, void *stream);
+LB_API lb_status_t lb_spgemm_compute(const lb_csr_t *A, const lb_csr_t *B, const int32_t *c_row_offsets,
+                                     int32_t *c_col_idx, float *c_values, void *workspace, size_t workspace_bytes,
+                                     void *stream);
+
 /* ---- Graph traversal on the same schedules (Sec. 5.3 SSSP example; BFS,
  * named in Sec. 6).
  * The graph G is a square CSR read as adjacency: vertex u's out-edges are
@@ -402,6 +424,7 @@ LB_API int32_t lb_probe_default_grid(void);
  * "merge_consume", "merge_fixup", "thread_mapped", "group_mapped",
  * "backward", "batched_consume", "batched_fixup", "fill", "coo_partition",
  * "coo_consume", "coo_fixup", "coo_tiles", "transpose", "permute_values",
+ * "spgemm_products", "spgemm_count", "spgemm_compute",
  * "work_queue", "traversal_init",
  * "sssp_advance", "bfs_advance"), the summed
  * duration in milliseconds and the launch count since the last reset. */

@@ -30,7 +30,7 @@ _lib = _abi.load()
 __all__ = ["CSR", "Pattern", "Batch", "spmv", "spmm", "spmv_backward", "SpMV", "spmv_diff",
            "batched_spmm", "tune", "tune_batched", "merge_path_partition", "group_tile_owner",
            "sssp", "bfs", "traversal_workspace_size", "COO", "CSC", "spmv_coo", "spmv_csc",
-           "coo_merge_path_partition", "coo_workspace_size", "csc_workspace_size", "transpose_pattern",
+           "coo_merge_path_partition", "coo_workspace_size", "csc_workspace_size", "transpose_pattern", "spgemm",
            "validate", "resolve_schedule", "profile_enable", "profile_reset", "profile_read", "LBError"]
 
 _DT = {torch.float32: _abi.F32, torch.bfloat16: _abi.BF16, torch.float64: _abi.F64}
@@ -590,3 +590,27 @@ def spmv_csc(A: CSC, x: torch.Tensor, schedule="merge_path", y: torch.Tensor | N
     """y = A x for a CSC matrix (float32 x and y; float atomics: not bit-reproducible)."""
     return _format_spmv(_lib.lb_csc_workspace_size, _lib.lb_spmv_csc, "lb_spmv_csc", A, x, schedule, y, workspace,
                         params)
+
+
+# ---------------------------------------------------------------------------- SpGEMM
+
+def spgemm(A: CSR, B: CSR, workspace: torch.Tensor | None = None) -> CSR:
+    """C = A B (Gustavson): count each row's columns, allocate, multiply.
+    float32 inputs; C's columns ascending.  Synchronizes the current stream."""
+    if A.shape[1] != B.shape[0]:
+        raise ValueError("A.cols must equal B.rows")
+    a, b = A.c_struct(), B.c_struct()
+    n = ctypes.c_size_t(0)
+    _abi.check(_lib.lb_spgemm_workspace_size(ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)),
+               "lb_spgemm_workspace_size")
+    ws = _workspace(max(n.value, 1), A.device, workspace)
+    c_ro = torch.empty(A.shape[0] + 1, dtype=torch.int32, device=A.device)
+    nnz = ctypes.c_int64(0)
+    st = _stream(A.device)
+    _abi.check(_lib.lb_spgemm_count(ctypes.byref(a), ctypes.byref(b), _ptr(c_ro), ctypes.byref(nnz), _ptr(ws),
+                                    ws.numel(), st), "lb_spgemm_count")
+    c_ci = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=A.device)
+    c_val = torch.empty(max(nnz.value, 1), dtype=torch.float32, device=A.device)
+    _abi.check(_lib.lb_spgemm_compute(ctypes.byref(a), ctypes.byref(b), _ptr(c_ro), _ptr(c_ci), _ptr(c_val),
+                                      _ptr(ws), ws.numel(), st), "lb_spgemm_compute")
+    return CSR(c_ro, c_ci[:nnz.value], c_val[:nnz.value], (A.shape[0], B.shape[1]))

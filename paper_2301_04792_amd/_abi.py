@@ -105,6 +105,9 @@ SIGNATURES = {
     "lb_transpose_pattern": (ST, [PCSR, P, P, P, P, SZ, P]),
     "lb_backward_transposed_workspace_size": (ST, [PCSR, PSCHED, ctypes.POINTER(SZ)]),
     "lb_spmv_backward_transposed": (ST, [PCSR, P, P, P, P, ST, P, P, P, PSCHED, P, SZ, P]),
+    "lb_spgemm_workspace_size": (ST, [PCSR, PCSR, ctypes.POINTER(SZ)]),
+    "lb_spgemm_count": (ST, [PCSR, PCSR, P, ctypes.POINTER(I64), P, SZ, P]),
+    "lb_spgemm_compute": (ST, [PCSR, PCSR, P, P, P, P, SZ, P]),
     "lb_coo_workspace_size": (ST, [PCOO, PSCHED, ctypes.POINTER(SZ)]),
     "lb_spmv_coo": (ST, [PCOO, P, ST, P, PSCHED, P, SZ, P]),
     "lb_coo_merge_path_partition": (ST, [P, I64, I64, I64, I64, P, P, P]),

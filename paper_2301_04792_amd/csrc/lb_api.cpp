@@ -570,6 +570,58 @@ LB_API lb_status_t lb_spmv_backward_transposed(const lb_csr_t *A, const int32_t 
                                                r.block_size, r.items_per_thread, workspace, hs));
 }
 
+lb_status_t check_spgemm(const lb_csr_t *A, const lb_csr_t *B) {
+    lb_status_t st = check_csr(A);
+    if (st != LB_OK) return st;
+    st = check_csr(B);
+    if (st != LB_OK) return st;
+    if (B->rows != A->cols) return LB_ERR_INVALID_ARG;
+    if (A->value_dtype != LB_F32 || B->value_dtype != LB_F32) return LB_ERR_UNSUPPORTED;
+    return LB_OK;
+}
+
+lbk::spgemm_dev to_spgemm(const lb_csr_t *A, const lb_csr_t *B) {
+    return {static_cast<int32_t>(A->rows), static_cast<int32_t>(A->cols), static_cast<int32_t>(B->cols),
+            A->row_offsets, A->col_idx, static_cast<const float *>(A->values), B->row_offsets, B->col_idx,
+            static_cast<const float *>(B->values)};
+}
+
+LB_API lb_status_t lb_spgemm_workspace_size(const lb_csr_t *A, const lb_csr_t *B, size_t *bytes) {
+    if (!bytes) return LB_ERR_INVALID_ARG;
+    const lb_status_t st = check_spgemm(A, B);
+    if (st != LB_OK) return st;
+    *bytes = lbk::spgemm_ws_bytes(A->rows, B->cols);
+    return LB_OK;
+}
+
+LB_API lb_status_t lb_spgemm_count(const lb_csr_t *A, const lb_csr_t *B, int32_t *c_row_offsets, int64_t *c_nnz,
+                                   void *workspace, size_t workspace_bytes, void *stream) {
+    size_t need = 0;
+    lb_status_t st = lb_spgemm_workspace_size(A, B, &need);
+    if (st != LB_OK) return st;
+    if (!c_row_offsets || !c_nnz) return LB_ERR_INVALID_ARG;
+    if (!workspace || workspace_bytes < need) return LB_ERR_WORKSPACE_TOO_SMALL;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    int64_t total = 0;
+    const hipError_t e = lbk::spgemm_count(to_spgemm(A, B), c_row_offsets, &total, workspace, hs);
+    if (e != hipSuccess) return hip_status(e);
+    if (total > kMaxCoord) return LB_ERR_OVERFLOW;
+    *c_nnz = total;
+    return LB_OK;
+}
+
+LB_API lb_status_t lb_spgemm_compute(const lb_csr_t *A, const lb_csr_t *B, const int32_t *c_row_offsets,
+                                     int32_t *c_col_idx, float *c_values, void *workspace, size_t workspace_bytes,
+                                     void *stream) {
+    size_t need = 0;
+    lb_status_t st = lb_spgemm_workspace_size(A, B, &need);
+    if (st != LB_OK) return st;
+    if (!c_row_offsets || !c_col_idx || !c_values) return LB_ERR_INVALID_ARG;
+    if (!workspace || workspace_bytes < need) return LB_ERR_WORKSPACE_TOO_SMALL;
+    return hip_status(lbk::spgemm_compute(to_spgemm(A, B), c_row_offsets, c_col_idx, c_values, workspace,
+                                          static_cast<hipStream_t>(stream)));
+}
+
 LB_API lb_status_t lb_coo_workspace_size(const lb_coo_t *A, const lb_schedule_t *s, size_t *bytes) {
     if (!bytes) return LB_ERR_INVALID_ARG;
     lb_status_t st = check_coo(A);

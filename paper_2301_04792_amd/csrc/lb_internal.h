@@ -134,6 +134,23 @@ hipError_t backward_transposed(const csr_dev &A, const int32_t *at_ro, const int
                                const void *x, const float *dy, float *dx, float *dvalues, int block, int items,
                                void *ws, hipStream_t s);
 
+// ---- SpGEMM (k_spgemm.hip) ---------------------------------------------------------------
+// C = A B with A m x k and B k x n (float32 values).
+struct spgemm_dev {
+    int32_t m, k, n;
+    const int32_t *a_ro, *a_ci;
+    const float *a_val;
+    const int32_t *b_ro, *b_ci;
+    const float *b_val;
+};
+constexpr int kSpgemmSlots = 32;  // blocks of the large-row tier, each with a dense n-column slot
+size_t spgemm_ws_bytes(int64_t m, int64_t n);
+// Per-row column counts turned into C's row offsets (m + 1, int32 where the
+// total fits); *total_host receives nnz(C).  Synchronizes s.
+hipError_t spgemm_count(const spgemm_dev &P, int32_t *c_ro, int64_t *total_host, void *ws, hipStream_t s);
+hipError_t spgemm_compute(const spgemm_dev &P, const int32_t *c_ro, int32_t *c_ci, float *c_val, void *ws,
+                          hipStream_t s);
+
 // ---- COO and CSC ---------------------------------------------------------------------------
 // A row-sorted COO matrix: row_idx[nnz] non-decreasing, col_idx[nnz], values[nnz].
 struct coo_dev {

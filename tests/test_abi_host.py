@@ -300,3 +300,24 @@ def test_transposed_backward_host_checks():
     assert bwd(wsb=need - 1) == _abi.ERR_WORKSPACE_TOO_SMALL
     assert bwd(at=0) == _abi.ERR_INVALID_ARG  # dx needs the transposed pattern
     assert bwd(dt=_abi.BF16) == _abi.ERR_UNSUPPORTED
+
+
+def test_spgemm_host_checks():
+    L = _abi.load()
+    A, B = csr(100, 50, 400), csr(50, 70, 300)
+    n = ctypes.c_size_t(0)
+    assert L.lb_spgemm_workspace_size(ctypes.byref(A), ctypes.byref(B), ctypes.byref(n)) == _abi.OK
+    need = n.value
+    assert need > 0
+    assert L.lb_spgemm_workspace_size(ctypes.byref(A), ctypes.byref(csr(49, 70, 300)),
+                                      ctypes.byref(n)) == _abi.ERR_INVALID_ARG  # inner sizes differ
+    assert L.lb_spgemm_workspace_size(ctypes.byref(A), ctypes.byref(csr(50, 70, 300, dtype=_abi.BF16)),
+                                      ctypes.byref(n)) == _abi.ERR_UNSUPPORTED
+    nnz = ctypes.c_int64(0)
+    assert L.lb_spgemm_count(ctypes.byref(A), ctypes.byref(B), FAKE, ctypes.byref(nnz), FAKE, need - 1, None) \
+        == _abi.ERR_WORKSPACE_TOO_SMALL
+    assert L.lb_spgemm_count(ctypes.byref(A), ctypes.byref(B), 0, ctypes.byref(nnz), FAKE, need, None) \
+        == _abi.ERR_INVALID_ARG
+    assert L.lb_spgemm_count(ctypes.byref(A), ctypes.byref(B), FAKE, None, FAKE, need, None) == _abi.ERR_INVALID_ARG
+    assert L.lb_spgemm_compute(ctypes.byref(A), ctypes.byref(B), FAKE, 0, FAKE, FAKE, need, None) \
+        == _abi.ERR_INVALID_ARG
