@@ -11,7 +11,7 @@ back-to-back steps with the inputs already in HBM.
 The same JSON line carries the roofline of the dominant kernel (merge-path
 consume, timed by the library's HIP events on the launch stream), the FP64
 oracle timed on the host cores, and per-schedule, BF16, forward+backward,
-COO/CSC, batched and graph-traversal (SSSP, BFS) figures on the other workloads
+COO/CSC, batched, graph-traversal (SSSP, BFS) and SpGEMM figures on the other workloads
 (skip them with --quick).  Accuracy is asserted by the GPU tests, not here:
 the oracle runs in this script only as the timed CPU baseline.
 
@@ -574,6 +574,34 @@ def main():
     del Bd
 
     result["graph_powerlaw1M"] = run_graph(lb, S, dev, args.no_cpu)
+
+    # ------------------------------------------------------------ SpGEMM
+    gm = {"note": "ms per whole C = A A (count, allocation, compute); products = sum over A entries of B row lengths"}
+    for name, A in (("laplacian1024_squared", S.laplacian_5pt(3, 1024)[0]),
+                    ("powerlaw100k_cap2000_squared", S.powerlaw_csr(80, 100_000, 100_000, 1.8, 2000, 0.1)[0])):
+        Ad = lb.CSR.from_host(A, dev)
+        prods = int(np.diff(A.row_offsets.astype(np.int64))[A.col_idx].sum())
+        C = lb.spgemm(Ad, Ad)
+        ms = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            C = lb.spgemm(Ad, Ad)
+            torch.cuda.synchronize()
+            ms.append((time.perf_counter() - t0) * 1e3)
+        t = float(np.median(ms))
+        gm[name] = {"nnz_a": A.nnz, "products": prods, "nnz_c": C.nnz, "ms": round(t, 3),
+                    "gproducts_per_s": round(prods / (t * 1e-3) / 1e9, 3),
+                    "gflops": round(2 * prods / (t * 1e-3) / 1e9, 3)}
+        if not args.no_cpu:  # CPU baseline: the oracle, timed
+            import oracle
+
+            t0 = time.perf_counter()
+            oracle.spgemm(A, A)
+            gm[name]["cpu_oracle_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+        del Ad, C
+    result["spgemm"] = gm
+    log(f"[bench] spgemm: {gm}")
 
     print(json.dumps(result), flush=True)
     return 0
