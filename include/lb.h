@@ -424,7 +424,8 @@ LB_API int32_t lb_probe_default_grid(void);
  * "merge_consume", "merge_fixup", "thread_mapped", "group_mapped",
  * "backward", "batched_consume", "batched_fixup", "fill", "coo_partition",
  * "coo_consume", "coo_fixup", "coo_tiles", "transpose", "permute_values",
- * "spgemm_products", "spgemm_count", "spgemm_compute",
+ * "spgemm_products", "spgemm_count_t0" .. "spgemm_count_t3",
+ * "spgemm_compute_t0" .. "spgemm_compute_t3" (one per row tier),
  * "work_queue", "traversal_init",
  * "sssp_advance", "bfs_advance"), the summed
  * duration in milliseconds and the launch count since the last reset. */

@@ -7,12 +7,15 @@
 // of the selected B row, which ranges from a few to millions on power-law
 // inputs.  Rows are sorted into three tiers by p_i, each with its own
 // accumulator:
+//   tier 0 (p_i <= 32):    an 8-lane group per row, the same with a fixed
+//                           32-element network, eight rows per wavefront;
 //   tier 1 (p_i <= 256):   one wavefront per row; the products, keyed by
 //                           (column, product index), are bitonic-sorted in
 //                           the wavefront's LDS; equal columns are then
 //                           adjacent, in product order;
 //   tier 2 (p_i <= 4096):  one block per row, the same in block LDS;
-//   tier 3 (larger):       blocks of a work queue, each owning a slot of
+//   tier 3 (larger):       blocks of a work queue (32 to 512, as many as
+//                           1 GiB of slots holds), each owning a slot of
 //                           global memory with a dense float accumulator
 //                           and a two-level column bitmap; products are
 //                           enumerated by the group_mapped_scan schedule
@@ -32,6 +35,7 @@ using namespace lb;
 
 namespace {
 
+constexpr int kTier0 = 32;  // an 8-lane group per row, 8 rows per wavefront
 constexpr int kTier1 = 256;
 constexpr int kTier2 = 4096;
 constexpr int kBlock = 256;
@@ -45,8 +49,8 @@ struct gemm_args {
     const int32_t *b_ro, *b_ci;
     const float *b_val;
     const int64_t *prod;   // products per row
-    int32_t *lists;        // tier lists: [0, m) tier 1, [m, 2m) tier 2, [2m, 3m) tier 3
-    int32_t *list_len;     // 3 counters, then the tier-3 work-queue ticket
+    int32_t *lists;        // tier lists: [0, m) tier 1, [m, 2m) tier 2, [2m, 3m) tier 3, [3m, 4m) tier 0
+    int32_t *list_len;     // counters of tiers 1, 2, 3, the tier-3 work-queue ticket, the tier-0 counter
     int32_t *c_ro;         // count pass: per-row column counts; compute pass: C's row offsets
     int32_t *c_ci;
     float *c_val;
@@ -69,7 +73,8 @@ __device__ __forceinline__ int32_t next_pow2(int32_t v) {
 
 // ---------------------------------------------------------------- products per row and tiers
 
-__global__ __launch_bounds__(256) void gemm_products(gemm_args g, int64_t *__restrict__ prod) {
+// A wavefront per row of A (rows of eight or more entries on average).
+__global__ __launch_bounds__(256) void gemm_products_rows(gemm_args g, int64_t *__restrict__ prod) {
     const group_mapped<kWave, csr_tile_set> sch{{g.a_ro, g.m, 0}};
     for (int64_t i : sch.tiles()) {
         int64_t p = 0;
@@ -83,20 +88,62 @@ __global__ __launch_bounds__(256) void gemm_products(gemm_args g, int64_t *__res
     }
 }
 
+// For short rows: group_mapped_scan over A's rows: a wavefront takes 64 rows and strides
+// their flattened entries, so short and long rows share the lanes; each
+// step sums its entries' B row lengths per row (a segmented sum over the
+// lanes) into the rows' LDS counters (exact, int64).
+__global__ __launch_bounds__(256) void gemm_products(gemm_args g, int64_t *__restrict__ prod) {
+    using sched = group_mapped_scan<kWave, csr_tile_set>;
+    __shared__ typename sched::storage s_st[sched::GPB];
+    __shared__ unsigned long long s_cnt[sched::GPB][kWave];
+    const int gi = threadIdx.x / kWave, gl = lane_id();
+    sched sch(csr_tile_set{g.a_ro, g.m, 0}, s_st);
+    for (int64_t round : sch.rounds()) {  // uniform across the block
+        s_cnt[gi][gl] = 0;
+        const int32_t total = sch.load(round);  // ends with a barrier: the counters are clear
+        const int32_t steps = (total + kWave - 1) / kWave;
+        for (int32_t st = 0; st < steps; ++st) {  // uniform within the wavefront
+            const int32_t at = st * kWave + gl;
+            int32_t q = kWave;  // past the last row: inactive lane
+            unsigned long long v = 0;
+            if (at < total) {
+                q = sch.get_tile(at);
+                const int32_t j = g.a_ci[sch.atom(at, q)];
+                v = static_cast<unsigned long long>(g.b_ro[j + 1] - g.b_ro[j]);
+            }
+            // the step's atoms are in row order: sum each run of equal q over
+            // the lanes, then its last lane adds the run to the row's counter
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                const unsigned long long v2 = __shfl_up(v, off, kWave);
+                const int32_t q2 = __shfl_up(q, off, kWave);
+                if (gl >= off && q2 == q) v += v2;
+            }
+            const int32_t qn = __shfl_down(q, 1, kWave);
+            if (q < kWave && (gl == kWave - 1 || qn != q)) s_cnt[gi][q] += v;
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+        const int64_t i = (round + gi) * kWave + gl;
+        if (i < g.m) prod[i] = static_cast<int64_t>(s_cnt[gi][gl]);
+        sch.done();
+    }
+}
+
 // Thread per row: append the row to its tier's list, one atomic per wavefront and tier.
 __global__ __launch_bounds__(256) void gemm_classify(gemm_args g) {
     for (int64_t i0 = static_cast<int64_t>(blockIdx.x) * blockDim.x; i0 < g.m;
          i0 += static_cast<int64_t>(gridDim.x) * blockDim.x) {  // uniform per wavefront
         const int64_t i = i0 + threadIdx.x;
         const int64_t p = i < g.m ? g.prod[i] : -1;
-        const int tier = p < 0 ? -1 : (p <= kTier1 ? 0 : (p <= kTier2 ? 1 : 2));
+        const int tier = p < 0 ? -1 : (p <= kTier0 ? 3 : (p <= kTier1 ? 0 : (p <= kTier2 ? 1 : 2)));
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
+        for (int t = 0; t < 4; ++t) {
             const uint64_t mask = __ballot(tier == t);
             if (mask == 0) continue;
             const int leader = __ffsll(static_cast<unsigned long long>(mask)) - 1;
             int32_t base = 0;
-            if (lane_id() == leader) base = atomicAdd(g.list_len + t, __popcll(mask));
+            if (lane_id() == leader) base = atomicAdd(g.list_len + (t == 3 ? 4 : t), __popcll(mask));
             base = __shfl(base, leader);
             if (tier == t)
                 g.lists[static_cast<int64_t>(t) * g.m + base + __popcll(mask & ((1ull << lane_id()) - 1))] =
@@ -130,6 +177,79 @@ __device__ __forceinline__ void lds_bitonic(uint64_t *key, float *val, int32_t n
             }
             sync();
         }
+    }
+}
+
+// Tier 0: an 8-lane group per row (p <= 32), eight rows per wavefront; all
+// groups run the same 32-element sort network, so the wavefront stays in
+// step (a group whose rows ran out is masked off).
+template <bool COMPUTE>
+__global__ __launch_bounds__(kBlock) void gemm_tier0(gemm_args g) {
+    constexpr int GL = 8;
+    constexpr int GPB = kBlock / GL;
+    __shared__ uint64_t s_key[GPB][kTier0];
+    __shared__ float s_val[GPB][COMPUTE ? kTier0 : 1];
+    const int gl = threadIdx.x & (GL - 1), gi = threadIdx.x / GL;
+    const int shift = lane_id() & ~(GL - 1);  // the group's first lane in the wavefront
+    uint64_t *key = s_key[gi];
+    float *val = s_val[gi];
+    const int32_t rows = g.list_len[4];
+    const int64_t groups = static_cast<int64_t>(gridDim.x) * GPB;
+    for (int64_t r = static_cast<int64_t>(blockIdx.x) * GPB + gi; r < rows; r += groups) {
+        const int32_t i = g.lists[3 * static_cast<int64_t>(g.m) + r];
+        const int32_t p = static_cast<int32_t>(g.prod[i]);
+        const int32_t a0 = g.a_ro[i], a1 = g.a_ro[i + 1];
+        int32_t base = 0;
+        for (int32_t c0 = a0; c0 < a1; c0 += GL) {
+            const int32_t e = c0 + gl;
+            int32_t j = 0, len = 0;
+            if (e < a1) {
+                j = g.a_ci[e];
+                len = g.b_ro[j + 1] - g.b_ro[j];
+            }
+            const int32_t incl = group_scan_incl<GL>(len);
+            const int32_t start = base + incl - len;
+            if (len > 0) {
+                const int32_t f0 = g.b_ro[j];
+                const float a = COMPUTE ? g.a_val[e] : 0.f;
+                for (int32_t t = 0; t < len; ++t) {
+                    const int32_t q = start + t;
+                    key[q] = (static_cast<uint64_t>(g.b_ci[f0 + t]) << 32) | static_cast<uint32_t>(q);
+                    if constexpr (COMPUTE) val[q] = a * g.b_val[f0 + t];
+                }
+            }
+            base += __shfl(incl, GL - 1, GL);
+        }
+        for (int32_t q = p + gl; q < kTier0; q += GL) key[q] = kPad;
+        wave_sync();
+        lds_bitonic<COMPUTE>(key, val, kTier0, gl, GL, wave_sync);
+        int32_t rank = 0;
+        float carry = 0.f;
+        const int32_t out0 = COMPUTE ? g.c_ro[i] : 0;
+        for (int32_t c0 = 0; c0 < p; c0 += GL) {
+            const int32_t q = c0 + gl;
+            const bool in = q < p;
+            const uint32_t col = in ? static_cast<uint32_t>(key[q] >> 32) : 0xffffffffu;
+            const uint32_t prev = q > 0 && in ? static_cast<uint32_t>(key[q - 1] >> 32) : 0xffffffffu;
+            const bool head = in && (q == 0 || col != prev);
+            const uint32_t hm = static_cast<uint32_t>((__ballot(head) >> shift) & 0xffu);
+            if constexpr (COMPUTE) {
+                const bool tail = in && (q == p - 1 || static_cast<uint32_t>(key[q + 1] >> 32) != col);
+                seg_t sv = group_seg_scan_incl<GL>(seg_t{in ? val[q] : 0.f, head});
+                if (!sv.f) sv.v += carry;
+                const int32_t my_rank = rank + __popc(hm & ((2u << gl) - 1)) - 1;
+                if (tail) {
+                    g.c_ci[out0 + my_rank] = static_cast<int32_t>(col);
+                    g.c_val[out0 + my_rank] = sv.v;
+                }
+                carry = __shfl(sv.v, GL - 1, GL);
+            }
+            rank += __popc(hm);
+        }
+        if constexpr (!COMPUTE) {
+            if (gl == 0) g.c_ro[i] = rank;
+        }
+        wave_sync();
     }
 }
 
@@ -451,12 +571,12 @@ static gemm_ws gemm_carve(void *base, int64_t m, int64_t n) {
     w.total = reinterpret_cast<int64_t *>(p);
     p += 256;
     w.lists = reinterpret_cast<int32_t *>(p);
-    p += align256(static_cast<size_t>(3 * m) * 4);
+    p += align256(static_cast<size_t>(4 * m) * 4);
     w.list_len = reinterpret_cast<int32_t *>(p);
     p += 256;
     w.slot_words = (n + 31) / 32 + ((n + 31) / 32 + 31) / 32;
     w.slot_acc = reinterpret_cast<float *>(p);
-    p += align256(static_cast<size_t>(kSpgemmSlots) * n * 4);
+    p += align256(static_cast<size_t>(spgemm_slots(n)) * n * 4);
     w.slot_bits = reinterpret_cast<uint32_t *>(p);
     return w;
 }
@@ -464,8 +584,8 @@ static gemm_ws gemm_carve(void *base, int64_t m, int64_t n) {
 size_t spgemm_ws_bytes(int64_t m, int64_t n) {
     const int64_t words = (n + 31) / 32 + ((n + 31) / 32 + 31) / 32;
     return 2 * align256(static_cast<size_t>(m) * 8) + align256(static_cast<size_t>(m / kScanTile + 2) * 8) + 256 +
-           align256(static_cast<size_t>(3 * m) * 4) + 256 + align256(static_cast<size_t>(kSpgemmSlots) * n * 4) +
-           align256(static_cast<size_t>(kSpgemmSlots) * words * 4);
+           align256(static_cast<size_t>(4 * m) * 4) + 256 + align256(static_cast<size_t>(spgemm_slots(n)) * n * 4) +
+           align256(static_cast<size_t>(spgemm_slots(n)) * words * 4);
 }
 
 static hipError_t gemm_pass(const spgemm_dev &P, int32_t *c_ro, int32_t *c_ci, float *c_val, void *ws, bool compute,
@@ -473,34 +593,64 @@ static hipError_t gemm_pass(const spgemm_dev &P, int32_t *c_ro, int32_t *c_ci, f
     const gemm_ws w = gemm_carve(ws, P.m, P.n);
     gemm_args g{P.m, P.n, P.a_ro, P.a_ci, P.a_val, P.b_ro, P.b_ci, P.b_val, w.prod, w.lists, w.list_len,
                 c_ro, c_ci, c_val, w.slot_acc, w.slot_bits, w.slot_words};
-    hipError_t e = fill_f32(reinterpret_cast<float *>(w.list_len), 4, 0.f, s);  // +0.0f is all zero bits
+    hipError_t e = fill_f32(reinterpret_cast<float *>(w.list_len), 5, 0.f, s);  // +0.0f is all zero bits
     if (e != hipSuccess) return e;
     {
         prof_scope p(s, "spgemm_products");
-        constexpr int GPB = group_block<kWave>::GPB;  // grid-stride over rows, a wavefront each
-        hipLaunchKernelGGL(gemm_products, dim3(static_cast<uint32_t>(capped(P.m, GPB))), dim3(256), 0, s, g, w.prod);
+        // short rows (fewer than 8 entries on average) share wavefronts; longer ones get one each
+        if (P.m > 0 && static_cast<int64_t>(P.a_nnz) < 8 * static_cast<int64_t>(P.m)) {
+            constexpr int RPB = group_block<kWave>::BLOCK;  // rows per block round: 4 groups of 64
+            hipLaunchKernelGGL(gemm_products, dim3(static_cast<uint32_t>(capped(P.m, RPB))), dim3(256), 0, s, g,
+                               w.prod);
+        } else {
+            constexpr int GPB = group_block<kWave>::GPB;  // grid-stride: at most 2^16 blocks
+            const int64_t want = (static_cast<int64_t>(P.m) + GPB - 1) / GPB;
+            hipLaunchKernelGGL(gemm_products_rows, dim3(static_cast<uint32_t>(want < 65536 ? want : 65536)), dim3(256),
+                               0, s, g, w.prod);
+        }
         hipLaunchKernelGGL(gemm_classify, dim3(static_cast<uint32_t>(capped(P.m, 256))), dim3(256), 0, s, g);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     // tier-3 slots start clear (the kernel clears what it used)
-    e = fill_f32(reinterpret_cast<float *>(w.slot_bits), static_cast<int64_t>(kSpgemmSlots) * w.slot_words, 0.f, s);
-    if (e == hipSuccess && compute) e = fill_f32(w.slot_acc, static_cast<int64_t>(kSpgemmSlots) * P.n, 0.f, s);
+    const int64_t slots = spgemm_slots(P.n);
+    e = fill_f32(reinterpret_cast<float *>(w.slot_bits), slots * w.slot_words, 0.f, s);
+    if (e == hipSuccess && compute) e = fill_f32(w.slot_acc, slots * P.n, 0.f, s);
     if (e != hipSuccess) return e;
+    // one launch per tier (each reads its list's length on the device)
+    const uint32_t grid12 = static_cast<uint32_t>(capped(P.m, 1) < 2048 ? capped(P.m, 1) : 2048);
+    const char *names[2][4] = {{"spgemm_count_t0", "spgemm_count_t1", "spgemm_count_t2", "spgemm_count_t3"},
+                               {"spgemm_compute_t0", "spgemm_compute_t1", "spgemm_compute_t2", "spgemm_compute_t3"}};
+    const int c = compute ? 1 : 0;
     {
-        prof_scope p(s, compute ? "spgemm_compute" : "spgemm_count");
-        const uint32_t grid12 = static_cast<uint32_t>(capped(P.m, 1) < 2048 ? capped(P.m, 1) : 2048);
-        if (compute) {
-            hipLaunchKernelGGL(gemm_tier1<true>, dim3(grid12), dim3(kBlock), 0, s, g);
-            hipLaunchKernelGGL(gemm_tier2<true>, dim3(grid12), dim3(kBlock), 0, s, g);
-            hipLaunchKernelGGL(gemm_tier3<true>, dim3(kSpgemmSlots), dim3(kBlock), 0, s, g);
-        } else {
-            hipLaunchKernelGGL(gemm_tier1<false>, dim3(grid12), dim3(kBlock), 0, s, g);
-            hipLaunchKernelGGL(gemm_tier2<false>, dim3(grid12), dim3(kBlock), 0, s, g);
-            hipLaunchKernelGGL(gemm_tier3<false>, dim3(kSpgemmSlots), dim3(kBlock), 0, s, g);
-        }
-        e = hipGetLastError();
+        prof_scope p(s, names[c][0]);
+        if (compute)
+            hipLaunchKernelGGL(gemm_tier0<true>, dim3(grid12), dim3(kBlock), 0, s, g);
+        else
+            hipLaunchKernelGGL(gemm_tier0<false>, dim3(grid12), dim3(kBlock), 0, s, g);
     }
+    {
+        prof_scope p(s, names[c][1]);
+        if (compute)
+            hipLaunchKernelGGL(gemm_tier1<true>, dim3(grid12), dim3(kBlock), 0, s, g);
+        else
+            hipLaunchKernelGGL(gemm_tier1<false>, dim3(grid12), dim3(kBlock), 0, s, g);
+    }
+    {
+        prof_scope p(s, names[c][2]);
+        if (compute)
+            hipLaunchKernelGGL(gemm_tier2<true>, dim3(grid12), dim3(kBlock), 0, s, g);
+        else
+            hipLaunchKernelGGL(gemm_tier2<false>, dim3(grid12), dim3(kBlock), 0, s, g);
+    }
+    {
+        prof_scope p(s, names[c][3]);
+        if (compute)
+            hipLaunchKernelGGL(gemm_tier3<true>, dim3(static_cast<uint32_t>(slots)), dim3(kBlock), 0, s, g);
+        else
+            hipLaunchKernelGGL(gemm_tier3<false>, dim3(static_cast<uint32_t>(slots)), dim3(kBlock), 0, s, g);
+    }
+    e = hipGetLastError();
     return e;
 }
 

@@ -582,7 +582,7 @@ lb_status_t check_spgemm(const lb_csr_t *A, const lb_csr_t *B) {
 
 lbk::spgemm_dev to_spgemm(const lb_csr_t *A, const lb_csr_t *B) {
     return {static_cast<int32_t>(A->rows), static_cast<int32_t>(A->cols), static_cast<int32_t>(B->cols),
-            A->row_offsets, A->col_idx, static_cast<const float *>(A->values), B->row_offsets, B->col_idx,
+            static_cast<int32_t>(A->nnz), A->row_offsets, A->col_idx, static_cast<const float *>(A->values), B->row_offsets, B->col_idx,
             static_cast<const float *>(B->values)};
 }
 

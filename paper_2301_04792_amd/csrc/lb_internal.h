@@ -137,13 +137,19 @@ hipError_t backward_transposed(const csr_dev &A, const int32_t *at_ro, const int
 // ---- SpGEMM (k_spgemm.hip) ---------------------------------------------------------------
 // C = A B with A m x k and B k x n (float32 values).
 struct spgemm_dev {
-    int32_t m, k, n;
+    int32_t m, k, n, a_nnz;
     const int32_t *a_ro, *a_ci;
     const float *a_val;
     const int32_t *b_ro, *b_ci;
     const float *b_val;
 };
-constexpr int kSpgemmSlots = 32;  // blocks of the large-row tier, each with a dense n-column slot
+// Blocks of the large-row tier, each with a dense n-column slot (n floats and
+// n / 32 + n / 1024 bitmap words): as many as 1 GiB holds, from 32 to 512.
+inline int64_t spgemm_slots(int64_t n) {
+    const int64_t per = n * 4 + ((n + 31) / 32 + ((n + 31) / 32 + 31) / 32) * 4 + 512;
+    const int64_t s = (int64_t(1) << 30) / (per > 0 ? per : 1);
+    return s < 32 ? 32 : (s > 512 ? 512 : s);
+}
 size_t spgemm_ws_bytes(int64_t m, int64_t n);
 // Per-row column counts turned into C's row offsets (m + 1, int32 where the
 // total fits); *total_host receives nnz(C).  Synchronizes s.
