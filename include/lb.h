@@ -334,15 +334,19 @@ LB_API lb_status_t lb_spmv_csc(const lb_csc_t *A, const void *x, lb_dtype_t x_dt
  * A->cols), both float32.  Row i of C holds every column reached by a
  * product A[i, j] * B[j, c], ascending (structural: kept even if the sum is
  * 0), with value sum_j A[i, j] * B[j, c] in float32.  Rows are accumulated
- * by product count: up to 256 products one wavefront, up to 4096 one block
+ * by product count: up to 32 products an 8-lane group, up to 256 one
+ * wavefront, up to 4096 one block
  * (both sort (column, product index) in LDS and sum in product order:
  * deterministic), beyond that a dense slot per block of a work queue (float
  * atomics: summation order varies run to run).
  * lb_spgemm_count (synchronizing) writes C's row offsets (A->rows + 1,
  * device) and *c_nnz (host); the caller allocates col_idx and values of
  * *c_nnz entries; lb_spgemm_compute fills them.  Both take the workspace of
- * lb_spgemm_workspace_size (contents on entry irrelevant).  nnz(C) must fit
- * int32 (else LB_ERR_OVERFLOW from the count). */
+ * lb_spgemm_workspace_size (contents on entry irrelevant): per-row counts
+ * and tier lists (about 40 bytes per row of A) plus the large-row slots, a
+ * dense float accumulator and bitmap over B's columns each, as many as
+ * 1 GiB holds (32 to 512 slots).  nnz(C) must fit int32 (else
+ * LB_ERR_OVERFLOW from the count). */
 LB_API lb_status_t lb_spgemm_workspace_size(const lb_csr_t *A, const lb_csr_t *B, size_t *bytes);
 LB_API lb_status_t lb_spgemm_count(const lb_csr_t *A, const lb_csr_t *B, int32_t *c_row_offsets, int64_t *c_nnz,
                                    void *workspace, size_t workspace_bytes, void *stream);
