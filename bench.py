@@ -3,8 +3,10 @@
 
 One step = one y = A x over the power-law matrix (m = n = 2,000,000, row
 lengths min(Zipf(1.8), 200,000), 10 % empty rows, uniform columns, FP32)
-with the merge-path schedule (what the Sec. 6.2 heuristic picks for it):
-partition, consume and carry fix-up.  `value` is effective HBM GB/s over
+with the schedule the autotuner picks by timing its candidates on this
+matrix (merge-path, as the Sec. 6.2 heuristic also picks; the tuned form
+splits x into two column bands over the XCDs): partition, consume, band
+combine and carry fix-up.  `value` is effective HBM GB/s over
 algorithmic bytes B = nnz*(s_v + 4) + (m + 1)*4 + n*s_x + m*4 for K
 back-to-back steps with the inputs already in HBM.
 
@@ -88,15 +90,30 @@ def _counter_per_dispatch(rows, kernel_substr, counter):
     return sum(vals) / len(vals), len(vals), name
 
 
+def _consume_config(kernel_name):
+    """(block, items, x_bands) from a merge_spmv_consume<...> kernel name."""
+    import re
+
+    m = re.search(r"merge_spmv_consume<(\d+), (\d+), [^,]+, [^,]+, (\d+)>", kernel_name)
+    return (int(m.group(1)), int(m.group(2)), int(m.group(3))) if m else None
+
+
+def _config_args(cfg):
+    return f"--schedule merge_path --block {cfg[0]} --items {cfg[1]} --x-bands {cfg[2]}"
+
+
 def summarize_profiles(out_dir, prof_root):
     """Write profiles/*.md and the traffic JSON from rocprofv3 CSV output
-    (made by the commands recorded in each summary)."""
+    (made by the commands recorded in each summary; the merge-path
+    configuration in them is the one named by the profiled kernel)."""
     os.makedirs(out_dir, exist_ok=True)
-    cmd_trace = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_trace -o trace -- "
-                 "python3 bench.py --quick --no-cpu --schedule merge_path --steps 10 --warmup 3")
     stats = _find(os.path.join(prof_root, "prof_trace"), "kernel_stats.csv")
     if stats:
         rows = _read_csv(stats)
+        names = [r["Name"] for r in rows if _consume_config(r["Name"])]
+        cfg = _consume_config(names[0]) if names else (256, 8, 1)
+        cmd_trace = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_trace -o trace -- "
+                     f"python3 bench.py --quick --no-cpu {_config_args(cfg)} --steps 10 --warmup 3")
         lines = ["# Kernel trace: power-law 2M SpMV, merge-path (bench --quick)", "",
                  f"Command: `{cmd_trace}`", "",
                  "| kernel | calls | avg µs | min µs | max µs | % time |", "|---|---|---|---|---|---|"]
@@ -143,12 +160,10 @@ def summarize_profiles(out_dir, prof_root):
             read_b = f_k * 1024.0 * ff
             write_b = w_k * 1024.0 * fw
             name = name_f
-            import re as _re
-
-            m = _re.search(r"merge_spmv_consume<(\d+), (\d+),", name)
+            cfg = _consume_config(name) or (None, None, None)
             data = {"kernel": kern, "workload": "powerlaw_m2M_zipf1.8_cap200k_empty10pct",
                     "kernel_source_hash": kernel_source_hash(),
-                    "block_size": int(m.group(1)) if m else None, "items_per_thread": int(m.group(2)) if m else None,
+                    "block_size": cfg[0], "items_per_thread": cfg[1], "x_bands": cfg[2],
                     "fetch_kb_per_dispatch": f_k, "write_kb_per_dispatch": w_k, "dispatches": [nf, nw],
                     "copy_calibration": {"known_bytes": known, "fetch_kb": max(copy_f), "write_kb": max(copy_w),
                                          "fetch_factor": ff, "write_factor": fw},
@@ -156,9 +171,9 @@ def summarize_profiles(out_dir, prof_root):
                     "hbm_bytes_per_launch": read_b + write_b,
                     "commands": [
                         "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof_fetch -o fetch -- "
-                        "python3 bench.py --quick --no-cpu --schedule merge_path --steps 3 --warmup 1 --pmc-calib",
+                        f"python3 bench.py --quick --no-cpu {_config_args(cfg)} --steps 3 --warmup 1 --pmc-calib",
                         "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof_write -o write -- "
-                        "python3 bench.py --quick --no-cpu --schedule merge_path --steps 3 --warmup 1 --pmc-calib"]}
+                        f"python3 bench.py --quick --no-cpu {_config_args(cfg)} --steps 3 --warmup 1 --pmc-calib"]}
             try:
                 import synthetic as S
 
@@ -256,6 +271,7 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--items", type=int, default=0, help="merge-path items per thread (0 = default)")
     ap.add_argument("--block", type=int, default=0, help="merge-path block size (0 = default)")
+    ap.add_argument("--x-bands", type=int, default=0, help="merge-path column bands of x, 1 or 2 (0 = default)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--schedule", default="auto",
                     help="headline schedule: auto (autotuned) or merge_path / group_mapped / thread_mapped")
@@ -340,6 +356,8 @@ def main():
         params["items_per_thread"] = args.items
     if args.block:
         params["block_size"] = args.block
+    if args.x_bands:
+        params["x_bands"] = args.x_bands
     head = args.schedule
     if head == "auto" and not params:
         lb.autotune_clear()
@@ -364,7 +382,8 @@ def main():
     consume_ms, launches = kernel_avg_ms(step, args.steps, dominant)
     others = {}
     if dominant == "merge_consume":
-        others = {n: round(kernel_avg_ms(step, args.steps, n)[0], 5) for n in ("merge_partition", "merge_fixup")}
+        others = {n: round(kernel_avg_ms(step, args.steps, n)[0], 5) for n in
+                  ("merge_partition", "merge_fixup") + (("merge_combine",) if sched["x_bands"] == 2 else ())}
     achieved = B / (consume_ms * 1e-3) / 1e9
     log(f"[bench] {dominant} {consume_ms * 1e3:.1f} us ({achieved:.0f} GB/s), others {others}, "
         f"cold call {ms_cold * 1e3:.1f} us")
@@ -392,10 +411,13 @@ def main():
         try:
             with open(TRAFFIC_FILE) as f:
                 tr = json.load(f)
+            same_cfg = (tr.get("block_size"), tr.get("items_per_thread"), tr.get("x_bands")) == \
+                (sched["block_size"], sched["items_per_thread"], sched["x_bands"])
             if tr.get("kernel_source_hash") == kernel_source_hash() and tr.get("nnz") == A.nnz \
-                    and dominant == "merge_consume":
+                    and dominant == "merge_consume" and same_cfg:
                 traffic = tr.get("hbm_bytes_per_launch")
                 traffic_cfg = {"block_size": tr.get("block_size"), "items_per_thread": tr.get("items_per_thread"),
+                               "x_bands": tr.get("x_bands"),
                                "unscaled_bytes": round((tr.get("fetch_kb_per_dispatch", 0) +
                                                         tr.get("write_kb_per_dispatch", 0)) * 1024)}
         except (OSError, ValueError):
@@ -416,7 +438,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "powerlaw_m2M_zipf1.8_cap200k_empty10pct", "m": A.m, "n": A.n, "nnz": A.nnz,
                    "seed": 2, "schedule": sched["schedule"], "block_size": sched["block_size"],
-                   "items_per_thread": sched["items_per_thread"]},
+                   "items_per_thread": sched["items_per_thread"], "x_bands": sched["x_bands"]},
         "pct_of_peak": round(100 * value / PEAK_GBS, 2),
         "gflops": round(2 * A.nnz / (ms * 1e-3) / 1e9, 2),
         "algorithmic_bytes": B,
@@ -458,6 +480,7 @@ def main():
     # ------------------------------------------------------------ per schedule on the same matrix
     per = {}
     for name, p in (("merge_path", {}), ("merge_path", {"block_size": 512, "items_per_thread": 8}),
+                    ("merge_path", {"x_bands": 2}), ("merge_path", {"block_size": 512, "items_per_thread": 8, "x_bands": 2}),
                     ("thread_mapped", {}), ("group_mapped", {"group_size": 64}),
                     ("group_mapped", {"group_size": 256}), ("group_mapped", {"group_size": 32, "tiles_per_group": 32}),
                     ("group_mapped", {"group_size": 1024, "tiles_per_group": 1024}),

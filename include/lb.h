@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define LB_ABI_VERSION 1
+#define LB_ABI_VERSION 2
 #define LB_API __attribute__((visibility("default")))
 
 typedef enum lb_status_t {
@@ -101,7 +101,18 @@ typedef struct lb_csr_t {
  *                    and batched passes take up to 8 columns of X at a
  *                    time, fewer for large block_size * items_per_thread;
  *                    group-mapped derived from group_size (ignored).
- *  grid_size         blocks; 0 = one block per chunk of work. */
+ *  grid_size         blocks; 0 = one block per chunk of work.
+ *  x_bands           LB_MERGE_PATH in lb_spmv: 1 or 2 (default 1).  With 2,
+ *                    every merge-path unit is consumed by two blocks placed on
+ *                    different XCDs (blocks are dealt to the 8 XCDs round
+ *                    robin), one for the columns below ceil(cols / 2) and one
+ *                    for the rest, so each XCD's L2 caches only its half of x;
+ *                    y is the sum of the two halves' row sums, added in that
+ *                    order (deterministic).  Pays when x is larger than one
+ *                    XCD's L2 (4 MiB) and its columns are scattered; costs a
+ *                    second read of col_idx (served mostly by the Infinity
+ *                    Cache) and a rows-sized buffer in the workspace.  Other
+ *                    entry points accept only 0 or 1. */
 typedef struct lb_schedule_t {
     lb_sched_kind_t kind;
     int32_t group_size;
@@ -109,6 +120,7 @@ typedef struct lb_schedule_t {
     int32_t items_per_thread;
     int32_t block_size;
     int32_t grid_size;
+    int32_t x_bands;
 } lb_schedule_t;
 
 /* Independent CSR matrices stored back to back (a block-diagonal matrix).

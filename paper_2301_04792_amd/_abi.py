@@ -33,12 +33,12 @@ class CSR(ctypes.Structure):
 class Schedule(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("group_size", ctypes.c_int32),
                 ("tiles_per_group", ctypes.c_int32), ("items_per_thread", ctypes.c_int32),
-                ("block_size", ctypes.c_int32), ("grid_size", ctypes.c_int32)]
+                ("block_size", ctypes.c_int32), ("grid_size", ctypes.c_int32), ("x_bands", ctypes.c_int32)]
 
     def as_dict(self):
         return {"schedule": NAME_BY_KIND.get(self.kind, self.kind), "group_size": self.group_size,
                 "tiles_per_group": self.tiles_per_group, "items_per_thread": self.items_per_thread,
-                "block_size": self.block_size, "grid_size": self.grid_size}
+                "block_size": self.block_size, "grid_size": self.grid_size, "x_bands": self.x_bands}
 
 
 class Batch(ctypes.Structure):
@@ -132,13 +132,13 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
-                          f"python -m paper_2301_04792_amd.build")
+                          f"python paper_2301_04792_amd/build.py")
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         f = getattr(lib, name)
         f.restype = res
         f.argtypes = args
-    if lib.lb_abi_version() != 1:
+    if lib.lb_abi_version() != 2:
         raise ImportError("liblb.so ABI version mismatch")
     _lib = lib
     return lib

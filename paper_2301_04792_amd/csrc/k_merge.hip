@@ -25,6 +25,18 @@
 //  3. merge_fixup: rows that cross block boundaries receive the carries of
 //     the blocks before them, summed in block order (deterministic; no
 //     atomics on y).
+//
+// Column bands (XCD-aware form, x_bands = 2).  x of a large matrix with
+// scattered columns does not fit one XCD's L2, so its gathers miss to the
+// Infinity Cache.  With two bands every unit is consumed twice, by two
+// blocks that the round-robin dealing of blocks to XCDs puts on different
+// XCDs: one multiplies only the nonzeros with col < cb, the other only the
+// rest, so each XCD's L2 holds half of x.  The band-0 block writes its row
+// sums to y, the band-1 block to a rows-sized buffer; merge_combine adds the
+// buffer to y, and the fix-up adds both bands' carries (stored interleaved,
+// unit-major, so carry_row stays non-decreasing).  Both blocks read the
+// whole unit's col_idx (the second read mostly hits the Infinity Cache, so
+// these loads are temporal) and load values only for their own band.
 #include "lb_device.h"
 #include "lb_internal.h"
 
@@ -82,17 +94,30 @@ hipError_t merge_partition(const int32_t *ro, int32_t rows, int32_t nnz, int32_t
 // the kernel stays at ~20 VGPRs and full occupancy, which hides the stream
 // and gather latency better than a register prefetch pipeline that costs
 // occupancy.
-template <int BLOCK, int ITEMS, typename VT, typename XT>
+// BANDS = 1: block b consumes unit b.  BANDS = 2: block b consumes band
+// (b mod 8) mod 2 of unit (b / 8) * 4 + (b mod 8) / 2, the grid has
+// 8 * ceil(T / 4) blocks and those past the last unit return at once; every
+// (unit, band) pair has exactly one block whatever the hardware's dealing.
+template <int BLOCK, int ITEMS, typename VT, typename XT, int BANDS>
 __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
     int32_t rows, int32_t nnz, const int32_t *__restrict__ ro, const int32_t *__restrict__ ci, const VT *__restrict__ val,
     const XT *__restrict__ x, float *__restrict__ y, const int32_t *__restrict__ part_i,
-    const int32_t *__restrict__ part_j, int32_t *__restrict__ carry_row, float *__restrict__ carry_val) {
+    const int32_t *__restrict__ part_j, int32_t *__restrict__ carry_row, float *__restrict__ carry_val,
+    int32_t T, int32_t cb, float *__restrict__ y_hi) {
+    static_assert(BANDS == 1 || BANDS == 2, "one or two column bands");
     constexpr int W = BLOCK * ITEMS;
     __shared__ int32_t s_buf[W];  // row ends [0, nrows), then products [nrows, nrows + nnzs)
     __shared__ seg_t s_wave[BLOCK / kWave];
 
     const int tid = threadIdx.x;
-    const int b = blockIdx.x;
+    int b = blockIdx.x, band = 0;
+    if constexpr (BANDS == 2) {
+        const int xcd = static_cast<int>(blockIdx.x % kXcds);
+        band = xcd & 1;
+        b = static_cast<int>(blockIdx.x / kXcds) * (kXcds / 2) + xcd / 2;
+        if (b >= T) return;  // uniform across the block, before any barrier
+        if (band == 1) y = y_hi;
+    }
     const int32_t i0 = part_i[b], j0 = part_j[b];
     const int32_t i1 = part_i[b + 1], j1 = part_j[b + 1];
     const int32_t nrows = i1 - i0, nnzs = j1 - j0;
@@ -110,24 +135,46 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
     const int32_t re_last = i1 > i0 ? i1 : i0 + 1 <= rows ? i0 + 1 : rows;  // a valid row_offsets index
     const int32_t nz_last = nnzs > 0 ? j1 - 1 : (j0 < nnz ? j0 : nnz - 1);  // a valid nonzero index
     int32_t re[ITEMS], c[ITEMS];
-    VT v[ITEMS];
-    float xv[ITEMS];
+    float pv[ITEMS];
+    if constexpr (BANDS == 1) {
+        VT v[ITEMS];
+        float xv[ITEMS];
 #pragma unroll
-    for (int u = 0; u < ITEMS; ++u) {
-        const int32_t k = tid + u * BLOCK;
-        const int32_t rk = i0 + 1 + k;
-        const int32_t jk = j0 + k;
-        re[u] = ro[rk < re_last ? rk : re_last];
-        c[u] = ld_stream(ci + (jk < nz_last ? jk : nz_last));
-        v[u] = ld_stream(val + (jk < nz_last ? jk : nz_last));
+        for (int u = 0; u < ITEMS; ++u) {
+            const int32_t k = tid + u * BLOCK;
+            const int32_t rk = i0 + 1 + k;
+            const int32_t jk = j0 + k;
+            re[u] = ro[rk < re_last ? rk : re_last];
+            c[u] = ld_stream(ci + (jk < nz_last ? jk : nz_last));
+            v[u] = ld_stream(val + (jk < nz_last ? jk : nz_last));
+        }
+#pragma unroll
+        for (int u = 0; u < ITEMS; ++u) xv[u] = to_f32(x[c[u]]);
+#pragma unroll
+        for (int u = 0; u < ITEMS; ++u) pv[u] = to_f32(v[u]) * xv[u];
+    } else {
+        // band 0 takes col < cb, band 1 col >= cb; a value is loaded only
+        // for a nonzero of the block's own band
+#pragma unroll
+        for (int u = 0; u < ITEMS; ++u) {
+            const int32_t k = tid + u * BLOCK;
+            const int32_t rk = i0 + 1 + k;
+            const int32_t jk = j0 + k;
+            re[u] = ro[rk < re_last ? rk : re_last];
+            c[u] = ci[jk < nz_last ? jk : nz_last];
+        }
+#pragma unroll
+        for (int u = 0; u < ITEMS; ++u) {
+            const int32_t jk = j0 + tid + u * BLOCK;
+            const bool mine = (c[u] >= cb) == (band == 1);
+            pv[u] = mine ? to_f32(val[jk < nz_last ? jk : nz_last]) * to_f32(x[c[u]]) : 0.f;
+        }
     }
-#pragma unroll
-    for (int u = 0; u < ITEMS; ++u) xv[u] = to_f32(x[c[u]]);
 #pragma unroll
     for (int u = 0; u < ITEMS; ++u) {
         const int k = tid + u * BLOCK;
         if (k < nrows) s_re[k] = re[u] - j0;
-        if (k < nnzs) s_pv[k] = to_f32(v[u]) * xv[u];
+        if (k < nnzs) s_pv[k] = pv[u];
     }
     __syncthreads();
 
@@ -171,9 +218,15 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
     const seg_t in = block_seg_scan_excl<BLOCK>(seg_t{acc, first >= 0}, s_wave, tot);
     if (first >= 0) y[i0 + first] = first_sum + in.v;
     if (tid == 0) {
-        carry_row[b] = i1;  // the row still open at the block's end (rows if none)
-        carry_val[b] = tot.v;
+        carry_row[b * BANDS + band] = i1;  // the row still open at the block's end (rows if none)
+        carry_val[b * BANDS + band] = tot.v;
     }
+}
+
+// y[r] += y_hi[r]: the second band's row sums.
+__global__ __launch_bounds__(256) void merge_combine(float *__restrict__ y, const float *__restrict__ y_hi,
+                                                     int64_t rows) {
+    for (int64_t r : grid_stride_range(0, rows)) y[r] += y_hi[r];
 }
 
 // ------------------------------------------------------------------ fix-up
@@ -236,21 +289,42 @@ hipError_t launch_fixup(int64_t T, int32_t rows, int32_t kc, const int32_t *carr
 // ------------------------------------------------------------------ dispatch
 
 template <int BLOCK, int ITEMS, typename VT>
-static hipError_t run_merge_spmv(const csr_dev &A, const void *x, float *y, void *ws, hipStream_t s) {
+static hipError_t run_merge_spmv(const csr_dev &A, const void *x, float *y, int bands, void *ws, hipStream_t s) {
     constexpr int W = BLOCK * ITEMS;
     const int64_t T = merge_units(A.rows, A.nnz, W);
-    merge_ws w = merge_ws_carve(ws, T);
+    const bool two = bands == 2;
+    merge_ws w = merge_ws_carve(ws, two ? 2 * T : T);
+    float *y_hi = two ? reinterpret_cast<float *>(static_cast<char *>(ws) + merge_ws_bytes(2 * T, 1)) : nullptr;
     hipError_t e = merge_partition(A.ro, A.rows, A.nnz, W, static_cast<int32_t>(T), w.part_i, w.part_j, s);
     if (e != hipSuccess) return e;
     {
         prof_scope p(s, "merge_consume");
-        hipLaunchKernelGGL((merge_spmv_consume<BLOCK, ITEMS, VT, VT>), dim3(static_cast<uint32_t>(T)), dim3(BLOCK), 0,
-                           s, A.rows, A.nnz, A.ro, A.ci, static_cast<const VT *>(A.val), static_cast<const VT *>(x), y, w.part_i,
-                           w.part_j, w.carry_row, w.carry_val);
+        const VT *val = static_cast<const VT *>(A.val);
+        const VT *xv = static_cast<const VT *>(x);
+        const int32_t cb = static_cast<int32_t>((A.cols + 1) / 2);
+        if (two) {
+            const int64_t per = kXcds / 2;  // units per row of kXcds blocks
+            const int64_t grid = (T + per - 1) / per * kXcds;
+            hipLaunchKernelGGL((merge_spmv_consume<BLOCK, ITEMS, VT, VT, 2>), dim3(static_cast<uint32_t>(grid)),
+                               dim3(BLOCK), 0, s, A.rows, A.nnz, A.ro, A.ci, val, xv, y, w.part_i, w.part_j,
+                               w.carry_row, w.carry_val, static_cast<int32_t>(T), cb, y_hi);
+        } else {
+            hipLaunchKernelGGL((merge_spmv_consume<BLOCK, ITEMS, VT, VT, 1>), dim3(static_cast<uint32_t>(T)),
+                               dim3(BLOCK), 0, s, A.rows, A.nnz, A.ro, A.ci, val, xv, y, w.part_i, w.part_j,
+                               w.carry_row, w.carry_val, static_cast<int32_t>(T), cb, y_hi);
+        }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    return launch_fixup(T, A.rows, 1, w.carry_row, w.carry_val, y, 1, s, "merge_fixup");
+    if (two) {
+        prof_scope p(s, "merge_combine");
+        const int64_t g = (A.rows + 255) / 256;
+        hipLaunchKernelGGL(merge_combine, dim3(static_cast<uint32_t>(g < 2048 ? g : 2048)), dim3(256), 0, s, y, y_hi,
+                           static_cast<int64_t>(A.rows));
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return launch_fixup(two ? 2 * T : T, A.rows, 1, w.carry_row, w.carry_val, y, 1, s, "merge_fixup");
 }
 
 bool merge_config_supported(int block, int items) {
@@ -260,12 +334,13 @@ bool merge_config_supported(int block, int items) {
     return false;
 }
 
-hipError_t merge_spmv(const csr_dev &A, const void *x, float *y, int block, int items, void *ws,
+hipError_t merge_spmv(const csr_dev &A, const void *x, float *y, int block, int items, int bands, void *ws,
                       hipStream_t s) {
-#define X(B, I)                                                                  \
-    if (block == B && items == I) {                                              \
-        if (A.dt == LB_BF16) return run_merge_spmv<B, I, bf16_bits>(A, x, y, ws, s); \
-        return run_merge_spmv<B, I, float>(A, x, y, ws, s);                      \
+    if (bands != 1 && bands != 2) return hipErrorInvalidValue;
+#define X(B, I)                                                                         \
+    if (block == B && items == I) {                                                     \
+        if (A.dt == LB_BF16) return run_merge_spmv<B, I, bf16_bits>(A, x, y, bands, ws, s); \
+        return run_merge_spmv<B, I, float>(A, x, y, bands, ws, s);                      \
     }
     LB_MERGE_CONFIGS(X)
 #undef X

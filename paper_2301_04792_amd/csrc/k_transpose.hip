@@ -169,7 +169,7 @@ hipError_t backward_transposed(const csr_dev &A, const int32_t *at_ro, const int
         if (e != hipSuccess) return e;
     }
     const csr_dev AT{A.cols, A.rows, A.nnz, at_ro, at_ci, vt, LB_F32};
-    return merge_spmv(AT, dy, dx, block, items, mws, s);
+    return merge_spmv(AT, dy, dx, block, items, 1, mws, s);
 }
 
 }  // namespace lbk

@@ -92,7 +92,7 @@ void tune_load_locked() {
     if (!p || !*p) return;
     std::ifstream f(p);
     std::string line;
-    // one entry per line: rows cols nnz k dtype batched kind group tiles items block grid
+    // one entry per line: rows cols nnz k dtype batched kind group tiles items block grid [x_bands]
     while (std::getline(f, line)) {
         std::istringstream ss(line);
         tune_key key{};
@@ -100,6 +100,7 @@ void tune_load_locked() {
         int kind = 0;
         if (ss >> key.rows >> key.cols >> key.nnz >> key.k >> key.dtype >> key.batched >> kind >> s.group_size >>
             s.tiles_per_group >> s.items_per_thread >> s.block_size >> s.grid_size) {
+            if (!(ss >> s.x_bands)) s.x_bands = 1;
             s.kind = static_cast<lb_sched_kind_t>(kind);
             g_tune[key] = s;
         }
@@ -115,7 +116,7 @@ void tune_save_locked() {
         const lb_schedule_t &s = kv.second;
         f << k.rows << ' ' << k.cols << ' ' << k.nnz << ' ' << k.k << ' ' << k.dtype << ' ' << k.batched << ' '
           << static_cast<int>(s.kind) << ' ' << s.group_size << ' ' << s.tiles_per_group << ' '
-          << s.items_per_thread << ' ' << s.block_size << ' ' << s.grid_size << '\n';
+          << s.items_per_thread << ' ' << s.block_size << ' ' << s.grid_size << ' ' << s.x_bands << '\n';
     }
 }
 
@@ -141,6 +142,9 @@ lb_status_t fill_defaults(const lb_schedule_t *in, lb_schedule_t *out) {
     lb_schedule_t s = *in;
     if (s.group_size < 0 || s.tiles_per_group < 0 || s.items_per_thread < 0 || s.block_size < 0 || s.grid_size < 0)
         return LB_ERR_INVALID_ARG;
+    if (s.x_bands < 0 || s.x_bands > 2) return LB_ERR_INVALID_ARG;
+    if (s.x_bands == 0) s.x_bands = 1;
+    if (s.x_bands == 2 && s.kind != LB_MERGE_PATH) return LB_ERR_UNSUPPORTED;
     switch (s.kind) {
         case LB_THREAD_MAPPED:
             if (s.block_size == 0) s.block_size = kDefaultBlock;
@@ -204,8 +208,14 @@ lb_status_t resolve(const lb_csr_t *A, int32_t k, const lb_schedule_t *in, lb_sc
         else
             s = heuristic(A);
     }
-    return fill_defaults(&s, out);
+    const lb_status_t st = fill_defaults(&s, out);
+    if (st != LB_OK) return st;
+    if (out->x_bands != 1 && k != 1) return LB_ERR_UNSUPPORTED;  // column bands: lb_spmv only
+    return LB_OK;
 }
+
+// Entry points other than lb_spmv take one column band only.
+lb_status_t one_band(const lb_schedule_t &s) { return s.x_bands == 1 ? LB_OK : LB_ERR_UNSUPPORTED; }
 
 int spmm_pass_cols(int32_t k) { return k >= 8 ? 8 : (k >= 4 ? 4 : (k >= 2 ? 2 : 1)); }
 
@@ -214,6 +224,7 @@ size_t ws_bytes_for(const lb_csr_t *A, const lb_schedule_t &s, int32_t k) {
     if (s.kind != LB_MERGE_PATH) return 0;
     const int64_t W = static_cast<int64_t>(s.block_size) * s.items_per_thread;
     const int64_t T = lbk::merge_units(A->rows, A->nnz, W);
+    if (s.x_bands == 2) return lbk::merge_banded_ws_bytes(T, A->rows);
     return lbk::merge_ws_bytes(T, k <= 0 ? 1 : spmm_pass_cols(k));
 }
 
@@ -249,7 +260,7 @@ lb_status_t coo_schedule(const lb_coo_t *A, const lb_schedule_t *in, lb_schedule
     }
     lb_status_t st = fill_defaults(&s, out);
     if (st != LB_OK) return st;
-    if (out->kind == LB_WORK_QUEUE) return LB_ERR_UNSUPPORTED;
+    if (out->kind == LB_WORK_QUEUE || out->x_bands != 1) return LB_ERR_UNSUPPORTED;
     if (out->kind == LB_GROUP_MAPPED) {
         if (out->tiles_per_group != 1) return LB_ERR_UNSUPPORTED;
         if (!lbk::traversal_group_supported(out->group_size)) return LB_ERR_UNSUPPORTED;
@@ -261,7 +272,8 @@ lb_status_t csc_schedule(const lb_schedule_t *in, lb_schedule_t *out) {
     lb_schedule_t s = in ? *in : lb_schedule_t{LB_MERGE_PATH, 0, 0, 0, 0, 0};
     if (s.kind == LB_AUTO) s.kind = LB_MERGE_PATH;
     if (s.kind != LB_MERGE_PATH) return LB_ERR_UNSUPPORTED;
-    return fill_defaults(&s, out);
+    const lb_status_t st = fill_defaults(&s, out);
+    return st != LB_OK ? st : one_band(*out);
 }
 
 // ------------------------------------------------------------------ graph traversal checks
@@ -285,6 +297,8 @@ lb_status_t traversal_cfg(const lb_csr_t *G, const lb_schedule_t *in, lbk::trav_
     lb_schedule_t s = in ? *in : lb_schedule_t{LB_AUTO, 0, 0, 0, 0, 0};
     if (s.group_size < 0 || s.tiles_per_group < 0 || s.items_per_thread < 0 || s.block_size < 0 || s.grid_size < 0)
         return LB_ERR_INVALID_ARG;
+    if (s.x_bands < 0 || s.x_bands > 2) return LB_ERR_INVALID_ARG;
+    if (s.x_bands > 1) return LB_ERR_UNSUPPORTED;
     if (s.kind == LB_AUTO) {  // the Sec. 6.2 rule, as for SpMV; groups of at least 8 lanes
         const lb_schedule_t h = heuristic(G);
         s.kind = h.kind;
@@ -397,8 +411,12 @@ std::vector<lb_schedule_t> candidates(const lb_csr_t *A, int32_t k) {
             c.push_back({LB_GROUP_MAPPED, g, g, 0, 0, 0});
         }
         for (int g : {64, 256}) c.push_back({LB_WORK_QUEUE, g, g, 0, 0, 0});
+        // two column bands of x: only when x is larger than one XCD's L2
+        const int64_t x_bytes = A->cols * (A->value_dtype == LB_BF16 ? 2 : 4);
+        if (x_bytes >= (int64_t(4) << 20))
+            for (const auto &bi : {std::pair<int, int>{256, 8}, {256, 12}, {512, 8}, {128, 16}})
+                c.push_back({LB_MERGE_PATH, 0, 0, bi.second, bi.first, 0, 2});
     }
-    (void)A;
     return c;
 }
 
@@ -502,7 +520,8 @@ LB_API lb_status_t lb_spmv(const lb_csr_t *A, const void *x, lb_dtype_t x_dtype,
             return hip_status(lbk::group_mapped_spmv(d, x, y, r.group_size, r.group_size, r.grid_size,
                                                      static_cast<int32_t *>(workspace), hs));
         case LB_MERGE_PATH:
-            return hip_status(lbk::merge_spmv(d, x, y, r.block_size, r.items_per_thread, workspace, hs));
+            return hip_status(
+                lbk::merge_spmv(d, x, y, r.block_size, r.items_per_thread, r.x_bands, workspace, hs));
         default: return LB_ERR_INVALID_ARG;
     }
 }
@@ -531,7 +550,8 @@ lb_status_t backward_transposed_schedule(const lb_schedule_t *s, lb_schedule_t *
     lb_schedule_t in = s ? *s : lb_schedule_t{LB_MERGE_PATH, 0, 0, 0, 0, 0};
     if (in.kind == LB_AUTO) in.kind = LB_MERGE_PATH;
     if (in.kind != LB_MERGE_PATH) return LB_ERR_UNSUPPORTED;
-    return fill_defaults(&in, out);
+    const lb_status_t st = fill_defaults(&in, out);
+    return st != LB_OK ? st : one_band(*out);
 }
 
 LB_API lb_status_t lb_backward_transposed_workspace_size(const lb_csr_t *A, const lb_schedule_t *s, size_t *bytes) {
@@ -737,7 +757,7 @@ LB_API lb_status_t lb_spmm(const lb_csr_t *A, const void *X, lb_dtype_t x_dtype,
     lb_schedule_t r;
     st = resolve(A, k, s, &r);
     if (st != LB_OK) return st;
-    if (r.kind == LB_GROUP_MAPPED || r.kind == LB_WORK_QUEUE) return LB_ERR_UNSUPPORTED;
+    if (r.kind == LB_GROUP_MAPPED || r.kind == LB_WORK_QUEUE || one_band(r) != LB_OK) return LB_ERR_UNSUPPORTED;
     const size_t need = ws_bytes_for(A, r, k);
     if (need > 0 && (workspace_bytes < need || !workspace)) return LB_ERR_WORKSPACE_TOO_SMALL;
     hipStream_t hs = static_cast<hipStream_t>(stream);
@@ -767,6 +787,7 @@ LB_API lb_status_t lb_spmv_backward(const lb_csr_t *A, const void *x, lb_dtype_t
     lb_schedule_t r;
     st = fill_defaults(&in, &r);
     if (st != LB_OK) return st;
+    if (one_band(r) != LB_OK) return LB_ERR_UNSUPPORTED;
     const size_t need = ws_bytes_for(A, r, 0);
     if (workspace_bytes < need || !workspace) return LB_ERR_WORKSPACE_TOO_SMALL;
     hipStream_t hs = static_cast<hipStream_t>(stream);
@@ -821,7 +842,8 @@ static lb_status_t resolve_batched(const lb_batch_t *B, int32_t k, const lb_sche
             in = lb_schedule_t{LB_MERGE_PATH, 0, 0, 0, 0, 0};
     }
     if (in.kind != LB_MERGE_PATH) return LB_ERR_UNSUPPORTED;
-    return fill_defaults(&in, out);
+    const lb_status_t st = fill_defaults(&in, out);
+    return st != LB_OK ? st : one_band(*out);
 }
 
 LB_API lb_status_t lb_batched_workspace_size(const lb_batch_t *B, const lb_schedule_t *s, int32_t k, size_t *bytes) {
@@ -902,9 +924,12 @@ LB_API lb_status_t lb_autotune_workspace_size(const lb_csr_t *A, int32_t k, size
     if (!bytes || k < 1 || k > kMaxK) return LB_ERR_INVALID_ARG;
     lb_status_t st = check_csr(A);
     if (st != LB_OK) return st;
-    // the largest candidate workspace: the smallest merge-path unit
+    // the largest candidate workspace: the smallest merge-path unit, or the
+    // two-band candidates' (units of at least 2048 items, plus a rows buffer)
     const int64_t T = lbk::merge_units(A->rows, A->nnz, 128 * 4);
-    *bytes = lbk::merge_ws_bytes(T, spmm_pass_cols(k));
+    const size_t one = lbk::merge_ws_bytes(T, spmm_pass_cols(k));
+    const size_t two = k == 1 ? lbk::merge_banded_ws_bytes(lbk::merge_units(A->rows, A->nnz, 2048), A->rows) : 0;
+    *bytes = one > two ? one : two;
     return LB_OK;
 }
 

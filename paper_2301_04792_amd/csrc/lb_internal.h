@@ -58,6 +58,11 @@ inline size_t merge_ws_bytes(int64_t T, int kc) {
     return 2 * align256(static_cast<size_t>(T + 1) * 4) + align256(static_cast<size_t>(T) * 4) +
            align256(static_cast<size_t>(T) * 4 * kc);
 }
+// Two column bands: carries for 2T (unit, band) pairs, then the second
+// band's row sums (rows floats).
+inline size_t merge_banded_ws_bytes(int64_t T, int64_t rows) {
+    return merge_ws_bytes(2 * T, 1) + align256(static_cast<size_t>(rows) * 4);
+}
 inline merge_ws merge_ws_carve(void *base, int64_t T) {
     char *p = static_cast<char *>(base);
     merge_ws w;
@@ -87,7 +92,9 @@ bool merge_config_supported(int block, int items);
 hipError_t launch_fixup(int64_t T, int32_t rows, int32_t kc, const int32_t *carry_row,
                         const float *carry_val, float *y, int64_t ldy, hipStream_t s, const char *tag);
 
-hipError_t merge_spmv(const csr_dev &A, const void *x, float *y, int block, int items, void *ws,
+// bands 1 or 2 (column bands of x, one per half of the XCDs); the workspace
+// is merge_ws_bytes(T, 1) for one band, merge_banded_ws_bytes(T, rows) for two.
+hipError_t merge_spmv(const csr_dev &A, const void *x, float *y, int block, int items, int bands, void *ws,
                       hipStream_t s);
 
 hipError_t merge_spmm(const csr_dev &A, const void *X, int32_t k, int64_t ldx, float *Y, int64_t ldy,

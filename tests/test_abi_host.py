@@ -35,7 +35,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_version_and_status_strings():
     L = _abi.load()
-    assert L.lb_abi_version() == 1
+    assert L.lb_abi_version() == 2
     for st in range(8):
         assert L.lb_status_string(st)
     assert L.lb_status_string(99) == b"unknown status"
@@ -321,3 +321,35 @@ def test_spgemm_host_checks():
     assert L.lb_spgemm_count(ctypes.byref(A), ctypes.byref(B), FAKE, None, FAKE, need, None) == _abi.ERR_INVALID_ARG
     assert L.lb_spgemm_compute(ctypes.byref(A), ctypes.byref(B), FAKE, 0, FAKE, FAKE, need, None) \
         == _abi.ERR_INVALID_ARG
+
+
+def test_x_bands_host_checks():
+    """Two column bands: merge-path lb_spmv only; a wider workspace."""
+    L = _abi.load()
+    A = csr(1000, 1000, 5000)
+    st, out = resolve(A, sched("merge_path"))
+    assert st == _abi.OK and out.x_bands == 1
+    st, out = resolve(A, sched("merge_path", x_bands=2))
+    assert st == _abi.OK and out.x_bands == 2
+    assert resolve(A, sched("merge_path", x_bands=3))[0] == _abi.ERR_INVALID_ARG
+    assert resolve(A, sched("merge_path", x_bands=-1))[0] == _abi.ERR_INVALID_ARG
+    for kind in ("thread_mapped", "group_mapped", "work_queue"):
+        assert resolve(A, sched(kind, x_bands=2))[0] == _abi.ERR_UNSUPPORTED
+    assert resolve(A, sched("merge_path", x_bands=2), k=4)[0] == _abi.ERR_UNSUPPORTED
+    n = ctypes.c_size_t(0)
+    two = sched("merge_path", x_bands=2)
+    assert L.lb_workspace_size(ctypes.byref(A), ctypes.byref(two), 1, ctypes.byref(n)) == _abi.OK
+    T = -(-(1000 + 5000) // 2048)
+    a = lambda b: (b + 255) // 256 * 256  # noqa: E731
+    assert n.value == 2 * a((2 * T + 1) * 4) + a(2 * T * 4) + a(2 * T * 4) + a(1000 * 4)
+    assert L.lb_workspace_size(ctypes.byref(A), ctypes.byref(two), 0, ctypes.byref(n)) == _abi.ERR_UNSUPPORTED
+    assert spmv_call(A, s=two, wsb=n.value - 1) == _abi.ERR_WORKSPACE_TOO_SMALL
+    assert L.lb_spmm(ctypes.byref(A), FAKE, _abi.F32, 1, 1, FAKE, 1, ctypes.byref(two), FAKE, 1 << 30, None) == _abi.ERR_UNSUPPORTED
+    assert L.lb_spmv_backward(ctypes.byref(A), FAKE, _abi.F32, FAKE, FAKE, FAKE, ctypes.byref(two), FAKE, 1 << 30, None) == _abi.ERR_UNSUPPORTED
+    B = _abi.Batch(3, 100, 100, 500, FAKE, FAKE, FAKE, _abi.F32, FAKE, FAKE, FAKE)
+    assert L.lb_batched_workspace_size(ctypes.byref(B), ctypes.byref(two), 1, ctypes.byref(n)) == _abi.ERR_UNSUPPORTED
+    # the autotuner's workspace covers the two-band candidates of a large x
+    big = csr(4_000_000, 4_000_000, 40_000_000)
+    assert L.lb_autotune_workspace_size(ctypes.byref(big), 1, ctypes.byref(n)) == _abi.OK
+    T2 = -(-(4_000_000 + 40_000_000) // 2048)
+    assert n.value >= 2 * a((2 * T2 + 1) * 4) + 2 * a(2 * T2 * 4) + a(4_000_000 * 4)

@@ -28,6 +28,8 @@ def powerlaw2m():
 
 @pytest.mark.parametrize("name,params", [("merge_path", {}), ("merge_path", {"block_size": 512, "items_per_thread": 8}),
                                          ("merge_path", {"block_size": 256, "items_per_thread": 12}),
+                                         ("merge_path", {"x_bands": 2}),
+                                         ("merge_path", {"block_size": 512, "items_per_thread": 8, "x_bands": 2}),
                                          ("group_mapped", {"group_size": 64}), ("thread_mapped", {})])
 def test_powerlaw2m(powerlaw2m, name, params):
     A, x, ref, scale = powerlaw2m
@@ -79,7 +81,7 @@ def test_laplacian2048(dtype):
         xd = torch.from_numpy(x).to(DEV)
     Ld = lb.CSR.from_host(L, DEV)
     ref, scale = oracle_spmv(L, xh)
-    for params in ({}, {"block_size": 256, "items_per_thread": 12}):
+    for params in ({}, {"block_size": 256, "items_per_thread": 12}, {"x_bands": 2}):
         y = lb.spmv(Ld, xd, "merge_path", **params).cpu().numpy()
         assert_rows_close(y, ref, scale, what=f"laplacian {dtype} {params}")
     # 2^22 rows x 1024-lane groups: 2^32 threads unless the launch is capped

@@ -24,6 +24,7 @@ GROUP_CONFIGS = [(g, k) for g in (1, 2, 8, 32, 64, 128, 256, 1024) for k in (1, 
 SCHEDULES = ([("thread_mapped", {}), ("thread_mapped", {"block_size": 64}), ("auto", {})]
              + [("group_mapped", {"group_size": g, "tiles_per_group": k}) for g, k in GROUP_CONFIGS]
              + [("merge_path", {"block_size": b, "items_per_thread": i}) for b, i in MERGE_CONFIGS]
+             + [("merge_path", {"block_size": b, "items_per_thread": i, "x_bands": 2}) for b, i in MERGE_CONFIGS]
              + [("work_queue", {"group_size": g}) for g in (8, 64, 256, 1024)]
              + [("work_queue", {"group_size": 64, "grid_size": 1}), ("work_queue", {"group_size": 32, "grid_size": 7})])
 SCHED_IDS = [f"{n}-{'-'.join(f'{k}{v}' for k, v in p.items())}" for n, p in SCHEDULES]
@@ -58,7 +59,9 @@ def test_c1_all_schedules(c1, name, params):
                                          ("group_mapped", {"group_size": 16, "tiles_per_group": 16}),
                                          ("group_mapped", {"group_size": 256, "tiles_per_group": 256}),
                                          ("merge_path", {}), ("merge_path", {"block_size": 128, "items_per_thread": 4}),
-                                         ("merge_path", {"block_size": 512, "items_per_thread": 16})])
+                                         ("merge_path", {"block_size": 512, "items_per_thread": 16}),
+                                         ("merge_path", {"x_bands": 2}),
+                                         ("merge_path", {"block_size": 128, "items_per_thread": 4, "x_bands": 2})])
 def test_special_shapes(mname, name, params):
     A, x = S.special_matrices()[mname]
     Ad, xd = upload(A, x)
@@ -85,12 +88,44 @@ def test_integer_inputs_bit_exact(integer_powerlaw, name, params):
     assert np.array_equal(y, ref), f"{name} {params}: {int((y != ref).sum())} rows differ"
 
 
-def test_merge_path_bit_reproducible(c1):
+@pytest.mark.parametrize("bands", [1, 2])
+def test_merge_path_bit_reproducible(c1, bands):
     A, x = S.powerlaw_csr(5, 200_000, 200_000, 1.8, 50_000, 0.1)
     Ad, xd = upload(A, x)
-    y1 = lb.spmv(Ad, xd, "merge_path")
-    y2 = lb.spmv(Ad, xd, "merge_path")
+    y1 = lb.spmv(Ad, xd, "merge_path", x_bands=bands)
+    y2 = lb.spmv(Ad, xd, "merge_path", x_bands=bands)
     assert torch.equal(y1, y2)
+    ref, scale = oracle_spmv(A, x)
+    assert_rows_close(y1.cpu().numpy(), ref, scale, what=f"bands {bands}")
+
+
+@pytest.mark.parametrize("cols", [1, 2, 3, 1000, 4097])
+def test_x_bands_column_split(cols):
+    """Two bands split the columns at ceil(cols / 2): matrices whose nonzeros
+    all sit in one band, in both, or on the boundary column give the oracle's
+    rows (integer inputs: bit-exact) and the one-band result."""
+    rng = np.random.default_rng(cols)
+    m = 3000
+    L = rng.integers(0, 9, size=m)
+    ro = np.zeros(m + 1, dtype=np.int32)
+    ro[1:] = np.cumsum(L)
+    cb = (cols + 1) // 2
+    cases = {"low": (0, cb), "high": (cb, cols), "both": (0, cols), "edge": (max(cb - 1, 0), min(cb + 1, cols))}
+    for what, (lo, hi) in cases.items():
+        if hi <= lo:
+            continue
+        ci = rng.integers(lo, hi, size=int(ro[-1])).astype(np.int32)
+        for r in range(m):  # sorted within rows, duplicates allowed (summed)
+            ci[ro[r]:ro[r + 1]] = np.sort(ci[ro[r]:ro[r + 1]])
+        vals = rng.integers(-3, 4, size=ci.size).astype(np.float32)
+        A = S.CSRHost(ro, ci, vals, (m, cols))
+        x = rng.integers(-3, 4, size=cols).astype(np.float32)
+        Ad, xd = upload(A, x)
+        y2 = lb.spmv(Ad, xd, "merge_path", x_bands=2, block_size=128, items_per_thread=4)
+        y1 = lb.spmv(Ad, xd, "merge_path", block_size=128, items_per_thread=4)
+        ref, _ = oracle_spmv(A, x)
+        assert np.array_equal(y2.cpu().numpy().astype(np.float64), ref), (cols, what)
+        assert torch.equal(y1, y2), (cols, what)
 
 
 def _partition_cases():
@@ -126,7 +161,8 @@ def test_group_get_tile(K):
 
 @pytest.mark.parametrize("name,params", [("thread_mapped", {}), ("group_mapped", {"group_size": 32}),
                                          ("group_mapped", {"group_size": 64, "tiles_per_group": 64}),
-                                         ("merge_path", {}), ("merge_path", {"block_size": 512, "items_per_thread": 16})])
+                                         ("merge_path", {}), ("merge_path", {"block_size": 512, "items_per_thread": 16}),
+                                         ("merge_path", {"x_bands": 2})])
 def test_bf16_inputs(name, params):
     """BF16 values and x, FP32 products and sums, against the oracle on the
     same BF16 inputs (1e-5 rule) and on the FP32 originals (quantisation
