@@ -399,11 +399,15 @@ def main():
     lb.probe_stream_read(flush, pout)
     stream_ms, _ = kernel_avg_ms(lambda: lb.probe_stream_read(flush, pout), 5, "probe_stream")
     gather_ms, _ = kernel_avg_ms(lambda: lb.probe_gather(Ad.col_idx, xd, pout), 5, "probe_gather")
+    gather2_ms, _ = kernel_avg_ms(lambda: lb.probe_gather(Ad.col_idx, xd, pout, bands=2), 5, "probe_gather")
     ceilings = {"stream_read_gbs": round(flush.numel() * 4 / (stream_ms * 1e-3) / 1e9, 1),
                 "gather_only_ms": round(gather_ms, 5),
                 "gather_bound_gbs": round(B / (gather_ms * 1e-3) / 1e9, 1),
-                "note": "gather_only = sum of x[col_idx[j]] over all nonzeros; no SpMV kernel on this "
-                        "matrix can finish faster, so gather_bound_gbs caps its effective bandwidth"}
+                "gather_only_2band_ms": round(gather2_ms, 5),
+                "gather_bound_2band_gbs": round(B / (gather2_ms * 1e-3) / 1e9, 1),
+                "note": "gather_only = sum of x[col_idx[j]] over all nonzeros, with every XCD gathering from "
+                        "all of x (1 band) or each XCD from its half (2 bands, as the x_bands = 2 merge path); "
+                        "an SpMV kernel that gathers the same way cannot finish faster"}
     log(f"[bench] ceilings: {ceilings}")
 
     traffic, traffic_cfg = None, None

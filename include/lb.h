@@ -424,14 +424,19 @@ LB_API lb_status_t lb_bfs(const lb_csr_t *G, int64_t source, int32_t *depth, con
  *    device buffer) with non-temporal 16-byte loads and writes one partial
  *    sum per thread to out[grid * 256] (grid = 0 picks CUs x 8); the
  *    streaming-read ceiling of HBM.
- *  lb_probe_gather: sum over j of x[idx[j]] for j in [0, n) (idx read
- *    non-temporally, x gathered through the caches), one partial sum per
- *    thread to out[grid * 256]; with a matrix's col_idx as idx it times the
- *    x gather alone, the floor of any SpMV kernel on that matrix.
- * Both are asynchronous on `stream`; idx values must lie in x's range. */
+ *  lb_probe_gather: sum over j of x[idx[j]] for j in [0, n), x of cols
+ *    floats, one partial sum per thread to out[grid * 256]; with a matrix's
+ *    col_idx as idx it times the x gather alone, the floor of an SpMV kernel
+ *    on that matrix that gathers the same way.  bands = 1: idx read
+ *    non-temporally in a grid stride over all XCDs; bands = 2: the gather of
+ *    the two-band merge path (x_bands = 2): chunks of 2048 entries go to
+ *    pairs of blocks on different XCDs, each reading the whole chunk and
+ *    gathering only the entries of its half of x (grid rounded down to a
+ *    multiple of 8, at least 8).
+ * Both are asynchronous on `stream`; idx values must lie in [0, cols). */
 LB_API lb_status_t lb_probe_stream_read(const void *buf, size_t bytes, float *out, int32_t grid, void *stream);
-LB_API lb_status_t lb_probe_gather(const int32_t *idx, int64_t n, const float *x, float *out, int32_t grid,
-                                   void *stream);
+LB_API lb_status_t lb_probe_gather(const int32_t *idx, int64_t n, const float *x, int64_t cols, float *out,
+                                   int32_t grid, int32_t bands, void *stream);
 LB_API int32_t lb_probe_default_grid(void);
 
 /* Kernel timing.  While enabled, every launch made by this library records a

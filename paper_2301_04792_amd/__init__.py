@@ -410,12 +410,15 @@ def probe_stream_read(buf: torch.Tensor, out: torch.Tensor | None = None) -> tor
     return out
 
 
-def probe_gather(idx: torch.Tensor, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-    """Launch the gather probe: partial sums of x[idx] (measurement hook)."""
+def probe_gather(idx: torch.Tensor, x: torch.Tensor, out: torch.Tensor | None = None, bands: int = 1) -> torch.Tensor:
+    """Launch the gather probe: partial sums of x[idx], one band over all
+    XCDs or the two-band split of the x_bands = 2 merge path (measurement hook)."""
     grid = _lib.lb_probe_default_grid()
     out = out if out is not None else torch.empty(grid * 256, dtype=torch.float32, device=x.device)
-    _abi.check(_lib.lb_probe_gather(_ptr(idx), idx.numel(), _ptr(x), _ptr(out), grid, _stream(x.device)),
-               "lb_probe_gather")
+    if out.numel() < grid * 256:
+        raise ValueError("out holds one float per thread of the probe's grid")
+    _abi.check(_lib.lb_probe_gather(_ptr(idx), idx.numel(), _ptr(x), x.numel(), _ptr(out), grid, bands,
+                                    _stream(x.device)), "lb_probe_gather")
     return out
 
 

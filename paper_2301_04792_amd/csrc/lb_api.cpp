@@ -1035,12 +1035,16 @@ LB_API lb_status_t lb_probe_stream_read(const void *buf, size_t bytes, float *ou
     return hip_status(lbk::probe_stream_read(buf, bytes, out, grid, static_cast<hipStream_t>(stream)));
 }
 
-LB_API lb_status_t lb_probe_gather(const int32_t *idx, int64_t n, const float *x, float *out, int32_t grid,
-                                   void *stream) {
-    if (n < 0 || grid < 0 || !out || (n > 0 && (!idx || !x))) return LB_ERR_INVALID_ARG;
+LB_API lb_status_t lb_probe_gather(const int32_t *idx, int64_t n, const float *x, int64_t cols, float *out,
+                                   int32_t grid, int32_t bands, void *stream) {
+    if (n < 0 || cols < 0 || grid < 0 || !out || (n > 0 && (!idx || !x || cols == 0))) return LB_ERR_INVALID_ARG;
+    if (bands != 1 && bands != 2) return LB_ERR_INVALID_ARG;
+    if (cols > kMaxCoord) return LB_ERR_OVERFLOW;
     if (n == 0) return LB_OK;
     if (grid == 0) grid = lb_probe_default_grid();
-    return hip_status(lbk::probe_gather(idx, n, x, out, grid, static_cast<hipStream_t>(stream)));
+    if (bands == 2) grid = grid < 8 ? 8 : grid / 8 * 8;
+    return hip_status(lbk::probe_gather(idx, n, x, static_cast<int32_t>((cols + 1) / 2), out, grid, bands,
+                                        static_cast<hipStream_t>(stream)));
 }
 
 // ------------------------------------------------------------------ profiling

@@ -247,7 +247,8 @@ hipError_t bfs(const csr_dev &G, int32_t source, int32_t *depth, const trav_cfg 
 
 // ---- measurement probes -----------------------------------------------------------------
 hipError_t probe_stream_read(const void *buf, size_t bytes, float *out, int grid, hipStream_t s);
-hipError_t probe_gather(const int32_t *idx, int64_t n, const float *x, float *out, int grid, hipStream_t s);
+hipError_t probe_gather(const int32_t *idx, int64_t n, const float *x, int32_t cb, float *out, int grid, int bands,
+                        hipStream_t s);
 
 // ---- utilities ------------------------------------------------------------------------
 hipError_t fill_f32(float *p, int64_t n, float v, hipStream_t s);

@@ -353,3 +353,12 @@ def test_x_bands_host_checks():
     assert L.lb_autotune_workspace_size(ctypes.byref(big), 1, ctypes.byref(n)) == _abi.OK
     T2 = -(-(4_000_000 + 40_000_000) // 2048)
     assert n.value >= 2 * a((2 * T2 + 1) * 4) + 2 * a(2 * T2 * 4) + a(4_000_000 * 4)
+
+
+def test_probe_host_checks():
+    L = _abi.load()
+    assert L.lb_probe_gather(FAKE, 10, FAKE, 10, FAKE, 8, 3, None) == _abi.ERR_INVALID_ARG
+    assert L.lb_probe_gather(FAKE, 10, FAKE, 0, FAKE, 8, 1, None) == _abi.ERR_INVALID_ARG
+    assert L.lb_probe_gather(FAKE, -1, FAKE, 10, FAKE, 8, 1, None) == _abi.ERR_INVALID_ARG
+    assert L.lb_probe_gather(FAKE, 0, FAKE, 10, FAKE, 8, 2, None) == _abi.OK  # nothing to launch
+    assert L.lb_probe_stream_read(FAKE, 10, FAKE, 8, None) == _abi.ERR_INVALID_ARG  # not a multiple of 16

@@ -428,3 +428,16 @@ def test_backward_transposed_integer_and_autograd():
     scale = oracle.spmv_transpose(B.row_offsets, B.col_idx, B.values, w.cpu().numpy().astype(np.float64), B.n,
                                   abs_terms=True)
     assert_rows_close(gx_t.cpu().numpy(), ref, scale, what="autograd transposed dx")
+
+
+@pytest.mark.parametrize("bands", [1, 2])
+def test_gather_probe_sums(bands):
+    """The measurement probe gathers every x[idx[j]] exactly once in either
+    band form (integer x: the partial sums are exact)."""
+    rng = np.random.default_rng(bands)
+    n, cols = 1_000_003, 70_001
+    idx = torch.from_numpy(rng.integers(0, cols, size=n).astype(np.int32)).to(DEV)
+    x = torch.from_numpy(rng.integers(-2, 3, size=cols).astype(np.float32)).to(DEV)
+    out = lb.probe_gather(idx, x, bands=bands)
+    expect = x.double()[idx.long()].sum().item()
+    assert out.double().sum().item() == expect
