@@ -35,8 +35,10 @@
 // sums to y, the band-1 block to a rows-sized buffer; merge_combine adds the
 // buffer to y, and the fix-up adds both bands' carries (stored interleaved,
 // unit-major, so carry_row stays non-decreasing).  Both blocks read the
-// whole unit's col_idx (the second read mostly hits the Infinity Cache, so
-// these loads are temporal) and load values only for their own band.
+// whole unit's col_idx and values (the second read mostly hits the Infinity
+// Cache, so these loads are temporal; loading values only for the block's
+// own band was measured slower, as it waits for the column first) and
+// gather only their own band's x.
 #include "lb_device.h"
 #include "lb_internal.h"
 
@@ -153,8 +155,9 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
 #pragma unroll
         for (int u = 0; u < ITEMS; ++u) pv[u] = to_f32(v[u]) * xv[u];
     } else {
-        // band 0 takes col < cb, band 1 col >= cb; a value is loaded only
-        // for a nonzero of the block's own band
+        // band 0 takes col < cb, band 1 col >= cb: x is gathered only for a
+        // nonzero of the block's own band
+        VT v[ITEMS];
 #pragma unroll
         for (int u = 0; u < ITEMS; ++u) {
             const int32_t k = tid + u * BLOCK;
@@ -162,12 +165,12 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
             const int32_t jk = j0 + k;
             re[u] = ro[rk < re_last ? rk : re_last];
             c[u] = ci[jk < nz_last ? jk : nz_last];
+            v[u] = val[jk < nz_last ? jk : nz_last];
         }
 #pragma unroll
         for (int u = 0; u < ITEMS; ++u) {
-            const int32_t jk = j0 + tid + u * BLOCK;
             const bool mine = (c[u] >= cb) == (band == 1);
-            pv[u] = mine ? to_f32(val[jk < nz_last ? jk : nz_last]) * to_f32(x[c[u]]) : 0.f;
+            pv[u] = mine ? to_f32(v[u]) * to_f32(x[c[u]]) : 0.f;
         }
     }
 #pragma unroll
