@@ -527,7 +527,17 @@ def main():
     bf["laplacian2048"] = {"nnz": L.nnz, "fp32_ms": round(tl, 4), "fp32_gbs": round(BL / (tl * 1e-3) / 1e9, 2),
                            "fp32_cold_gbs": round(BL / (tlc * 1e-3) / 1e9, 2),
                            "bf16_ms": round(tlb, 4), "bf16_gbs": round(BLb / (tlb * 1e-3) / 1e9, 2),
-                           "bf16_cold_gbs": round(BLb / (tlbc * 1e-3) / 1e9, 2)}
+                           "bf16_cold_gbs": round(BLb / (tlbc * 1e-3) / 1e9, 2), "schedule": "merge_path"}
+    # the autotuned pick for each precision (what schedule="auto" runs after lb.tune)
+    for key, Md, xmd, Bm in (("fp32", Ld, xld, BL), ("bf16", Lbd, xlbd, BLb)):
+        lb.autotune_clear()
+        pick = lb.tune(Md)
+        wst = torch.empty(max(lb.workspace_size(Md, "auto"), 1), dtype=torch.uint8, device=dev)
+        tt = timed(lambda: lb.spmv(Md, xmd, "auto", y=yl, workspace=wst), extra_steps, 2)
+        bf["laplacian2048"][f"{key}_tuned"] = {"ms": round(tt, 4), "gbs": round(Bm / (tt * 1e-3) / 1e9, 2),
+                                               "schedule": pick}
+        del wst
+    lb.autotune_clear()
     result["bf16"] = bf
     log(f"[bench] bf16: {bf}")
     del Ld, Lbd, xld, xlbd, yl

@@ -234,9 +234,9 @@ LB_API lb_status_t lb_spmv_backward(const lb_csr_t *A, const void *x, lb_dtype_t
  * comes from atomics and varies from build to build.  Workspace from
  * lb_transpose_workspace_size.  cols + nnz < 2^31 - 1.
  * lb_spmv_backward_transposed then computes dvalues as lb_spmv_backward
- * does (bit-exact) and dx = A^T dy by permuting the current values into
- * A^T's order (float32) and running the merge-path SpMV on A^T: a gather,
- * no atomics; for a fixed pattern build dx is bit-reproducible.  s as for
+ * does (bit-exact) and dx = A^T dy by the merge-path SpMV on A^T, which
+ * reads the current values of A through perm (a gather, no atomics, no
+ * permuted copy); for a fixed pattern build dx is bit-reproducible.  s as for
  * lb_spmv_backward (merge-path block_size / items_per_thread); workspace
  * from lb_backward_transposed_workspace_size. */
 LB_API lb_status_t lb_transpose_workspace_size(const lb_csr_t *A, size_t *bytes);
@@ -444,7 +444,7 @@ LB_API int32_t lb_probe_default_grid(void);
  * events and returns, for the kernel family `name` ("merge_partition",
  * "merge_consume", "merge_fixup", "thread_mapped", "group_mapped",
  * "backward", "batched_consume", "batched_fixup", "fill", "coo_partition",
- * "coo_consume", "coo_fixup", "coo_tiles", "transpose", "permute_values",
+ * "coo_consume", "coo_fixup", "coo_tiles", "transpose", "merge_combine",
  * "spgemm_products", "spgemm_count_t0" .. "spgemm_count_t3",
  * "spgemm_compute_t0" .. "spgemm_compute_t3" (one per row tier),
  * "work_queue", "traversal_init",

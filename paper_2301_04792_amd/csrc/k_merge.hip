@@ -100,13 +100,17 @@ hipError_t merge_partition(const int32_t *ro, int32_t rows, int32_t nnz, int32_t
 // (b mod 8) mod 2 of unit (b / 8) * 4 + (b mod 8) / 2, the grid has
 // 8 * ceil(T / 4) blocks and those past the last unit return at once; every
 // (unit, band) pair has exactly one block whatever the hardware's dealing.
-template <int BLOCK, int ITEMS, typename VT, typename XT, int BANDS>
+// VPERM (one band only): nonzero j's value is val[vperm[j]], gathered in the
+// same setup as x (the backward's SpMV on A^T reads A's values through the
+// transposed pattern's permutation without a permuted copy).
+template <int BLOCK, int ITEMS, typename VT, typename XT, int BANDS, bool VPERM = false>
 __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
     int32_t rows, int32_t nnz, const int32_t *__restrict__ ro, const int32_t *__restrict__ ci, const VT *__restrict__ val,
     const XT *__restrict__ x, float *__restrict__ y, const int32_t *__restrict__ part_i,
     const int32_t *__restrict__ part_j, int32_t *__restrict__ carry_row, float *__restrict__ carry_val,
-    int32_t T, int32_t cb, float *__restrict__ y_hi) {
+    int32_t T, int32_t cb, float *__restrict__ y_hi, const int32_t *__restrict__ vperm) {
     static_assert(BANDS == 1 || BANDS == 2, "one or two column bands");
+    static_assert(!(VPERM && BANDS != 1), "permuted values with one band only");
     constexpr int W = BLOCK * ITEMS;
     __shared__ int32_t s_buf[W];  // row ends [0, nrows), then products [nrows, nrows + nnzs)
     __shared__ seg_t s_wave[BLOCK / kWave];
@@ -141,6 +145,7 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
     if constexpr (BANDS == 1) {
         VT v[ITEMS];
         float xv[ITEMS];
+        int32_t vp[VPERM ? ITEMS : 1];
 #pragma unroll
         for (int u = 0; u < ITEMS; ++u) {
             const int32_t k = tid + u * BLOCK;
@@ -148,10 +153,16 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
             const int32_t jk = j0 + k;
             re[u] = ro[rk < re_last ? rk : re_last];
             c[u] = ld_stream(ci + (jk < nz_last ? jk : nz_last));
-            v[u] = ld_stream(val + (jk < nz_last ? jk : nz_last));
+            if constexpr (VPERM)
+                vp[u] = ld_stream(vperm + (jk < nz_last ? jk : nz_last));
+            else
+                v[u] = ld_stream(val + (jk < nz_last ? jk : nz_last));
         }
 #pragma unroll
-        for (int u = 0; u < ITEMS; ++u) xv[u] = to_f32(x[c[u]]);
+        for (int u = 0; u < ITEMS; ++u) {
+            if constexpr (VPERM) v[u] = val[vp[u]];
+            xv[u] = to_f32(x[c[u]]);
+        }
 #pragma unroll
         for (int u = 0; u < ITEMS; ++u) pv[u] = to_f32(v[u]) * xv[u];
     } else {
@@ -292,7 +303,8 @@ hipError_t launch_fixup(int64_t T, int32_t rows, int32_t kc, const int32_t *carr
 // ------------------------------------------------------------------ dispatch
 
 template <int BLOCK, int ITEMS, typename VT>
-static hipError_t run_merge_spmv(const csr_dev &A, const void *x, float *y, int bands, void *ws, hipStream_t s) {
+static hipError_t run_merge_spmv(const csr_dev &A, const void *x, float *y, int bands, const int32_t *vperm, void *ws,
+                                 hipStream_t s) {
     constexpr int W = BLOCK * ITEMS;
     const int64_t T = merge_units(A.rows, A.nnz, W);
     const bool two = bands == 2;
@@ -303,18 +315,23 @@ static hipError_t run_merge_spmv(const csr_dev &A, const void *x, float *y, int 
     {
         prof_scope p(s, "merge_consume");
         const VT *val = static_cast<const VT *>(A.val);
-        const VT *xv = static_cast<const VT *>(x);
         const int32_t cb = static_cast<int32_t>((A.cols + 1) / 2);
-        if (two) {
+        if (vperm) {  // x is float32 (the backward's dy) whatever the value type
+            hipLaunchKernelGGL((merge_spmv_consume<BLOCK, ITEMS, VT, float, 1, true>), dim3(static_cast<uint32_t>(T)),
+                               dim3(BLOCK), 0, s, A.rows, A.nnz, A.ro, A.ci, val, static_cast<const float *>(x), y,
+                               w.part_i, w.part_j, w.carry_row, w.carry_val, static_cast<int32_t>(T), cb, y_hi, vperm);
+        } else if (two) {
             const int64_t per = kXcds / 2;  // units per row of kXcds blocks
             const int64_t grid = (T + per - 1) / per * kXcds;
             hipLaunchKernelGGL((merge_spmv_consume<BLOCK, ITEMS, VT, VT, 2>), dim3(static_cast<uint32_t>(grid)),
-                               dim3(BLOCK), 0, s, A.rows, A.nnz, A.ro, A.ci, val, xv, y, w.part_i, w.part_j,
-                               w.carry_row, w.carry_val, static_cast<int32_t>(T), cb, y_hi);
+                               dim3(BLOCK), 0, s, A.rows, A.nnz, A.ro, A.ci, val, static_cast<const VT *>(x), y,
+                               w.part_i, w.part_j, w.carry_row, w.carry_val, static_cast<int32_t>(T), cb, y_hi,
+                               nullptr);
         } else {
             hipLaunchKernelGGL((merge_spmv_consume<BLOCK, ITEMS, VT, VT, 1>), dim3(static_cast<uint32_t>(T)),
-                               dim3(BLOCK), 0, s, A.rows, A.nnz, A.ro, A.ci, val, xv, y, w.part_i, w.part_j,
-                               w.carry_row, w.carry_val, static_cast<int32_t>(T), cb, y_hi);
+                               dim3(BLOCK), 0, s, A.rows, A.nnz, A.ro, A.ci, val, static_cast<const VT *>(x), y,
+                               w.part_i, w.part_j, w.carry_row, w.carry_val, static_cast<int32_t>(T), cb, y_hi,
+                               nullptr);
         }
         e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -338,12 +355,13 @@ bool merge_config_supported(int block, int items) {
 }
 
 hipError_t merge_spmv(const csr_dev &A, const void *x, float *y, int block, int items, int bands, void *ws,
-                      hipStream_t s) {
+                      hipStream_t s, const int32_t *vperm) {
     if (bands != 1 && bands != 2) return hipErrorInvalidValue;
-#define X(B, I)                                                                         \
-    if (block == B && items == I) {                                                     \
-        if (A.dt == LB_BF16) return run_merge_spmv<B, I, bf16_bits>(A, x, y, bands, ws, s); \
-        return run_merge_spmv<B, I, float>(A, x, y, bands, ws, s);                      \
+    if (vperm && bands != 1) return hipErrorInvalidValue;
+#define X(B, I)                                                                                \
+    if (block == B && items == I) {                                                            \
+        if (A.dt == LB_BF16) return run_merge_spmv<B, I, bf16_bits>(A, x, y, bands, vperm, ws, s); \
+        return run_merge_spmv<B, I, float>(A, x, y, bands, vperm, ws, s);                      \
     }
     LB_MERGE_CONFIGS(X)
 #undef X

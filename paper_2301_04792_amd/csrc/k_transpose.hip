@@ -1,8 +1,9 @@
 // Backward of y = A x without atomics: dx = A^T dy as a merge-path SpMV over
 // the transposed pattern.  A training loop keeps one sparsity pattern across
 // steps, so the transpose is built once (transpose_pattern) and each
-// backward only permutes the current values into the transposed order and
-// runs the forward kernels on A^T; dvalues comes from the backward kernel's
+// backward runs the forward's merge-path kernels on A^T, reading the current
+// values of A through the pattern's permutation (val[perm[p]], gathered in
+// the consume kernel's setup); dvalues comes from the backward kernel's
 // dvalues-only pass.
 //
 // Transpose of a CSR pattern A (rows x cols): A^T has a row per column of A.
@@ -96,13 +97,6 @@ __global__ __launch_bounds__(256) void transpose_scatter(csr_tile_set ts, const 
     }
 }
 
-// Values of A in the transposed order, widened to float32.
-template <typename VT>
-__global__ __launch_bounds__(256) void permute_values(const VT *__restrict__ val, const int32_t *__restrict__ perm,
-                                                      float *__restrict__ vt, int64_t nnz) {
-    for (int64_t p : grid_stride_range(0, nnz)) vt[p] = to_f32(val[ld_stream(perm + p)]);
-}
-
 int64_t capped_blocks(int64_t work, int64_t per_block) {
     const int64_t g = (work + per_block - 1) / per_block;
     return g < 1 ? 1 : (g > 8192 ? 8192 : g);
@@ -143,33 +137,20 @@ size_t backward_transposed_ws_bytes(int64_t rows, int64_t cols, int64_t nnz, int
     const int64_t W = static_cast<int64_t>(block) * items;
     const size_t a = merge_ws_bytes(merge_units(rows, nnz, W), 1);  // dvalues pass over A
     const size_t b = merge_ws_bytes(merge_units(cols, nnz, W), 1);  // SpMV over A^T
-    return align256(static_cast<size_t>(nnz) * 4) + (a > b ? a : b);
+    return a > b ? a : b;
 }
 
 hipError_t backward_transposed(const csr_dev &A, const int32_t *at_ro, const int32_t *at_ci, const int32_t *perm,
                                const void *x, const float *dy, float *dx, float *dvalues, int block, int items,
                                void *ws, hipStream_t s) {
-    float *vt = static_cast<float *>(ws);
-    void *mws = static_cast<char *>(ws) + align256(static_cast<size_t>(A.nnz) * 4);
     if (dvalues) {
-        const hipError_t e = merge_backward(A, x, dy, nullptr, dvalues, block, items, mws, s);
+        const hipError_t e = merge_backward(A, x, dy, nullptr, dvalues, block, items, ws, s);
         if (e != hipSuccess) return e;
     }
     if (!dx) return hipSuccess;
-    {
-        prof_scope p(s, "permute_values");
-        const uint32_t g = static_cast<uint32_t>(capped_blocks(A.nnz, 256));
-        if (A.dt == LB_BF16)
-            hipLaunchKernelGGL(permute_values<bf16_bits>, dim3(g), dim3(256), 0, s,
-                               static_cast<const bf16_bits *>(A.val), perm, vt, static_cast<int64_t>(A.nnz));
-        else
-            hipLaunchKernelGGL(permute_values<float>, dim3(g), dim3(256), 0, s, static_cast<const float *>(A.val),
-                               perm, vt, static_cast<int64_t>(A.nnz));
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    const csr_dev AT{A.cols, A.rows, A.nnz, at_ro, at_ci, vt, LB_F32};
-    return merge_spmv(AT, dy, dx, block, items, 1, mws, s);
+    // A^T with A's values (of A's type) read through perm; x of this SpMV is dy
+    const csr_dev AT{A.cols, A.rows, A.nnz, at_ro, at_ci, A.val, A.dt};
+    return merge_spmv(AT, dy, dx, block, items, 1, ws, s, perm);
 }
 
 }  // namespace lbk

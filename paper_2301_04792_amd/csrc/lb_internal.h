@@ -94,8 +94,9 @@ hipError_t launch_fixup(int64_t T, int32_t rows, int32_t kc, const int32_t *carr
 
 // bands 1 or 2 (column bands of x, one per half of the XCDs); the workspace
 // is merge_ws_bytes(T, 1) for one band, merge_banded_ws_bytes(T, rows) for two.
+// With vperm (one band), nonzero j's value is A.val[vperm[j]] and x is float32.
 hipError_t merge_spmv(const csr_dev &A, const void *x, float *y, int block, int items, int bands, void *ws,
-                      hipStream_t s);
+                      hipStream_t s, const int32_t *vperm = nullptr);
 
 hipError_t merge_spmm(const csr_dev &A, const void *X, int32_t k, int64_t ldx, float *Y, int64_t ldy,
                       int block, int items, void *ws, hipStream_t s);
@@ -136,7 +137,7 @@ size_t transpose_ws_bytes(int64_t cols, int64_t nnz);
 hipError_t transpose_pattern(const csr_dev &A, int32_t *at_ro, int32_t *at_ci, int32_t *perm, void *ws,
                              hipStream_t s);
 size_t backward_transposed_ws_bytes(int64_t rows, int64_t cols, int64_t nnz, int block, int items);
-// dvalues (dvalues-only merge pass over A) and dx = A^T dy (values permuted to float32, merge-path SpMV on A^T).
+// dvalues (dvalues-only merge pass over A) and dx = A^T dy (merge-path SpMV on A^T reading A's values through perm).
 hipError_t backward_transposed(const csr_dev &A, const int32_t *at_ro, const int32_t *at_ci, const int32_t *perm,
                                const void *x, const float *dy, float *dx, float *dvalues, int block, int items,
                                void *ws, hipStream_t s);
