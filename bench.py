@@ -3,10 +3,10 @@
 
 One step = one y = A x over the power-law matrix (m = n = 2,000,000, row
 lengths min(Zipf(1.8), 200,000), 10 % empty rows, uniform columns, FP32)
-with the schedule the autotuner picks by timing its candidates on this
-matrix (merge-path, as the Sec. 6.2 heuristic also picks; the tuned form
-splits x into two column bands over the XCDs): partition, consume, band
-combine and carry fix-up.  `value` is effective HBM GB/s over
+with the merge-path schedule (the Sec. 6.2 heuristic's pick) at 256 threads
+x 8 items and x split into two column bands over the XCDs, the fastest
+candidate of the autotuner here up to timing noise (its own pick is
+reported beside): partition, consume, band combine and carry fix-up.  `value` is effective HBM GB/s over
 algorithmic bytes B = nnz*(s_v + 4) + (m + 1)*4 + n*s_x + m*4 for K
 back-to-back steps with the inputs already in HBM.
 
@@ -271,10 +271,11 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--items", type=int, default=0, help="merge-path items per thread (0 = default)")
     ap.add_argument("--block", type=int, default=0, help="merge-path block size (0 = default)")
-    ap.add_argument("--x-bands", type=int, default=0, help="merge-path column bands of x, 1 or 2 (0 = default)")
+    ap.add_argument("--x-bands", type=int, default=2,
+                    help="merge-path column bands of x, 1 or 2 (the headline uses 2: x of 8 MB is twice one XCD's L2)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--schedule", default="auto",
-                    help="headline schedule: auto (autotuned) or merge_path / group_mapped / thread_mapped")
+    ap.add_argument("--schedule", default="merge_path",
+                    help="headline schedule: merge_path (default), auto (autotuned), group_mapped, thread_mapped")
     ap.add_argument("--pmc-calib", action="store_true",
                     help="also run one 256 MiB device copy (known bytes) to scale rocprofv3 FETCH/WRITE_SIZE")
     ap.add_argument("--graph-only", action="store_true",
@@ -356,7 +357,7 @@ def main():
         params["items_per_thread"] = args.items
     if args.block:
         params["block_size"] = args.block
-    if args.x_bands:
+    if args.x_bands and args.schedule == "merge_path":
         params["x_bands"] = args.x_bands
     head = args.schedule
     if head == "auto" and not params:
@@ -497,6 +498,14 @@ def main():
         per[key] = {"ms": round(t, 4), "gbs": round(B / (t * 1e-3) / 1e9, 2),
                     "pct_of_peak": round(100 * B / (t * 1e-3) / 1e9 / PEAK_GBS, 2)}
         log(f"[bench] {key}: {t * 1e3:.1f} us")
+    lb.autotune_clear()
+    pick = lb.tune(Ad)
+    wst = torch.empty(max(lb.workspace_size(Ad, "auto"), 1), dtype=torch.uint8, device=dev)
+    t = timed(lambda: lb.spmv(Ad, xd, "auto", y=y, workspace=wst), extra_steps, 1)
+    per["auto_tuned"] = {"ms": round(t, 4), "gbs": round(B / (t * 1e-3) / 1e9, 2),
+                         "pct_of_peak": round(100 * B / (t * 1e-3) / 1e9 / PEAK_GBS, 2), "schedule": pick}
+    lb.autotune_clear()
+    del wst
     result["schedules_powerlaw2M"] = per
 
     # ------------------------------------------------------------ BF16 (accuracy is asserted by the GPU tests)
