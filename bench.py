@@ -94,7 +94,7 @@ def _consume_config(kernel_name):
     """(block, items, x_bands) from a merge_spmv_consume<...> kernel name."""
     import re
 
-    m = re.search(r"merge_spmv_consume<(\d+), (\d+), [^,]+, [^,]+, (\d+)>", kernel_name)
+    m = re.search(r"merge_spmv_consume<(\d+), (\d+), [^,]+, [^,]+, (\d+)[,>]", kernel_name)
     return (int(m.group(1)), int(m.group(2)), int(m.group(3))) if m else None
 
 
