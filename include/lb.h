@@ -332,9 +332,12 @@ LB_API lb_status_t lb_coo_merge_path_partition(const int32_t *row_idx, int64_t r
 /* CSC: y = A x with columns as tiles: entry j adds values[j] * x[c] into
  * y[row_idx[j]].  x is float32 (values float32 or BF16); y (rows float32)
  * is zeroed by the call and accumulated with float atomics, so it is not
- * bit-reproducible run to run.  LB_MERGE_PATH or LB_AUTO (the merge-path
- * split of the columns; block_size/items_per_thread as for CSR).
- * cols + nnz < 2^31 - 1.  Workspace from lb_csc_workspace_size. */
+ * bit-reproducible run to run.  Each block first sums its unit's products
+ * per row in LDS, so a row hit from many columns costs one atomic per
+ * block.  LB_MERGE_PATH or LB_AUTO (the merge-path split of the columns;
+ * block_size/items_per_thread as for CSR, default 512 x 8 here: larger
+ * units combine more).  cols + nnz < 2^31 - 1.  Workspace from
+ * lb_csc_workspace_size. */
 LB_API lb_status_t lb_csc_workspace_size(const lb_csc_t *A, const lb_schedule_t *s, size_t *bytes);
 LB_API lb_status_t lb_spmv_csc(const lb_csc_t *A, const void *x, lb_dtype_t x_dtype, float *y,
                                const lb_schedule_t *s, void *workspace, size_t workspace_bytes,

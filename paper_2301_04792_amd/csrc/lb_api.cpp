@@ -271,6 +271,10 @@ lb_status_t coo_schedule(const lb_coo_t *A, const lb_schedule_t *in, lb_schedule
 lb_status_t csc_schedule(const lb_schedule_t *in, lb_schedule_t *out) {
     lb_schedule_t s = in ? *in : lb_schedule_t{LB_MERGE_PATH, 0, 0, 0, 0, 0};
     if (s.kind == LB_AUTO) s.kind = LB_MERGE_PATH;
+    if (s.block_size == 0 && s.items_per_thread == 0) {  // larger units combine more rows per block
+        s.block_size = 512;
+        s.items_per_thread = 8;
+    }
     if (s.kind != LB_MERGE_PATH) return LB_ERR_UNSUPPORTED;
     const lb_status_t st = fill_defaults(&s, out);
     return st != LB_OK ? st : one_band(*out);
@@ -719,9 +723,11 @@ LB_API lb_status_t lb_spmv_csc(const lb_csc_t *A, const void *x, lb_dtype_t x_dt
     if (A->rows == 0) return LB_OK;
     hipError_t e = lbk::fill_f32(y, A->rows, 0.f, hs);
     if (e != hipSuccess || A->nnz == 0) return hip_status(e);
-    // the scatter of the backward pass: columns are its tiles, x its per-tile value
+    // the scatter of the backward pass: columns are its tiles, x its per-tile
+    // value; a long row of A is hit from many columns, so each block first
+    // sums its products per row in LDS
     return hip_status(lbk::merge_backward(to_dev(&c), nullptr, static_cast<const float *>(x), y, nullptr,
-                                          r.block_size, r.items_per_thread, workspace, hs));
+                                          r.block_size, r.items_per_thread, workspace, hs, true));
 }
 
 LB_API lb_status_t lb_traversal_workspace_size(const lb_csr_t *G, size_t *bytes) {

@@ -101,8 +101,10 @@ hipError_t merge_spmv(const csr_dev &A, const void *x, float *y, int block, int 
 hipError_t merge_spmm(const csr_dev &A, const void *X, int32_t k, int64_t ldx, float *Y, int64_t ldy,
                       int block, int items, void *ws, hipStream_t s);
 
+// combine_dx (dx only): products are summed per target in LDS before the
+// global atomics (for scatters whose targets repeat within a unit).
 hipError_t merge_backward(const csr_dev &A, const void *x, const float *dy, float *dx, float *dvalues,
-                          int block, int items, void *ws, hipStream_t s);
+                          int block, int items, void *ws, hipStream_t s, bool combine_dx = false);
 
 // ---- batched ------------------------------------------------------------------------
 struct batch_dev {

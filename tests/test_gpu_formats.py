@@ -107,8 +107,26 @@ def test_csc():
     Ai, xi = S.integer_valued(A, 6)
     K = S.to_csc(Ai)
     exact = oracle.spmv_csc(Ai.m, K.col_offsets, K.row_idx, K.values, xi)
-    y = lb.spmv_csc(lb.CSC.from_host(K, DEV), xdev(xi)).cpu().numpy()
-    assert np.array_equal(y.astype(np.float64), exact)
+    Kd = lb.CSC.from_host(K, DEV)
+    # every table size of the per-block combining (1024, 2048, 4096 slots;
+    # 8192-item units can overflow 4096 slots and send products straight on)
+    for params in ({}, {"block_size": 128, "items_per_thread": 4}, {"block_size": 128, "items_per_thread": 8},
+                   {"block_size": 128, "items_per_thread": 12}, {"block_size": 512, "items_per_thread": 16}):
+        y = lb.spmv_csc(Kd, xdev(xi), "merge_path", **params).cpu().numpy()
+        assert np.array_equal(y.astype(np.float64), exact), params
+    # a dense row: every column scatters into the same row of y
+    m, n = 64, 20_000
+    rng = np.random.default_rng(36)
+    dense = np.zeros((m, n), dtype=np.float32)
+    dense[7, :] = rng.integers(-2, 3, size=n)
+    dense[rng.integers(0, m, size=3000), rng.integers(0, n, size=3000)] = 1.0
+    r, c = np.nonzero(dense)  # row-major order: a CSR
+    ro = np.zeros(m + 1, dtype=np.int32)
+    ro[1:] = np.cumsum(np.bincount(r, minlength=m))
+    Kh = S.to_csc(S.CSRHost(ro, c.astype(np.int32), dense[r, c], (m, n)))
+    xh = rng.integers(-2, 3, size=n).astype(np.float32)
+    yh = lb.spmv_csc(lb.CSC.from_host(Kh, DEV), xdev(xh)).cpu().numpy()
+    assert np.array_equal(yh.astype(np.float64), dense.astype(np.float64) @ xh.astype(np.float64))
     # BF16 values with float32 x
     Kb = S.to_csc(A.with_values(S.to_bf16_bits(A.values)))
     x = S.random_vector(35, A.n)
