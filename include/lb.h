@@ -112,7 +112,17 @@ typedef struct lb_csr_t {
  *                    XCD's L2 (4 MiB) and its columns are scattered; costs a
  *                    second read of col_idx (served mostly by the Infinity
  *                    Cache) and a rows-sized buffer in the workspace.  Other
- *                    entry points accept only 0 or 1. */
+ *                    entry points accept only 0 or 1.
+ *  vector_width      LB_MERGE_PATH in lb_spmv with one band: 1 or 4 (default
+ *                    1).  With 4 each lane loads four consecutive nonzeros
+ *                    (one 16-byte column load, one 16- or 8-byte value load)
+ *                    instead of one: more bytes in flight per instruction,
+ *                    which pays on matrices with local columns (stencils);
+ *                    on scattered columns it costs the x gathers' line
+ *                    sharing.  Runs the one-nonzero form when nnz < 4 or
+ *                    col_idx / values are not 16- / 16- (BF16: 8-) byte
+ *                    aligned; items_per_thread must be a multiple of 4.
+ *                    Other entry points accept only 0 or 1. */
 typedef struct lb_schedule_t {
     lb_sched_kind_t kind;
     int32_t group_size;
@@ -121,6 +131,7 @@ typedef struct lb_schedule_t {
     int32_t block_size;
     int32_t grid_size;
     int32_t x_bands;
+    int32_t vector_width;
 } lb_schedule_t;
 
 /* Independent CSR matrices stored back to back (a block-diagonal matrix).

@@ -52,11 +52,12 @@ def _stream(device: torch.device):
 
 
 def make_schedule(schedule="merge_path", group_size=0, tiles_per_group=0, items_per_thread=0,
-                  block_size=0, grid_size=0, x_bands=0) -> _abi.Schedule:
+                  block_size=0, grid_size=0, x_bands=0, vector_width=0) -> _abi.Schedule:
     if isinstance(schedule, _abi.Schedule):
         return schedule
     kind = _abi.KIND_BY_NAME[schedule] if isinstance(schedule, str) else int(schedule)
-    return _abi.Schedule(kind, group_size, tiles_per_group, items_per_thread, block_size, grid_size, x_bands)
+    return _abi.Schedule(kind, group_size, tiles_per_group, items_per_thread, block_size, grid_size, x_bands,
+                         vector_width)
 
 
 class Pattern:

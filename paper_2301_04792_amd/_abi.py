@@ -33,12 +33,14 @@ class CSR(ctypes.Structure):
 class Schedule(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("group_size", ctypes.c_int32),
                 ("tiles_per_group", ctypes.c_int32), ("items_per_thread", ctypes.c_int32),
-                ("block_size", ctypes.c_int32), ("grid_size", ctypes.c_int32), ("x_bands", ctypes.c_int32)]
+                ("block_size", ctypes.c_int32), ("grid_size", ctypes.c_int32), ("x_bands", ctypes.c_int32),
+                ("vector_width", ctypes.c_int32)]
 
     def as_dict(self):
         return {"schedule": NAME_BY_KIND.get(self.kind, self.kind), "group_size": self.group_size,
                 "tiles_per_group": self.tiles_per_group, "items_per_thread": self.items_per_thread,
-                "block_size": self.block_size, "grid_size": self.grid_size, "x_bands": self.x_bands}
+                "block_size": self.block_size, "grid_size": self.grid_size, "x_bands": self.x_bands,
+                "vector_width": self.vector_width}
 
 
 class Batch(ctypes.Structure):

@@ -103,7 +103,15 @@ hipError_t merge_partition(const int32_t *ro, int32_t rows, int32_t nnz, int32_t
 // VPERM (one band only): nonzero j's value is val[vperm[j]], gathered in the
 // same setup as x (the backward's SpMV on A^T reads A's values through the
 // transposed pattern's permutation without a permuted copy).
-template <int BLOCK, int ITEMS, typename VT, typename XT, int BANDS, bool VPERM = false>
+// VEC = 4 (one band, no VPERM): each lane loads four consecutive nonzeros
+// with one 16-byte column load and one 16- (float) or 8-byte (BF16) value
+// load, from groups aligned to 4 in the arrays, so a lane has four times
+// the bytes in flight per instruction.  The x gathers of a wavefront then
+// stride by 4 nonzeros, which costs the line sharing that lane-consecutive
+// gathers get from long sorted rows, so this form pays only where columns
+// are local (a stencil).  The launcher requires nnz >= 4 and aligned
+// col_idx / values.
+template <int BLOCK, int ITEMS, typename VT, typename XT, int BANDS, bool VPERM = false, int VEC = 1>
 __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
     int32_t rows, int32_t nnz, const int32_t *__restrict__ ro, const int32_t *__restrict__ ci, const VT *__restrict__ val,
     const XT *__restrict__ x, float *__restrict__ y, const int32_t *__restrict__ part_i,
@@ -111,6 +119,7 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
     int32_t T, int32_t cb, float *__restrict__ y_hi, const int32_t *__restrict__ vperm) {
     static_assert(BANDS == 1 || BANDS == 2, "one or two column bands");
     static_assert(!(VPERM && BANDS != 1), "permuted values with one band only");
+    static_assert(VEC == 1 || (VEC == 4 && BANDS == 1 && !VPERM && ITEMS % 4 == 0), "vector loads: one band");
     constexpr int W = BLOCK * ITEMS;
     __shared__ int32_t s_buf[W];  // row ends [0, nrows), then products [nrows, nrows + nnzs)
     __shared__ seg_t s_wave[BLOCK / kWave];
@@ -142,7 +151,49 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
     const int32_t nz_last = nnzs > 0 ? j1 - 1 : (j0 < nnz ? j0 : nnz - 1);  // a valid nonzero index
     int32_t re[ITEMS], c[ITEMS];
     float pv[ITEMS];
-    if constexpr (BANDS == 1) {
+    if constexpr (VEC == 4) {
+        using vec_t = typename vec4_of<VT>::type;
+        typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+        // groups [vs, vs + 4) with vs a multiple of 4: the block's W / 4
+        // groups start at base; a group is used when it lies inside the
+        // array (vs <= last_full) and holds a nonzero of the unit
+        const int32_t base = j0 & ~3;
+        const int32_t last_full = (nnz & ~3) - 4;  // >= 0: nnz >= 4
+        const int32_t vmax = last_full < (nz_last & ~3) ? last_full : (nz_last & ~3);
+        VT v[ITEMS];
+#pragma unroll
+        for (int u = 0; u < ITEMS; ++u) {
+            const int32_t rk = i0 + 1 + tid + u * BLOCK;
+            re[u] = ro[rk < re_last ? rk : re_last];
+        }
+#pragma unroll
+        for (int q = 0; q < ITEMS / 4; ++q) {
+            const int32_t vs = base + 4 * (tid + q * BLOCK);
+            const int32_t vc = vs <= vmax ? vs : vmax;
+            const i32x4 c4 = ld_stream(reinterpret_cast<const i32x4 *>(ci + vc));
+            const vec_t v4 = ld_stream(reinterpret_cast<const vec_t *>(val + vc));
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                c[4 * q + e] = c4[e];
+                v[4 * q + e] = v4[e];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < ITEMS; ++u) pv[u] = to_f32(v[u]) * to_f32(x[c[u]]);
+#pragma unroll
+        for (int u = 0; u < ITEMS; ++u) {
+            const int k = tid + u * BLOCK;
+            if (k < nrows) s_re[k] = re[u] - j0;
+            const int32_t vs = base + 4 * (tid + (u / 4) * BLOCK);
+            const int32_t kp = vs + (u % 4) - j0;
+            if (vs <= vmax && kp >= 0 && kp < nnzs) s_pv[kp] = pv[u];
+        }
+        // nonzeros past the used groups (the unit running past base + W, or
+        // the array's last nnz mod 4 entries): at most 3
+        const int32_t cov_end = base + W < vmax + 4 ? base + W : vmax + 4;
+        const int32_t g = (cov_end > j0 ? cov_end : j0) + tid;
+        if (tid < 3 && g < j1) s_pv[g - j0] = to_f32(val[g]) * to_f32(x[ci[g]]);
+    } else if constexpr (BANDS == 1) {
         VT v[ITEMS];
         float xv[ITEMS];
         int32_t vp[VPERM ? ITEMS : 1];
@@ -184,11 +235,13 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
             pv[u] = mine ? to_f32(v[u]) * to_f32(x[c[u]]) : 0.f;
         }
     }
+    if constexpr (VEC == 1) {
 #pragma unroll
-    for (int u = 0; u < ITEMS; ++u) {
-        const int k = tid + u * BLOCK;
-        if (k < nrows) s_re[k] = re[u] - j0;
-        if (k < nnzs) s_pv[k] = pv[u];
+        for (int u = 0; u < ITEMS; ++u) {
+            const int k = tid + u * BLOCK;
+            if (k < nrows) s_re[k] = re[u] - j0;
+            if (k < nnzs) s_pv[k] = pv[u];
+        }
     }
     __syncthreads();
 
@@ -302,9 +355,16 @@ hipError_t launch_fixup(int64_t T, int32_t rows, int32_t kc, const int32_t *carr
 
 // ------------------------------------------------------------------ dispatch
 
+// The four-nonzero load form needs whole aligned groups: nnz >= 4, col_idx
+// 16-byte aligned and the values aligned to their 4-element vector.
+static bool vector_loads_ok(const csr_dev &A) {
+    const uintptr_t va = A.dt == LB_BF16 ? 8 : 16;
+    return A.nnz >= 4 && reinterpret_cast<uintptr_t>(A.ci) % 16 == 0 && reinterpret_cast<uintptr_t>(A.val) % va == 0;
+}
+
 template <int BLOCK, int ITEMS, typename VT>
-static hipError_t run_merge_spmv(const csr_dev &A, const void *x, float *y, int bands, const int32_t *vperm, void *ws,
-                                 hipStream_t s) {
+static hipError_t run_merge_spmv(const csr_dev &A, const void *x, float *y, int bands, const int32_t *vperm, int vec,
+                                 void *ws, hipStream_t s) {
     constexpr int W = BLOCK * ITEMS;
     const int64_t T = merge_units(A.rows, A.nnz, W);
     const bool two = bands == 2;
@@ -320,6 +380,11 @@ static hipError_t run_merge_spmv(const csr_dev &A, const void *x, float *y, int 
             hipLaunchKernelGGL((merge_spmv_consume<BLOCK, ITEMS, VT, float, 1, true>), dim3(static_cast<uint32_t>(T)),
                                dim3(BLOCK), 0, s, A.rows, A.nnz, A.ro, A.ci, val, static_cast<const float *>(x), y,
                                w.part_i, w.part_j, w.carry_row, w.carry_val, static_cast<int32_t>(T), cb, y_hi, vperm);
+        } else if (vec == 4 && vector_loads_ok(A)) {
+            hipLaunchKernelGGL((merge_spmv_consume<BLOCK, ITEMS, VT, VT, 1, false, 4>), dim3(static_cast<uint32_t>(T)),
+                               dim3(BLOCK), 0, s, A.rows, A.nnz, A.ro, A.ci, val, static_cast<const VT *>(x), y,
+                               w.part_i, w.part_j, w.carry_row, w.carry_val, static_cast<int32_t>(T), cb, y_hi,
+                               nullptr);
         } else if (two) {
             const int64_t per = kXcds / 2;  // units per row of kXcds blocks
             const int64_t grid = (T + per - 1) / per * kXcds;
@@ -355,13 +420,15 @@ bool merge_config_supported(int block, int items) {
 }
 
 hipError_t merge_spmv(const csr_dev &A, const void *x, float *y, int block, int items, int bands, void *ws,
-                      hipStream_t s, const int32_t *vperm) {
+                      hipStream_t s, const int32_t *vperm, int vec) {
     if (bands != 1 && bands != 2) return hipErrorInvalidValue;
-    if (vperm && bands != 1) return hipErrorInvalidValue;
-#define X(B, I)                                                                                \
-    if (block == B && items == I) {                                                            \
-        if (A.dt == LB_BF16) return run_merge_spmv<B, I, bf16_bits>(A, x, y, bands, vperm, ws, s); \
-        return run_merge_spmv<B, I, float>(A, x, y, bands, vperm, ws, s);                      \
+    if (vec != 1 && vec != 4) return hipErrorInvalidValue;
+    if ((vperm || vec == 4) && bands != 1) return hipErrorInvalidValue;
+    if (vperm && vec != 1) return hipErrorInvalidValue;
+#define X(B, I)                                                                                     \
+    if (block == B && items == I) {                                                                 \
+        if (A.dt == LB_BF16) return run_merge_spmv<B, I, bf16_bits>(A, x, y, bands, vperm, vec, ws, s); \
+        return run_merge_spmv<B, I, float>(A, x, y, bands, vperm, vec, ws, s);                      \
     }
     LB_MERGE_CONFIGS(X)
 #undef X

@@ -92,7 +92,7 @@ void tune_load_locked() {
     if (!p || !*p) return;
     std::ifstream f(p);
     std::string line;
-    // one entry per line: rows cols nnz k dtype batched kind group tiles items block grid [x_bands]
+    // one entry per line: rows cols nnz k dtype batched kind group tiles items block grid [x_bands vector_width]
     while (std::getline(f, line)) {
         std::istringstream ss(line);
         tune_key key{};
@@ -101,6 +101,7 @@ void tune_load_locked() {
         if (ss >> key.rows >> key.cols >> key.nnz >> key.k >> key.dtype >> key.batched >> kind >> s.group_size >>
             s.tiles_per_group >> s.items_per_thread >> s.block_size >> s.grid_size) {
             if (!(ss >> s.x_bands)) s.x_bands = 1;
+            if (!(ss >> s.vector_width)) s.vector_width = 1;
             s.kind = static_cast<lb_sched_kind_t>(kind);
             g_tune[key] = s;
         }
@@ -116,7 +117,8 @@ void tune_save_locked() {
         const lb_schedule_t &s = kv.second;
         f << k.rows << ' ' << k.cols << ' ' << k.nnz << ' ' << k.k << ' ' << k.dtype << ' ' << k.batched << ' '
           << static_cast<int>(s.kind) << ' ' << s.group_size << ' ' << s.tiles_per_group << ' '
-          << s.items_per_thread << ' ' << s.block_size << ' ' << s.grid_size << ' ' << s.x_bands << '\n';
+          << s.items_per_thread << ' ' << s.block_size << ' ' << s.grid_size << ' ' << s.x_bands << ' '
+          << s.vector_width << '\n';
     }
 }
 
@@ -145,6 +147,9 @@ lb_status_t fill_defaults(const lb_schedule_t *in, lb_schedule_t *out) {
     if (s.x_bands < 0 || s.x_bands > 2) return LB_ERR_INVALID_ARG;
     if (s.x_bands == 0) s.x_bands = 1;
     if (s.x_bands == 2 && s.kind != LB_MERGE_PATH) return LB_ERR_UNSUPPORTED;
+    if (s.vector_width == 0) s.vector_width = 1;
+    if (s.vector_width != 1 && s.vector_width != 4) return LB_ERR_INVALID_ARG;
+    if (s.vector_width == 4 && (s.kind != LB_MERGE_PATH || s.x_bands != 1)) return LB_ERR_UNSUPPORTED;
     switch (s.kind) {
         case LB_THREAD_MAPPED:
             if (s.block_size == 0) s.block_size = kDefaultBlock;
@@ -161,6 +166,7 @@ lb_status_t fill_defaults(const lb_schedule_t *in, lb_schedule_t *out) {
             if (s.block_size == 0) s.block_size = kDefaultBlock;
             if (s.items_per_thread == 0) s.items_per_thread = kDefaultItems;
             if (!lbk::merge_config_supported(s.block_size, s.items_per_thread)) return LB_ERR_UNSUPPORTED;
+            if (s.vector_width == 4 && s.items_per_thread % 4 != 0) return LB_ERR_UNSUPPORTED;
             break;
         case LB_WORK_QUEUE:
             if (s.group_size == 0) s.group_size = kDefaultGroup;
@@ -210,12 +216,16 @@ lb_status_t resolve(const lb_csr_t *A, int32_t k, const lb_schedule_t *in, lb_sc
     }
     const lb_status_t st = fill_defaults(&s, out);
     if (st != LB_OK) return st;
-    if (out->x_bands != 1 && k != 1) return LB_ERR_UNSUPPORTED;  // column bands: lb_spmv only
+    // column bands and vector loads: lb_spmv only
+    if ((out->x_bands != 1 || out->vector_width != 1) && k != 1) return LB_ERR_UNSUPPORTED;
     return LB_OK;
 }
 
-// Entry points other than lb_spmv take one column band only.
-lb_status_t one_band(const lb_schedule_t &s) { return s.x_bands == 1 ? LB_OK : LB_ERR_UNSUPPORTED; }
+// Entry points other than lb_spmv take the plain merge-path consume only
+// (one column band, one nonzero per lane and load).
+lb_status_t one_band(const lb_schedule_t &s) {
+    return s.x_bands == 1 && s.vector_width == 1 ? LB_OK : LB_ERR_UNSUPPORTED;
+}
 
 int spmm_pass_cols(int32_t k) { return k >= 8 ? 8 : (k >= 4 ? 4 : (k >= 2 ? 2 : 1)); }
 
@@ -260,7 +270,7 @@ lb_status_t coo_schedule(const lb_coo_t *A, const lb_schedule_t *in, lb_schedule
     }
     lb_status_t st = fill_defaults(&s, out);
     if (st != LB_OK) return st;
-    if (out->kind == LB_WORK_QUEUE || out->x_bands != 1) return LB_ERR_UNSUPPORTED;
+    if (out->kind == LB_WORK_QUEUE || one_band(*out) != LB_OK) return LB_ERR_UNSUPPORTED;
     if (out->kind == LB_GROUP_MAPPED) {
         if (out->tiles_per_group != 1) return LB_ERR_UNSUPPORTED;
         if (!lbk::traversal_group_supported(out->group_size)) return LB_ERR_UNSUPPORTED;
@@ -302,7 +312,8 @@ lb_status_t traversal_cfg(const lb_csr_t *G, const lb_schedule_t *in, lbk::trav_
     if (s.group_size < 0 || s.tiles_per_group < 0 || s.items_per_thread < 0 || s.block_size < 0 || s.grid_size < 0)
         return LB_ERR_INVALID_ARG;
     if (s.x_bands < 0 || s.x_bands > 2) return LB_ERR_INVALID_ARG;
-    if (s.x_bands > 1) return LB_ERR_UNSUPPORTED;
+    if (s.vector_width != 0 && s.vector_width != 1 && s.vector_width != 4) return LB_ERR_INVALID_ARG;
+    if (s.x_bands > 1 || s.vector_width > 1) return LB_ERR_UNSUPPORTED;
     if (s.kind == LB_AUTO) {  // the Sec. 6.2 rule, as for SpMV; groups of at least 8 lanes
         const lb_schedule_t h = heuristic(G);
         s.kind = h.kind;
@@ -419,7 +430,10 @@ std::vector<lb_schedule_t> candidates(const lb_csr_t *A, int32_t k) {
         const int64_t x_bytes = A->cols * (A->value_dtype == LB_BF16 ? 2 : 4);
         if (x_bytes >= (int64_t(4) << 20))
             for (const auto &bi : {std::pair<int, int>{256, 8}, {256, 12}, {512, 8}, {128, 16}})
-                c.push_back({LB_MERGE_PATH, 0, 0, bi.second, bi.first, 0, 2});
+                c.push_back({LB_MERGE_PATH, 0, 0, bi.second, bi.first, 0, 2, 1});
+        // four nonzeros per lane and load (pays where columns are local)
+        for (const auto &bi : {std::pair<int, int>{256, 8}, {256, 12}, {128, 16}, {512, 8}})
+            c.push_back({LB_MERGE_PATH, 0, 0, bi.second, bi.first, 0, 1, 4});
     }
     return c;
 }
@@ -524,8 +538,8 @@ LB_API lb_status_t lb_spmv(const lb_csr_t *A, const void *x, lb_dtype_t x_dtype,
             return hip_status(lbk::group_mapped_spmv(d, x, y, r.group_size, r.group_size, r.grid_size,
                                                      static_cast<int32_t *>(workspace), hs));
         case LB_MERGE_PATH:
-            return hip_status(
-                lbk::merge_spmv(d, x, y, r.block_size, r.items_per_thread, r.x_bands, workspace, hs));
+            return hip_status(lbk::merge_spmv(d, x, y, r.block_size, r.items_per_thread, r.x_bands, workspace, hs,
+                                              nullptr, r.vector_width));
         default: return LB_ERR_INVALID_ARG;
     }
 }

@@ -32,6 +32,18 @@ __device__ __forceinline__ T ld_stream(const T *p) {
     return __builtin_nontemporal_load(p);
 }
 
+// Four consecutive elements as one vector load (16 bytes of float, 8 of BF16).
+template <typename T>
+struct vec4_of;
+template <>
+struct vec4_of<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct vec4_of<bf16_bits> {
+    typedef uint16_t type __attribute__((ext_vector_type(4)));
+};
+
 // ---------------------------------------------------------------- merge-path split (Sec. 5.2.1)
 
 // Count of the positions r in [lo, hi) with key(r) < d, where key is

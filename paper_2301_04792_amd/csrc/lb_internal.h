@@ -95,8 +95,11 @@ hipError_t launch_fixup(int64_t T, int32_t rows, int32_t kc, const int32_t *carr
 // bands 1 or 2 (column bands of x, one per half of the XCDs); the workspace
 // is merge_ws_bytes(T, 1) for one band, merge_banded_ws_bytes(T, rows) for two.
 // With vperm (one band), nonzero j's value is A.val[vperm[j]] and x is float32.
+// vec 4 (one band, no vperm): four consecutive nonzeros per lane and load;
+// the one-nonzero form runs instead when nnz < 4 or col_idx / values are
+// not aligned to their vectors.
 hipError_t merge_spmv(const csr_dev &A, const void *x, float *y, int block, int items, int bands, void *ws,
-                      hipStream_t s, const int32_t *vperm = nullptr);
+                      hipStream_t s, const int32_t *vperm = nullptr, int vec = 1);
 
 hipError_t merge_spmm(const csr_dev &A, const void *X, int32_t k, int64_t ldx, float *Y, int64_t ldy,
                       int block, int items, void *ws, hipStream_t s);

@@ -362,3 +362,27 @@ def test_probe_host_checks():
     assert L.lb_probe_gather(FAKE, -1, FAKE, 10, FAKE, 8, 1, None) == _abi.ERR_INVALID_ARG
     assert L.lb_probe_gather(FAKE, 0, FAKE, 10, FAKE, 8, 2, None) == _abi.OK  # nothing to launch
     assert L.lb_probe_stream_read(FAKE, 10, FAKE, 8, None) == _abi.ERR_INVALID_ARG  # not a multiple of 16
+
+
+def test_vector_width_host_checks():
+    L = _abi.load()
+    A = csr(1000, 1000, 5000)
+    st, out = resolve(A, sched("merge_path"))
+    assert st == _abi.OK and out.vector_width == 1
+    st, out = resolve(A, sched("merge_path", vector_width=4))
+    assert st == _abi.OK and out.vector_width == 4
+    for bad in (2, 3, 8, -1):
+        assert resolve(A, sched("merge_path", vector_width=bad))[0] == _abi.ERR_INVALID_ARG
+    for kind in ("thread_mapped", "group_mapped", "work_queue"):
+        assert resolve(A, sched(kind, vector_width=4))[0] == _abi.ERR_UNSUPPORTED
+    assert resolve(A, sched("merge_path", vector_width=4, x_bands=2))[0] == _abi.ERR_UNSUPPORTED
+    assert resolve(A, sched("merge_path", vector_width=4), k=2)[0] == _abi.ERR_UNSUPPORTED
+    vec = sched("merge_path", vector_width=4)
+    assert L.lb_spmm(ctypes.byref(A), FAKE, _abi.F32, 1, 1, FAKE, 1, ctypes.byref(vec), FAKE, 1 << 30, None) == _abi.ERR_UNSUPPORTED
+    assert L.lb_spmv_backward(ctypes.byref(A), FAKE, _abi.F32, FAKE, FAKE, FAKE, ctypes.byref(vec), FAKE, 1 << 30, None) == _abi.ERR_UNSUPPORTED
+    n = ctypes.c_size_t(0)
+    one = sched("merge_path")
+    assert L.lb_workspace_size(ctypes.byref(A), ctypes.byref(vec), 1, ctypes.byref(n)) == _abi.OK
+    m = ctypes.c_size_t(0)
+    assert L.lb_workspace_size(ctypes.byref(A), ctypes.byref(one), 1, ctypes.byref(m)) == _abi.OK
+    assert n.value == m.value  # same split and carries

@@ -81,7 +81,8 @@ def test_laplacian2048(dtype):
         xd = torch.from_numpy(x).to(DEV)
     Ld = lb.CSR.from_host(L, DEV)
     ref, scale = oracle_spmv(L, xh)
-    for params in ({}, {"block_size": 256, "items_per_thread": 12}, {"x_bands": 2}):
+    for params in ({}, {"block_size": 256, "items_per_thread": 12}, {"x_bands": 2},
+                   {"block_size": 256, "items_per_thread": 12, "vector_width": 4}):
         y = lb.spmv(Ld, xd, "merge_path", **params).cpu().numpy()
         assert_rows_close(y, ref, scale, what=f"laplacian {dtype} {params}")
     # 2^22 rows x 1024-lane groups: 2^32 threads unless the launch is capped

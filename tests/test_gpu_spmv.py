@@ -25,6 +25,7 @@ SCHEDULES = ([("thread_mapped", {}), ("thread_mapped", {"block_size": 64}), ("au
              + [("group_mapped", {"group_size": g, "tiles_per_group": k}) for g, k in GROUP_CONFIGS]
              + [("merge_path", {"block_size": b, "items_per_thread": i}) for b, i in MERGE_CONFIGS]
              + [("merge_path", {"block_size": b, "items_per_thread": i, "x_bands": 2}) for b, i in MERGE_CONFIGS]
+             + [("merge_path", {"block_size": b, "items_per_thread": i, "vector_width": 4}) for b, i in MERGE_CONFIGS]
              + [("work_queue", {"group_size": g}) for g in (8, 64, 256, 1024)]
              + [("work_queue", {"group_size": 64, "grid_size": 1}), ("work_queue", {"group_size": 32, "grid_size": 7})])
 SCHED_IDS = [f"{n}-{'-'.join(f'{k}{v}' for k, v in p.items())}" for n, p in SCHEDULES]
@@ -61,7 +62,9 @@ def test_c1_all_schedules(c1, name, params):
                                          ("merge_path", {}), ("merge_path", {"block_size": 128, "items_per_thread": 4}),
                                          ("merge_path", {"block_size": 512, "items_per_thread": 16}),
                                          ("merge_path", {"x_bands": 2}),
-                                         ("merge_path", {"block_size": 128, "items_per_thread": 4, "x_bands": 2})])
+                                         ("merge_path", {"block_size": 128, "items_per_thread": 4, "x_bands": 2}),
+                                         ("merge_path", {"vector_width": 4}),
+                                         ("merge_path", {"block_size": 128, "items_per_thread": 4, "vector_width": 4})])
 def test_special_shapes(mname, name, params):
     A, x = S.special_matrices()[mname]
     Ad, xd = upload(A, x)
@@ -162,7 +165,7 @@ def test_group_get_tile(K):
 @pytest.mark.parametrize("name,params", [("thread_mapped", {}), ("group_mapped", {"group_size": 32}),
                                          ("group_mapped", {"group_size": 64, "tiles_per_group": 64}),
                                          ("merge_path", {}), ("merge_path", {"block_size": 512, "items_per_thread": 16}),
-                                         ("merge_path", {"x_bands": 2})])
+                                         ("merge_path", {"x_bands": 2}), ("merge_path", {"vector_width": 4})])
 def test_bf16_inputs(name, params):
     """BF16 values and x, FP32 products and sums, against the oracle on the
     same BF16 inputs (1e-5 rule) and on the FP32 originals (quantisation
@@ -441,3 +444,31 @@ def test_gather_probe_sums(bands):
     out = lb.probe_gather(idx, x, bands=bands)
     expect = x.double()[idx.long()].sum().item()
     assert out.double().sum().item() == expect
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_vector_loads_unaligned_and_tails(dtype):
+    """Four-nonzero loads: arrays one element off their vector alignment run
+    the one-nonzero form; nnz not a multiple of 4, tiny nnz and units inside
+    one long row (the tail nonzeros past the block's groups) stay exact."""
+    rng = np.random.default_rng(41)
+    for nnz_target in (3, 5, 4099, 30_001):
+        m = 700
+        L = rng.multinomial(nnz_target, np.ones(m) / m) if nnz_target > 10 else np.r_[nnz_target, np.zeros(m - 1, int)]
+        if nnz_target == 30_001:
+            L[5] += 20_000  # one long row: units with no row end
+        A, _ = S.csr._from_lengths(42, L, 50_000)
+        Ai, xi = S.integer_valued(A, 7)
+        ref, _ = oracle_spmv(Ai, xi)
+        Ad, xd = upload(Ai, xi, dtype)
+        for B, I in ((128, 4), (256, 8), (64 * 2, 16)):
+            y = lb.spmv(Ad, xd, "merge_path", vector_width=4, block_size=B, items_per_thread=I)
+            assert np.array_equal(y.cpu().numpy().astype(np.float64), ref), (nnz_target, B, I)
+        # col_idx and values one element past an aligned start
+        ci = torch.empty(A.nnz + 1, dtype=torch.int32, device=DEV)
+        ci[1:] = Ad.col_idx
+        vv = torch.empty(A.nnz + 1, dtype=Ad.values.dtype, device=DEV)
+        vv[1:] = Ad.values
+        Au = lb.CSR(Ad.row_offsets, ci[1:], vv[1:], Ad.shape)
+        y = lb.spmv(Au, xd, "merge_path", vector_width=4)
+        assert np.array_equal(y.cpu().numpy().astype(np.float64), ref), ("unaligned", nnz_target)
