@@ -6,7 +6,7 @@ lengths min(Zipf(1.8), 200,000), 10 % empty rows, uniform columns, FP32)
 with the merge-path schedule (the Sec. 6.2 heuristic's pick) at 256 threads
 x 8 items and x split into two column bands over the XCDs, the fastest
 candidate of the autotuner here up to timing noise (its own pick is
-reported beside): partition, consume, band combine and carry fix-up.  `value` is effective HBM GB/s over
+reported beside): partition, consume, and the band sums plus carries.  `value` is effective HBM GB/s over
 algorithmic bytes B = nnz*(s_v + 4) + (m + 1)*4 + n*s_x + m*4 for K
 back-to-back steps with the inputs already in HBM.
 
@@ -391,7 +391,7 @@ def main():
     others = {}
     if dominant == "merge_consume":
         others = {n: round(kernel_avg_ms(step, args.steps, n)[0], 5) for n in
-                  ("merge_partition", "merge_fixup") + (("merge_combine",) if sched["x_bands"] == 2 else ())}
+                  ("merge_partition",) + (("merge_finish",) if sched["x_bands"] == 2 else ("merge_fixup",))}
     achieved = B / (consume_ms * 1e-3) / 1e9
     log(f"[bench] {dominant} {consume_ms * 1e3:.1f} us ({achieved:.0f} GB/s), others {others}, "
         f"cold call {ms_cold * 1e3:.1f} us")

@@ -458,7 +458,7 @@ LB_API int32_t lb_probe_default_grid(void);
  * events and returns, for the kernel family `name` ("merge_partition",
  * "merge_consume", "merge_fixup", "thread_mapped", "group_mapped",
  * "backward", "batched_consume", "batched_fixup", "fill", "coo_partition",
- * "coo_consume", "coo_fixup", "coo_tiles", "transpose", "merge_combine",
+ * "coo_consume", "coo_fixup", "coo_tiles", "transpose", "merge_finish",
  * "spgemm_products", "spgemm_count_t0" .. "spgemm_count_t3",
  * "spgemm_compute_t0" .. "spgemm_compute_t3" (one per row tier),
  * "work_queue", "traversal_init",

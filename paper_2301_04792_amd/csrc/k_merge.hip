@@ -32,9 +32,10 @@
 // blocks that the round-robin dealing of blocks to XCDs puts on different
 // XCDs: one multiplies only the nonzeros with col < cb, the other only the
 // rest, so each XCD's L2 holds half of x.  The band-0 block writes its row
-// sums to y, the band-1 block to a rows-sized buffer; merge_combine adds the
-// buffer to y, and the fix-up adds both bands' carries (stored interleaved,
-// unit-major, so carry_row stays non-decreasing).  Both blocks read the
+// sums to y, the band-1 block to a rows-sized buffer; merge_finish_banded
+// then adds, per row, the buffer and the carries of both bands (stored
+// interleaved, unit-major, so carry_row stays non-decreasing), in place of
+// the fix-up.  Both blocks read the
 // whole unit's col_idx and values (the second read mostly hits the Infinity
 // Cache, so these loads are temporal; loading values only for the block's
 // own band was measured slower, as it waits for the column first) and
@@ -290,10 +291,35 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
     }
 }
 
-// y[r] += y_hi[r]: the second band's row sums.
-__global__ __launch_bounds__(256) void merge_combine(float *__restrict__ y, const float *__restrict__ y_hi,
-                                                     int64_t rows) {
-    for (int64_t r : grid_stride_range(0, rows)) y[r] += y_hi[r];
+// Two bands, after the consume: one wavefront per unit v.  The rows that
+// close in v, [part_i[v], part_i[v+1]), get the second band's sums
+// (y += y_hi); the first of them, i0 = part_i[v], also gets the carries of
+// the units before v that ended inside row i0.  Those carries are the run of
+// entries equal to i0 that ends at carry index 2v - 1 (unit v-1 always ended
+// in row i0), read backwards 64 at a time until a chunk is not all i0.
+// Each row has exactly one writer and a fixed summation order.
+__global__ __launch_bounds__(256) void merge_finish_banded(int32_t T, const int32_t *__restrict__ part_i,
+                                                           const int32_t *__restrict__ carry_row,
+                                                           const float *__restrict__ carry_val,
+                                                           float *__restrict__ y, const float *__restrict__ y_hi) {
+    const int lane = lane_id();
+    const int64_t v = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+    if (v >= T) return;  // uniform across the wavefront
+    const int32_t i0 = part_i[v], i1 = part_i[v + 1];
+    if (i0 >= i1) return;  // no row closes in this unit: its carry goes to a later one
+    // the first 64 rows' sums are loaded before the carry chain, which they
+    // do not depend on
+    const int32_t r0 = i0 + lane;
+    const float first = r0 < i1 ? y[r0] + y_hi[r0] : 0.f;
+    float carried = 0.f;
+    for (int64_t hi = 2 * v;; hi -= kWave) {  // carry entries [0, 2v) precede unit v
+        const int64_t q = hi - 1 - lane;
+        const bool match = q >= 0 && carry_row[q] == i0;
+        carried += group_sum<kWave>(match ? carry_val[q] : 0.f);
+        if (__popcll(__ballot(match)) < kWave) break;  // the run started inside this chunk
+    }
+    if (r0 < i1) y[r0] = lane == 0 ? first + carried : first;
+    for (int32_t r = r0 + kWave; r < i1; r += kWave) y[r] = y[r] + y_hi[r];
 }
 
 // ------------------------------------------------------------------ fix-up
@@ -402,14 +428,13 @@ static hipError_t run_merge_spmv(const csr_dev &A, const void *x, float *y, int 
         if (e != hipSuccess) return e;
     }
     if (two) {
-        prof_scope p(s, "merge_combine");
-        const int64_t g = (A.rows + 255) / 256;
-        hipLaunchKernelGGL(merge_combine, dim3(static_cast<uint32_t>(g < 2048 ? g : 2048)), dim3(256), 0, s, y, y_hi,
-                           static_cast<int64_t>(A.rows));
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        prof_scope p(s, "merge_finish");
+        const int64_t g = (T + 3) / 4;  // a wavefront per unit
+        hipLaunchKernelGGL(merge_finish_banded, dim3(static_cast<uint32_t>(g)), dim3(256), 0, s,
+                           static_cast<int32_t>(T), w.part_i, w.carry_row, w.carry_val, y, y_hi);
+        return hipGetLastError();
     }
-    return launch_fixup(two ? 2 * T : T, A.rows, 1, w.carry_row, w.carry_val, y, 1, s, "merge_fixup");
+    return launch_fixup(T, A.rows, 1, w.carry_row, w.carry_val, y, 1, s, "merge_fixup");
 }
 
 bool merge_config_supported(int block, int items) {
