@@ -79,6 +79,7 @@ def _bind(lib):
     lib.orc_dvalues.argtypes = [I64, P, P, P, P, INT, P]
     lib.orc_merge_walk.argtypes = [I64, I64, P, I64, I64, P, P]
     lib.orc_num_threads.argtypes = []
+    lib.orc_set_num_threads.argtypes = [INT]
     lib.orc_sssp.argtypes = [I64, P, P, P, I64, P]
     lib.orc_spmv_coo.argtypes = [I64, I64, P, P, P, INT, P, INT, INT, P]
     lib.orc_spgemm_count.argtypes = [I64, I64, P, P, P, P, P]
@@ -86,6 +87,7 @@ def _bind(lib):
     lib.orc_spmv_csc.argtypes = [I64, I64, P, P, P, INT, P, INT, INT, P]
     lib.orc_bfs.argtypes = [I64, P, P, I64, P]
     for f in ("orc_spmv", "orc_spmm", "orc_spmv_transpose", "orc_dvalues", "orc_merge_walk", "orc_num_threads",
+              "orc_set_num_threads",
               "orc_sssp", "orc_bfs", "orc_spmv_coo", "orc_spmv_csc", "orc_spgemm_count", "orc_spgemm_compute"):
         getattr(lib, f).restype = INT
     return lib
@@ -228,6 +230,10 @@ class Oracle:
 
     def num_threads(self) -> int:
         return int(self.lib.orc_num_threads())
+
+    def set_num_threads(self, n: int) -> None:
+        if self.lib.orc_set_num_threads(int(n)):
+            raise ValueError("thread count must be at least 1")
 
     def batched_spmm(self, batch, X):
         """Per-matrix SpMM; X holds the matrices' right-hand sides back to back

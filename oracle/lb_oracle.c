@@ -76,6 +76,17 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Sets the thread count of the parallel loops (timing only: every result is
+ * the same for any count, each row being summed by one thread in order). */
+int orc_set_num_threads(int n)
+{
+    if (n < 1) return 1;
+#ifdef _OPENMP
+    omp_set_num_threads(n);
+#endif
+    return 0;
+}
+
 /* y[r] = sum_j values[j] * x[col_idx[j]] over row r; optionally with |.| of
  * every term (abs_terms != 0), which gives the per-row tolerance scale. */
 int orc_spmv(int64_t m, const int32_t *row_offsets, const int32_t *col_idx,
