@@ -461,7 +461,12 @@ def main():
                      "peak": PEAK_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_GBS, 4),
                      "traffic": traffic, "traffic_profiled_config": traffic_cfg,
                      "avg_launch_ms": round(consume_ms, 5), "launches": launches,
-                     "algorithmic_bytes_per_launch": B, "other_kernels_ms": others},
+                     "algorithmic_bytes_per_launch": B, "other_kernels_ms": others,
+                     # the measured ceiling of a kernel that gathers x the same way (ceilings above)
+                     "gather_ceiling_gbs": ceilings["gather_bound_2band_gbs" if sched.get("x_bands") == 2
+                                                    else "gather_bound_gbs"],
+                     "frac_of_gather_ceiling": round(achieved / ceilings["gather_bound_2band_gbs" if
+                                                     sched.get("x_bands") == 2 else "gather_bound_gbs"], 4)},
     }
 
     # ------------------------------------------------------------ CPU oracle baseline
