@@ -386,3 +386,35 @@ def test_vector_width_host_checks():
     m = ctypes.c_size_t(0)
     assert L.lb_workspace_size(ctypes.byref(A), ctypes.byref(one), 1, ctypes.byref(m)) == _abi.OK
     assert n.value == m.value  # same split and carries
+
+
+def test_autotune_cache_file_is_read(tmp_path):
+    """A cache file named by LB_AUTOTUNE_CACHE supplies schedule="auto"
+    (read once, when the library first needs it), in the current line format
+    and in the older one without the trailing x_bands / vector_width."""
+    import subprocess
+    import sys
+    import textwrap
+
+    cache = tmp_path / "tune.txt"
+    # rows cols nnz k dtype batched kind group tiles items block grid [x_bands vector_width]
+    cache.write_text("2000000 2000000 65000000 1 0 0 2 0 0 8 256 0 2 1\n"
+                     "4000 4000 60000 1 0 0 2 0 0 12 512 0\n")
+    code = textwrap.dedent(f"""
+        import ctypes, sys
+        sys.path.insert(0, {ROOT!r})
+        from paper_2301_04792_amd import _abi
+        L = _abi.load()
+        out = []
+        for rows, nnz in ((2000000, 65000000), (4000, 60000)):
+            A = _abi.CSR(rows, rows, nnz, 0x10000, 0x10000, 0x10000, _abi.F32)
+            s = _abi.Schedule(3, 0, 0, 0, 0, 0, 0, 0)
+            r = _abi.Schedule()
+            assert L.lb_resolve_schedule(ctypes.byref(A), 1, ctypes.byref(s), ctypes.byref(r)) == 0
+            out.append((r.kind, r.items_per_thread, r.block_size, r.x_bands, r.vector_width))
+        print(out)
+    """)
+    env = dict(os.environ, LB_AUTOTUNE_CACHE=str(cache))
+    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=300)
+    assert res.returncode == 0, res.stderr[-2000:]
+    assert res.stdout.strip() == "[(2, 8, 256, 2, 1), (2, 12, 512, 1, 1)]"
