@@ -276,6 +276,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--schedule", default="merge_path",
                     help="headline schedule: merge_path (default), auto (autotuned), group_mapped, thread_mapped")
+    ap.add_argument("--graph", action="store_true",
+                    help="time the headline's K steps as one HIP graph replay instead of eager launches")
     ap.add_argument("--pmc-calib", action="store_true",
                     help="also run one 256 MiB device copy (known bytes) to scale rocprofv3 FETCH/WRITE_SIZE")
     ap.add_argument("--graph-only", action="store_true",
@@ -334,6 +336,42 @@ def main():
             out.append(a.elapsed_time(b))
         return float(np.median(out))
 
+    def graph_timed(fn, out, steps):
+        """ms per call of `steps` calls captured once in a HIP graph and
+        replayed once (the same kernels without the host's launch gaps); its
+        replays are first checked bit-equal to the eager result, with eager
+        calls between them.  None if they differ."""
+        fn()
+        torch.cuda.synchronize()
+        expect = out.clone()
+        side = torch.cuda.Stream(dev)
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            for _ in range(3):
+                fn()
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            for _ in range(steps):
+                fn()
+        for _ in range(2):
+            out.zero_()
+            graph.replay()
+            torch.cuda.synchronize()
+            if not torch.equal(out, expect):
+                log("[bench] graph replay differs from the eager result: not timed")
+                return None
+            fn()
+            torch.cuda.synchronize()
+        a_ev = torch.cuda.Event(enable_timing=True)
+        b_ev = torch.cuda.Event(enable_timing=True)
+        a_ev.record(stream)
+        graph.replay()
+        b_ev.record(stream)
+        torch.cuda.synchronize()
+        return a_ev.elapsed_time(b_ev) / steps
+
     def kernel_avg_ms(fn, steps, name):
         lb.profile_reset()
         lb.profile_enable(True)
@@ -383,9 +421,14 @@ def main():
         for _ in range(20):
             step()
         torch.cuda.synchronize()
-    ms = timed(step, args.steps, args.warmup)
+    ms_eager = timed(step, args.steps, args.warmup)
+    ms, timing = ms_eager, "eager"
+    if args.graph:
+        ms_g = graph_timed(step, y, args.steps)
+        if ms_g is not None:
+            ms, timing = ms_g, "hip_graph"
     value = B / (ms * 1e-3) / 1e9
-    log(f"[bench] {sched}: {ms * 1e3:.1f} us/step, {value:.0f} GB/s")
+    log(f"[bench] {sched}: {ms * 1e3:.1f} us/step ({timing}; eager {ms_eager * 1e3:.1f}), {value:.0f} GB/s")
     ms_cold = cold(step, 10)
     consume_ms, launches = kernel_avg_ms(step, args.steps, dominant)
     others = {}
@@ -443,6 +486,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms, 5),
+        "timing": timing,
+        "eager_ms_per_step": round(ms_eager, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -563,9 +608,13 @@ def main():
         lb.autotune_clear()
         pick = lb.tune(Md)
         wst = torch.empty(max(lb.workspace_size(Md, "auto"), 1), dtype=torch.uint8, device=dev)
-        tt = timed(lambda: lb.spmv(Md, xmd, "auto", y=yl, workspace=wst), extra_steps, 2)
+        fl = (lambda Md=Md, xmd=xmd, wst=wst: lb.spmv(Md, xmd, "auto", y=yl, workspace=wst))
+        tt = timed(fl, extra_steps, 2)
+        tg = graph_timed(fl, yl, 20)  # a launch-bound size: the graph removes the gaps between launches
         bf["laplacian2048"][f"{key}_tuned"] = {"ms": round(tt, 4), "gbs": round(Bm / (tt * 1e-3) / 1e9, 2),
-                                               "schedule": pick}
+                                               "schedule": pick,
+                                               "hip_graph_ms": round(tg, 4) if tg is not None else None,
+                                               "hip_graph_gbs": round(Bm / (tg * 1e-3) / 1e9, 2) if tg else None}
         del wst
     lb.autotune_clear()
     result["bf16"] = bf

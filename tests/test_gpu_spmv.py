@@ -472,3 +472,40 @@ def test_vector_loads_unaligned_and_tails(dtype):
         Au = lb.CSR(Ad.row_offsets, ci[1:], vv[1:], Ad.shape)
         y = lb.spmv(Au, xd, "merge_path", vector_width=4)
         assert np.array_equal(y.cpu().numpy().astype(np.float64), ref), ("unaligned", nnz_target)
+
+
+@pytest.mark.parametrize("name,params", [("merge_path", {}), ("merge_path", {"x_bands": 2}),
+                                         ("merge_path", {"items_per_thread": 12, "vector_width": 4}),
+                                         ("thread_mapped", {}), ("group_mapped", {"group_size": 64, "tiles_per_group": 64}),
+                                         ("work_queue", {"group_size": 256})])
+def test_hip_graph_replays_match_eager(name, params):
+    """SpMV launches captured in a HIP graph (as the benchmark times the
+    headline): every replay, with eager work and synchronizations between
+    replays, equals the eager result bit for bit."""
+    A, x = S.powerlaw_csr(51, 150_000, 150_000, 1.8, 40_000, 0.1)
+    Ad, xd = upload(A, x)
+    ws = torch.empty(max(lb.workspace_size(Ad, name, **params), 1), dtype=torch.uint8, device=DEV)
+    y = torch.empty(A.m, dtype=torch.float32, device=DEV)
+    lb.spmv(Ad, xd, name, y=y, workspace=ws, **params)
+    torch.cuda.synchronize()
+    eager = y.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        lb.spmv(Ad, xd, name, y=y, workspace=ws, **params)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(3):
+            lb.spmv(Ad, xd, name, y=y, workspace=ws, **params)
+    for rep in range(4):
+        y.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(y, eager), (name, params, rep)
+        z = lb.spmv(Ad, xd * 2, name, workspace=ws, **params)  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(z, 2 * eager) or np.allclose(z.cpu().numpy(), 2 * eager.cpu().numpy(), rtol=1e-5, atol=1e-6)
+    ref, scale = oracle_spmv(A, x)
+    assert_rows_close(eager.cpu().numpy(), ref, scale, what=f"graph {name}")
