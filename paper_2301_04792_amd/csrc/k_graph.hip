@@ -172,8 +172,10 @@ __global__ __launch_bounds__(group_block<G>::BLOCK) void advance_scan_kernel(tra
 // prefixes are added in; (4) the split at every unit boundary of the merge
 // of offs[1..nf] with the edges 0..E_f-1 (the SpMV split); (5) a persistent
 // consume: each unit stages its frontier entries in LDS and each thread
-// walks kMergeItems merge items, relaxing the edges it meets.  Every grid
-// is sized for the largest frontier (every vertex); blocks past the
+// walks kMergeItems merge items, relaxing the edges it meets; the unit's new
+// frontier vertices are appended with one atomic per block (a block prefix
+// sum of the threads' counts), not one per wavefront and merge item.  Every
+// grid is sized for the largest frontier (every vertex); blocks past the
 // frontier's work leave at once.
 
 constexpr int kScanThreads = 256;
@@ -283,6 +285,8 @@ __global__ __launch_bounds__(kMergeBlock) void advance_merge_kernel(trav_args t,
     __shared__ int32_t s_end[kMergeW + 1];
     __shared__ int32_t s_base[kMergeW + 1];
     __shared__ float s_du[BFS ? 1 : kMergeW + 1];
+    __shared__ int32_t s_wave[kMergeBlock / kWave];
+    __shared__ int32_t s_out;
     const int32_t nf = frontier_size(t);
     const int32_t T = nf > 0 ? meta[1] : 0;
     const int tid = threadIdx.x;
@@ -313,21 +317,33 @@ __global__ __launch_bounds__(kMergeBlock) void advance_merge_kernel(trav_args t,
                 hi = mid;
         }
         int32_t it = lo, jt = d - lo;
+        bool want[kMergeItems];
+        int32_t nv[kMergeItems];
+        int32_t mine = 0;
 #pragma unroll
-        for (int s = 0; s < kMergeItems; ++s) {  // every lane takes part in each append
-            bool want = false;
-            int32_t v = 0;
+        for (int s = 0; s < kMergeItems; ++s) {
+            want[s] = false;
+            nv[s] = 0;
             if (d + s < dend) {
                 if (it < nrows && s_end[it] <= jt) {
                     ++it;  // entry it's edges are done
                 } else {
                     const int32_t j = j0 + jt;
-                    want = relax<BFS>(t, BFS ? 0.f : s_du[it], s_base[it] + j, v);
+                    want[s] = relax<BFS>(t, BFS ? 0.f : s_du[it], s_base[it] + j, nv[s]);
                     ++jt;
                 }
             }
-            frontier_push(want, v, t.q_out, t.cnt_out);
+            mine += want[s] ? 1 : 0;
         }
+        // the unit's new frontier vertices go out with one atomic per block:
+        // a block prefix sum of the threads' counts places each thread's run
+        const int32_t incl = block_scan_incl<kMergeBlock>(mine, s_wave);
+        if (tid == kMergeBlock - 1) s_out = incl > 0 ? atomicAdd(t.cnt_out, incl) : 0;
+        __syncthreads();
+        int32_t pos = s_out + incl - mine;
+#pragma unroll
+        for (int s = 0; s < kMergeItems; ++s)
+            if (want[s]) t.q_out[pos++] = nv[s];
         __syncthreads();
     }
 }

@@ -130,24 +130,58 @@ __global__ __launch_bounds__(256) void gemm_products(gemm_args g, int64_t *__res
     }
 }
 
-// Thread per row: append the row to its tier's list, one atomic per wavefront and tier.
+// Rows into their tier's list.  A block takes kClassRows consecutive rows
+// in two passes: it counts its rows per tier (per wavefront, then in LDS),
+// reserves its stretch of each list with one atomicAdd per tier, and writes
+// each wavefront's rows from its own offset in that stretch.  (One atomic per
+// wavefront and tier put ~16k atomics on the one counter of a 1M-row
+// matrix whose rows share a tier, ~200 µs of serialized atomics.)
+constexpr int kClassRows = 1024;
+
+__device__ __forceinline__ int gemm_tier_of(int64_t p) {
+    return p < 0 ? -1 : (p <= kTier0 ? 3 : (p <= kTier1 ? 0 : (p <= kTier2 ? 1 : 2)));
+}
+
 __global__ __launch_bounds__(256) void gemm_classify(gemm_args g) {
-    for (int64_t i0 = static_cast<int64_t>(blockIdx.x) * blockDim.x; i0 < g.m;
-         i0 += static_cast<int64_t>(gridDim.x) * blockDim.x) {  // uniform per wavefront
-        const int64_t i = i0 + threadIdx.x;
-        const int64_t p = i < g.m ? g.prod[i] : -1;
-        const int tier = p < 0 ? -1 : (p <= kTier0 ? 3 : (p <= kTier1 ? 0 : (p <= kTier2 ? 1 : 2)));
+    __shared__ int32_t s_cnt[4][4];  // [wavefront][list]
+    __shared__ int32_t s_base[4];
+    const int w = wave_id(), lane = lane_id();
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kClassRows;
+    const int64_t r1 = r0 + kClassRows < g.m ? r0 + kClassRows : g.m;
+    // pass 1: this wavefront's rows per list (list t holds tier t + 1 for t < 3, tier 0 for t = 3)
+    int32_t cnt[4] = {0, 0, 0, 0};
+    for (int64_t i0 = r0 + w * kWave; i0 < r1; i0 += 256) {  // uniform per wavefront
+        const int64_t i = i0 + lane;
+        const int t = gemm_tier_of(i < r1 ? g.prod[i] : -1);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const uint64_t mask = __ballot(tier == t);
-            if (mask == 0) continue;
-            const int leader = __ffsll(static_cast<unsigned long long>(mask)) - 1;
-            int32_t base = 0;
-            if (lane_id() == leader) base = atomicAdd(g.list_len + (t == 3 ? 4 : t), __popcll(mask));
-            base = __shfl(base, leader);
-            if (tier == t)
-                g.lists[static_cast<int64_t>(t) * g.m + base + __popcll(mask & ((1ull << lane_id()) - 1))] =
+        for (int q = 0; q < 4; ++q) cnt[q] += __popcll(__ballot(t == q));
+    }
+    if (lane == 0)
+        for (int q = 0; q < 4; ++q) s_cnt[w][q] = cnt[q];
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int q = threadIdx.x;
+        const int32_t total = s_cnt[0][q] + s_cnt[1][q] + s_cnt[2][q] + s_cnt[3][q];
+        s_base[q] = total > 0 ? atomicAdd(g.list_len + (q == 3 ? 4 : q), total) : 0;
+    }
+    __syncthreads();
+    // pass 2: the same rows in the same order, each list from this wavefront's offset
+    int32_t off[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        off[q] = s_base[q];
+        for (int v = 0; v < w; ++v) off[q] += s_cnt[v][q];
+    }
+    for (int64_t i0 = r0 + w * kWave; i0 < r1; i0 += 256) {
+        const int64_t i = i0 + lane;
+        const int t = gemm_tier_of(i < r1 ? g.prod[i] : -1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint64_t mask = __ballot(t == q);
+            if (t == q)
+                g.lists[static_cast<int64_t>(q) * g.m + off[q] + __popcll(mask & ((1ull << lane) - 1))] =
                     static_cast<int32_t>(i);
+            off[q] += __popcll(mask);
         }
     }
 }
@@ -608,7 +642,8 @@ static hipError_t gemm_pass(const spgemm_dev &P, int32_t *c_ro, int32_t *c_ci, f
             hipLaunchKernelGGL(gemm_products_rows, dim3(static_cast<uint32_t>(want < 65536 ? want : 65536)), dim3(256),
                                0, s, g, w.prod);
         }
-        hipLaunchKernelGGL(gemm_classify, dim3(static_cast<uint32_t>(capped(P.m, 256))), dim3(256), 0, s, g);
+        const int64_t cb = (static_cast<int64_t>(P.m) + kClassRows - 1) / kClassRows;
+        hipLaunchKernelGGL(gemm_classify, dim3(static_cast<uint32_t>(cb < 1 ? 1 : cb)), dim3(256), 0, s, g);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
