@@ -68,6 +68,50 @@ __device__ __forceinline__ void frontier_push(bool want, int32_t v, int32_t *q_o
     if (want) q_out[base + __popcll(m & ((1ull << lane_id()) - 1))] = v;
 }
 
+// Block-staged appends for the thread- and group-mapped advances: a push
+// takes its slot in an LDS buffer from an LDS counter (one LDS atomic per
+// wavefront), and flush() reserves the buffer's stretch of the next
+// frontier with one global atomic per block, then copies it out.  Pushes
+// past the buffer's capacity go straight to the frontier.  One global atomic
+// per wavefront and step put every wavefront of the grid on the one frontier
+// counter; staging takes that counter off the critical path.
+template <int CAP>
+struct staged_frontier {
+    int32_t *buf;  // LDS, CAP entries
+    int32_t *n;    // LDS: entries pushed (may exceed CAP: the rest went straight out)
+    int32_t *base; // LDS: the block's first slot in the frontier
+    // every thread of the block calls it, before the first push
+    __device__ void start() {
+        if (threadIdx.x == 0) *n = 0;
+        __syncthreads();
+    }
+    // every active lane of the wavefront calls it
+    __device__ void push(bool want, int32_t v, int32_t *q_out, int32_t *cnt_out) {
+        const uint64_t m = __ballot(want);
+        if (m == 0) return;
+        const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+        int32_t pos0 = 0;
+        if (lane_id() == leader) pos0 = atomicAdd(n, __popcll(m));
+        pos0 = __shfl(pos0, leader);
+        const int32_t pos = pos0 + __popcll(m & ((1ull << lane_id()) - 1));
+        const bool spill = want && pos >= CAP;
+        if (want && !spill) buf[pos] = v;
+        frontier_push(spill, v, q_out, cnt_out);
+    }
+    // every thread of the block calls it; the buffer is empty afterwards
+    __device__ void flush(int32_t *q_out, int32_t *cnt_out) {
+        __syncthreads();
+        const int32_t k = *n < CAP ? *n : CAP;
+        if (threadIdx.x == 0) *base = k > 0 ? atomicAdd(cnt_out, k) : 0;
+        __syncthreads();
+        for (int32_t i = threadIdx.x; i < k; i += blockDim.x) q_out[*base + i] = buf[i];
+        __syncthreads();
+        if (threadIdx.x == 0) *n = 0;
+        __syncthreads();
+    }
+};
+constexpr int kStageCap = 2048;
+
 // Relaxes edge e of a vertex whose distance is du; returns true when the
 // target v must join the next frontier.
 template <bool BFS>
@@ -108,6 +152,10 @@ __device__ __forceinline__ float tile_dist(const trav_args &t, int32_t u) {
 
 template <bool BFS>
 __global__ __launch_bounds__(1024) void advance_thread_kernel(trav_args t) {
+    __shared__ int32_t s_buf[kStageCap];
+    __shared__ int32_t s_n, s_base;
+    staged_frontier<kStageCap> out{s_buf, &s_n, &s_base};
+    out.start();
     const int32_t nf = frontier_size(t);
     const thread_mapped<indexed_tile_set> sch{{t.q_in, t.ro, nf}};
     for (int64_t p : sch.tiles()) {
@@ -116,13 +164,18 @@ __global__ __launch_bounds__(1024) void advance_thread_kernel(trav_args t) {
         for (int64_t e : sch.atoms(tile)) {
             int32_t v;
             const bool want = relax<BFS>(t, du, static_cast<int32_t>(e), v);
-            frontier_push(want, v, t.q_out, t.cnt_out);
+            out.push(want, v, t.q_out, t.cnt_out);
         }
     }
+    out.flush(t.q_out, t.cnt_out);
 }
 
 template <int G, bool BFS>
 __global__ __launch_bounds__(group_block<G>::BLOCK) void advance_group_kernel(trav_args t) {
+    __shared__ int32_t s_buf[kStageCap];
+    __shared__ int32_t s_n, s_base;
+    staged_frontier<kStageCap> out{s_buf, &s_n, &s_base};
+    out.start();
     const int32_t nf = frontier_size(t);
     const group_mapped<G, indexed_tile_set> sch{{t.q_in, t.ro, nf}};
     for (int64_t p : sch.tiles()) {
@@ -131,9 +184,10 @@ __global__ __launch_bounds__(group_block<G>::BLOCK) void advance_group_kernel(tr
         for (int64_t e : sch.atoms(tile)) {
             int32_t v;
             const bool want = relax<BFS>(t, du, static_cast<int32_t>(e), v);
-            frontier_push(want, v, t.q_out, t.cnt_out);
+            out.push(want, v, t.q_out, t.cnt_out);
         }
     }
+    out.flush(t.q_out, t.cnt_out);
 }
 
 template <int G, bool BFS, bool QUEUE>
@@ -141,6 +195,10 @@ __global__ __launch_bounds__(group_block<G>::BLOCK) void advance_scan_kernel(tra
     using sched = group_mapped_scan<G, indexed_tile_set>;
     __shared__ typename sched::storage st[sched::GPB];
     __shared__ int32_t s_slot;
+    __shared__ int32_t s_buf[kStageCap];
+    __shared__ int32_t s_n, s_base;
+    staged_frontier<kStageCap> out{s_buf, &s_n, &s_base};
+    out.start();
     const int32_t nf = frontier_size(t);
     sched sch(indexed_tile_set{t.q_in, t.ro, nf}, st);
     auto round_body = [&](int64_t round) {  // called by every thread of the block
@@ -151,8 +209,9 @@ __global__ __launch_bounds__(group_block<G>::BLOCK) void advance_scan_kernel(tra
             const int32_t e = sch.atom(static_cast<int32_t>(a), q);
             int32_t v;
             const bool want = relax<BFS>(t, tile_dist<BFS>(t, u), e, v);
-            frontier_push(want, v, t.q_out, t.cnt_out);
+            out.push(want, v, t.q_out, t.cnt_out);
         }
+        out.flush(t.q_out, t.cnt_out);  // per round: the buffer never holds more than one round
         sch.done();
     };
     if constexpr (QUEUE) {
