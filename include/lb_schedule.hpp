@@ -101,32 +101,43 @@ struct infinite_range {
 };
 
 // A work queue for persistent blocks: rounds [0, count) are handed out at run
-// time, `step` at a time, by one atomicAdd on a device counter (thread 0
-// claims, LDS broadcasts), so a block that finishes early takes more work.
-// Uniform across the block: every thread of the block iterates it.  The
-// counter must hold 0 when the launch starts; s_slot is one int of LDS.
+// time by atomicAdd on a device counter (thread 0 claims, LDS broadcasts),
+// so a block that finishes early takes more work.  The iterator yields round
+// starts `step` apart; one claim takes `batch` of them (batch > 1 trades
+// balance for fewer atomics on the one counter, which serialise when
+// thousands of blocks claim small rounds).  Uniform across the block: every
+// thread of the block iterates it.  The counter must hold 0 when the launch
+// starts; s_slot is one int of LDS.
 struct queue_rounds {
     int32_t *ticket;
     int32_t *s_slot;
-    int64_t step, count;  // rounds claimed per claim; rounds in all
+    int64_t step, count;  // rounds per yielded start; rounds in all
+    int64_t batch = 1;    // yielded starts per claim
     __device__ int64_t claim() const {
         __syncthreads();  // every thread has read the previous claim
-        if (threadIdx.x == 0) *s_slot = atomicAdd(ticket, static_cast<int32_t>(step));
+        if (threadIdx.x == 0) *s_slot = atomicAdd(ticket, static_cast<int32_t>(step * batch));
         __syncthreads();
         return *s_slot;
     }
     struct iterator {
         const queue_rounds *q;
         int64_t v;
+        int64_t left;  // starts of the current claim after v
         __device__ int64_t operator*() const { return v; }
         __device__ iterator &operator++() {
-            v = q->claim();
+            if (left > 0) {
+                v += q->step;
+                --left;
+            } else {
+                v = q->claim();
+                left = q->batch - 1;
+            }
             return *this;
         }
         __device__ bool operator!=(const iterator &o) const { return v < o.v; }
     };
-    __device__ iterator begin() const { return {this, claim()}; }
-    __device__ iterator end() const { return {this, count}; }
+    __device__ iterator begin() const { return {this, claim(), batch - 1}; }
+    __device__ iterator end() const { return {this, count, 0}; }
 };
 
 // ---------------------------------------------------------------- collectives used by the schedules
@@ -293,8 +304,9 @@ struct group_mapped_scan {
 
     // The same rounds handed out by a work queue (a persistent grid claims
     // them at run time; `ticket` must be 0 at launch, s_slot one int of LDS).
-    __device__ queue_rounds queued_rounds(int32_t *ticket, int32_t *s_slot) const {
-        return {ticket, s_slot, GPB, (ts.num_tiles + G - 1) / G};
+    // batch: rounds of GPB chunks per claim.
+    __device__ queue_rounds queued_rounds(int32_t *ticket, int32_t *s_slot, int64_t batch = 1) const {
+        return {ticket, s_slot, GPB, (ts.num_tiles + G - 1) / G, batch < 1 ? 1 : batch};
     }
 
     // Loads the group's chunk for this round and returns its atom count.

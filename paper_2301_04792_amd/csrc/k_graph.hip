@@ -215,7 +215,8 @@ __global__ __launch_bounds__(group_block<G>::BLOCK) void advance_scan_kernel(tra
         sch.done();
     };
     if constexpr (QUEUE) {
-        for (int64_t round : sch.queued_rounds(t.ticket, &s_slot)) round_body(round);
+        const int64_t rounds = ((static_cast<int64_t>(nf) + G - 1) / G + sched::GPB - 1) / sched::GPB;
+        for (int64_t round : sch.queued_rounds(t.ticket, &s_slot, claim_batch(rounds))) round_body(round);
     } else {
         for (int64_t round : sch.rounds()) round_body(round);  // uniform across the block
     }

@@ -216,7 +216,8 @@ __global__ __launch_bounds__(group_block<G>::BLOCK) void group_mapped_scan_kerne
         sch.done();
     };
     if constexpr (QUEUE) {  // persistent grid, rounds claimed from the work queue
-        for (int64_t round : sch.queued_rounds(ticket, &s_slot)) round_body(round);
+        const int64_t rounds = ((ts.num_tiles + G - 1) / G + GPB - 1) / GPB;
+        for (int64_t round : sch.queued_rounds(ticket, &s_slot, claim_batch(rounds))) round_body(round);
     } else {
         for (int64_t round : sch.rounds()) round_body(round);  // uniform across the block
     }

@@ -19,6 +19,14 @@ namespace lb {
 
 constexpr int kXcds = 8;  // accelerator dies of an MI355X; workgroups are dealt to them round-robin
 
+// Rounds per work-queue claim so that a whole launch makes at most about
+// kMaxClaims claims on its one counter (rounds: rounds of the launch).
+constexpr int64_t kMaxClaims = 4096;
+__device__ __forceinline__ int64_t claim_batch(int64_t rounds) {
+    const int64_t b = rounds / kMaxClaims;
+    return b < 1 ? 1 : b;
+}
+
 using bf16_bits = uint16_t;
 
 __device__ __forceinline__ float to_f32(float v) { return v; }
