@@ -14,8 +14,11 @@
 //    it, so nothing is cleared between iterations.
 //  * BFS: depth is int32, -1 = unvisited; the compare-and-swap from -1 to
 //    i + 1 that succeeds claims the vertex.
-// Appends are aggregated per wavefront: one atomicAdd reserves the slots of
-// every appending lane and each lane writes at its rank among them.
+// Appends are aggregated per block: the merge-path advance places a unit's
+// new vertices with a block prefix sum and one atomicAdd; the other
+// schedules stage them in an LDS buffer and reserve its stretch with one
+// atomicAdd per block (per round for the prefix-sum form).  Pushes past the
+// buffer fall back to one atomicAdd per wavefront.
 //
 // Under merge-path an iteration is five launches (degree scan, split,
 // consume; see below); under the other schedules one.  Each advance launch
