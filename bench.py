@@ -112,7 +112,7 @@ def summarize_profiles(out_dir, prof_root):
         rows = _read_csv(stats)
         names = [r["Name"] for r in rows if _consume_config(r["Name"])]
         cfg = _consume_config(names[0]) if names else (256, 8, 1)
-        cmd_trace = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_trace -o trace -- "
+        cmd_trace = ("rocprofv3 --kernel-trace --stats --output-format csv -d prof_out/prof_trace -o trace -- "
                      f"python3 bench.py --quick --no-cpu {_config_args(cfg)} --steps 10 --warmup 3")
         lines = ["# Kernel trace: power-law 2M SpMV, merge-path (bench --quick)", "",
                  f"Command: `{cmd_trace}`", "",
@@ -126,7 +126,7 @@ def summarize_profiles(out_dir, prof_root):
             f.write("\n".join(lines) + "\n")
     gstats = _find(os.path.join(prof_root, "prof_graph"), "kernel_stats.csv")
     if gstats:
-        cmd_graph = ("rocprofv3 --kernel-trace --stats --output-format csv -d gpurun_out/prof_graph -o graph -- "
+        cmd_graph = ("rocprofv3 --kernel-trace --stats --output-format csv -d prof_out/prof_graph -o graph -- "
                      "python3 bench.py --graph-only --no-cpu")
         rows = _read_csv(gstats)
         lines = ["# Kernel trace: SSSP and BFS on the 1M-vertex power-law graph (bench --graph-only)", "",
@@ -170,9 +170,9 @@ def summarize_profiles(out_dir, prof_root):
                     "hbm_read_bytes_per_launch": read_b, "hbm_write_bytes_per_launch": write_b,
                     "hbm_bytes_per_launch": read_b + write_b,
                     "commands": [
-                        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof_fetch -o fetch -- "
+                        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d prof_out/prof_fetch -o fetch -- "
                         f"python3 bench.py --quick --no-cpu {_config_args(cfg)} --steps 3 --warmup 1 --pmc-calib",
-                        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof_write -o write -- "
+                        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d prof_out/prof_write -o write -- "
                         f"python3 bench.py --quick --no-cpu {_config_args(cfg)} --steps 3 --warmup 1 --pmc-calib"]}
             try:
                 import synthetic as S
