@@ -64,6 +64,9 @@ def test_powerlaw2m_bf16(powerlaw2m):
     y = lb.spmv(Ad, xd, "merge_path").cpu().numpy()
     ref, scale = oracle_spmv(Ab, xb)
     assert_rows_close(y, ref, scale, what="powerlaw2M bf16")
+    for params in ({"x_bands": 2}, {"vector_width": 4, "items_per_thread": 12}):
+        yp = lb.spmv(Ad, xd, "merge_path", **params).cpu().numpy()
+        assert_rows_close(yp, ref, scale, what=f"powerlaw2M bf16 {params}")
     u = 2.0 ** -8
     worst = assert_rows_close(y, ref32, scale32, rtol=2 * u + u * u + 2e-5, what="bf16 vs fp32 inputs")
     print(f"  bf16 vs fp32-input oracle: max err / sum|a x| = {worst:.3e}", flush=True)
