@@ -127,3 +127,24 @@ def test_fullsize_powerlaw1M():
     for schedule in ("auto", "merge_path"):
         h, levels = lb.bfs(Gd.pattern, src, schedule)
         assert np.array_equal(h.cpu().numpy(), dref) and levels == int(dref.max()) + 1, schedule
+
+
+@pytest.mark.parametrize("schedule,params", SCHEDULES, ids=IDS)
+def test_star_overflows_the_staged_appends(schedule, params):
+    """A hub whose 150k out-edges all reach new vertices in one iteration:
+    a block's staged appends (2048 LDS slots) overflow and the rest go
+    straight to the frontier; with the chain behind it every schedule still
+    matches the oracle."""
+    n = 150_001
+    rng = np.random.default_rng(61)
+    hub = np.arange(1, n, dtype=np.int32)                  # 0 -> every other vertex
+    chain = np.arange(2, n, dtype=np.int32)                # i -> i + 1 for i in [1, n - 2]
+    L = np.zeros(n, dtype=np.int64)
+    L[0] = n - 1
+    L[1:n - 1] = 1
+    ro = np.zeros(n + 1, dtype=np.int32)
+    ro[1:] = np.cumsum(L)
+    ci = np.concatenate([hub, chain]).astype(np.int32)
+    w = np.concatenate([rng.uniform(1.0, 2.0, n - 1), rng.uniform(0.0, 1e-3, n - 2)]).astype(np.float32)
+    G = S.CSRHost(ro, ci, w, (n, n))
+    check(G, 0, schedule, params, what=f"star {schedule} {params}")
