@@ -290,8 +290,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the split would shard the merge path across GPUs, see DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(it would give each GPU an equal diagonal range of the merge path).", file=sys.stderr)
         return 2
 
     import numpy as np
