@@ -574,6 +574,22 @@ def main():
     del wst
     result["schedules_powerlaw2M"] = per
 
+    # ------------------------------------------------------------ the small uniform matrix (launch-bound)
+    A1, x1 = S.config_c1()
+    A1d = lb.CSR.from_host(A1, dev)
+    x1d = torch.from_numpy(x1).to(dev)
+    y1 = torch.empty(A1.m, dtype=torch.float32, device=dev)
+    small = {"m": A1.m, "nnz": A1.nnz, "note": "us per call, back to back; accuracy is asserted by the GPU tests"}
+    for name, p in (("thread_mapped", {}), ("group_mapped", {"group_size": 64}),
+                    ("group_mapped", {"group_size": 64, "tiles_per_group": 64}), ("merge_path", {})):
+        ws1 = torch.empty(max(lb.workspace_size(A1d, name, **p), 1), dtype=torch.uint8, device=dev)
+        t = timed(lambda name=name, p=p, ws1=ws1: lb.spmv(A1d, x1d, name, y=y1, workspace=ws1, **p), 50, 10)
+        key = name + ("" if not p else "_" + "_".join(f"{k}{v}" for k, v in p.items()))
+        small[key] = round(t * 1e3, 2)
+    result["uniform4096"] = small
+    log(f"[bench] uniform 4096: {small}")
+    del A1d, x1d, y1
+
     # ------------------------------------------------------------ BF16 (accuracy is asserted by the GPU tests)
     bf = {}
     Ab = A.with_values(S.to_bf16_bits(A.values))
