@@ -29,6 +29,11 @@
  *    compute calls; violating them is undefined behaviour.  lb_validate_csr
  *    checks them (synchronously) for debugging.
  *  - Errors are status codes; nothing throws across this boundary.
+ *  - Outputs that are accumulated with hardware float atomics -- dx of
+ *    lb_spmv_backward, y of lb_spmv_csc, and the workspace of lb_spgemm_*
+ *    (its large-row accumulators) -- must be ordinary device allocations
+ *    (hipMalloc, coarse-grained): those atomics are not guaranteed on
+ *    fine-grained memory (host-coherent, managed or host-registered).
  */
 #ifndef LB_H
 #define LB_H
@@ -228,7 +233,8 @@ LB_API lb_status_t lb_spmm(const lb_csr_t *A, const void *X, lb_dtype_t x_dtype,
                            void *workspace, size_t workspace_bytes, void *stream);
 
 /* Backward of y = A x.  dx = A^T dy (cols float32, zeroed by the call and
- * accumulated with float atomics: not bit-reproducible) and
+ * accumulated with float atomics: not bit-reproducible; dx must be
+ * coarse-grained device memory) and
  * dvalues[j] = dy[row(j)] * x[col_idx[j]] (nnz float32, a single rounding
  * of the exact product).  Either output may be NULL to skip it.  x is read
  * only for dvalues.  Runs over the merge-path split of A (s->kind must be
@@ -341,9 +347,9 @@ LB_API lb_status_t lb_coo_merge_path_partition(const int32_t *row_idx, int64_t r
                                                int32_t *out_row, int32_t *out_nz, void *stream);
 
 /* CSC: y = A x with columns as tiles: entry j adds values[j] * x[c] into
- * y[row_idx[j]].  x is float32 (values float32 or BF16); y (rows float32)
- * is zeroed by the call and accumulated with float atomics, so it is not
- * bit-reproducible run to run.  Each block first sums its unit's products
+ * y[row_idx[j]].  x is float32 (values float32 or BF16); y (rows float32,
+ * coarse-grained device memory) is zeroed by the call and accumulated with
+ * float atomics, so it is not bit-reproducible run to run.  Each block first sums its unit's products
  * per row in LDS, so a row hit from many columns costs one atomic per
  * block.  LB_MERGE_PATH or LB_AUTO (the merge-path split of the columns;
  * block_size/items_per_thread as for CSR, default 512 x 8 here: larger

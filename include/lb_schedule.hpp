@@ -240,7 +240,7 @@ struct indexed_tile_set {
 
 // ---------------------------------------------------------------- schedules (Sec. 4.2)
 
-// Thread-mapped (Sec. 5.1): tile position p goes to global thread p and the
+// Thread-mapped (Sec. 4.2 listing): tile position p goes to global thread p and the
 // threads stride by the grid; a thread walks its tile's atoms in order.
 template <class TS>
 struct thread_mapped {
@@ -258,7 +258,8 @@ struct group_block {
     static constexpr int GPB = BLOCK / G;  // groups per block
 };
 
-// Group-mapped with one tile per group (Sec. 5.2.3, K = 1): groups take
+// Group-mapped with one tile per group (Sec. 5.2.2, warp- and block-level;
+// K = 1): groups take
 // tiles in a grid stride; lane l of a group takes atoms begin + l,
 // begin + l + G, ...
 template <int G, class TS>

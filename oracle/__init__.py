@@ -235,9 +235,11 @@ class Oracle:
         if self.lib.orc_set_num_threads(int(n)):
             raise ValueError("thread count must be at least 1")
 
-    def batched_spmm(self, batch, X):
+    def batched_spmm(self, batch, X, abs_terms=False):
         """Per-matrix SpMM; X holds the matrices' right-hand sides back to back
-        (sum(n_b) rows, k columns).  Returns Y with sum(m_b) rows."""
+        (sum(n_b) rows, k columns).  Returns Y with sum(m_b) rows.  With
+        abs_terms, each entry is the sum of |a * x| over its terms instead
+        (the scale of the per-row tolerance)."""
         XX = _c(X)
         if XX.ndim == 1:
             XX = XX.reshape(-1, 1)
@@ -246,7 +248,7 @@ class Oracle:
             A = batch.matrix(b)
             c0 = int(batch.mat_col_base[b])
             r0 = int(batch.mat_row_base[b])
-            out[r0:r0 + A.m] = self.spmm(A.row_offsets, A.col_idx, A.values, XX[c0:c0 + A.n])
+            out[r0:r0 + A.m] = self.spmm(A.row_offsets, A.col_idx, A.values, XX[c0:c0 + A.n], abs_terms)
         return out
 
 
@@ -280,8 +282,8 @@ def merge_walk(row_offsets, nnz, W, T):
     return default().merge_walk(row_offsets, nnz, W, T)
 
 
-def batched_spmm(batch, X):
-    return default().batched_spmm(batch, X)
+def batched_spmm(batch, X, abs_terms=False):
+    return default().batched_spmm(batch, X, abs_terms)
 
 
 def spmv_coo(m, row_idx, col_idx, values, x, abs_terms=False):

@@ -5,7 +5,7 @@
 //
 // Work per row is its product count p_i = sum over A entries of the length
 // of the selected B row, which ranges from a few to millions on power-law
-// inputs.  Rows are sorted into three tiers by p_i, each with its own
+// inputs.  Rows are sorted into four tiers by p_i, each with its own
 // accumulator:
 //   tier 0 (p_i <= 32):    an 8-lane group per row, the same with a fixed
 //                           32-element network, eight rows per wavefront;

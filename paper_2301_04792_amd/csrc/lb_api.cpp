@@ -48,6 +48,9 @@ lb_status_t check_csr(const lb_csr_t *A) {
     if (A->rows > 0 && !A->row_offsets) return LB_ERR_INVALID_ARG;
     if (A->nnz > 0 && (!A->col_idx || !A->values)) return LB_ERR_INVALID_ARG;
     if (A->nnz > 0 && A->cols == 0) return LB_ERR_INVALID_ARG;
+    // offsets[0] = 0 and offsets[rows] = nnz: no rows means no nonzeros (this
+    // also covers a COO without rows and a CSC without columns)
+    if (A->nnz > 0 && A->rows == 0) return LB_ERR_INVALID_ARG;
     if (A->value_dtype != LB_F32 && A->value_dtype != LB_BF16 && A->value_dtype != LB_F64)
         return LB_ERR_INVALID_ARG;
     if (!dtype_built(A->value_dtype)) return LB_ERR_UNSUPPORTED;
@@ -828,6 +831,7 @@ static lb_status_t check_batch(const lb_batch_t *B) {
     if (B->count > 0 && (!B->mat_row_base || !B->mat_nnz_base || !B->mat_col_base)) return LB_ERR_INVALID_ARG;
     if (B->total_rows > 0 && !B->row_offsets) return LB_ERR_INVALID_ARG;
     if (B->total_nnz > 0 && (!B->col_idx || !B->values)) return LB_ERR_INVALID_ARG;
+    if (B->total_nnz > 0 && (B->total_rows == 0 || B->total_cols == 0)) return LB_ERR_INVALID_ARG;
     if (B->value_dtype != LB_F32 && B->value_dtype != LB_BF16 && B->value_dtype != LB_F64) return LB_ERR_INVALID_ARG;
     if (!dtype_built(B->value_dtype)) return LB_ERR_UNSUPPORTED;
     if (B->total_rows + B->total_nnz > kMaxCoord || B->total_cols > kMaxCoord || B->count > kMaxCoord)

@@ -1,4 +1,4 @@
-"""Helpers for GPU parity tests: upload, row sampling and the tolerance rule.
+"""Helpers for GPU parity tests: the oracle references and the tolerance rule.
 
 Tolerance (FP32 and BF16 inputs with FP32 accumulation): for every output
 row r, |y_gpu[r] - y_ref[r]| <= 1e-5 * sum_j |a_j * x_c(j)|, and rows whose
@@ -40,23 +40,3 @@ def oracle_spmv(A: CSRHost, x):
 def oracle_spmm(A: CSRHost, X):
     return (oracle.spmm(A.row_offsets, A.col_idx, A.values, X),
             oracle.spmm(A.row_offsets, A.col_idx, A.values, X, abs_terms=True))
-
-
-def sample_rows(A: CSRHost, count: int, seed: int = 0, extra=()):
-    """Sorted row sample: random rows, the longest rows, first/last rows."""
-    rng = np.random.default_rng(seed)
-    L = np.diff(A.row_offsets.astype(np.int64))
-    picks = set(rng.choice(A.m, size=min(count, A.m), replace=False).tolist())
-    picks.update(np.argsort(L)[-16:].tolist())
-    picks.update([0, A.m - 1, *extra])
-    return np.array(sorted(p for p in picks if 0 <= p < A.m), dtype=np.int64)
-
-
-def sub_rows(A: CSRHost, rows) -> CSRHost:
-    """The CSR of the selected rows (same columns)."""
-    ro = A.row_offsets.astype(np.int64)
-    starts, ends = ro[rows], ro[rows + 1]
-    lens = ends - starts
-    sub_ro = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
-    idx = np.concatenate([np.arange(s, e) for s, e in zip(starts, ends)]) if lens.sum() else np.zeros(0, np.int64)
-    return CSRHost(sub_ro, A.col_idx[idx], A.values[idx], (len(rows), A.n))

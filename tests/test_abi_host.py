@@ -132,6 +132,31 @@ def test_spmv_host_checks():
     assert spmv_call(csr(), s=sched("group_mapped", group_size=6)) == _abi.ERR_INVALID_ARG
     # rows == 0 is a no-op that touches nothing
     assert spmv_call(csr(rows=0, nnz=0, ro=0, ci=0, val=0), x=0, y=0) == _abi.OK
+    # but a matrix without rows cannot hold nonzeros (offsets[0] = 0 = offsets[rows] = nnz)
+    assert spmv_call(csr(rows=0, ro=0)) == _abi.ERR_INVALID_ARG
+
+
+def test_zero_extent_with_nonzeros_rejected():
+    """No rows (CSR, COO) or no columns (CSC) but nnz > 0: rejected on the
+    host by every entry point, before any launch."""
+    L = _abi.load()
+    s = sched("merge_path")
+    A0 = csr(rows=0, ro=0)
+    n = ctypes.c_size_t(0)
+    assert L.lb_workspace_size(ctypes.byref(A0), ctypes.byref(s), 0, ctypes.byref(n)) == _abi.ERR_INVALID_ARG
+    assert L.lb_spmv_backward(ctypes.byref(A0), FAKE, _abi.F32, FAKE, FAKE, FAKE, ctypes.byref(s), FAKE, 1 << 30,
+                              None) == _abi.ERR_INVALID_ARG
+    assert L.lb_spmm(ctypes.byref(A0), FAKE, _abi.F32, 2, 2, FAKE, 2, ctypes.byref(s), FAKE, 1 << 30,
+                     None) == _abi.ERR_INVALID_ARG
+    csc0 = _abi.CSC(1000, 0, 50, FAKE, FAKE, FAKE, _abi.F32)  # no columns, 50 entries
+    assert L.lb_spmv_csc(ctypes.byref(csc0), FAKE, _abi.F32, FAKE, ctypes.byref(s), FAKE, 1 << 30,
+                         None) == _abi.ERR_INVALID_ARG
+    coo0 = _abi.COO(0, 10, 50, FAKE, FAKE, FAKE, _abi.F32)  # no rows, 50 entries
+    assert L.lb_spmv_coo(ctypes.byref(coo0), FAKE, _abi.F32, FAKE, ctypes.byref(s), FAKE, 1 << 30,
+                         None) == _abi.ERR_INVALID_ARG
+    B0 = _abi.Batch(1, 0, 10, 50, FAKE, FAKE, FAKE, _abi.F32, FAKE, FAKE, FAKE)
+    assert L.lb_batched_spmm(ctypes.byref(B0), FAKE, _abi.F32, 1, FAKE, ctypes.byref(s), FAKE, 1 << 30,
+                             None) == _abi.ERR_INVALID_ARG
 
 
 def test_spmm_backward_batched_host_checks():

@@ -315,7 +315,9 @@ def test_batched_tiny_and_empty_matrices():
     Y = lb.batched_spmm(lb.Batch.from_host(B, DEV), torch.from_numpy(X).to(DEV), "merge_path",
                         block_size=128, items_per_thread=4).cpu().numpy()
     ref = oracle.batched_spmm(B, X)
-    assert np.allclose(Y, ref, rtol=0, atol=1e-5 * (np.abs(ref).max() + 1))
+    scale = oracle.batched_spmm(B, X, abs_terms=True)
+    assert (scale == 0).any(), "the batch must hold rows with no terms"
+    assert_rows_close(Y, ref, scale, what="batched tiny and empty members")
 
 
 def test_autotune_and_auto():
