@@ -56,7 +56,8 @@ typedef enum lb_status_t {
     LB_ERR_WORKSPACE_TOO_SMALL = 4,  /* workspace_bytes below lb_workspace_size() */
     LB_ERR_HIP = 5,                  /* a HIP call or launch failed; see lb_last_hip_error() */
     LB_ERR_INVALID_CSR = 6,          /* lb_validate_csr found a violated device-only precondition */
-    LB_ERR_NOT_CONVERGED = 7         /* a traversal still had a frontier after max_iterations */
+    LB_ERR_NOT_CONVERGED = 7,        /* a traversal still had a frontier after max_iterations */
+    LB_ERR_SCRATCH_LIMIT = 8         /* lb_spmv_noalloc: the call needs more than its static scratch */
 } lb_status_t;
 
 /* Element types.  LB_BF16 buffers hold bfloat16 bit patterns (the upper 16
@@ -222,6 +223,26 @@ LB_API lb_status_t lb_workspace_size(const lb_csr_t *A, const lb_schedule_t *s, 
 LB_API lb_status_t lb_spmv(const lb_csr_t *A, const void *x, lb_dtype_t x_dtype, float *y,
                            const lb_schedule_t *s, void *workspace, size_t workspace_bytes,
                            void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): lb_spmv
+ * with the same arguments minus the workspace.  The scratch that lb_spmv
+ * takes from its workspace (merge-path split, carries and, with two column
+ * bands, the second band's row sums; the work queue's counter) comes from a
+ * static device array of LB_NOALLOC_SCRATCH_BYTES per GPU, held from the
+ * library's first call on that GPU until the process ends.  A call whose
+ * lb_workspace_size(A, s, 1) exceeds it returns LB_ERR_SCRATCH_LIMIT before
+ * any launch (the merge-path default needs about 20 bytes per 2048 rows +
+ * nonzeros; two column bands add 4 bytes per row: a 2M-row, 65M-nonzero
+ * matrix fits).  The call makes no hipMalloc, hipFree or other allocating
+ * call; its first call on a GPU looks up that GPU's address of the array.
+ * Every call on one GPU shares the array: calls that overlap in time on one
+ * GPU (different streams, or host threads) race and give undefined results;
+ * calls ordered on one stream are safe.  Same numerics as lb_spmv: for the
+ * same schedule the result is bit-identical to lb_spmv's. */
+#define LB_NOALLOC_SCRATCH_BYTES (16u << 20)
+LB_API lb_status_t lb_spmv_noalloc(const lb_csr_t *A, const void *x, lb_dtype_t x_dtype, float *y,
+                                   const lb_schedule_t *s, void *stream);
 
 /* Y = A X with k right-hand sides (Sec. 5.3 SpMM listing, reading its
  * B(nz, col) as B(col_idx[nz], col)).  X row-major cols x k with leading

@@ -27,7 +27,7 @@ from ._abi import LBError  # noqa: F401
 
 _lib = _abi.load()
 
-__all__ = ["CSR", "Pattern", "Batch", "spmv", "spmm", "spmv_backward", "SpMV", "spmv_diff",
+__all__ = ["CSR", "Pattern", "Batch", "spmv", "spmv_noalloc", "spmm", "spmv_backward", "SpMV", "spmv_diff",
            "batched_spmm", "tune", "tune_batched", "merge_path_partition", "group_tile_owner",
            "sssp", "bfs", "traversal_workspace_size", "COO", "CSC", "spmv_coo", "spmv_csc",
            "coo_merge_path_partition", "coo_workspace_size", "csc_workspace_size", "transpose_pattern", "spgemm",
@@ -155,6 +155,21 @@ def spmv(A: CSR, x: torch.Tensor, schedule="merge_path", y: torch.Tensor | None 
     ws = _workspace(n.value, A.device, workspace)
     _abi.check(_lib.lb_spmv(ctypes.byref(c), _ptr(x), _dtype_code(x), _ptr(y), ctypes.byref(s), _ptr(ws),
                             n.value, _stream(A.device)), "lb_spmv")
+    return y
+
+
+def spmv_noalloc(A: CSR, x: torch.Tensor, y: torch.Tensor, schedule="merge_path", **params) -> torch.Tensor:
+    """y = A x through lb_spmv_noalloc: the library's static per-GPU scratch
+    instead of a workspace, no allocation in the call (y is the caller's).
+    Calls that overlap in time on one GPU race on that scratch."""
+    if x.dim() != 1 or x.numel() != A.shape[1]:
+        raise ValueError("x must be a vector of length cols")
+    if y.dim() != 1 or y.numel() != A.shape[0] or y.dtype != torch.float32 or not y.is_contiguous():
+        raise ValueError("y must be a contiguous float32 vector of length rows")
+    x = x.contiguous()
+    s = make_schedule(schedule, **params)
+    _abi.check(_lib.lb_spmv_noalloc(ctypes.byref(A.c_struct()), _ptr(x), _dtype_code(x), _ptr(y), ctypes.byref(s),
+                                    _stream(A.device)), "lb_spmv_noalloc")
     return y
 
 

@@ -13,7 +13,9 @@ LIB_PATH = os.environ.get("LB_LIBRARY", os.path.join(_PKG, "liblb.so"))
 
 # lb_status_t
 (OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_OVERFLOW, ERR_WORKSPACE_TOO_SMALL, ERR_HIP, ERR_INVALID_CSR,
- ERR_NOT_CONVERGED) = range(8)
+ ERR_NOT_CONVERGED, ERR_SCRATCH_LIMIT) = range(9)
+# static scratch of lb_spmv_noalloc per GPU (LB_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 16 << 20
 # lb_dtype_t
 F32, BF16, F64 = 0, 1, 2
 # lb_sched_kind_t
@@ -92,6 +94,7 @@ SIGNATURES = {
     "lb_resolve_schedule": (ST, [PCSR, I32, PSCHED, PSCHED]),
     "lb_workspace_size": (ST, [PCSR, PSCHED, I32, ctypes.POINTER(SZ)]),
     "lb_spmv": (ST, [PCSR, P, ST, P, PSCHED, P, SZ, P]),
+    "lb_spmv_noalloc": (ST, [PCSR, P, ST, P, PSCHED, P]),
     "lb_spmm": (ST, [PCSR, P, ST, I32, I64, P, I64, PSCHED, P, SZ, P]),
     "lb_spmv_backward": (ST, [PCSR, P, ST, P, P, P, PSCHED, P, SZ, P]),
     "lb_batched_workspace_size": (ST, [PBATCH, PSCHED, I32, ctypes.POINTER(SZ)]),

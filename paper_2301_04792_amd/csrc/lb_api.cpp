@@ -468,6 +468,94 @@ lb_status_t time_call(F &&f, hipStream_t hs, float *ms_out) {
     return LB_OK;
 }
 
+// ------------------------------------------------------------------ lb_spmv
+
+// Host checks and schedule resolution shared by lb_spmv and lb_spmv_noalloc;
+// *need receives the workspace bytes of the resolved schedule.
+lb_status_t spmv_prepare(const lb_csr_t *A, const void *x, lb_dtype_t x_dtype, float *y, const lb_schedule_t *s,
+                         lb_schedule_t *r, size_t *need) {
+    lb_status_t st = check_csr(A);
+    if (st != LB_OK) return st;
+    if (A->rows > 0 && !y) return LB_ERR_INVALID_ARG;
+    if (A->nnz > 0 && !x) return LB_ERR_INVALID_ARG;
+    if (x_dtype != A->value_dtype) return LB_ERR_UNSUPPORTED;
+    st = resolve(A, 1, s, r);
+    if (st != LB_OK) return st;
+    *need = ws_bytes_for(A, *r, 1);
+    return LB_OK;
+}
+
+// The launches of y = A x under the resolved schedule r; workspace holds at
+// least ws_bytes_for(A, r, 1) bytes.
+lb_status_t spmv_launch(const lb_csr_t *A, const void *x, float *y, const lb_schedule_t &r, void *workspace,
+                        hipStream_t hs) {
+    if (A->rows == 0) return LB_OK;
+    if (A->nnz == 0) return hip_status(lbk::fill_f32(y, A->rows, 0.f, hs));
+    const lbk::csr_dev d = to_dev(A);
+    switch (r.kind) {
+        case LB_THREAD_MAPPED: return hip_status(lbk::thread_mapped_spmv(d, x, y, r.block_size, r.grid_size, hs));
+        case LB_GROUP_MAPPED:
+            return hip_status(
+                lbk::group_mapped_spmv(d, x, y, r.group_size, r.tiles_per_group, r.grid_size, nullptr, hs));
+        case LB_WORK_QUEUE:
+            return hip_status(lbk::group_mapped_spmv(d, x, y, r.group_size, r.group_size, r.grid_size,
+                                                     static_cast<int32_t *>(workspace), hs));
+        case LB_MERGE_PATH:
+            return hip_status(lbk::merge_spmv(d, x, y, r.block_size, r.items_per_thread, r.x_bands, workspace, hs,
+                                              nullptr, r.vector_width));
+        default: return LB_ERR_INVALID_ARG;
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ static scratch
+
+// lb_spmv_noalloc's workspace: one copy per GPU, held until the process
+// ends.  In host code `scratch` names a host-side stand-in, not device
+// memory; host code uses only the per-device address that
+// hipGetSymbolAddress returns for it.  Nothing in it has to start at zero:
+// the merge-path launches write the split, carries and band sums before
+// reading them, and the work queue clears its counter with a fill kernel.
+static constexpr size_t kScratchBytes = LB_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// The device address of `scratch` on the device that runs `hs` (the current
+// device for the null stream), looked up once per device with that device
+// current.
+lb_status_t scratch_address(hipStream_t hs, void **out) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_status(e);
+    int dev = cur;
+    if (hs) {
+        hipDevice_t sd = 0;
+        e = hipStreamGetDevice(hs, &sd);
+        if (e != hipSuccess) return hip_status(e);
+        dev = static_cast<int>(sd);
+    }
+    if (dev < 0 || dev >= kMaxDevices) return LB_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        if (dev != cur && (e = hipSetDevice(dev)) != hipSuccess) return hip_status(e);
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        const hipError_t back = dev != cur ? hipSetDevice(cur) : hipSuccess;
+        if (e != hipSuccess) return hip_status(e);
+        if (back != hipSuccess) return hip_status(back);
+        if (!p) return LB_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LB_OK;
+}
+
 }  // namespace
 
 // ================================================================== C ABI
@@ -486,6 +574,7 @@ LB_API const char *lb_status_string(lb_status_t st) {
         case LB_ERR_HIP: return "HIP error";
         case LB_ERR_INVALID_CSR: return "CSR arrays violate a device-side precondition";
         case LB_ERR_NOT_CONVERGED: return "traversal frontier not empty after max_iterations";
+        case LB_ERR_SCRATCH_LIMIT: return "input needs more scratch than lb_spmv_noalloc's static buffer";
     }
     return "unknown status";
 }
@@ -518,33 +607,29 @@ LB_API lb_status_t lb_workspace_size(const lb_csr_t *A, const lb_schedule_t *s, 
 
 LB_API lb_status_t lb_spmv(const lb_csr_t *A, const void *x, lb_dtype_t x_dtype, float *y, const lb_schedule_t *s,
                            void *workspace, size_t workspace_bytes, void *stream) {
-    lb_status_t st = check_csr(A);
-    if (st != LB_OK) return st;
-    if (A->rows > 0 && !y) return LB_ERR_INVALID_ARG;
-    if (A->nnz > 0 && !x) return LB_ERR_INVALID_ARG;
-    if (x_dtype != A->value_dtype) return LB_ERR_UNSUPPORTED;
     lb_schedule_t r;
-    st = resolve(A, 1, s, &r);
+    size_t need = 0;
+    lb_status_t st = spmv_prepare(A, x, x_dtype, y, s, &r, &need);
     if (st != LB_OK) return st;
-    const size_t need = ws_bytes_for(A, r, 1);
     if (need > 0 && (workspace_bytes < need || !workspace)) return LB_ERR_WORKSPACE_TOO_SMALL;
+    return spmv_launch(A, x, y, r, workspace, static_cast<hipStream_t>(stream));
+}
+
+LB_API lb_status_t lb_spmv_noalloc(const lb_csr_t *A, const void *x, lb_dtype_t x_dtype, float *y,
+                                   const lb_schedule_t *s, void *stream) {
+    lb_schedule_t r;
+    size_t need = 0;
+    lb_status_t st = spmv_prepare(A, x, x_dtype, y, s, &r, &need);
+    if (st != LB_OK) return st;
+    if (need > kScratchBytes) return LB_ERR_SCRATCH_LIMIT;
     hipStream_t hs = static_cast<hipStream_t>(stream);
     if (A->rows == 0) return LB_OK;
-    if (A->nnz == 0) return hip_status(lbk::fill_f32(y, A->rows, 0.f, hs));
-    const lbk::csr_dev d = to_dev(A);
-    switch (r.kind) {
-        case LB_THREAD_MAPPED: return hip_status(lbk::thread_mapped_spmv(d, x, y, r.block_size, r.grid_size, hs));
-        case LB_GROUP_MAPPED:
-            return hip_status(
-                lbk::group_mapped_spmv(d, x, y, r.group_size, r.tiles_per_group, r.grid_size, nullptr, hs));
-        case LB_WORK_QUEUE:
-            return hip_status(lbk::group_mapped_spmv(d, x, y, r.group_size, r.group_size, r.grid_size,
-                                                     static_cast<int32_t *>(workspace), hs));
-        case LB_MERGE_PATH:
-            return hip_status(lbk::merge_spmv(d, x, y, r.block_size, r.items_per_thread, r.x_bands, workspace, hs,
-                                              nullptr, r.vector_width));
-        default: return LB_ERR_INVALID_ARG;
+    void *ws = nullptr;
+    if (need > 0) {
+        st = scratch_address(hs, &ws);
+        if (st != LB_OK) return st;
     }
+    return spmv_launch(A, x, y, r, ws, hs);
 }
 
 LB_API lb_status_t lb_transpose_workspace_size(const lb_csr_t *A, size_t *bytes) {

@@ -32,6 +32,9 @@ int main(void)
     lb_csr_t empty = {0, 5, 0, NULL, NULL, NULL, LB_F32};
     CHECK(lb_spmv(&empty, NULL, LB_F32, NULL, &in, NULL, 0, NULL) == LB_OK);
     CHECK(lb_merge_path_partition(NULL, 1, 1, 1, 1, (int32_t *)fake, (int32_t *)fake, NULL) == LB_ERR_INVALID_ARG);
+    lb_csr_t tall = {5000000, 5000000, 10000000, fake, fake, fake, LB_F32};
+    lb_schedule_t banded = {LB_MERGE_PATH, 0, 0, 0, 0, 0, 2, 0};
+    CHECK(lb_spmv_noalloc(&tall, fake, LB_F32, (float *)fake, &banded, NULL) == LB_ERR_SCRATCH_LIMIT);
     puts("ok");
     return 0;
 }

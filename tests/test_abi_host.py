@@ -36,8 +36,8 @@ def test_every_declared_symbol_is_exported():
 def test_version_and_status_strings():
     L = _abi.load()
     assert L.lb_abi_version() == 2
-    for st in range(8):
-        assert L.lb_status_string(st)
+    for st in range(9):
+        assert L.lb_status_string(st) not in (b"", b"unknown status")
     assert L.lb_status_string(99) == b"unknown status"
 
 
@@ -443,3 +443,24 @@ def test_autotune_cache_file_is_read(tmp_path):
     res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=300)
     assert res.returncode == 0, res.stderr[-2000:]
     assert res.stdout.strip() == "[(2, 8, 256, 2, 1), (2, 12, 512, 1, 1)]"
+
+
+def test_noalloc_rejects_inputs_beyond_its_scratch():
+    L = _abi.load()
+    # two column bands need 4 bytes per row beyond the split and carries: 5M rows > 16 MiB
+    A = csr(5_000_000, 5_000_000, 10_000_000)
+    s = sched("merge_path", x_bands=2)
+    n = ctypes.c_size_t(0)
+    assert L.lb_workspace_size(ctypes.byref(A), ctypes.byref(s), 1, ctypes.byref(n)) == _abi.OK
+    assert n.value > _abi.NOALLOC_SCRATCH_BYTES
+    assert L.lb_spmv_noalloc(ctypes.byref(A), FAKE, _abi.F32, FAKE, ctypes.byref(s), None) == _abi.ERR_SCRATCH_LIMIT
+    # host checks come first, as for lb_spmv
+    assert L.lb_spmv_noalloc(ctypes.byref(A), None, _abi.F32, FAKE, ctypes.byref(s), None) == _abi.ERR_INVALID_ARG
+    assert L.lb_spmv_noalloc(ctypes.byref(A), FAKE, _abi.BF16, FAKE, ctypes.byref(s), None) == _abi.ERR_UNSUPPORTED
+    big = csr(1 << 30, 10, 1 << 30)
+    assert L.lb_spmv_noalloc(ctypes.byref(big), FAKE, _abi.F32, FAKE, ctypes.byref(sched()), None) == \
+        _abi.ERR_OVERFLOW
+    # rows == 0: nothing to do, no device touched
+    empty = csr(0, 5, 0, ro=0, ci=0, val=0)
+    assert L.lb_spmv_noalloc(ctypes.byref(empty), None, _abi.F32, None, ctypes.byref(sched()), None) == _abi.OK
+    assert b"static" in L.lb_status_string(_abi.ERR_SCRATCH_LIMIT)
