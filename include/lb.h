@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define LB_ABI_VERSION 2
+#define LB_ABI_VERSION 3
 #define LB_API __attribute__((visibility("default")))
 
 typedef enum lb_status_t {
@@ -204,8 +204,8 @@ LB_API const char *lb_last_hip_error(void);
  * LB_AUTO follows Sec. 6.2: merge-path unless (rows < 500 or cols < 500) and
  * nnz < 10000, in which case thread-mapped when the mean row length is below
  * 8, else group-mapped with the next power of two of the mean row length
- * (at most 64) as group size.  A schedule stored by lb_autotune for the same
- * matrix shape takes precedence. */
+ * (at most 64) as group size.  A schedule stored by lb_autotune for the
+ * matrix (bound by lb_autotune or lb_autotune_lookup) takes precedence. */
 LB_API lb_status_t lb_resolve_schedule(const lb_csr_t *A, int32_t k, const lb_schedule_t *in,
                                        lb_schedule_t *out);
 
@@ -223,6 +223,98 @@ LB_API lb_status_t lb_workspace_size(const lb_csr_t *A, const lb_schedule_t *s, 
 LB_API lb_status_t lb_spmv(const lb_csr_t *A, const void *x, lb_dtype_t x_dtype, float *y,
                            const lb_schedule_t *s, void *workspace, size_t workspace_bytes,
                            void *stream);
+
+/* ---- Planned y = A x for a pattern used many times (an iterative solver, a
+ * serving loop).  A plan is built once per sparsity pattern; the values and
+ * x may change between calls.  Rows are split in two classes by length:
+ *  - short rows (fewer than long_min nonzeros) run the merge path of
+ *    lb_spmv (Sec. 5.2.1) over the whole matrix with the long rows' work
+ *    left out: the split at every unit boundary is computed once, in the
+ *    plan, and only the units holding short-row work are launched;
+ *  - long rows run a panel schedule: x is cut into panels of panel_cols
+ *    columns; a block stages one panel of x in LDS and consumes, for a
+ *    chunk of long rows, each row's segment of nonzeros whose columns fall
+ *    in the panel (contiguous in the row, as its columns are sorted).  The
+ *    segments are cut into tasks of at most 512 nonzeros, which the block's
+ *    wavefronts take from an LDS prefix sum of the segments' task counts
+ *    (the group-mapped schedule with get_tile, Sec. 5.2.3).  So the x
+ *    accesses of long rows hit LDS instead of the cache hierarchy.  Each
+ *    task's sum is stored, and a long row's result is the sum of its
+ *    tasks in (panel, task) order.
+ * No atomics: for a fixed plan the result is bit-reproducible run to run.
+ *
+ * The plan lives in a device buffer owned by the caller, read-only for the
+ * calls (several calls may share it).  lb_spmv_plan_build synchronizes
+ * `stream` and copies row_offsets (and a few plan tables) through host
+ * memory.  Call it first with buffer == NULL: it fills the output fields
+ * of *plan (plan_bytes is an upper bound then) and returns
+ * LB_ERR_WORKSPACE_TOO_SMALL without touching the device beyond reading
+ * row_offsets; then call it with a buffer of at least plan_bytes to build.
+ * Long rows must have strictly increasing columns (LB_ERR_INVALID_CSR
+ * otherwise, checked by the build); short rows have no such requirement.
+ *
+ * Inputs of lb_spmv_plan_t (0 = default):
+ *  block_size, items_per_thread  the short rows' merge path, as for lb_spmv
+ *                                (default 256 x 8); W = their product;
+ *  x_bands       1 or 2, as for lb_spmv (default: 2 when x has at least
+ *                4 MiB, else 1);
+ *  long_min      rows with at least this many nonzeros are long; at least
+ *                W (a long row then never lies strictly inside one merge-path
+ *                unit); default max(W, 16 * panels); -1 = no long rows;
+ *  panel_cols    columns per panel, a multiple of 64 up to 16384 (float32
+ *                x) or 32768 (BF16 x); default that maximum;
+ *  chunk_atoms   long-row nonzeros per (chunk, panel) block on average (the
+ *                plan groups consecutive long rows into chunks of about
+ *                chunk_atoms * panels nonzeros, at most 512 rows); default
+ *                16384;
+ *  streams       2: the long rows' launch runs on a second stream
+ *                of the same device, owned by the library (one per device,
+ *                created on first use, default priority), concurrently with
+ *                the short rows' launch; events order it after the work
+ *                already on `stream` and before the finishing launch, so
+ *                the call stays asynchronous and ordered on `stream` (and
+ *                can be captured in a HIP graph from `stream`); calls from
+ *                several host threads take turns on that stream.  1: all
+ *                launches on `stream` (default).
+ * Outputs: the matrix shape and dtype the plan was built for, its counts,
+ * plan_bytes (device bytes of the plan) and workspace_bytes (device bytes
+ * each lb_spmv_planned call needs). */
+typedef struct lb_spmv_plan_t {
+    int32_t block_size;
+    int32_t items_per_thread;
+    int32_t x_bands;
+    int32_t long_min;
+    int32_t panel_cols;
+    int32_t chunk_atoms;
+    int32_t streams;
+    lb_dtype_t value_dtype;
+    int64_t rows;
+    int64_t cols;
+    int64_t nnz;
+    int64_t long_nnz;    /* nonzeros in long rows */
+    int32_t long_rows;   /* rows with at least long_min nonzeros */
+    int32_t panels;      /* ceil(cols / panel_cols) */
+    int32_t chunks;      /* chunks of long rows (one block per chunk and panel) */
+    int32_t tasks;       /* long-row tasks (one stored sum each) */
+    int32_t units;       /* merge-path units of W items over the whole matrix */
+    int32_t active_units;/* units holding short-row work */
+    size_t plan_bytes;
+    size_t workspace_bytes;
+    const void *buffer;  /* the device buffer the plan was built in */
+} lb_spmv_plan_t;
+
+LB_API lb_status_t lb_spmv_plan_build(const lb_csr_t *A, lb_spmv_plan_t *plan, void *buffer, size_t buffer_bytes,
+                                      void *stream);
+
+/* y = A x with a plan built for A's pattern (rows, cols, nnz, value dtype
+ * and row_offsets must be those of the build; col_idx those of the build
+ * for the long rows).  x of A->value_dtype; y rows float32, overwritten.
+ * workspace: at least plan->workspace_bytes of device memory (the carries
+ * of the merge-path units, the second column band's row sums and the long
+ * rows' task sums), contents on entry irrelevant.  Asynchronous. */
+LB_API lb_status_t lb_spmv_planned(const lb_csr_t *A, const lb_spmv_plan_t *plan, const void *x,
+                                   lb_dtype_t x_dtype, float *y, void *workspace, size_t workspace_bytes,
+                                   void *stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): lb_spmv
@@ -324,20 +416,42 @@ LB_API lb_status_t lb_group_tile_owner(const lb_csr_t *A, int32_t tiles_per_grou
 /* Time candidate schedules for A with k right-hand sides on `stream`
  * (synchronizing) using the caller's x/X, y/Y and workspace (at least
  * lb_autotune_workspace_size bytes), store the fastest in a process-wide
- * cache keyed by (rows, cols, nnz, k, dtype) that lb_resolve_schedule
- * consults for LB_AUTO, and return it in *best.  If the environment variable
- * LB_AUTOTUNE_CACHE names a file, the cache is loaded from and saved to it. */
+ * cache and return it in *best.  A cache entry is keyed by the shape, k,
+ * the value dtype and a fingerprint of the sparsity pattern (Sec. 6.2
+ * picks a schedule per matrix), and belongs to the device it was timed on
+ * (lb_autotune_device_tag) and to this ABI version.  The call also binds A
+ * (its row_offsets and col_idx pointers and shape) to the fingerprint, so
+ * LB_AUTO on A resolves to the stored pick; a matrix without a binding
+ * gets the Sec. 6.2 rule.  If the environment variable LB_AUTOTUNE_CACHE
+ * names a file, the cache is loaded from it (entries of this device and ABI
+ * version; others are kept in the file untouched) and saved to it. */
 LB_API lb_status_t lb_autotune_workspace_size(const lb_csr_t *A, int32_t k, size_t *bytes);
 LB_API lb_status_t lb_autotune(const lb_csr_t *A, const void *X, lb_dtype_t x_dtype, int32_t k,
                                float *Y, void *workspace, size_t workspace_bytes,
                                lb_schedule_t *best, void *stream);
+
+/* The pattern fingerprint the tuning cache uses: FNV-1a (64-bit) over rows,
+ * cols, nnz, every row offset and col_idx at 4096 evenly spaced positions.
+ * Synchronizes `stream`.  Values do not enter it. */
+LB_API lb_status_t lb_pattern_fingerprint(const lb_csr_t *A, uint64_t *fingerprint, void *stream);
+
+/* Host only: bind A to `fingerprint` (so LB_AUTO on A uses a tuned pick for
+ * it) and report whether the cache holds one for k right-hand sides:
+ * *found = 1 and *out = the pick, or *found = 0.  With a cache file this
+ * reuses an earlier process's tuning at the cost of one fingerprint. */
+LB_API lb_status_t lb_autotune_lookup(const lb_csr_t *A, int32_t k, uint64_t fingerprint, int32_t *found,
+                                      lb_schedule_t *out);
+
+/* The device identity tuning entries are stored under: "<arch>:<CUs>" of the
+ * current device (e.g. "gfx950:256"), "none:0" without a device. */
+LB_API const char *lb_autotune_device_tag(void);
 
 /* Same for a batch (merge-path items_per_thread and block_size). */
 LB_API lb_status_t lb_batched_autotune(const lb_batch_t *B, const void *X, lb_dtype_t x_dtype,
                                        int32_t k, float *Y, void *workspace,
                                        size_t workspace_bytes, lb_schedule_t *best, void *stream);
 
-/* Forget every tuned schedule (process-wide). */
+/* Forget every tuned schedule and binding (process-wide). */
 LB_API void lb_autotune_clear(void);
 
 /* Debug check of the device-only CSR preconditions; synchronizes `stream`.
@@ -469,11 +583,12 @@ LB_API lb_status_t lb_bfs(const lb_csr_t *G, int64_t source, int32_t *depth, con
  *    floats, one partial sum per thread to out[grid * 256]; with a matrix's
  *    col_idx as idx it times the x gather alone, the floor of an SpMV kernel
  *    on that matrix that gathers the same way.  bands = 1: idx read
- *    non-temporally in a grid stride over all XCDs; bands = 2: the gather of
- *    the two-band merge path (x_bands = 2): chunks of 2048 entries go to
- *    pairs of blocks on different XCDs, each reading the whole chunk and
- *    gathering only the entries of its half of x (grid rounded down to a
- *    multiple of 8, at least 8).
+ *    non-temporally in a grid stride over all XCDs; bands = 2, 4 or 8: the
+ *    gather of a banded merge path (x_bands = 2): chunks of 2048 entries go
+ *    to `bands` blocks on different XCDs, each reading the whole chunk and
+ *    gathering only the entries of its band of x (columns [b * cb, (b + 1) *
+ *    cb), cb = ceil(cols / bands)), XCD x serving band x mod bands (grid
+ *    rounded down to a multiple of 8, at least 8).
  * Both are asynchronous on `stream`; idx values must lie in [0, cols). */
 LB_API lb_status_t lb_probe_stream_read(const void *buf, size_t bytes, float *out, int32_t grid, void *stream);
 LB_API lb_status_t lb_probe_gather(const int32_t *idx, int64_t n, const float *x, int64_t cols, float *out,

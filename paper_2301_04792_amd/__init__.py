@@ -27,8 +27,8 @@ from ._abi import LBError  # noqa: F401
 
 _lib = _abi.load()
 
-__all__ = ["CSR", "Pattern", "Batch", "spmv", "spmv_noalloc", "spmm", "spmv_backward", "SpMV", "spmv_diff",
-           "batched_spmm", "tune", "tune_batched", "merge_path_partition", "group_tile_owner",
+__all__ = ["CSR", "Pattern", "Batch", "spmv", "spmv_noalloc", "Plan", "spmv_planned", "spmm", "spmv_backward", "SpMV", "spmv_diff",
+           "batched_spmm", "tune", "tune_batched", "pattern_fingerprint", "autotune_lookup", "merge_path_partition", "group_tile_owner",
            "sssp", "bfs", "traversal_workspace_size", "COO", "CSC", "spmv_coo", "spmv_csc",
            "coo_merge_path_partition", "coo_workspace_size", "csc_workspace_size", "transpose_pattern", "spgemm",
            "validate", "resolve_schedule", "profile_enable", "profile_reset", "profile_read", "LBError"]
@@ -170,6 +170,52 @@ def spmv_noalloc(A: CSR, x: torch.Tensor, y: torch.Tensor, schedule="merge_path"
     s = make_schedule(schedule, **params)
     _abi.check(_lib.lb_spmv_noalloc(ctypes.byref(A.c_struct()), _ptr(x), _dtype_code(x), _ptr(y), ctypes.byref(s),
                                     _stream(A.device)), "lb_spmv_noalloc")
+    return y
+
+
+class Plan:
+    """A plan of y = A x for A's sparsity pattern (lb_spmv_plan_build): short
+    rows on the merge path, long rows on LDS panels of x.  Holds the plan's
+    device buffer (torch-allocated) and the ctypes struct; the matrix's
+    values may change between calls, the pattern may not."""
+
+    def __init__(self, A: CSR, block_size=0, items_per_thread=0, x_bands=0, long_min=0, panel_cols=0, chunk_atoms=0,
+                 streams=0):
+        self.shape = tuple(A.shape)
+        self.nnz = A.nnz
+        self.device = A.device
+        p = _abi.SpmvPlan()
+        p.block_size, p.items_per_thread, p.x_bands = block_size, items_per_thread, x_bands
+        p.long_min, p.panel_cols, p.chunk_atoms, p.streams = long_min, panel_cols, chunk_atoms, streams
+        c = A.c_struct()
+        st = _lib.lb_spmv_plan_build(ctypes.byref(c), ctypes.byref(p), None, 0, _stream(A.device))
+        if st not in (_abi.OK, _abi.ERR_WORKSPACE_TOO_SMALL):
+            _abi.check(st, "lb_spmv_plan_build")
+        self.buffer = torch.empty(max(int(p.plan_bytes), 1), dtype=torch.uint8, device=A.device)
+        _abi.check(_lib.lb_spmv_plan_build(ctypes.byref(c), ctypes.byref(p), _ptr(self.buffer), self.buffer.numel(),
+                                           _stream(A.device)), "lb_spmv_plan_build")
+        self.c = p
+
+    @property
+    def info(self) -> dict:
+        return self.c.as_dict()
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self.c.workspace_bytes)
+
+
+def spmv_planned(A: CSR, plan: Plan, x: torch.Tensor, y: torch.Tensor | None = None,
+                 workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """y = A x with a plan built for A's pattern (float32 y)."""
+    if x.dim() != 1 or x.numel() != A.shape[1]:
+        raise ValueError("x must be a vector of length cols")
+    x = x.contiguous()
+    if y is None:
+        y = torch.empty(A.shape[0], dtype=torch.float32, device=A.device)
+    ws = _workspace(plan.workspace_bytes, A.device, workspace)
+    _abi.check(_lib.lb_spmv_planned(ctypes.byref(A.c_struct()), ctypes.byref(plan.c), _ptr(x), _dtype_code(x),
+                                    _ptr(y), _ptr(ws), plan.workspace_bytes, _stream(A.device)), "lb_spmv_planned")
     return y
 
 
@@ -377,6 +423,25 @@ def tune_batched(batch: Batch, k: int = 1) -> dict:
     return best.as_dict()
 
 
+def pattern_fingerprint(A: CSR) -> int:
+    """The 64-bit pattern fingerprint of A the tuning cache keys on."""
+    fp = ctypes.c_uint64(0)
+    _abi.check(_lib.lb_pattern_fingerprint(ctypes.byref(A.c_struct()), ctypes.byref(fp), _stream(A.device)),
+               "lb_pattern_fingerprint")
+    return int(fp.value)
+
+
+def autotune_lookup(A: CSR, k: int = 1, fingerprint: int | None = None):
+    """Bind A to its fingerprint and return the cached pick (dict) or None."""
+    if fingerprint is None:
+        fingerprint = pattern_fingerprint(A)
+    found = ctypes.c_int32(0)
+    out = _abi.Schedule()
+    _abi.check(_lib.lb_autotune_lookup(ctypes.byref(A.c_struct()), k, ctypes.c_uint64(fingerprint),
+                                       ctypes.byref(found), ctypes.byref(out)), "lb_autotune_lookup")
+    return out.as_dict() if found.value else None
+
+
 def autotune_clear():
     _lib.lb_autotune_clear()
 
@@ -428,7 +493,7 @@ def probe_stream_read(buf: torch.Tensor, out: torch.Tensor | None = None) -> tor
 
 def probe_gather(idx: torch.Tensor, x: torch.Tensor, out: torch.Tensor | None = None, bands: int = 1) -> torch.Tensor:
     """Launch the gather probe: partial sums of x[idx], one band over all
-    XCDs or the two-band split of the x_bands = 2 merge path (measurement hook)."""
+    XCDs, or 2, 4 or 8 column bands spread over the XCDs (measurement hook)."""
     grid = _lib.lb_probe_default_grid()
     out = out if out is not None else torch.empty(grid * 256, dtype=torch.float32, device=x.device)
     if out.numel() < grid * 256:

@@ -16,6 +16,7 @@ LIB_PATH = os.environ.get("LB_LIBRARY", os.path.join(_PKG, "liblb.so"))
  ERR_NOT_CONVERGED, ERR_SCRATCH_LIMIT) = range(9)
 # static scratch of lb_spmv_noalloc per GPU (LB_NOALLOC_SCRATCH_BYTES)
 NOALLOC_SCRATCH_BYTES = 16 << 20
+ABI_VERSION = 3
 # lb_dtype_t
 F32, BF16, F64 = 0, 1, 2
 # lb_sched_kind_t
@@ -66,6 +67,21 @@ class CSC(ctypes.Structure):
                 ("values", ctypes.c_void_p), ("value_dtype", ctypes.c_int)]
 
 
+class SpmvPlan(ctypes.Structure):
+    _fields_ = [("block_size", ctypes.c_int32), ("items_per_thread", ctypes.c_int32), ("x_bands", ctypes.c_int32),
+                ("long_min", ctypes.c_int32), ("panel_cols", ctypes.c_int32), ("chunk_atoms", ctypes.c_int32),
+                ("streams", ctypes.c_int32),
+                ("value_dtype", ctypes.c_int),
+                ("rows", ctypes.c_int64), ("cols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("long_nnz", ctypes.c_int64), ("long_rows", ctypes.c_int32), ("panels", ctypes.c_int32),
+                ("chunks", ctypes.c_int32), ("tasks", ctypes.c_int32), ("units", ctypes.c_int32),
+                ("active_units", ctypes.c_int32), ("plan_bytes", ctypes.c_size_t),
+                ("workspace_bytes", ctypes.c_size_t), ("buffer", ctypes.c_void_p)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "buffer"}
+
+
 class LBError(RuntimeError):
     def __init__(self, status: int, what: str, detail: str = ""):
         self.status = status
@@ -95,6 +111,8 @@ SIGNATURES = {
     "lb_workspace_size": (ST, [PCSR, PSCHED, I32, ctypes.POINTER(SZ)]),
     "lb_spmv": (ST, [PCSR, P, ST, P, PSCHED, P, SZ, P]),
     "lb_spmv_noalloc": (ST, [PCSR, P, ST, P, PSCHED, P]),
+    "lb_spmv_plan_build": (ST, [PCSR, ctypes.POINTER(SpmvPlan), P, SZ, P]),
+    "lb_spmv_planned": (ST, [PCSR, ctypes.POINTER(SpmvPlan), P, ST, P, P, SZ, P]),
     "lb_spmm": (ST, [PCSR, P, ST, I32, I64, P, I64, PSCHED, P, SZ, P]),
     "lb_spmv_backward": (ST, [PCSR, P, ST, P, P, P, PSCHED, P, SZ, P]),
     "lb_batched_workspace_size": (ST, [PBATCH, PSCHED, I32, ctypes.POINTER(SZ)]),
@@ -105,6 +123,9 @@ SIGNATURES = {
     "lb_autotune": (ST, [PCSR, P, ST, I32, P, P, SZ, PSCHED, P]),
     "lb_batched_autotune": (ST, [PBATCH, P, ST, I32, P, P, SZ, PSCHED, P]),
     "lb_autotune_clear": (None, []),
+    "lb_pattern_fingerprint": (ST, [PCSR, ctypes.POINTER(ctypes.c_uint64), P]),
+    "lb_autotune_lookup": (ST, [PCSR, I32, ctypes.c_uint64, ctypes.POINTER(I32), PSCHED]),
+    "lb_autotune_device_tag": (ctypes.c_char_p, []),
     "lb_validate_csr": (ST, [PCSR, P]),
     "lb_transpose_workspace_size": (ST, [PCSR, ctypes.POINTER(SZ)]),
     "lb_transpose_pattern": (ST, [PCSR, P, P, P, P, SZ, P]),
@@ -143,7 +164,7 @@ def load():
         f = getattr(lib, name)
         f.restype = res
         f.argtypes = args
-    if lib.lb_abi_version() != 2:
+    if lib.lb_abi_version() != ABI_VERSION:
         raise ImportError("liblb.so ABI version mismatch")
     _lib = lib
     return lib

@@ -112,15 +112,26 @@ hipError_t merge_partition(const int32_t *ro, int32_t rows, int32_t nnz, int32_t
 // gathers get from long sorted rows, so this form pays only where columns
 // are local (a stencil).  The launcher requires nnz >= 4 and aligned
 // col_idx / values.
-template <int BLOCK, int ITEMS, typename VT, typename XT, int BANDS, bool VPERM = false, int VEC = 1>
+// PLAN (planned SpMV, short rows only): the block's unit is active[b] (T is
+// then the number of active units), the split comes from the plan, and the
+// long rows (at least long_min nonzeros) are left out: their nonzeros give
+// zero products and their y and carries are not this kernel's.  As
+// long_min >= W, only the unit's first row i0 (begun before the unit) and
+// its open row i1 can be long, so the short nonzeros are the one range
+// [ja, jb); carry_row is not written (the carry of unit u belongs to row
+// part_i[u + 1]).
+template <int BLOCK, int ITEMS, typename VT, typename XT, int BANDS, bool VPERM = false, int VEC = 1,
+          bool PLAN = false>
 __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
     int32_t rows, int32_t nnz, const int32_t *__restrict__ ro, const int32_t *__restrict__ ci, const VT *__restrict__ val,
     const XT *__restrict__ x, float *__restrict__ y, const int32_t *__restrict__ part_i,
     const int32_t *__restrict__ part_j, int32_t *__restrict__ carry_row, float *__restrict__ carry_val,
-    int32_t T, int32_t cb, float *__restrict__ y_hi, const int32_t *__restrict__ vperm) {
+    int32_t T, int32_t cb, float *__restrict__ y_hi, const int32_t *__restrict__ vperm,
+    const int32_t *__restrict__ active = nullptr, int32_t long_min = 0) {
     static_assert(BANDS == 1 || BANDS == 2, "one or two column bands");
     static_assert(!(VPERM && BANDS != 1), "permuted values with one band only");
     static_assert(VEC == 1 || (VEC == 4 && BANDS == 1 && !VPERM && ITEMS % 4 == 0), "vector loads: one band");
+    static_assert(!PLAN || (VEC == 1 && !VPERM), "planned form: one nonzero per lane, own values");
     constexpr int W = BLOCK * ITEMS;
     __shared__ int32_t s_buf[W];  // row ends [0, nrows), then products [nrows, nrows + nnzs)
     __shared__ seg_t s_wave[BLOCK / kWave];
@@ -134,11 +145,25 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
         if (b >= T) return;  // uniform across the block, before any barrier
         if (band == 1) y = y_hi;
     }
+    const int slot = b;  // carry slot (the unit index; the active-list index when planned)
+    if constexpr (PLAN) b = active[b];
     const int32_t i0 = part_i[b], j0 = part_j[b];
     const int32_t i1 = part_i[b + 1], j1 = part_j[b + 1];
     const int32_t nrows = i1 - i0, nnzs = j1 - j0;
     int32_t *s_re = s_buf;
     float *s_pv = reinterpret_cast<float *>(s_buf + nrows);
+    // [ja, jb): the nonzeros whose products this block sums (all of the unit's
+    // unless planned); skip_first: row i0 is long, its y is not written here
+    int32_t ja = j0, jb = j1;
+    bool skip_first = false;
+    if constexpr (PLAN) {
+        if (i0 < i1 && ro[i0 + 1] - ro[i0] >= long_min) {
+            skip_first = true;
+            ja = ro[i0 + 1];
+        }
+        if (i1 < rows && i1 > i0 && ro[i1 + 1] - ro[i1] >= long_min) jb = ro[i1];
+        if (jb < ja) jb = ja;
+    }
 
     // Setup: row ends relative to j0 (in [0, nnzs]) and products, coalesced;
     // consecutive lanes take consecutive nonzeros so that the x gathers of a
@@ -149,7 +174,9 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
     // the same cache line), so the compiler's wait counts stay exact and all
     // ITEMS gathers of a lane are in flight together.
     const int32_t re_last = i1 > i0 ? i1 : i0 + 1 <= rows ? i0 + 1 : rows;  // a valid row_offsets index
-    const int32_t nz_last = nnzs > 0 ? j1 - 1 : (j0 < nnz ? j0 : nnz - 1);  // a valid nonzero index
+    // nonzero loads are clamped into [nz_first, nz_last], valid indices
+    const int32_t nz_last = jb > ja ? jb - 1 : (ja < nnz ? ja : nnz - 1);
+    const int32_t nz_first = ja < nz_last ? ja : nz_last;
     int32_t re[ITEMS], c[ITEMS];
     float pv[ITEMS];
     if constexpr (VEC == 4) {
@@ -203,12 +230,13 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
             const int32_t k = tid + u * BLOCK;
             const int32_t rk = i0 + 1 + k;
             const int32_t jk = j0 + k;
+            const int32_t jc = jk < nz_first ? nz_first : (jk < nz_last ? jk : nz_last);
             re[u] = ro[rk < re_last ? rk : re_last];
-            c[u] = ld_stream(ci + (jk < nz_last ? jk : nz_last));
+            c[u] = ld_stream(ci + jc);
             if constexpr (VPERM)
-                vp[u] = ld_stream(vperm + (jk < nz_last ? jk : nz_last));
+                vp[u] = ld_stream(vperm + jc);
             else
-                v[u] = ld_stream(val + (jk < nz_last ? jk : nz_last));
+                v[u] = ld_stream(val + jc);
         }
 #pragma unroll
         for (int u = 0; u < ITEMS; ++u) {
@@ -216,7 +244,13 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
             xv[u] = to_f32(x[c[u]]);
         }
 #pragma unroll
-        for (int u = 0; u < ITEMS; ++u) pv[u] = to_f32(v[u]) * xv[u];
+        for (int u = 0; u < ITEMS; ++u) {
+            pv[u] = to_f32(v[u]) * xv[u];
+            if constexpr (PLAN) {
+                const int32_t jk = j0 + tid + u * BLOCK;
+                if (jk < ja || jk >= jb) pv[u] = 0.f;
+            }
+        }
     } else {
         // band 0 takes col < cb, band 1 col >= cb: x is gathered only for a
         // nonzero of the block's own band
@@ -226,13 +260,18 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
             const int32_t k = tid + u * BLOCK;
             const int32_t rk = i0 + 1 + k;
             const int32_t jk = j0 + k;
+            const int32_t jc = jk < nz_first ? nz_first : (jk < nz_last ? jk : nz_last);
             re[u] = ro[rk < re_last ? rk : re_last];
-            c[u] = ci[jk < nz_last ? jk : nz_last];
-            v[u] = val[jk < nz_last ? jk : nz_last];
+            c[u] = ci[jc];
+            v[u] = val[jc];
         }
 #pragma unroll
         for (int u = 0; u < ITEMS; ++u) {
-            const bool mine = (c[u] >= cb) == (band == 1);
+            bool mine = (c[u] >= cb) == (band == 1);
+            if constexpr (PLAN) {
+                const int32_t jk = j0 + tid + u * BLOCK;
+                mine = mine && jk >= ja && jk < jb;
+            }
             pv[u] = mine ? to_f32(v[u]) * to_f32(x[c[u]]) : 0.f;
         }
     }
@@ -284,10 +323,10 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
 
     seg_t tot;
     const seg_t in = block_seg_scan_excl<BLOCK>(seg_t{acc, first >= 0}, s_wave, tot);
-    if (first >= 0) y[i0 + first] = first_sum + in.v;
+    if (first >= 0 && !(skip_first && first == 0)) y[i0 + first] = first_sum + in.v;
     if (tid == 0) {
-        carry_row[b * BANDS + band] = i1;  // the row still open at the block's end (rows if none)
-        carry_val[b * BANDS + band] = tot.v;
+        if constexpr (!PLAN) carry_row[slot * BANDS + band] = i1;  // the row still open at the block's end (rows if none)
+        carry_val[(PLAN ? b : slot) * BANDS + band] = tot.v;
     }
 }
 
@@ -435,6 +474,40 @@ static hipError_t run_merge_spmv(const csr_dev &A, const void *x, float *y, int 
         return hipGetLastError();
     }
     return launch_fixup(T, A.rows, 1, w.carry_row, w.carry_val, y, 1, s, "merge_fixup");
+}
+
+template <int BLOCK, int ITEMS, typename VT>
+static hipError_t run_planned_consume(const csr_dev &A, const plan_dev &pl, const void *x, float *y,
+                                      float *carry_val, float *y_hi, hipStream_t s) {
+    prof_scope p(s, "merge_consume");
+    const VT *val = static_cast<const VT *>(A.val);
+    const VT *xx = static_cast<const VT *>(x);
+    const int32_t cb = static_cast<int32_t>((A.cols + 1) / 2);
+    if (pl.bands == 2) {
+        const int64_t per = kXcds / 2;
+        const int64_t grid = (pl.NA + per - 1) / per * kXcds;
+        hipLaunchKernelGGL((merge_spmv_consume<BLOCK, ITEMS, VT, VT, 2, false, 1, true>),
+                           dim3(static_cast<uint32_t>(grid)), dim3(BLOCK), 0, s, A.rows, A.nnz, A.ro, A.ci, val, xx, y,
+                           pl.part_i, pl.part_j, nullptr, carry_val, pl.NA, cb, y_hi, nullptr, pl.active, pl.long_min);
+    } else {
+        hipLaunchKernelGGL((merge_spmv_consume<BLOCK, ITEMS, VT, VT, 1, false, 1, true>),
+                           dim3(static_cast<uint32_t>(pl.NA)), dim3(BLOCK), 0, s, A.rows, A.nnz, A.ro, A.ci, val, xx,
+                           y, pl.part_i, pl.part_j, nullptr, carry_val, pl.NA, cb, nullptr, nullptr, pl.active,
+                           pl.long_min);
+    }
+    return hipGetLastError();
+}
+
+hipError_t merge_spmv_planned_consume(const csr_dev &A, const plan_dev &pl, const void *x, float *y,
+                                      float *carry_val, float *y_hi, hipStream_t s) {
+#define X(B, I)                                                                                    \
+    if (pl.block == B && pl.items == I) {                                                          \
+        if (A.dt == LB_BF16) return run_planned_consume<B, I, bf16_bits>(A, pl, x, y, carry_val, y_hi, s); \
+        return run_planned_consume<B, I, float>(A, pl, x, y, carry_val, y_hi, s);                  \
+    }
+    LB_MERGE_CONFIGS(X)
+#undef X
+    return hipErrorInvalidValue;
 }
 
 bool merge_config_supported(int block, int items) {

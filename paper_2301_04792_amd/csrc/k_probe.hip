@@ -42,20 +42,23 @@ hipError_t probe_stream_read(const void *buf, size_t bytes, float *out, int grid
     return hipGetLastError();
 }
 
-// The two-band gather (as in the x_bands = 2 merge path): block b takes
-// band (b mod 8) mod 2 of the chunks slot, slot + grid / 2, ... with slot =
-// (b / 8) * 4 + (b mod 8) / 2, so both bands of a chunk run on different
-// XCDs; grid is a multiple of 8.
+// The banded gather (as in the x_bands = 2 merge path, generalised to
+// BANDS in {2, 4, 8}): block b serves band (b mod 8) mod BANDS of the chunks
+// slot, slot + grid / BANDS, ... with slot = (b / 8) * (8 / BANDS) +
+// (b mod 8) / BANDS, so the bands of a chunk run on different XCDs and XCD
+// x only gathers from band x mod BANDS of x (columns [band * cb, (band + 1)
+// * cb)); grid is a multiple of 8.
 constexpr int kBandChunk = 256 * 8;
 
+template <int BANDS>
 __global__ __launch_bounds__(256) void probe_gather_banded_kernel(const int32_t *__restrict__ idx, int64_t n,
                                                                   int32_t cb, const float *__restrict__ x,
                                                                   float *__restrict__ out) {
     const int xcd = static_cast<int>(blockIdx.x % kXcds);
-    const bool high = (xcd & 1) != 0;
-    const int64_t slots = gridDim.x / 2;
+    const int band = xcd % BANDS;
+    const int64_t slots = gridDim.x / BANDS;
     float a = 0.f;
-    for (int64_t u = static_cast<int64_t>(blockIdx.x / kXcds) * (kXcds / 2) + xcd / 2; u * kBandChunk < n;
+    for (int64_t u = static_cast<int64_t>(blockIdx.x / kXcds) * (kXcds / BANDS) + xcd / BANDS; u * kBandChunk < n;
          u += slots) {
         const int64_t base = u * kBandChunk + threadIdx.x;
         int32_t c[8];
@@ -63,7 +66,7 @@ __global__ __launch_bounds__(256) void probe_gather_banded_kernel(const int32_t 
         for (int k = 0; k < 8; ++k) c[k] = base + k * 256 < n ? idx[base + k * 256] : -1;
 #pragma unroll
         for (int k = 0; k < 8; ++k)
-            if (c[k] >= 0 && (c[k] >= cb) == high) a += x[c[k]];
+            if (c[k] >= 0 && c[k] / cb == band) a += x[c[k]];
     }
     out[static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x] = a;
 }
@@ -72,7 +75,11 @@ hipError_t probe_gather(const int32_t *idx, int64_t n, const float *x, int32_t c
                         hipStream_t s) {
     prof_scope p(s, "probe_gather");
     if (bands == 2)
-        hipLaunchKernelGGL(probe_gather_banded_kernel, dim3(grid), dim3(256), 0, s, idx, n, cb, x, out);
+        hipLaunchKernelGGL(probe_gather_banded_kernel<2>, dim3(grid), dim3(256), 0, s, idx, n, cb, x, out);
+    else if (bands == 4)
+        hipLaunchKernelGGL(probe_gather_banded_kernel<4>, dim3(grid), dim3(256), 0, s, idx, n, cb, x, out);
+    else if (bands == 8)
+        hipLaunchKernelGGL(probe_gather_banded_kernel<8>, dim3(grid), dim3(256), 0, s, idx, n, cb, x, out);
     else
         hipLaunchKernelGGL(probe_gather_kernel, dim3(grid), dim3(256), 0, s, idx, n, x, out);
     return hipGetLastError();

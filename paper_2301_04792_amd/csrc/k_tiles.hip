@@ -322,6 +322,19 @@ hipError_t fill_f32(float *p, int64_t n, float v, hipStream_t s) {
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void sample_kernel(const int32_t *__restrict__ a, int64_t n, int32_t count,
+                                                     int32_t *__restrict__ out) {
+    const int32_t i = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < count) out[i] = n > 0 ? a[static_cast<int64_t>(i) * n / count] : 0;
+}
+
+hipError_t gather_samples(const int32_t *a, int64_t n, int32_t count, int32_t *out, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sample_kernel, dim3(static_cast<uint32_t>((count + 255) / 256)), dim3(256), 0, s, a, n, count,
+                       out);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void validate_kernel(csr_tile_set ts, int32_t cols, const int32_t *__restrict__ ci,
                                                        int32_t *__restrict__ flags) {
     int32_t f = 0;

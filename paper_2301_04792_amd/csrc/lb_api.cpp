@@ -72,21 +72,65 @@ lbk::csr_dev to_dev(const lb_csr_t *A) {
 
 // ------------------------------------------------------------------ autotune cache
 
+// A tuned pick is kept for a matrix shape, k, dtype, batched flag and a
+// fingerprint of the sparsity pattern, on the device it was timed on (arch
+// and CU count) and for this ABI version.  The fingerprint cannot be taken
+// inside an asynchronous call (it reads the pattern), so LB_AUTO finds it
+// through a binding: lb_autotune and lb_autotune_lookup bind the matrix's
+// device arrays (pointers and shape) to its fingerprint.  A matrix without
+// a binding gets the Sec. 6.2 rule.
 struct tune_key {
     int64_t rows, cols, nnz;
     int32_t k;
     int32_t dtype;
     int32_t batched;
+    uint64_t fp;
     bool operator<(const tune_key &o) const {
-        return std::tie(rows, cols, nnz, k, dtype, batched) < std::tie(o.rows, o.cols, o.nnz, o.k, o.dtype, o.batched);
+        return std::tie(rows, cols, nnz, k, dtype, batched, fp) <
+               std::tie(o.rows, o.cols, o.nnz, o.k, o.dtype, o.batched, o.fp);
+    }
+};
+
+struct bind_key {
+    const void *ro, *ci;
+    int64_t rows, cols, nnz;
+    int32_t batched;
+    bool operator<(const bind_key &o) const {
+        return std::tie(ro, ci, rows, cols, nnz, batched) < std::tie(o.ro, o.ci, o.rows, o.cols, o.nnz, o.batched);
     }
 };
 
 std::mutex g_tune_mu;
 std::map<tune_key, lb_schedule_t> g_tune;
+std::map<bind_key, uint64_t> g_bind;
+std::vector<std::string> g_tune_foreign;  // file lines of other devices or ABI versions, kept verbatim
 bool g_tune_loaded = false;
+std::string g_device_tag;
 
 const char *tune_path() { return std::getenv("LB_AUTOTUNE_CACHE"); }
+
+// "<arch>:<compute units>" of the current device, "none:0" without one.
+std::string device_tag_now() {
+    int dev = 0, n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0 || hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return "none:0";
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return "none:0";
+    }
+    std::string arch(prop.gcnArchName);
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+    return arch + ":" + std::to_string(prop.multiProcessorCount);
+}
+
+const std::string &device_tag_locked() {
+    if (g_device_tag.empty()) g_device_tag = device_tag_now();
+    return g_device_tag;
+}
 
 void tune_load_locked() {
     if (g_tune_loaded) return;
@@ -95,16 +139,24 @@ void tune_load_locked() {
     if (!p || !*p) return;
     std::ifstream f(p);
     std::string line;
-    // one entry per line: rows cols nnz k dtype batched kind group tiles items block grid [x_bands vector_width]
+    const std::string &tag = device_tag_locked();
+    // one entry per line: lbtune abi device rows cols nnz k dtype batched fingerprint(hex)
+    //                     kind group tiles items block grid x_bands vector_width
     while (std::getline(f, line)) {
         std::istringstream ss(line);
+        std::string magic, dev;
+        int abi = 0;
+        if (!(ss >> magic >> abi >> dev) || magic != "lbtune") continue;  // not an entry: dropped
+        if (abi != LB_ABI_VERSION || dev != tag) {
+            g_tune_foreign.push_back(line);
+            continue;
+        }
         tune_key key{};
         lb_schedule_t s{};
         int kind = 0;
-        if (ss >> key.rows >> key.cols >> key.nnz >> key.k >> key.dtype >> key.batched >> kind >> s.group_size >>
-            s.tiles_per_group >> s.items_per_thread >> s.block_size >> s.grid_size) {
-            if (!(ss >> s.x_bands)) s.x_bands = 1;
-            if (!(ss >> s.vector_width)) s.vector_width = 1;
+        if (ss >> key.rows >> key.cols >> key.nnz >> key.k >> key.dtype >> key.batched >> std::hex >> key.fp >>
+            std::dec >> kind >> s.group_size >> s.tiles_per_group >> s.items_per_thread >> s.block_size >>
+            s.grid_size >> s.x_bands >> s.vector_width) {
             s.kind = static_cast<lb_sched_kind_t>(kind);
             g_tune[key] = s;
         }
@@ -115,10 +167,13 @@ void tune_save_locked() {
     const char *p = tune_path();
     if (!p || !*p) return;
     std::ofstream f(p, std::ios::trunc);
+    for (const std::string &l : g_tune_foreign) f << l << '\n';
+    const std::string &tag = device_tag_locked();
     for (const auto &kv : g_tune) {
         const tune_key &k = kv.first;
         const lb_schedule_t &s = kv.second;
-        f << k.rows << ' ' << k.cols << ' ' << k.nnz << ' ' << k.k << ' ' << k.dtype << ' ' << k.batched << ' '
+        f << "lbtune " << LB_ABI_VERSION << ' ' << tag << ' ' << k.rows << ' ' << k.cols << ' ' << k.nnz << ' '
+          << k.k << ' ' << k.dtype << ' ' << k.batched << ' ' << std::hex << k.fp << std::dec << ' '
           << static_cast<int>(s.kind) << ' ' << s.group_size << ' ' << s.tiles_per_group << ' '
           << s.items_per_thread << ' ' << s.block_size << ' ' << s.grid_size << ' ' << s.x_bands << ' '
           << s.vector_width << '\n';
@@ -140,6 +195,43 @@ void tune_store(const tune_key &key, const lb_schedule_t &s) {
     g_tune[key] = s;
     tune_save_locked();
 }
+
+void tune_bind(const bind_key &b, uint64_t fp) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_bind[b] = fp;
+}
+
+// The tuned pick for a bound matrix (false when unbound or untuned).
+bool tune_lookup_bound(const bind_key &b, const tune_key &shape, lb_schedule_t *out) {
+    uint64_t fp = 0;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_bind.find(b);
+        if (it == g_bind.end()) return false;
+        fp = it->second;
+    }
+    tune_key key = shape;
+    key.fp = fp;
+    return tune_lookup(key, out);
+}
+
+// FNV-1a, 64 bit.
+struct fnv64 {
+    uint64_t h = 0xcbf29ce484222325ull;
+    void add(const void *p, size_t n) {
+        const unsigned char *c = static_cast<const unsigned char *>(p);
+        for (size_t i = 0; i < n; ++i) {
+            h ^= c[i];
+            h *= 0x100000001b3ull;
+        }
+    }
+    template <typename T>
+    void add(const T &v) {
+        add(&v, sizeof v);
+    }
+};
+
+constexpr int32_t kFingerprintSamples = 4096;
 
 // ------------------------------------------------------------------ schedule checks
 
@@ -211,8 +303,9 @@ lb_status_t resolve(const lb_csr_t *A, int32_t k, const lb_schedule_t *in, lb_sc
     lb_schedule_t s = *in;
     if (s.kind == LB_AUTO) {
         lb_schedule_t tuned;
-        const tune_key key{A->rows, A->cols, A->nnz, k, static_cast<int32_t>(A->value_dtype), 0};
-        if (tune_lookup(key, &tuned))
+        const tune_key key{A->rows, A->cols, A->nnz, k, static_cast<int32_t>(A->value_dtype), 0, 0};
+        const bind_key b{A->row_offsets, A->col_idx, A->rows, A->cols, A->nnz, 0};
+        if (tune_lookup_bound(b, key, &tuned))
             s = tuned;
         else
             s = heuristic(A);
@@ -507,6 +600,73 @@ lb_status_t spmv_launch(const lb_csr_t *A, const void *x, float *y, const lb_sch
     }
 }
 
+// ------------------------------------------------------------------ planned SpMV
+
+constexpr int64_t kChunkAtomsPerPanel = 16384;  // long-row nonzeros per (chunk, panel) block, on average
+
+// Resolves the plan's inputs for A (defaults, checks) into *out; host only.
+lb_status_t plan_params(const lb_csr_t *A, const lb_spmv_plan_t *in, lb_spmv_plan_t *out) {
+    lb_spmv_plan_t p{};
+    p.block_size = in->block_size ? in->block_size : kDefaultBlock;
+    p.items_per_thread = in->items_per_thread ? in->items_per_thread : kDefaultItems;
+    if (p.block_size < 0 || p.items_per_thread < 0) return LB_ERR_INVALID_ARG;
+    if (!lbk::merge_config_supported(p.block_size, p.items_per_thread)) return LB_ERR_UNSUPPORTED;
+    const int64_t W = static_cast<int64_t>(p.block_size) * p.items_per_thread;
+    const int64_t sx = A->value_dtype == LB_BF16 ? 2 : 4;
+    p.x_bands = in->x_bands ? in->x_bands : (A->cols * sx >= (int64_t(4) << 20) ? 2 : 1);
+    if (p.x_bands != 1 && p.x_bands != 2) return LB_ERR_INVALID_ARG;
+    p.panel_cols = in->panel_cols ? in->panel_cols : static_cast<int32_t>(lbk::kPanelBytes / sx);
+    p.streams = in->streams ? in->streams : 1;
+    p.chunk_atoms = in->chunk_atoms ? in->chunk_atoms : static_cast<int32_t>(kChunkAtomsPerPanel);
+    if (p.chunk_atoms < lbk::kPanelTask) return LB_ERR_INVALID_ARG;
+    if (p.streams != 1 && p.streams != 2) return LB_ERR_INVALID_ARG;
+    if (!lbk::panel_cols_ok(p.panel_cols, A->value_dtype)) return LB_ERR_INVALID_ARG;
+    const int64_t NP = (A->cols + p.panel_cols - 1) / p.panel_cols;
+    if (in->long_min == -1) {
+        p.long_min = 0x7fffffff;  // no row is long
+    } else if (in->long_min == 0) {
+        p.long_min = static_cast<int32_t>(std::max<int64_t>(W, 16 * NP));
+    } else {
+        if (in->long_min < W) return LB_ERR_INVALID_ARG;
+        p.long_min = in->long_min;
+    }
+    p.value_dtype = A->value_dtype;
+    p.rows = A->rows;
+    p.cols = A->cols;
+    p.nnz = A->nnz;
+    p.panels = static_cast<int32_t>(NP);
+    p.units = static_cast<int32_t>(lbk::merge_units(A->rows, A->nnz, W));
+    *out = p;
+    return LB_OK;
+}
+
+lbk::plan_dev plan_dev_of(const lb_spmv_plan_t &p) {
+    lbk::plan_dev d{};
+    d.rows = static_cast<int32_t>(p.rows);
+    d.T = p.units;
+    d.NA = p.active_units;
+    d.NL = p.long_rows;
+    d.NP = p.panels;
+    d.NC = p.chunks;
+    d.P = p.panel_cols;
+    d.long_min = p.long_min;
+    d.bands = p.x_bands;
+    d.streams = p.streams;
+    d.block = p.block_size;
+    d.items = p.items_per_thread;
+    d.ntasks = p.tasks;
+    const lbk::plan_layout L = lbk::plan_layout_of(p.units, p.units, p.long_rows, p.panels, p.chunks);
+    const char *b = static_cast<const char *>(p.buffer);
+    d.part_i = reinterpret_cast<const int32_t *>(b + L.part_i);
+    d.part_j = reinterpret_cast<const int32_t *>(b + L.part_j);
+    d.active = reinterpret_cast<const int32_t *>(b + L.active);
+    d.LR = reinterpret_cast<const int32_t *>(b + L.LR);
+    d.chunk_q = reinterpret_cast<const int32_t *>(b + L.chunk_q);
+    d.sb = reinterpret_cast<const int32_t *>(b + L.sb);
+    d.tb = reinterpret_cast<const int32_t *>(b + L.tb);
+    return d;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ static scratch
@@ -553,6 +713,46 @@ lb_status_t scratch_address(hipStream_t hs, void **out) {
         g_scratch_ptr[dev] = p;
     }
     *out = g_scratch_ptr[dev];
+    return LB_OK;
+}
+
+}  // namespace
+
+// Samples of col_idx for pattern fingerprints (host code uses only the
+// address hipGetSymbolAddress returns; calls are serialised by g_fp_mu).
+static __device__ int32_t g_fp_samples[kFingerprintSamples];
+
+namespace {
+
+std::mutex g_fp_mu;
+
+// Fingerprint of a pattern: FNV-1a over the sizes, every row offset, the
+// column indices at kFingerprintSamples evenly spaced positions and (a
+// batch) the matrices' base tables.  Synchronizes hs.
+lb_status_t fingerprint(int64_t rows, int64_t cols, int64_t nnz, const int32_t *ro, const int32_t *ci,
+                        const int64_t *const *bases, int64_t count, hipStream_t hs, uint64_t *out) {
+    std::lock_guard<std::mutex> g(g_fp_mu);
+    std::vector<int32_t> h_ro(static_cast<size_t>(rows) + 1, 0), h_smp(kFingerprintSamples, 0);
+    std::vector<int64_t> h_base(bases ? 3 * static_cast<size_t>(count + 1) : 0);
+    int32_t *d_smp = nullptr;
+    hipError_t e = hipGetSymbolAddress(reinterpret_cast<void **>(&d_smp), HIP_SYMBOL(g_fp_samples));
+    if (e == hipSuccess && rows > 0)
+        e = hipMemcpyAsync(h_ro.data(), ro, h_ro.size() * 4, hipMemcpyDeviceToHost, hs);
+    if (e == hipSuccess && nnz > 0) e = lbk::gather_samples(ci, nnz, kFingerprintSamples, d_smp, hs);
+    if (e == hipSuccess && nnz > 0) e = hipMemcpyAsync(h_smp.data(), d_smp, h_smp.size() * 4, hipMemcpyDeviceToHost, hs);
+    for (int t = 0; bases && t < 3 && e == hipSuccess; ++t)
+        e = hipMemcpyAsync(h_base.data() + t * (count + 1), bases[t], static_cast<size_t>(count + 1) * 8,
+                           hipMemcpyDeviceToHost, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) return hip_status(e);
+    fnv64 h;
+    h.add(rows);
+    h.add(cols);
+    h.add(nnz);
+    h.add(h_ro.data(), h_ro.size() * 4);
+    h.add(h_smp.data(), h_smp.size() * 4);
+    h.add(h_base.data(), h_base.size() * 8);
+    *out = h.h;
     return LB_OK;
 }
 
@@ -630,6 +830,138 @@ LB_API lb_status_t lb_spmv_noalloc(const lb_csr_t *A, const void *x, lb_dtype_t 
         if (st != LB_OK) return st;
     }
     return spmv_launch(A, x, y, r, ws, hs);
+}
+
+LB_API lb_status_t lb_spmv_plan_build(const lb_csr_t *A, lb_spmv_plan_t *plan, void *buffer, size_t buffer_bytes,
+                                      void *stream) {
+    lb_status_t st = check_csr(A);
+    if (st != LB_OK) return st;
+    if (!plan) return LB_ERR_INVALID_ARG;
+    lb_spmv_plan_t p;
+    st = plan_params(A, plan, &p);
+    if (st != LB_OK) return st;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const int64_t rows = A->rows, NP = p.panels;
+    // row lengths on the host: the long rows, their chunks and a bound on the tasks
+    std::vector<int32_t> ro(static_cast<size_t>(rows) + 1, 0);
+    if (rows > 0) {
+        hipError_t e = hipMemcpyAsync(ro.data(), A->row_offsets, ro.size() * 4, hipMemcpyDeviceToHost, hs);
+        if (e == hipSuccess) e = hipStreamSynchronize(hs);
+        if (e != hipSuccess) return hip_status(e);
+    }
+    std::vector<int32_t> LR, chunk_q{0};
+    int64_t long_nnz = 0, task_bound = 0, acc = 0;
+    const int64_t target = static_cast<int64_t>(p.chunk_atoms) * std::max<int64_t>(NP, 1);
+    for (int64_t r = 0; r < rows; ++r) {
+        const int64_t len = static_cast<int64_t>(ro[r + 1]) - ro[r];
+        if (len < p.long_min) continue;
+        if (acc >= target || static_cast<int64_t>(LR.size()) - chunk_q.back() >= lbk::kPanelRows) {
+            chunk_q.push_back(static_cast<int32_t>(LR.size()));
+            acc = 0;
+        }
+        LR.push_back(static_cast<int32_t>(r));
+        long_nnz += len;
+        acc += len;
+        task_bound += (len + lbk::kPanelTask - 1) / lbk::kPanelTask + NP;
+    }
+    if (!LR.empty()) chunk_q.push_back(static_cast<int32_t>(LR.size()));
+    if (task_bound > kMaxCoord) return LB_ERR_OVERFLOW;
+    p.long_rows = static_cast<int32_t>(LR.size());
+    p.long_nnz = long_nnz;
+    p.chunks = static_cast<int32_t>(chunk_q.size()) - 1;
+    const int64_t T = p.units;
+    const lbk::plan_layout L = lbk::plan_layout_of(T, T, p.long_rows, NP, p.chunks);
+    p.plan_bytes = L.total;
+    p.active_units = static_cast<int32_t>(T);  // bounds until the build
+    p.tasks = static_cast<int32_t>(task_bound);
+    p.workspace_bytes = lbk::plan_ws_bytes(T, p.x_bands, rows, task_bound);
+    p.buffer = nullptr;
+    if (!buffer || buffer_bytes < p.plan_bytes) {
+        *plan = p;
+        return LB_ERR_WORKSPACE_TOO_SMALL;
+    }
+    char *b = static_cast<char *>(buffer);
+    int32_t *flags = reinterpret_cast<int32_t *>(b + L.flags);
+    int32_t *part_i = reinterpret_cast<int32_t *>(b + L.part_i);
+    int32_t *part_j = reinterpret_cast<int32_t *>(b + L.part_j);
+    int32_t *d_LR = reinterpret_cast<int32_t *>(b + L.LR);
+    int32_t *d_chunk = reinterpret_cast<int32_t *>(b + L.chunk_q);
+    int32_t *sb = reinterpret_cast<int32_t *>(b + L.sb);
+    int32_t *tb = reinterpret_cast<int32_t *>(b + L.tb);
+    int32_t *active = reinterpret_cast<int32_t *>(b + L.active);
+    const int64_t nsb = static_cast<int64_t>(p.long_rows) * (NP + 1);
+    std::vector<int32_t> h_sb(static_cast<size_t>(nsb)), h_part(static_cast<size_t>(T + 1));
+    int32_t h_flags = 0;
+    hipError_t e = hipMemsetAsync(flags, 0, 4, hs);
+    if (e == hipSuccess && rows > 0)
+        e = lbk::merge_partition(A->row_offsets, static_cast<int32_t>(rows), static_cast<int32_t>(A->nnz),
+                                 p.block_size * p.items_per_thread, static_cast<int32_t>(T), part_i, part_j, hs);
+    if (e == hipSuccess && !LR.empty()) e = hipMemcpyAsync(d_LR, LR.data(), LR.size() * 4, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess && !LR.empty())
+        e = hipMemcpyAsync(d_chunk, chunk_q.data(), chunk_q.size() * 4, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess && nsb > 0)
+        e = lbk::plan_segments_launch(p.long_rows, static_cast<int32_t>(NP), p.panel_cols, d_LR, A->row_offsets,
+                                      A->col_idx, sb, flags, hs);
+    if (e == hipSuccess && nsb > 0) e = hipMemcpyAsync(h_sb.data(), sb, h_sb.size() * 4, hipMemcpyDeviceToHost, hs);
+    if (e == hipSuccess && rows > 0)
+        e = hipMemcpyAsync(h_part.data(), part_i, h_part.size() * 4, hipMemcpyDeviceToHost, hs);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h_flags, flags, 4, hipMemcpyDeviceToHost, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) return hip_status(e);
+    if (h_flags & 1) return LB_ERR_INVALID_CSR;
+    // task table: row-major exclusive prefix of ceil(segment / kPanelTask)
+    std::vector<int32_t> h_tb(static_cast<size_t>(nsb));
+    int64_t ntasks = 0;
+    for (int64_t q = 0; q < p.long_rows; ++q) {
+        const int32_t *sq = h_sb.data() + q * (NP + 1);
+        int32_t *tq = h_tb.data() + q * (NP + 1);
+        for (int64_t pp = 0; pp < NP; ++pp) {
+            tq[pp] = static_cast<int32_t>(ntasks);
+            ntasks += (static_cast<int64_t>(sq[pp + 1]) - sq[pp] + lbk::kPanelTask - 1) / lbk::kPanelTask;
+        }
+        tq[NP] = static_cast<int32_t>(ntasks);
+    }
+    // units with short-row work: a row strictly inside closes in it, or its
+    // first closing row or its open row is short
+    std::vector<int32_t> h_active;
+    h_active.reserve(static_cast<size_t>(T));
+    auto is_short = [&](int64_t r) { return static_cast<int64_t>(ro[r + 1]) - ro[r] < p.long_min; };
+    for (int64_t u = 0; u < T; ++u) {
+        const int64_t i0 = h_part[u], i1 = h_part[u + 1];
+        if (i1 > i0 + 1 || (i0 < i1 && is_short(i0)) || (i1 < rows && is_short(i1)))
+            h_active.push_back(static_cast<int32_t>(u));
+    }
+    e = hipSuccess;
+    if (nsb > 0) e = hipMemcpyAsync(tb, h_tb.data(), h_tb.size() * 4, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess && !h_active.empty())
+        e = hipMemcpyAsync(active, h_active.data(), h_active.size() * 4, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) return hip_status(e);
+    p.active_units = static_cast<int32_t>(h_active.size());
+    p.tasks = static_cast<int32_t>(ntasks);
+    p.workspace_bytes = lbk::plan_ws_bytes(T, p.x_bands, rows, ntasks);
+    p.buffer = buffer;
+    *plan = p;
+    return LB_OK;
+}
+
+LB_API lb_status_t lb_spmv_planned(const lb_csr_t *A, const lb_spmv_plan_t *plan, const void *x, lb_dtype_t x_dtype,
+                                   float *y, void *workspace, size_t workspace_bytes, void *stream) {
+    lb_status_t st = check_csr(A);
+    if (st != LB_OK) return st;
+    if (!plan) return LB_ERR_INVALID_ARG;
+    if (plan->rows != A->rows || plan->cols != A->cols || plan->nnz != A->nnz ||
+        plan->value_dtype != A->value_dtype)
+        return LB_ERR_INVALID_ARG;
+    if (A->rows > 0 && (!y || !plan->buffer)) return LB_ERR_INVALID_ARG;
+    if (A->nnz > 0 && !x) return LB_ERR_INVALID_ARG;
+    if (x_dtype != A->value_dtype) return LB_ERR_UNSUPPORTED;
+    if (plan->workspace_bytes > 0 && (workspace_bytes < plan->workspace_bytes || !workspace))
+        return LB_ERR_WORKSPACE_TOO_SMALL;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    if (A->rows == 0) return LB_OK;
+    if (A->nnz == 0) return hip_status(lbk::fill_f32(y, A->rows, 0.f, hs));
+    return hip_status(lbk::planned_spmv(to_dev(A), plan_dev_of(*plan), x, y, workspace, hs));
 }
 
 LB_API lb_status_t lb_transpose_workspace_size(const lb_csr_t *A, size_t *bytes) {
@@ -944,8 +1276,9 @@ static lb_status_t resolve_batched(const lb_batch_t *B, int32_t k, const lb_sche
     lb_schedule_t in = s ? *s : lb_schedule_t{LB_AUTO, 0, 0, 0, 0, 0};
     if (in.kind == LB_AUTO) {
         lb_schedule_t tuned;
-        const tune_key key{B->total_rows, B->total_cols, B->total_nnz, k, static_cast<int32_t>(B->value_dtype), 1};
-        if (tune_lookup(key, &tuned))
+        const tune_key key{B->total_rows, B->total_cols, B->total_nnz, k, static_cast<int32_t>(B->value_dtype), 1, 0};
+        const bind_key b{B->row_offsets, B->col_idx, B->total_rows, B->total_cols, B->total_nnz, 1};
+        if (tune_lookup_bound(b, key, &tuned))
             in = tuned;
         else
             in = lb_schedule_t{LB_MERGE_PATH, 0, 0, 0, 0, 0};
@@ -1052,6 +1385,9 @@ LB_API lb_status_t lb_autotune(const lb_csr_t *A, const void *X, lb_dtype_t x_dt
     lb_autotune_workspace_size(A, k, &need);
     if (workspace_bytes < need || !workspace) return LB_ERR_WORKSPACE_TOO_SMALL;
     hipStream_t hs = static_cast<hipStream_t>(stream);
+    uint64_t fp = 0;
+    st = fingerprint(A->rows, A->cols, A->nnz, A->row_offsets, A->col_idx, nullptr, 0, hs, &fp);
+    if (st != LB_OK) return st;
     // The Sec. 6.2 pick with default parameters is the incumbent; a candidate
     // replaces it only if it is more than 2 % faster, so timing noise does
     // not flip the choice between equivalent configurations.
@@ -1082,7 +1418,8 @@ LB_API lb_status_t lb_autotune(const lb_csr_t *A, const void *X, lb_dtype_t x_dt
             fill_defaults(&c, &best_s);
         }
     }
-    tune_store(tune_key{A->rows, A->cols, A->nnz, k, static_cast<int32_t>(A->value_dtype), 0}, best_s);
+    tune_store(tune_key{A->rows, A->cols, A->nnz, k, static_cast<int32_t>(A->value_dtype), 0, fp}, best_s);
+    tune_bind(bind_key{A->row_offsets, A->col_idx, A->rows, A->cols, A->nnz, 0}, fp);
     *best = best_s;
     return LB_OK;
 }
@@ -1093,6 +1430,11 @@ LB_API lb_status_t lb_batched_autotune(const lb_batch_t *B, const void *X, lb_dt
     if (st != LB_OK) return st;
     if (!best || k < 1 || k > kMaxK) return LB_ERR_INVALID_ARG;
     hipStream_t hs = static_cast<hipStream_t>(stream);
+    uint64_t fp = 0;
+    const int64_t *bases[3] = {B->mat_row_base, B->mat_nnz_base, B->mat_col_base};
+    st = fingerprint(B->total_rows, B->total_cols, B->total_nnz, B->row_offsets, B->col_idx, bases, B->count, hs,
+                     &fp);
+    if (st != LB_OK) return st;
     float best_ms = 1e30f;
     lb_schedule_t best_s{};
     bool any = false;
@@ -1116,8 +1458,9 @@ LB_API lb_status_t lb_batched_autotune(const lb_batch_t *B, const void *X, lb_dt
         }
     }
     if (!any) return LB_ERR_WORKSPACE_TOO_SMALL;
-    tune_store(tune_key{B->total_rows, B->total_cols, B->total_nnz, k, static_cast<int32_t>(B->value_dtype), 1},
+    tune_store(tune_key{B->total_rows, B->total_cols, B->total_nnz, k, static_cast<int32_t>(B->value_dtype), 1, fp},
                best_s);
+    tune_bind(bind_key{B->row_offsets, B->col_idx, B->total_rows, B->total_cols, B->total_nnz, 1}, fp);
     *best = best_s;
     return LB_OK;
 }
@@ -1125,7 +1468,32 @@ LB_API lb_status_t lb_batched_autotune(const lb_batch_t *B, const void *X, lb_dt
 LB_API void lb_autotune_clear(void) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune.clear();
+    g_bind.clear();
     g_tune_loaded = true;  // do not reload the file after an explicit clear
+}
+
+LB_API lb_status_t lb_pattern_fingerprint(const lb_csr_t *A, uint64_t *fp, void *stream) {
+    lb_status_t st = check_csr(A);
+    if (st != LB_OK) return st;
+    if (!fp) return LB_ERR_INVALID_ARG;
+    return fingerprint(A->rows, A->cols, A->nnz, A->row_offsets, A->col_idx, nullptr, 0,
+                       static_cast<hipStream_t>(stream), fp);
+}
+
+LB_API lb_status_t lb_autotune_lookup(const lb_csr_t *A, int32_t k, uint64_t fp, int32_t *found, lb_schedule_t *out) {
+    lb_status_t st = check_csr(A);
+    if (st != LB_OK) return st;
+    if (!found || !out || k < 1 || k > kMaxK) return LB_ERR_INVALID_ARG;
+    tune_bind(bind_key{A->row_offsets, A->col_idx, A->rows, A->cols, A->nnz, 0}, fp);
+    lb_schedule_t s{};
+    *found = tune_lookup(tune_key{A->rows, A->cols, A->nnz, k, static_cast<int32_t>(A->value_dtype), 0, fp}, &s);
+    if (*found) *out = s;
+    return LB_OK;
+}
+
+LB_API const char *lb_autotune_device_tag(void) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    return device_tag_locked().c_str();
 }
 
 // ------------------------------------------------------------------ measurement probes
@@ -1147,12 +1515,12 @@ LB_API lb_status_t lb_probe_stream_read(const void *buf, size_t bytes, float *ou
 LB_API lb_status_t lb_probe_gather(const int32_t *idx, int64_t n, const float *x, int64_t cols, float *out,
                                    int32_t grid, int32_t bands, void *stream) {
     if (n < 0 || cols < 0 || grid < 0 || !out || (n > 0 && (!idx || !x || cols == 0))) return LB_ERR_INVALID_ARG;
-    if (bands != 1 && bands != 2) return LB_ERR_INVALID_ARG;
+    if (bands != 1 && bands != 2 && bands != 4 && bands != 8) return LB_ERR_INVALID_ARG;
     if (cols > kMaxCoord) return LB_ERR_OVERFLOW;
     if (n == 0) return LB_OK;
     if (grid == 0) grid = lb_probe_default_grid();
-    if (bands == 2) grid = grid < 8 ? 8 : grid / 8 * 8;
-    return hip_status(lbk::probe_gather(idx, n, x, static_cast<int32_t>((cols + 1) / 2), out, grid, bands,
+    if (bands > 1) grid = grid < 8 ? 8 : grid / 8 * 8;
+    return hip_status(lbk::probe_gather(idx, n, x, static_cast<int32_t>((cols + bands - 1) / bands), out, grid, bands,
                                         static_cast<hipStream_t>(stream)));
 }
 

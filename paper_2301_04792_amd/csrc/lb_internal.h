@@ -101,6 +101,97 @@ hipError_t launch_fixup(int64_t T, int32_t rows, int32_t kc, const int32_t *carr
 hipError_t merge_spmv(const csr_dev &A, const void *x, float *y, int block, int items, int bands, void *ws,
                       hipStream_t s, const int32_t *vperm = nullptr, int vec = 1);
 
+// ---- planned SpMV (k_plan.hip) ----------------------------------------------------------
+// Long rows: a block of kPanelBlock threads per (chunk, panel) stages
+// kPanelBytes of x in LDS; a chunk holds at most kPanelRows long rows; a
+// task is at most kPanelTask nonzeros of one (row, panel) segment; a
+// wavefront works on kPanelBatch tasks at a time.
+constexpr int kPanelBlock = 512;
+constexpr int kPanelTask = 256;
+constexpr int kPanelBatch = 8;
+constexpr int kPanelRows = 512;
+constexpr int kPanelBytes = 65536;
+
+// The plan as the kernels see it (device pointers into the plan buffer).
+struct plan_dev {
+    int32_t rows;
+    int32_t T, NA;       // merge-path units, active units
+    int32_t NL, NP, NC;  // long rows, panels, chunks
+    int32_t P;           // columns per panel
+    int32_t long_min;
+    int32_t bands, block, items;
+    int32_t streams;     // 2: the long rows' launch on the library's second stream
+    int32_t ntasks;
+    const int32_t *part_i, *part_j;  // the split at every unit boundary, T + 1 each
+    const int32_t *active;           // NA unit ids, ascending
+    const int32_t *LR;               // NL long row ids, ascending
+    const int32_t *chunk_q;          // NC + 1: chunk c = long rows [chunk_q[c], chunk_q[c+1])
+    const int32_t *sb;               // NL x (NP + 1): segment bounds (nonzero positions)
+    const int32_t *tb;               // NL x (NP + 1): first task of each (row, panel), row-major
+};
+
+// Plan buffer: a 256-byte header (build flags), then the tables above, each
+// 256-byte aligned; NA_cap entries are reserved for the active list.
+struct plan_layout {
+    size_t flags, part_i, part_j, active, LR, chunk_q, sb, tb, total;
+};
+inline plan_layout plan_layout_of(int64_t T, int64_t NA_cap, int64_t NL, int64_t NP, int64_t NC) {
+    plan_layout L{};
+    size_t o = 0;
+    L.flags = o;
+    o += 256;
+    L.part_i = o;
+    o += align256(static_cast<size_t>(T + 1) * 4);
+    L.part_j = o;
+    o += align256(static_cast<size_t>(T + 1) * 4);
+    L.active = o;
+    o += align256(static_cast<size_t>(NA_cap) * 4);
+    L.LR = o;
+    o += align256(static_cast<size_t>(NL) * 4);
+    L.chunk_q = o;
+    o += align256(static_cast<size_t>(NC + 1) * 4);
+    L.sb = o;
+    o += align256(static_cast<size_t>(NL) * (NP + 1) * 4);
+    L.tb = o;
+    o += align256(static_cast<size_t>(NL) * (NP + 1) * 4);
+    L.total = o;
+    return L;
+}
+
+// Per-call workspace: carry_val[T * bands], y_hi[rows] (two bands), part[ntasks].
+struct plan_ws {
+    float *carry_val;
+    float *y_hi;
+    float *part;
+};
+inline size_t plan_ws_bytes(int64_t T, int bands, int64_t rows, int64_t ntasks) {
+    return align256(static_cast<size_t>(T) * bands * 4) + (bands == 2 ? align256(static_cast<size_t>(rows) * 4) : 0) +
+           align256(static_cast<size_t>(ntasks) * 4);
+}
+inline plan_ws plan_ws_carve(void *base, const plan_dev &pl) {
+    char *p = static_cast<char *>(base);
+    plan_ws w{};
+    w.carry_val = reinterpret_cast<float *>(p);
+    p += align256(static_cast<size_t>(pl.T) * pl.bands * 4);
+    if (pl.bands == 2) {
+        w.y_hi = reinterpret_cast<float *>(p);
+        p += align256(static_cast<size_t>(pl.rows) * 4);
+    }
+    w.part = reinterpret_cast<float *>(p);
+    return w;
+}
+
+// True if P columns per panel are supported for x of type xt.
+bool panel_cols_ok(int64_t P, lb_dtype_t xt);
+// Segment bounds of the long rows (flags bit 0: a long row's columns do not strictly increase).
+hipError_t plan_segments_launch(int32_t NL, int32_t NP, int32_t P, const int32_t *LR, const int32_t *ro,
+                                const int32_t *ci, int32_t *sb, int32_t *flags, hipStream_t s);
+// The short rows' merge-path consume over the active units (k_merge.hip).
+hipError_t merge_spmv_planned_consume(const csr_dev &A, const plan_dev &pl, const void *x, float *y,
+                                      float *carry_val, float *y_hi, hipStream_t s);
+// y = A x with a built plan; ws holds plan_ws_bytes(...).
+hipError_t planned_spmv(const csr_dev &A, const plan_dev &pl, const void *x, float *y, void *ws, hipStream_t s);
+
 hipError_t merge_spmm(const csr_dev &A, const void *X, int32_t k, int64_t ldx, float *Y, int64_t ldy,
                       int block, int items, void *ws, hipStream_t s);
 
@@ -258,6 +349,8 @@ hipError_t probe_gather(const int32_t *idx, int64_t n, const float *x, int32_t c
 
 // ---- utilities ------------------------------------------------------------------------
 hipError_t fill_f32(float *p, int64_t n, float v, hipStream_t s);
+// out[i] = a[i * n / count] for i < count (0 when n == 0).
+hipError_t gather_samples(const int32_t *a, int64_t n, int32_t count, int32_t *out, hipStream_t s);
 // Writes violation flags (bit 0: offsets, bit 1: columns) into *flags_dev.
 hipError_t validate_csr(const csr_dev &A, int32_t *flags_dev, hipStream_t s);
 

@@ -35,7 +35,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_version_and_status_strings():
     L = _abi.load()
-    assert L.lb_abi_version() == 2
+    assert L.lb_abi_version() == 3
     for st in range(9):
         assert L.lb_status_string(st) not in (b"", b"unknown status")
     assert L.lb_status_string(99) == b"unknown status"
@@ -413,36 +413,59 @@ def test_vector_width_host_checks():
     assert n.value == m.value  # same split and carries
 
 
-def test_autotune_cache_file_is_read(tmp_path):
-    """A cache file named by LB_AUTOTUNE_CACHE supplies schedule="auto"
-    (read once, when the library first needs it), in the current line format
-    and in the older one without the trailing x_bands / vector_width."""
+def test_autotune_cache_is_keyed_by_pattern_device_and_abi(tmp_path):
+    """Cache entries carry the ABI version, the device tag, the shape and a
+    pattern fingerprint.  Two patterns of one shape keep separate picks;
+    lines of another ABI version or device, or in the older format without
+    a fingerprint, are not used;
+    lb_autotune_lookup binds the matrix so that schedule="auto" resolves to
+    its pick, while an unbound matrix of the same shape gets the Sec. 6.2
+    rule.  Runs in a child process (the cache file is read once)."""
     import subprocess
     import sys
     import textwrap
 
     cache = tmp_path / "tune.txt"
-    # rows cols nnz k dtype batched kind group tiles items block grid [x_bands vector_width]
-    cache.write_text("2000000 2000000 65000000 1 0 0 2 0 0 8 256 0 2 1\n"
-                     "4000 4000 60000 1 0 0 2 0 0 12 512 0\n")
+    tag = _abi.load().lb_autotune_device_tag().decode()
+    abi = _abi.ABI_VERSION
+    # lbtune abi device rows cols nnz k dtype batched fingerprint kind group tiles items block grid x_bands vw
+    cache.write_text(
+        f"lbtune {abi} {tag} 2000000 2000000 65000000 1 0 0 abc1 2 0 0 8 256 0 2 1\n"
+        f"lbtune {abi} {tag} 2000000 2000000 65000000 1 0 0 abc2 2 0 0 12 512 0 1 1\n"
+        f"lbtune {abi - 1} {tag} 4000 4000 60000 1 0 0 abc3 2 0 0 16 128 0 1 1\n"
+        f"lbtune {abi} gfx000:1 4000 4000 60000 1 0 0 abc3 2 0 0 16 128 0 1 1\n"
+        "4000 4000 60000 1 0 0 2 0 0 12 512 0\n")
     code = textwrap.dedent(f"""
         import ctypes, sys
         sys.path.insert(0, {ROOT!r})
         from paper_2301_04792_amd import _abi
         L = _abi.load()
-        out = []
-        for rows, nnz in ((2000000, 65000000), (4000, 60000)):
-            A = _abi.CSR(rows, rows, nnz, 0x10000, 0x10000, 0x10000, _abi.F32)
-            s = _abi.Schedule(3, 0, 0, 0, 0, 0, 0, 0)
-            r = _abi.Schedule()
+        def csr(rows, nnz, ro):
+            return _abi.CSR(rows, rows, nnz, ro, 0x20000, 0x30000, _abi.F32)
+        def lookup(A, fp):
+            found, out = ctypes.c_int32(0), _abi.Schedule()
+            assert L.lb_autotune_lookup(ctypes.byref(A), 1, ctypes.c_uint64(fp), ctypes.byref(found),
+                                        ctypes.byref(out)) == 0
+            return (out.items_per_thread, out.block_size, out.x_bands) if found.value else None
+        def auto(A):
+            s, r = _abi.Schedule(3, 0, 0, 0, 0, 0, 0, 0), _abi.Schedule()
             assert L.lb_resolve_schedule(ctypes.byref(A), 1, ctypes.byref(s), ctypes.byref(r)) == 0
-            out.append((r.kind, r.items_per_thread, r.block_size, r.x_bands, r.vector_width))
+            return (r.kind, r.items_per_thread, r.block_size, r.x_bands)
+        A1, A2, A3 = csr(2000000, 65000000, 0x10000), csr(2000000, 65000000, 0x11000), csr(2000000, 65000000, 0x12000)
+        out = [auto(A1)]                                   # unbound: the Sec. 6.2 rule (merge-path defaults)
+        out += [lookup(A1, 0xabc1), lookup(A2, 0xabc2), lookup(A3, 0xabc9)]
+        out += [auto(A1), auto(A2), auto(A3)]
+        B = csr(4000, 60000, 0x13000)
+        out += [lookup(B, 0xabc3)]                         # other ABI, other device, old format: none used
         print(out)
+        # a store rewrites the file: the other ABI's and device's lines are kept
+        L.lb_autotune_clear()
     """)
     env = dict(os.environ, LB_AUTOTUNE_CACHE=str(cache))
     res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=300)
     assert res.returncode == 0, res.stderr[-2000:]
-    assert res.stdout.strip() == "[(2, 8, 256, 2, 1), (2, 12, 512, 1, 1)]"
+    assert res.stdout.strip() == ("[(2, 8, 256, 1), (8, 256, 2), (12, 512, 1), None, (2, 8, 256, 2), "
+                                  "(2, 12, 512, 1), (2, 8, 256, 1), None]")
 
 
 def test_noalloc_rejects_inputs_beyond_its_scratch():

@@ -1,0 +1,211 @@
+"""Parity of the planned SpMV (lb_spmv_plan_build + lb_spmv_planned, through
+the C ABI) with the FP64 oracle: short rows on the merge path with the long
+rows left out, long rows on LDS panels of x.  Plans are built with small
+units, long-row thresholds and panels so that modest matrices have many long
+rows, several chunks and many panels."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import synthetic as S
+import synthetic.csr as SC
+from tests.gpu_util import assert_rows_close, oracle_spmv
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2301_04792_amd as lb  # noqa: E402
+from paper_2301_04792_amd import _abi  # noqa: E402
+
+DEV = "cuda:0"
+
+# (block_size, items_per_thread, x_bands, long_min, panel_cols); 0 = default
+PLANS = [
+    (128, 4, 1, 512, 64),
+    (128, 4, 2, 512, 256),
+    (128, 8, 1, 1024, 128),
+    (256, 8, 2, 2048, 1024),
+    (256, 8, 1, 0, 0),
+    (256, 8, 2, 0, 0),
+    (512, 16, 1, 8192, 4096),
+    (256, 8, 1, -1, 0),  # no long rows: the merge path with the split precomputed
+]
+PLAN_IDS = [f"b{b}i{i}x{x}L{l}P{p}" for b, i, x, l, p in PLANS]
+
+
+def upload(A, x, dtype=torch.float32):
+    Ad = lb.CSR.from_host(A, DEV, dtype)
+    if x.dtype == np.uint16:
+        xd = torch.from_numpy(x.view(np.int16).copy()).view(torch.bfloat16).to(DEV)
+    else:
+        xd = torch.from_numpy(x).to(DEV).to(dtype)
+    return Ad, xd
+
+
+def planned(A, x, cfg, dtype=torch.float32):
+    b, i, xb, lm, p = cfg
+    Ad, xd = upload(A, x, dtype)
+    plan = lb.Plan(Ad, block_size=b, items_per_thread=i, x_bands=xb, long_min=lm, panel_cols=p)
+    return Ad, xd, plan, lb.spmv_planned(Ad, plan, xd)
+
+
+def matrices():
+    out = {}
+    out["powerlaw60k"] = S.powerlaw_csr(31, 60_000, 70_000, 1.6, 30_000, 0.1)
+    out["powerlaw_dense_tail"] = S.powerlaw_csr(32, 5_000, 40_000, 1.2, 40_000, 0.3)
+    out["uniform4096"] = S.config_c1()
+    out["long_and_empty"] = SC._from_lengths(33, [0, 9000, 0, 0, 1, 9000, 2047, 2048, 2049, 0, 4096, 3, 30000, 0], 40_000)
+    out["all_long"] = SC._from_lengths(34, [5000] * 40, 20_000)
+    out["one_long"] = SC._from_lengths(35, [60_000], 70_000)
+    out["long_first_last"] = SC._from_lengths(36, [12_000] + [2] * 3000 + [12_000], 15_000)
+    out["many_long_rows"] = SC._from_lengths(37, [600] * 2500 + [1] * 100, 9000)  # > 1024 long rows per chunk
+    return out
+
+
+MATS = matrices()
+
+
+@pytest.mark.parametrize("cfg", PLANS, ids=PLAN_IDS)
+@pytest.mark.parametrize("mname", sorted(MATS))
+def test_planned_matches_oracle(mname, cfg):
+    A, x = MATS[mname]
+    print(f"[plan {mname} {cfg}]", flush=True)
+    Ad, xd, plan, y = planned(A, x, cfg)
+    ref, scale = oracle_spmv(A, x)
+    assert_rows_close(y.cpu().numpy(), ref, scale, what=f"{mname} {cfg} {plan.info}")
+
+
+@pytest.mark.parametrize("mname", sorted(S.special_matrices().keys()))
+@pytest.mark.parametrize("cfg", [PLANS[0], PLANS[1], PLANS[4]], ids=[PLAN_IDS[0], PLAN_IDS[1], PLAN_IDS[4]])
+def test_planned_special_shapes(mname, cfg):
+    A, x = S.special_matrices()[mname]
+    print(f"[plan special {mname} {cfg}]", flush=True)
+    Ad, xd, plan, y = planned(A, x, cfg)
+    if A.m == 0:
+        assert y.numel() == 0
+        return
+    ref, scale = oracle_spmv(A, x)
+    assert_rows_close(y.cpu().numpy(), ref, scale, what=f"{mname} {cfg}")
+
+
+@pytest.mark.parametrize("cfg", PLANS, ids=PLAN_IDS)
+def test_planned_integer_bit_exact(cfg):
+    """Integer values and x: every partial sum is exact in FP32, so the
+    planned result equals the oracle bit for bit (long rows cut into many
+    panels and tasks, short rows cut by units)."""
+    A, x = S.integer_valued(S.powerlaw_csr(38, 80_000, 80_000, 1.5, 60_000, 0.1)[0], 5)
+    Ad, xd, plan, y = planned(A, x, cfg)
+    ref, _ = oracle_spmv(A, x)
+    got = y.cpu().numpy().astype(np.float64)
+    assert plan.c.long_rows > 0 or cfg[3] == -1
+    assert np.array_equal(got, ref), f"{cfg}: {int((got != ref).sum())} rows differ"
+
+
+@pytest.mark.parametrize("cfg", [PLANS[1], PLANS[5]], ids=[PLAN_IDS[1], PLAN_IDS[5]])
+def test_planned_bf16(cfg):
+    A, x = S.powerlaw_csr(39, 100_000, 100_000, 1.8, 30_000, 0.1)
+    Ab = A.with_values(S.to_bf16_bits(A.values))
+    xb = S.to_bf16_bits(x)
+    Ad, xd, plan, y = planned(Ab, xb, cfg, torch.bfloat16)
+    ref, scale = oracle_spmv(Ab, xb)
+    assert_rows_close(y.cpu().numpy(), ref, scale, what=f"bf16 {cfg}")
+
+
+def test_planned_reproducible_and_values_change():
+    """For a fixed plan the result is bit-reproducible; the plan depends on
+    the pattern only, so new values (and x) on the same pattern give the
+    oracle's result for them."""
+    A, x = S.powerlaw_csr(40, 150_000, 150_000, 1.8, 50_000, 0.1)
+    cfg = (128, 8, 2, 1024, 512)
+    Ad, xd, plan, y1 = planned(A, x, cfg)
+    y2 = lb.spmv_planned(Ad, plan, xd)
+    assert torch.equal(y1, y2)
+    v2 = S.random_vector(41, A.nnz, role=3)
+    x2 = S.random_vector(42, A.n)
+    A2 = A.with_values(v2)
+    Ad2 = lb.CSR.from_host(A2, DEV)
+    y3 = lb.spmv_planned(Ad2, plan, torch.from_numpy(x2).to(DEV))
+    ref, scale = oracle_spmv(A2, x2)
+    assert_rows_close(y3.cpu().numpy(), ref, scale, what="new values")
+
+
+def test_planned_matches_merge_path_on_short_rows_only():
+    """With no long rows the planned call runs the same merge-path consume
+    with the same split.  With two bands its finishing pass also sums the
+    carries in the same order as lb_spmv's, so the two agree bit for bit;
+    with one band lb_spmv's fix-up sums carry runs in another order, so only
+    the rows that no unit boundary cuts must agree bit for bit."""
+    A, x = S.powerlaw_csr(43, 100_000, 100_000, 1.8, 30_000, 0.1)
+    ref, scale = oracle_spmv(A, x)
+    for bands in (1, 2):
+        Ad, xd, plan, y = planned(A, x, (256, 8, bands, -1, 0))
+        y_ref = lb.spmv(Ad, xd, "merge_path", block_size=256, items_per_thread=8, x_bands=bands)
+        if bands == 2:
+            assert torch.equal(y, y_ref)
+        else:
+            W = 256 * 8
+            ro = A.row_offsets.astype(np.int64)
+            start = ro[:-1] + np.arange(A.m)  # merge position of each row's first item
+            end = ro[1:] + np.arange(A.m)     # merge position of each row's end
+            uncut = start // W == end // W
+            assert np.array_equal(y.cpu().numpy()[uncut], y_ref.cpu().numpy()[uncut])
+        assert_rows_close(y.cpu().numpy(), ref, scale, what=f"bands {bands}")
+
+
+def test_plan_build_rejects_unsorted_long_row():
+    lens = [10, 3000, 5]
+    A, x = SC._from_lengths(44, lens, 10_000)
+    ci = A.col_idx.copy()
+    ci[10 + 100], ci[10 + 101] = ci[10 + 101], ci[10 + 100]  # swap two columns of the long row
+    Ad = lb.CSR.from_host(SC.CSRHost(A.row_offsets, ci, A.values, A.shape), DEV)
+    with pytest.raises(lb.LBError) as e:
+        lb.Plan(Ad, block_size=128, items_per_thread=4, long_min=512)
+    assert e.value.status == _abi.ERR_INVALID_CSR
+    # the same row below long_min is a short row: no order needed
+    plan = lb.Plan(Ad, block_size=128, items_per_thread=4, long_min=4096)
+    y = lb.spmv_planned(Ad, plan, torch.from_numpy(x).to(DEV))
+    Au = SC.CSRHost(A.row_offsets, ci, A.values, A.shape)
+    ref, scale = oracle_spmv(Au, x)
+    assert_rows_close(y.cpu().numpy(), ref, scale, what="unsorted short row")
+
+
+def test_planned_rejects_other_shapes_and_small_workspace():
+    A, x = S.config_c1()
+    Ad, xd, plan, _ = planned(A, x, PLANS[0])
+    B, _ = SC._from_lengths(45, [3] * 4096, 4096)
+    Bd = lb.CSR.from_host(B, DEV)
+    y = torch.empty(4096, device=DEV)
+    st = lb._lib.lb_spmv_planned(ctypes.byref(Bd.c_struct()), ctypes.byref(plan.c), ctypes.c_void_p(xd.data_ptr()),
+                                 _abi.F32, ctypes.c_void_p(y.data_ptr()), None, 0, None)
+    assert st == _abi.ERR_INVALID_ARG
+    if plan.workspace_bytes > 0:
+        ws = torch.empty(plan.workspace_bytes - 1, dtype=torch.uint8, device=DEV)
+        st = lb._lib.lb_spmv_planned(ctypes.byref(Ad.c_struct()), ctypes.byref(plan.c),
+                                     ctypes.c_void_p(xd.data_ptr()), _abi.F32, ctypes.c_void_p(y.data_ptr()),
+                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), None)
+        assert st == _abi.ERR_WORKSPACE_TOO_SMALL
+
+
+def test_planned_second_stream_and_chunk_sizes():
+    """The long rows' launch on the library's second stream, and other chunk
+    sizes, give the same bits as one stream with the default chunks (same
+    tasks, same order), ordered on the caller's stream."""
+    A, x = S.powerlaw_csr(46, 120_000, 120_000, 1.6, 60_000, 0.1)
+    Ad, xd = upload(A, x)
+    base = lb.Plan(Ad, block_size=128, items_per_thread=8, long_min=1024, panel_cols=512)
+    y1 = lb.spmv_planned(Ad, base, xd)
+    two = lb.Plan(Ad, block_size=128, items_per_thread=8, long_min=1024, panel_cols=512, streams=2)
+    y = torch.empty_like(y1)
+    for _ in range(3):
+        y.fill_(float("nan"))
+        lb.spmv_planned(Ad, two, xd, y=y)
+        assert torch.equal(y, y1)
+    for ca in (512, 4096, 1 << 20):
+        pl = lb.Plan(Ad, block_size=128, items_per_thread=8, long_min=1024, panel_cols=512, chunk_atoms=ca)
+        assert torch.equal(lb.spmv_planned(Ad, pl, xd), y1), ca
+    ref, scale = oracle_spmv(A, x)
+    assert_rows_close(y1.cpu().numpy(), ref, scale, what="second stream")

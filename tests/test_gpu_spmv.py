@@ -435,9 +435,9 @@ def test_backward_transposed_integer_and_autograd():
     assert_rows_close(gx_t.cpu().numpy(), ref, scale, what="autograd transposed dx")
 
 
-@pytest.mark.parametrize("bands", [1, 2])
+@pytest.mark.parametrize("bands", [1, 2, 4, 8])
 def test_gather_probe_sums(bands):
-    """The measurement probe gathers every x[idx[j]] exactly once in either
+    """The measurement probe gathers every x[idx[j]] exactly once in every
     band form (integer x: the partial sums are exact)."""
     rng = np.random.default_rng(bands)
     n, cols = 1_000_003, 70_001
