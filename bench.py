@@ -3,21 +3,24 @@
 
 One step = one y = A x over the power-law matrix (m = n = 2,000,000, row
 lengths min(Zipf(1.8), 200,000), 10 % empty rows, uniform columns, FP32)
-with the merge-path schedule (the Sec. 6.2 heuristic's pick) at 256 threads
-x 8 items and x split into two column bands over the XCDs, the fastest
-candidate of the autotuner here up to timing noise (its own pick is
-reported beside): partition, consume, and the band sums plus carries.  `value` is effective HBM GB/s over
-algorithmic bytes B = nnz*(s_v + 4) + (m + 1)*4 + n*s_x + m*4 for K
-back-to-back steps with the inputs already in HBM.
+through lb_spmv_planned: a plan built once for the pattern (outside the
+timed region; its build time is reported) runs the short rows on the merge
+path (256 threads x 8 items, two column bands over the XCDs, the split
+precomputed) and the long rows on LDS panels of x, then one finishing pass.
+`value` is effective HBM GB/s over algorithmic bytes
+B = nnz*(s_v + 4) + (m + 1)*4 + n*s_x + m*4 of the median of the K timed
+steps, each run cold: a 1 GiB write before it (outside its events) evicts
+L2 and the Infinity Cache, the inputs stay in HBM.  The warm figure (K
+back-to-back steps) and the unplanned merge path are reported beside it.
 
-The same JSON line carries the roofline of the dominant kernel (merge-path
-consume, timed by the library's HIP events on the launch stream), the FP64
-oracle timed on the host cores, and per-schedule, BF16, forward+backward,
-COO/CSC, batched, graph-traversal (SSSP, BFS) and SpGEMM figures on the other workloads
-(skip them with --quick).  Accuracy is asserted by the GPU tests, not here:
-the oracle runs in this script only as the timed CPU baseline.
+The same JSON line carries the roofline of the dominant kernel (timed by the
+library's HIP events on the launch stream) with every kernel of the call,
+the FP64 oracle timed on the host cores (its output also gives the
+headline's accuracy, checked outside the timed region), the host CPU, and
+per-schedule, BF16, forward+backward, COO/CSC, batched, graph-traversal (SSSP,
+BFS) and SpGEMM figures on the other workloads (skip them with --quick).
 
-    python bench.py [--steps K] [--warmup W] [--quick]
+    python bench.py [--steps K] [--warmup W] [--quick] [--schedule merge_path]
 """
 from __future__ import annotations
 
@@ -33,9 +36,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_GBS = 8000.0
+SECTIONS = {"schedules", "uniform", "bf16", "fwdbwd", "formats", "batched", "graph", "spgemm"}
 METRIC = "SpMV effective HBM GB/s (% of peak) per schedule; fwd+bwd and batched GB/s"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "merge_consume_powerlaw2M_traffic.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2301_04792_amd", "csrc", f) for f in ("k_merge.hip", "lb_device.h")]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "planned_spmv_powerlaw2M_traffic.json")
+kPanelBytes = 65536  # LDS bytes of x per panel block (the library's default panel: 16384 FP32 columns)
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2301_04792_amd", "csrc", f)
+                  for f in ("k_merge.hip", "k_plan.hip", "lb_device.h", "lb_internal.h")]
 
 
 def log(*a):
@@ -49,6 +55,20 @@ def spmv_bytes(m, n, nnz, sv=4, sx=4, k=1):
 def backward_bytes(m, n, nnz, sv=4, sx=4):
     # values + col_idx read, dvalues written, row_offsets, dy, x read, dx written
     return nnz * (sv + 4) + nnz * 4 + (m + 1) * 4 + m * 4 + n * sx + n * 4
+
+
+def host_facts():
+    """CPU model and logical CPUs of the machine the bench runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count()}
 
 
 def kernel_source_hash():
@@ -98,109 +118,145 @@ def _consume_config(kernel_name):
     return (int(m.group(1)), int(m.group(2)), int(m.group(3))) if m else None
 
 
-def _config_args(cfg):
-    return f"--schedule merge_path --block {cfg[0]} --items {cfg[1]} --x-bands {cfg[2]}"
+# Profiled runs: tag -> (title, bench.py arguments).  Each kernel trace is
+# made by `rocprofv3 --kernel-trace --stats --output-format csv -d
+# prof_out/<tag> -o t -- python3 bench.py <arguments>` and summarised into
+# profiles/<tag>_kernel_trace.md.
+TRACES = {
+    "planned_spmv_powerlaw2M": ("planned SpMV on the power-law 2M matrix (the headline)",
+                                "--quick --no-cpu --steps 10 --warmup 3"),
+    "merge_path_powerlaw2M": ("unplanned two-band merge path on the power-law 2M matrix",
+                              "--quick --no-cpu --schedule merge_path --x-bands 2 --steps 10 --warmup 3"),
+    "bf16_laplacian_powerlaw2M": ("BF16 on the power-law 2M matrix and the 2048^2 Laplacian (FP32 and BF16), "
+                                  "merge path, planned and autotuned", "--only bf16 --no-cpu"),
+    "fwd_bwd_powerlaw1M": ("forward, scatter backward and transposed backward on the power-law 1M matrix",
+                           "--only fwdbwd --no-cpu"),
+    "formats_powerlaw1M": ("COO and CSC on the power-law 1M matrix", "--only formats --no-cpu"),
+    "batched512": ("batched SpMM over 512 power-law matrices, k = 1 and k = 8 (autotuned)",
+                   "--only batched --no-cpu"),
+    "spgemm": ("SpGEMM (Laplacian 1024^2 squared, power-law 100k squared)", "--only spgemm --no-cpu"),
+    "traversal_powerlaw1M": ("SSSP and BFS on the 1M-vertex power-law graph, every schedule",
+                             "--graph-only --no-cpu"),
+}
+# Counter passes: tag -> (bench.py arguments, counter sets); each set is one
+# `rocprofv3 --pmc <set> --output-format csv -d prof_out/<tag>_<i> -o c --
+# python3 bench.py <arguments>` run, summarised into profiles/<tag>_counters.md.
+COUNTERS = {
+    "planned_spmv_powerlaw2M": ("--quick --no-cpu --steps 3 --warmup 1 --pmc-calib",
+                                ["FETCH_SIZE", "WRITE_SIZE",
+                                 "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY "
+                                 "SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS SQ_INSTS_VALU",
+                                 "TCC_HIT_sum TCC_MISS_sum", "TA_BUSY_avr TA_ADDR_STALLED_BY_TC_CYCLES_sum "
+                                 "TCP_PENDING_STALL_CYCLES_sum TCP_TCC_READ_REQ_sum"]),
+    "fwd_bwd_powerlaw1M": ("--only fwdbwd --no-cpu --steps 3 --pmc-calib",
+                           ["FETCH_SIZE", "WRITE_SIZE", "TCC_ATOMIC_sum TCC_EA0_ATOMIC_sum",
+                            "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY"]),
+    "batched512": ("--only batched --no-cpu --steps 3 --pmc-calib",
+                   ["FETCH_SIZE", "WRITE_SIZE", "TCC_HIT_sum TCC_MISS_sum",
+                    "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_ACTIVE_INST_LDS"]),
+}
+
+
+def _short_name(name, width=100):
+    return name if len(name) <= width else name[:width - 3] + "..."
+
+
+def _copy_calibration(rows):
+    """(fetch factor, write factor) from the 256 MiB device copy run with --pmc-calib, or None."""
+    f = [float(r["Counter_Value"]) for r in rows if r.get("Counter_Name") == "FETCH_SIZE"
+         and "copy" in r.get("Kernel_Name", "").lower()]
+    w = [float(r["Counter_Value"]) for r in rows if r.get("Counter_Name") == "WRITE_SIZE"
+         and "copy" in r.get("Kernel_Name", "").lower()]
+    known = float(1 << 28)
+    return (known / (max(f) * 1024.0) if f else None, known / (max(w) * 1024.0) if w else None,
+            max(f) if f else None, max(w) if w else None)
 
 
 def summarize_profiles(out_dir, prof_root):
-    """Write profiles/*.md and the traffic JSON from rocprofv3 CSV output
-    (made by the commands recorded in each summary; the merge-path
-    configuration in them is the one named by the profiled kernel)."""
-    os.makedirs(out_dir, exist_ok=True)
-    stats = _find(os.path.join(prof_root, "prof_trace"), "kernel_stats.csv")
-    if stats:
-        rows = _read_csv(stats)
-        names = [r["Name"] for r in rows if _consume_config(r["Name"])]
-        cfg = _consume_config(names[0]) if names else (256, 8, 1)
-        cmd_trace = ("rocprofv3 --kernel-trace --stats --output-format csv -d prof_out/prof_trace -o trace -- "
-                     f"python3 bench.py --quick --no-cpu {_config_args(cfg)} --steps 10 --warmup 3")
-        lines = ["# Kernel trace: power-law 2M SpMV, merge-path (bench --quick)", "",
-                 f"Command: `{cmd_trace}`", "",
-                 "| kernel | calls | avg µs | min µs | max µs | % time |", "|---|---|---|---|---|---|"]
-        for r in rows[:12]:
-            name = r["Name"]
-            name = name if len(name) < 110 else name[:107] + "..."
-            lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
-                         f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
-        with open(os.path.join(out_dir, "merge_consume_powerlaw2M_kernel_trace.md"), "w") as f:
-            f.write("\n".join(lines) + "\n")
-    gstats = _find(os.path.join(prof_root, "prof_graph"), "kernel_stats.csv")
-    if gstats:
-        cmd_graph = ("rocprofv3 --kernel-trace --stats --output-format csv -d prof_out/prof_graph -o graph -- "
-                     "python3 bench.py --graph-only --no-cpu")
-        rows = _read_csv(gstats)
-        lines = ["# Kernel trace: SSSP and BFS on the 1M-vertex power-law graph (bench --graph-only)", "",
-                 f"Command: `{cmd_graph}`", "",
-                 "Every schedule of the traversal section runs; each call is one init launch plus the",
-                 "advance launches of its host batches (launches after the frontier empties exit at once).", "",
-                 "| kernel | calls | avg µs | min µs | max µs | % time |", "|---|---|---|---|---|---|"]
-        for r in rows[:16]:
-            name = r["Name"]
-            name = name if len(name) < 110 else name[:107] + "..."
-            lines.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
-                         f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
-        with open(os.path.join(out_dir, "traversal_powerlaw1M_kernel_trace.md"), "w") as f:
-            f.write("\n".join(lines) + "\n")
-    fetch = _find(os.path.join(prof_root, "prof_fetch"), "counter_collection.csv")
-    write = _find(os.path.join(prof_root, "prof_write"), "counter_collection.csv")
-    if fetch and write:
-        fr, wr = _read_csv(fetch), _read_csv(write)
-        kern = "merge_spmv_consume"
-        f_k, nf, name_f = _counter_per_dispatch(fr, kern, "FETCH_SIZE")
-        w_k, nw, name_w = _counter_per_dispatch(wr, kern, "WRITE_SIZE")
-        # calibration: the 256 MiB device copy run by bench.py --pmc-calib (reads and writes 2^28 bytes)
-        copy_f = [float(r["Counter_Value"]) for r in fr if r.get("Counter_Name") == "FETCH_SIZE"
-                  and "copy" in r.get("Kernel_Name", "").lower()]
-        copy_w = [float(r["Counter_Value"]) for r in wr if r.get("Counter_Name") == "WRITE_SIZE"
-                  and "copy" in r.get("Kernel_Name", "").lower()]
-        if f_k is not None and w_k is not None and copy_f and copy_w and name_f == name_w:
-            known = float(1 << 28)
-            ff = known / (max(copy_f) * 1024.0)
-            fw = known / (max(copy_w) * 1024.0)
-            read_b = f_k * 1024.0 * ff
-            write_b = w_k * 1024.0 * fw
-            name = name_f
-            cfg = _consume_config(name) or (None, None, None)
-            data = {"kernel": kern, "workload": "powerlaw_m2M_zipf1.8_cap200k_empty10pct",
-                    "kernel_source_hash": kernel_source_hash(),
-                    "block_size": cfg[0], "items_per_thread": cfg[1], "x_bands": cfg[2],
-                    "fetch_kb_per_dispatch": f_k, "write_kb_per_dispatch": w_k, "dispatches": [nf, nw],
-                    "copy_calibration": {"known_bytes": known, "fetch_kb": max(copy_f), "write_kb": max(copy_w),
-                                         "fetch_factor": ff, "write_factor": fw},
-                    "hbm_read_bytes_per_launch": read_b, "hbm_write_bytes_per_launch": write_b,
-                    "hbm_bytes_per_launch": read_b + write_b,
-                    "commands": [
-                        "rocprofv3 --pmc FETCH_SIZE --output-format csv -d prof_out/prof_fetch -o fetch -- "
-                        f"python3 bench.py --quick --no-cpu {_config_args(cfg)} --steps 3 --warmup 1 --pmc-calib",
-                        "rocprofv3 --pmc WRITE_SIZE --output-format csv -d prof_out/prof_write -o write -- "
-                        f"python3 bench.py --quick --no-cpu {_config_args(cfg)} --steps 3 --warmup 1 --pmc-calib"]}
-            try:
-                import synthetic as S
+    """Write profiles/*.md (and the headline's traffic JSON) from rocprofv3 CSV
+    output under prof_root, made by the commands in TRACES and COUNTERS."""
+    import collections
 
-                A, _ = S.config_c2()
-                data["nnz"] = A.nnz
-                data["algorithmic_bytes_per_launch"] = spmv_bytes(A.m, A.n, A.nnz)
-            except Exception:  # noqa: BLE001
-                pass
-            with open(TRAFFIC_FILE, "w") as f:
-                json.dump(data, f, indent=1)
-            lines = ["# HBM traffic of merge_spmv_consume on the power-law 2M matrix (rocprofv3 PMC)", "",
-                     *[f"Command: `{c}`" for c in data["commands"]], "",
-                     f"kernel: `{name[:120]}`", "",
-                     f"- FETCH_SIZE per dispatch: {f_k:.0f} KB; WRITE_SIZE per dispatch: {w_k:.0f} KB ({nf}/{nw} dispatches)",
-                     f"- calibration copy (2^28 bytes read and written): FETCH_SIZE {max(copy_f):.0f} KB, "
-                     f"WRITE_SIZE {max(copy_w):.0f} KB -> factors {ff:.3f} (read), {fw:.3f} (write)",
-                     f"- HBM bytes per launch: read {read_b / 1e6:.1f} MB + write {write_b / 1e6:.1f} MB = "
-                     f"{(read_b + write_b) / 1e6:.1f} MB",
-                     f"- algorithmic bytes per launch: {data.get('algorithmic_bytes_per_launch', 0) / 1e6:.1f} MB",
-                     "",
-                     "FETCH_SIZE counts the bytes L2 fetches over the fabric (from the Infinity Cache or HBM).",
-                     "On the copy and on the 1 GiB streaming probe it reads about half the known bytes, so the",
-                     "scale factor assumes every fetch is counted like those streaming fetches; the consume",
-                     "kernel's fetches are dominated by full-line fills for random x gathers, so the scaled",
-                     "figure is an upper estimate and the unscaled one a lower estimate."]
-            with open(os.path.join(out_dir, "merge_consume_powerlaw2M_pmc_traffic.md"), "w") as f:
-                f.write("\n".join(lines) + "\n")
+    os.makedirs(out_dir, exist_ok=True)
+    for tag, (title, bargs) in TRACES.items():
+        stats = _find(os.path.join(prof_root, tag), "kernel_stats.csv")
+        if not stats:
+            continue
+        rows = _read_csv(stats)
+        cmd = (f"rocprofv3 --kernel-trace --stats --output-format csv -d prof_out/{tag} -o t -- "
+               f"python3 bench.py {bargs}")
+        lines = [f"# Kernel trace: {title}", "", f"Command: `{cmd}`", "",
+                 "| kernel | calls | avg µs | min µs | max µs | % time |", "|---|---|---|---|---|---|"]
+        for r in rows[:24]:
+            lines.append(f"| `{_short_name(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                         f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                         f"{float(r['Percentage']):.1f} |")
+        with open(os.path.join(out_dir, f"{tag}_kernel_trace.md"), "w") as f:
+            f.write("\n".join(lines) + "\n")
+    for tag, (bargs, sets) in COUNTERS.items():
+        per = collections.defaultdict(dict)  # kernel -> counter -> mean per dispatch
+        calls = collections.defaultdict(int)
+        cmds, all_rows = [], []
+        for i, cset in enumerate(sets):
+            path = _find(os.path.join(prof_root, f"{tag}_{i}"), "counter_collection.csv")
+            if not path:
+                continue
+            cmds.append(f"rocprofv3 --pmc {cset} --output-format csv -d prof_out/{tag}_{i} -o c -- "
+                        f"python3 bench.py {bargs}")
+            rows = _read_csv(path)
+            all_rows += rows
+            acc = collections.defaultdict(list)
+            for r in rows:
+                acc[(r["Kernel_Name"], r["Counter_Name"])].append(float(r["Counter_Value"]))
+            for (k, c), v in acc.items():
+                per[k][c] = sum(v) / len(v)
+                calls[k] = max(calls[k], len(v))
+        if not per:
+            continue
+        ff, fw, cf, cw = _copy_calibration(all_rows)
+        counters = sorted({c for k in per for c in per[k]})
+        lines = [f"# Counters per dispatch: {TRACES.get(tag, (tag,))[0]}", ""] + [f"Command: `{c}`" for c in cmds] + [
+            "", "Mean value per dispatch of each kernel (FETCH_SIZE / WRITE_SIZE in KiB; the SQ cycle counters "
+                "are in the units rocprofv3 reports, summed over the chip).", ""]
+        if ff and fw:
+            lines += [f"Copy calibration (a 256 MiB device copy that reads and writes 2^28 bytes): FETCH_SIZE "
+                      f"{cf:.0f} KiB, WRITE_SIZE {cw:.0f} KiB, so HBM bytes = FETCH_SIZE x 1024 x {ff:.3f} and "
+                      f"WRITE_SIZE x 1024 x {fw:.3f}.", ""]
+        lines += ["| kernel | dispatches | " + " | ".join(counters) + " |", "|---|---|" + "---|" * len(counters)]
+        for k in sorted(per, key=lambda k: -per[k].get("FETCH_SIZE", 0)):
+            if "copy" in k.lower() or "fill" in k.lower():
+                continue
+            lines.append(f"| `{_short_name(k, 80)}` | {calls[k]} | " +
+                         " | ".join(f"{per[k][c]:.4g}" if c in per[k] else "" for c in counters) + " |")
+        with open(os.path.join(out_dir, f"{tag}_counters.md"), "w") as f:
+            f.write("\n".join(lines) + "\n")
+        if tag == "planned_spmv_powerlaw2M" and ff and fw:
+            # traffic of the headline's dominant kernel (the short rows' merge-path consume)
+            cand = [k for k in per if "merge_spmv_consume" in k and "FETCH_SIZE" in per[k] and "WRITE_SIZE" in per[k]]
+            if cand:
+                k = max(cand, key=lambda k: calls[k])
+                m = _consume_config(k) or (None, None, None)
+                read_b, write_b = per[k]["FETCH_SIZE"] * 1024.0 * ff, per[k]["WRITE_SIZE"] * 1024.0 * fw
+                data = {"kernel": "merge_consume", "schedule": "planned", "kernel_name": k,
+                        "workload": "powerlaw_m2M_zipf1.8_cap200k_empty10pct",
+                        "kernel_source_hash": kernel_source_hash(), "block_size": m[0], "items_per_thread": m[1],
+                        "x_bands": m[2], "long_min": None,
+                        "fetch_kb_per_dispatch": per[k]["FETCH_SIZE"], "write_kb_per_dispatch": per[k]["WRITE_SIZE"],
+                        "copy_calibration": {"fetch_factor": ff, "write_factor": fw},
+                        "hbm_read_bytes_per_launch": read_b, "hbm_write_bytes_per_launch": write_b,
+                        "hbm_bytes_per_launch": read_b + write_b, "commands": cmds}
+                try:
+                    import synthetic as S
+
+                    A, _ = S.config_c2()
+                    W = m[0] * m[1]
+                    NP = -(-A.n // (kPanelBytes // 4))
+                    data["long_min"] = max(W, 16 * NP)
+                    data["nnz"] = A.nnz
+                except Exception:  # noqa: BLE001
+                    pass
+                with open(TRAFFIC_FILE, "w") as f:
+                    json.dump(data, f, indent=1)
     return 0
 
 
@@ -274,12 +330,18 @@ def main():
     ap.add_argument("--x-bands", type=int, default=2,
                     help="merge-path column bands of x, 1 or 2 (the headline uses 2: x of 8 MB is twice one XCD's L2)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--schedule", default="merge_path",
-                    help="headline schedule: merge_path (default), auto (autotuned), group_mapped, thread_mapped")
+    ap.add_argument("--schedule", default="planned",
+                    help="headline schedule: planned (default: lb_spmv_planned, short rows on the merge path and "
+                         "long rows on LDS panels of x), merge_path, auto (autotuned), group_mapped, thread_mapped")
+    ap.add_argument("--long-min", type=int, default=0, help="planned: long-row threshold (0 = the plan's default)")
+    ap.add_argument("--panel-blocks", type=int, default=0, help="planned: blocks per panel (0 = default)")
+    ap.add_argument("--streams", type=int, default=0, help="planned: 1 or 2 streams (0 = default, 1)")
     ap.add_argument("--graph", action="store_true",
                     help="time the headline's K steps as one HIP graph replay instead of eager launches")
     ap.add_argument("--pmc-calib", action="store_true",
                     help="also run one 256 MiB device copy (known bytes) to scale rocprofv3 FETCH/WRITE_SIZE")
+    ap.add_argument("--only", default="",
+                    help="comma-separated sections to run without the headline: " + ", ".join(sorted(SECTIONS)))
     ap.add_argument("--graph-only", action="store_true",
                     help="run only the graph traversals (SSSP, BFS) and print their figures")
     ap.add_argument("--summarize-profiles", metavar="DIR",
@@ -383,357 +445,512 @@ def main():
         lb.profile_reset()
         return ms / max(n, 1), n
 
-    # ------------------------------------------------------------ headline workload
-    t0 = time.time()
-    A, x = S.config_c2()
-    log(f"[bench] power-law 2M generated: nnz={A.nnz} in {time.time() - t0:.1f}s")
-    Ad = lb.CSR.from_host(A, dev)
-    xd = torch.from_numpy(x).to(dev)
-    y = torch.empty(A.m, dtype=torch.float32, device=dev)
-    params = {}
-    if args.items:
-        params["items_per_thread"] = args.items
-    if args.block:
-        params["block_size"] = args.block
-    if args.x_bands and args.schedule == "merge_path":
-        params["x_bands"] = args.x_bands
-    head = args.schedule
-    if head == "auto" and not params:
-        lb.autotune_clear()
+    result = {}
+    value = None
+    if args.only:
+        wanted = set(args.only.split(","))
+        unknown = wanted - SECTIONS
+        if unknown:
+            print(f"unknown sections {sorted(unknown)}; choose from {sorted(SECTIONS)}", file=sys.stderr)
+            return 2
+        if wanted & {"schedules", "bf16"}:  # the headline matrix, untimed
+            A, x = S.config_c2()
+            Ad = lb.CSR.from_host(A, dev)
+            xd = torch.from_numpy(x).to(dev)
+            y = torch.empty(A.m, dtype=torch.float32, device=dev)
+            B = spmv_bytes(A.m, A.n, A.nnz)
+    else:
+        wanted = None
+        # ------------------------------------------------------------ headline workload
         t0 = time.time()
-        lb.tune(Ad)  # schedule and tile size picked by timing the candidates on this matrix
-        log(f"[bench] autotuned in {time.time() - t0:.1f}s")
-    elif head == "auto":
-        head = "merge_path"
-    sched = lb.resolve_schedule(Ad, head, **params)
-    ws = torch.empty(max(lb.workspace_size(Ad, head, **params), 1), dtype=torch.uint8, device=dev)
-    dominant = {"merge_path": "merge_consume", "group_mapped": "group_mapped",
-                "thread_mapped": "thread_mapped"}[sched["schedule"]]
+        A, x = S.config_c2()
+        log(f"[bench] power-law 2M generated: nnz={A.nnz} in {time.time() - t0:.1f}s")
+        Ad = lb.CSR.from_host(A, dev)
+        xd = torch.from_numpy(x).to(dev)
+        y = torch.empty(A.m, dtype=torch.float32, device=dev)
+        B = spmv_bytes(A.m, A.n, A.nnz)
+        params = {}
+        if args.items:
+            params["items_per_thread"] = args.items
+        if args.block:
+            params["block_size"] = args.block
+        head = args.schedule
+        plan_info, plan_build_ms = None, None
+        if head == "planned":
+            if args.x_bands:
+                params["x_bands"] = args.x_bands
+            for k, v in (("long_min", args.long_min), ("panel_blocks", args.panel_blocks), ("streams", args.streams)):
+                if v:
+                    params[k] = v
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan = lb.Plan(Ad, **params)  # once per pattern: reads row_offsets through the host
+            torch.cuda.synchronize()
+            plan_build_ms = (time.perf_counter() - t0) * 1e3
+            plan_info = plan.info
+            ws = torch.empty(max(plan.workspace_bytes, 1), dtype=torch.uint8, device=dev)
+            log(f"[bench] plan built in {plan_build_ms:.1f} ms: {plan_info}")
 
-    def step():
-        lb.spmv(Ad, xd, head, y=y, workspace=ws, **params)
+            def step():
+                lb.spmv_planned(Ad, plan, xd, y=y, workspace=ws)
+            sched = {"schedule": "planned", **{k: plan_info[k] for k in
+                     ("block_size", "items_per_thread", "x_bands", "long_min", "panel_cols", "panel_blocks", "streams")}}
+            kernels = ["merge_consume", "panel_consume", "plan_finish"]
+        else:
+            if args.x_bands and head == "merge_path":
+                params["x_bands"] = args.x_bands
+            if head == "auto" and not params:
+                lb.autotune_clear()
+                t0 = time.time()
+                lb.tune(Ad)  # schedule and tile size picked by timing the candidates on this matrix
+                log(f"[bench] autotuned in {time.time() - t0:.1f}s")
+            elif head == "auto":
+                head = "merge_path"
+            sched = lb.resolve_schedule(Ad, head, **params)
+            ws = torch.empty(max(lb.workspace_size(Ad, head, **params), 1), dtype=torch.uint8, device=dev)
 
-    B = spmv_bytes(A.m, A.n, A.nnz)
-    # bring the GPU's clocks up before the W warm-up steps: about 0.3 s of
-    # untimed steps (a cold GPU times the first hundred calls a few % slow)
-    t_end = time.time() + 0.3
-    while time.time() < t_end:
-        for _ in range(20):
+            def step():
+                lb.spmv(Ad, xd, head, y=y, workspace=ws, **params)
+            kernels = {"merge_path": ["merge_consume", "merge_partition",
+                                      "merge_finish" if sched["x_bands"] == 2 else "merge_fixup"],
+                       "group_mapped": ["group_mapped"], "thread_mapped": ["thread_mapped"]}[sched["schedule"]]
+
+        # bring the GPU's clocks up before the W warm-up steps: about 0.3 s of
+        # untimed steps (a cold GPU times the first hundred calls a few % slow)
+        t_end = time.time() + 0.3
+        while time.time() < t_end:
+            for _ in range(20):
+                step()
+            torch.cuda.synchronize()
+        for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
-    ms_eager = timed(step, args.steps, args.warmup)
-    ms, timing = ms_eager, "eager"
-    if args.graph:
-        ms_g = graph_timed(step, y, args.steps)
-        if ms_g is not None:
-            ms, timing = ms_g, "hip_graph"
-    value = B / (ms * 1e-3) / 1e9
-    log(f"[bench] {sched}: {ms * 1e3:.1f} us/step ({timing}; eager {ms_eager * 1e3:.1f}), {value:.0f} GB/s")
-    ms_cold = cold(step, 10)
-    consume_ms, launches = kernel_avg_ms(step, args.steps, dominant)
-    others = {}
-    if dominant == "merge_consume":
-        others = {n: round(kernel_avg_ms(step, args.steps, n)[0], 5) for n in
-                  ("merge_partition",) + (("merge_finish",) if sched["x_bands"] == 2 else ("merge_fixup",))}
-    achieved = B / (consume_ms * 1e-3) / 1e9
-    log(f"[bench] {dominant} {consume_ms * 1e3:.1f} us ({achieved:.0f} GB/s), others {others}, "
-        f"cold call {ms_cold * 1e3:.1f} us")
-    if args.pmc_calib:
-        src = torch.ones(1 << 26, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)  # reads and writes exactly 256 MiB
-        torch.cuda.synchronize()
-        del src, dst
+        # The K timed steps: each writes 1 GiB first (evicting L2 and the Infinity
+        # Cache, outside its events), then one call between events on the launch
+        # stream.  ms_per_step is their median: the cold figure.
+        per_step = []
+        t_region = time.perf_counter()
+        for r in range(args.steps):
+            flush.fill_(float(r))
+            a_ev = torch.cuda.Event(enable_timing=True)
+            b_ev = torch.cuda.Event(enable_timing=True)
+            a_ev.record(stream)
+            step()
+            b_ev.record(stream)
+            torch.cuda.synchronize()
+            per_step.append(a_ev.elapsed_time(b_ev))
+        region_s = time.perf_counter() - t_region
+        ms = float(np.median(per_step))
+        timing = "cold median"
+        ms_warm = timed(step, args.steps, 2)  # back to back, caches warm
+        ms_graph = None
+        if args.graph:
+            ms_graph = graph_timed(step, y, args.steps)
+        value = B / (ms * 1e-3) / 1e9
+        log(f"[bench] {sched}: cold {ms * 1e3:.1f} us/step (median of {args.steps}), warm {ms_warm * 1e3:.1f} us, "
+            f"{value:.0f} GB/s")
+        kt = {n: kernel_avg_ms(step, args.steps, n) for n in kernels}
+        kt = {n: v for n, v in kt.items() if v[1] > 0}
+        dominant = max(kt, key=lambda n: kt[n][0])
+        dom_ms, launches = kt[dominant]
+        if args.pmc_calib:
+            src = torch.ones(1 << 26, dtype=torch.float32, device=dev)
+            dst = torch.empty_like(src)
+            dst.copy_(src)  # reads and writes exactly 256 MiB
+            torch.cuda.synchronize()
+            del src, dst
 
-    # ceilings measured live: streaming read of 1 GiB, and the x gather alone
-    pout = torch.empty(lb._lib.lb_probe_default_grid() * 256, dtype=torch.float32, device=dev)
-    lb.probe_stream_read(flush, pout)
-    stream_ms, _ = kernel_avg_ms(lambda: lb.probe_stream_read(flush, pout), 5, "probe_stream")
-    gather_ms, _ = kernel_avg_ms(lambda: lb.probe_gather(Ad.col_idx, xd, pout), 5, "probe_gather")
-    gather2_ms, _ = kernel_avg_ms(lambda: lb.probe_gather(Ad.col_idx, xd, pout, bands=2), 5, "probe_gather")
-    ceilings = {"stream_read_gbs": round(flush.numel() * 4 / (stream_ms * 1e-3) / 1e9, 1),
-                "gather_only_ms": round(gather_ms, 5),
-                "gather_bound_gbs": round(B / (gather_ms * 1e-3) / 1e9, 1),
-                "gather_only_2band_ms": round(gather2_ms, 5),
-                "gather_bound_2band_gbs": round(B / (gather2_ms * 1e-3) / 1e9, 1),
-                "note": "gather_only = sum of x[col_idx[j]] over all nonzeros, with every XCD gathering from "
-                        "all of x (1 band) or each XCD from its half (2 bands, as the x_bands = 2 merge path); "
-                        "an SpMV kernel that gathers the same way cannot finish faster"}
-    log(f"[bench] ceilings: {ceilings}")
+        # algorithmic bytes of each kernel of the call (the planned call's parts)
+        lens = np.diff(A.row_offsets.astype(np.int64))
+        kernel_bytes = {}
+        if head == "planned":
+            long_nnz = int(plan_info["long_nnz"])
+            short_nnz = A.nnz - long_nnz
+            kernel_bytes["merge_consume"] = short_nnz * 8 + (A.m + 1) * 4 + A.m * 4 + A.n * 4
+            kernel_bytes["panel_consume"] = long_nnz * 8 + A.n * 4 + int(plan_info["tasks"]) * 4
+            kernel_bytes["plan_finish"] = int(plan_info["tasks"]) * 4 + int(plan_info["long_rows"]) * 4
+        else:
+            kernel_bytes[dominant] = B
+        B_dom = kernel_bytes.get(dominant, B)
+        achieved = B_dom / (dom_ms * 1e-3) / 1e9
 
-    traffic, traffic_cfg = None, None
-    if os.path.exists(TRAFFIC_FILE):
-        try:
-            with open(TRAFFIC_FILE) as f:
-                tr = json.load(f)
-            same_cfg = (tr.get("block_size"), tr.get("items_per_thread"), tr.get("x_bands")) == \
-                (sched["block_size"], sched["items_per_thread"], sched["x_bands"])
-            if tr.get("kernel_source_hash") == kernel_source_hash() and tr.get("nnz") == A.nnz \
-                    and dominant == "merge_consume" and same_cfg:
-                traffic = tr.get("hbm_bytes_per_launch")
-                traffic_cfg = {"block_size": tr.get("block_size"), "items_per_thread": tr.get("items_per_thread"),
-                               "x_bands": tr.get("x_bands"),
-                               "unscaled_bytes": round((tr.get("fetch_kb_per_dispatch", 0) +
-                                                        tr.get("write_kb_per_dispatch", 0)) * 1024)}
-        except (OSError, ValueError):
-            traffic = None
+        # ceilings measured live: streaming read of 1 GiB, and the x gather alone
+        pout = torch.empty(lb._lib.lb_probe_default_grid() * 256, dtype=torch.float32, device=dev)
+        lb.probe_stream_read(flush, pout)
+        stream_ms, _ = kernel_avg_ms(lambda: lb.probe_stream_read(flush, pout), 5, "probe_stream")
+        gather_ms, _ = kernel_avg_ms(lambda: lb.probe_gather(Ad.col_idx, xd, pout), 5, "probe_gather")
+        gather2_ms, _ = kernel_avg_ms(lambda: lb.probe_gather(Ad.col_idx, xd, pout, bands=2), 5, "probe_gather")
+        ceilings = {"stream_read_gbs": round(flush.numel() * 4 / (stream_ms * 1e-3) / 1e9, 1),
+                    "gather_only_ms": round(gather_ms, 5),
+                    "gather_bound_gbs": round(B / (gather_ms * 1e-3) / 1e9, 1),
+                    "gather_only_2band_ms": round(gather2_ms, 5),
+                    "gather_bound_2band_gbs": round(B / (gather2_ms * 1e-3) / 1e9, 1),
+                    "note": "gather_only = sum of x[col_idx[j]] over all nonzeros, with every XCD gathering from "
+                            "all of x (1 band) or each XCD from its half (2 bands, as the x_bands = 2 merge path); "
+                            "an SpMV kernel that gathers the same way cannot finish faster"}
+        short_gather_ms = None
+        if head == "planned":
+            short_mask = np.repeat(lens < int(plan_info["long_min"]), lens)
+            sidx = torch.from_numpy(np.ascontiguousarray(A.col_idx[short_mask])).to(dev)
+            short_gather_ms, _ = kernel_avg_ms(
+                lambda: lb.probe_gather(sidx, xd, pout, bands=plan_info["x_bands"]), 5, "probe_gather")
+            ceilings["short_rows_gather_only_ms"] = round(short_gather_ms, 5)
+            ceilings["short_rows_note"] = ("the same gather over the short rows' columns only, in the planned "
+                                           "short-row consume's band form: the floor of that kernel")
+            del sidx
+        log(f"[bench] ceilings: {ceilings}")
 
-    result = {
-        "metric": METRIC,
-        "value": round(value, 2),
-        "unit": "GB/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms, 5),
-        "timing": timing,
-        "eager_ms_per_step": round(ms_eager, 5),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "powerlaw_m2M_zipf1.8_cap200k_empty10pct", "m": A.m, "n": A.n, "nnz": A.nnz,
-                   "seed": 2, "schedule": sched["schedule"], "block_size": sched["block_size"],
-                   "items_per_thread": sched["items_per_thread"], "x_bands": sched["x_bands"]},
-        "pct_of_peak": round(100 * value / PEAK_GBS, 2),
-        "gflops": round(2 * A.nnz / (ms * 1e-3) / 1e9, 2),
-        "algorithmic_bytes": B,
-        "cold_ms_per_call": round(ms_cold, 5),
-        "cold_gbs": round(B / (ms_cold * 1e-3) / 1e9, 2),
-        "ceilings": ceilings,
-        "roofline": {"kernel": dominant, "bound": "hbm", "achieved": round(achieved, 2),
-                     "peak": PEAK_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_GBS, 4),
-                     "traffic": traffic, "traffic_profiled_config": traffic_cfg,
-                     "avg_launch_ms": round(consume_ms, 5), "launches": launches,
-                     "algorithmic_bytes_per_launch": B, "other_kernels_ms": others,
-                     # the measured ceiling of a kernel that gathers x the same way (ceilings above)
-                     "gather_ceiling_gbs": ceilings["gather_bound_2band_gbs" if sched.get("x_bands") == 2
-                                                    else "gather_bound_gbs"],
-                     "frac_of_gather_ceiling": round(achieved / ceilings["gather_bound_2band_gbs" if
-                                                     sched.get("x_bands") == 2 else "gather_bound_gbs"], 4)},
-    }
+        traffic, traffic_cfg = None, None
+        if os.path.exists(TRAFFIC_FILE):
+            try:
+                with open(TRAFFIC_FILE) as f:
+                    tr = json.load(f)
+                same = (tr.get("schedule") == sched["schedule"] and tr.get("kernel") == dominant and
+                        tr.get("kernel_source_hash") == kernel_source_hash() and tr.get("nnz") == A.nnz and
+                        all(tr.get(k) == sched.get(k) for k in ("block_size", "items_per_thread", "x_bands", "long_min")))
+                if same:
+                    traffic = tr.get("hbm_bytes_per_launch")
+                    traffic_cfg = {k: tr.get(k) for k in ("schedule", "block_size", "items_per_thread", "x_bands",
+                                                         "long_min")}
+                    traffic_cfg["unscaled_bytes"] = round((tr.get("fetch_kb_per_dispatch", 0) +
+                                                           tr.get("write_kb_per_dispatch", 0)) * 1024)
+            except (OSError, ValueError):
+                traffic = None
 
-    # ------------------------------------------------------------ CPU oracle baseline
-    if not args.no_cpu:
-        import oracle
+        ceiling_key = "gather_bound_2band_gbs" if sched.get("x_bands") == 2 else "gather_bound_gbs"
+        roofline = {"kernel": dominant, "bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / PEAK_GBS, 4), "traffic": traffic, "traffic_profiled_config": traffic_cfg,
+                    "avg_launch_ms": round(dom_ms, 5), "launches": launches,
+                    "algorithmic_bytes_per_launch": B_dom,
+                    "kernels_ms": {n: round(v[0], 5) for n, v in kt.items()},
+                    "kernels_gbs": {n: round(kernel_bytes[n] / (kt[n][0] * 1e-3) / 1e9, 1)
+                                    for n in kt if n in kernel_bytes}}
+        if head == "planned" and short_gather_ms:
+            roofline["gather_floor_ms"] = round(short_gather_ms, 5)
+            roofline["frac_of_gather_floor"] = round(short_gather_ms / dom_ms, 4) if dominant == "merge_consume" else None
+        else:
+            roofline["gather_ceiling_gbs"] = ceilings[ceiling_key]
+            roofline["frac_of_gather_ceiling"] = round(achieved / ceilings[ceiling_key], 4)
 
-        orc = oracle.default()
-        orc.spmv(A.row_offsets, A.col_idx, A.values, x)  # warm-up
-        reps, t_all = 0, []
-        start = time.time()
-        while reps < 5 and time.time() - start < 20:
-            t1 = time.perf_counter()
-            orc.spmv(A.row_offsets, A.col_idx, A.values, x)
-            t_all.append(time.perf_counter() - t1)
-            reps += 1
-        cpu_s = float(np.median(t_all))
-        threads = orc.num_threads()
-        orc.set_num_threads(1)  # the same oracle on one core, as context
-        t1 = []
-        for _ in range(2):
-            t_1 = time.perf_counter()
-            orc.spmv(A.row_offsets, A.col_idx, A.values, x)
-            t1.append(time.perf_counter() - t_1)
-        orc.set_num_threads(threads)
-        result["cpu_baseline"] = {"value": round(B / cpu_s / 1e9, 3), "unit": "GB/s", "cores": threads,
-                                  "kind": "oracle", "ms_per_call": round(cpu_s * 1e3, 2),
-                                  "sample": f"full power-law 2M matrix, FP64 oracle SpMV, median of {reps} calls",
-                                  "one_core_ms_per_call": round(min(t1) * 1e3, 2)}
-        log(f"[bench] cpu oracle: {cpu_s * 1e3:.0f} ms/call on {orc.num_threads()} threads")
+        cfg = {"workload": "powerlaw_m2M_zipf1.8_cap200k_empty10pct", "m": A.m, "n": A.n, "nnz": A.nnz, "seed": 2,
+               **sched}
+        result = {
+            "metric": METRIC,
+            "value": round(value, 2),
+            "unit": "GB/s",
+            "n_gpus": 1,
+            "steps": args.steps,
+            "warmup": args.warmup,
+            "ms_per_step": round(ms, 5),
+            "timing": timing,
+            "warm_ms_per_step": round(ms_warm, 5),
+            "warm_gbs": round(B / (ms_warm * 1e-3) / 1e9, 2),
+            "timed_region_s": round(region_s, 3),
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "f32",
+            "data": "synthetic",
+            "config": cfg,
+            "pct_of_peak": round(100 * value / PEAK_GBS, 2),
+            "gflops": round(2 * A.nnz / (ms * 1e-3) / 1e9, 2),
+            "algorithmic_bytes": B,
+            "ceilings": ceilings,
+            "roofline": roofline,
+            "host": host_facts(),
+        }
+        if ms_graph is not None:
+            result["hip_graph_ms_per_step"] = round(ms_graph, 5)
+        if plan_info is not None:
+            result["plan"] = {"build_ms": round(plan_build_ms, 2), "plan_bytes": int(plan_info["plan_bytes"]),
+                              "workspace_bytes": int(plan_info["workspace_bytes"]),
+                              **{k: int(plan_info[k]) for k in ("long_rows", "long_nnz", "panels", "tasks", "units",
+                                                                  "active_units")},
+                              "note": "built once per sparsity pattern, outside the timed region; values and x may "
+                                      "change between calls"}
+            # the same matrix on the unplanned merge path (two column bands), cold and warm
+            wsu = torch.empty(max(lb.workspace_size(Ad, "merge_path", x_bands=2), 1), dtype=torch.uint8, device=dev)
+            fu = (lambda: lb.spmv(Ad, xd, "merge_path", y=y, workspace=wsu, x_bands=2))
+            tu = timed(fu, args.steps, 2)
+            tuc = cold(fu, 10)
+            result["merge_path_unplanned"] = {"warm_ms": round(tu, 5), "cold_ms": round(tuc, 5),
+                                              "cold_gbs": round(B / (tuc * 1e-3) / 1e9, 2),
+                                              "warm_gbs": round(B / (tu * 1e-3) / 1e9, 2)}
+            del wsu
 
-    if args.quick:
-        print(json.dumps(result), flush=True)
-        return 0
+        # ------------------------------------------------------------ CPU oracle baseline
+        if not args.no_cpu:
+            import oracle
+
+            orc = oracle.default()
+            y_ref = orc.spmv(A.row_offsets, A.col_idx, A.values, x)  # warm-up (its result checks the GPU's below)
+            reps, t_all = 0, []
+            start = time.time()
+            while reps < 5 and time.time() - start < 20:
+                t1 = time.perf_counter()
+                orc.spmv(A.row_offsets, A.col_idx, A.values, x)
+                t_all.append(time.perf_counter() - t1)
+                reps += 1
+            cpu_s = float(np.median(t_all))
+            threads = orc.num_threads()
+            orc.set_num_threads(1)  # the same oracle on one core, as context
+            t1 = []
+            for _ in range(2):
+                t_1 = time.perf_counter()
+                orc.spmv(A.row_offsets, A.col_idx, A.values, x)
+                t1.append(time.perf_counter() - t_1)
+            orc.set_num_threads(threads)
+            result["cpu_baseline"] = {"value": round(B / cpu_s / 1e9, 3), "unit": "GB/s", "cores": threads,
+                                      "kind": "oracle", "ms_per_call": round(cpu_s * 1e3, 2),
+                                      "sample": f"full power-law 2M matrix, FP64 oracle SpMV, median of {reps} calls",
+                                      "one_core_ms_per_call": round(min(t1) * 1e3, 2)}
+            # accuracy of the headline's output (outside the timed region) against the oracle's
+            scale = orc.spmv(A.row_offsets, A.col_idx, A.values, x, abs_terms=True)
+            step()
+            torch.cuda.synchronize()
+            err = np.abs(y.cpu().numpy().astype(np.float64) - y_ref)
+            ratio = float(np.max(err / np.where(scale > 0, scale, 1.0)))
+            result["accuracy"] = {"max_err_over_sum_abs_terms": ratio, "tolerance": 1e-5,
+                                  "zero_rows_exact": bool(np.all(err[scale == 0] == 0))}
+            log(f"[bench] cpu oracle: {cpu_s * 1e3:.0f} ms/call on {orc.num_threads()} threads; max err ratio {ratio:.2e}")
+        if args.quick:
+            print(json.dumps(result), flush=True)
+            return 0
+
+    def want(name):
+        return wanted is None or name in wanted
+
 
     extra_steps = max(3, min(args.steps, 10))
 
-    # ------------------------------------------------------------ per schedule on the same matrix
-    per = {}
-    for name, p in (("merge_path", {}), ("merge_path", {"block_size": 512, "items_per_thread": 8}),
-                    ("merge_path", {"x_bands": 2}), ("merge_path", {"block_size": 512, "items_per_thread": 8, "x_bands": 2}),
-                    ("thread_mapped", {}), ("group_mapped", {"group_size": 64}),
-                    ("group_mapped", {"group_size": 256}), ("group_mapped", {"group_size": 32, "tiles_per_group": 32}),
-                    ("group_mapped", {"group_size": 1024, "tiles_per_group": 1024}),
-                    ("work_queue", {"group_size": 1024})):
-        wsz = lb.workspace_size(Ad, name, **p)
-        w2 = torch.empty(max(wsz, 1), dtype=torch.uint8, device=dev)
-        f = (lambda name=name, p=p, w2=w2: lb.spmv(Ad, xd, name, y=y, workspace=w2, **p))
-        t = timed(f, 3 if name == "thread_mapped" else extra_steps, 1)
-        key = name + ("" if not p else "_" + "_".join(f"{k}{v}" for k, v in p.items()))
-        per[key] = {"ms": round(t, 4), "gbs": round(B / (t * 1e-3) / 1e9, 2),
-                    "pct_of_peak": round(100 * B / (t * 1e-3) / 1e9 / PEAK_GBS, 2)}
-        log(f"[bench] {key}: {t * 1e3:.1f} us")
-    lb.autotune_clear()
-    pick = lb.tune(Ad)
-    wst = torch.empty(max(lb.workspace_size(Ad, "auto"), 1), dtype=torch.uint8, device=dev)
-    t = timed(lambda: lb.spmv(Ad, xd, "auto", y=y, workspace=wst), extra_steps, 1)
-    per["auto_tuned"] = {"ms": round(t, 4), "gbs": round(B / (t * 1e-3) / 1e9, 2),
-                         "pct_of_peak": round(100 * B / (t * 1e-3) / 1e9 / PEAK_GBS, 2), "schedule": pick}
-    lb.autotune_clear()
-    del wst
-    result["schedules_powerlaw2M"] = per
-
-    # ------------------------------------------------------------ the small uniform matrix (launch-bound)
-    A1, x1 = S.config_c1()
-    A1d = lb.CSR.from_host(A1, dev)
-    x1d = torch.from_numpy(x1).to(dev)
-    y1 = torch.empty(A1.m, dtype=torch.float32, device=dev)
-    small = {"m": A1.m, "nnz": A1.nnz, "note": "us per call, back to back; accuracy is asserted by the GPU tests"}
-    for name, p in (("thread_mapped", {}), ("group_mapped", {"group_size": 64}),
-                    ("group_mapped", {"group_size": 64, "tiles_per_group": 64}), ("merge_path", {})):
-        ws1 = torch.empty(max(lb.workspace_size(A1d, name, **p), 1), dtype=torch.uint8, device=dev)
-        t = timed(lambda name=name, p=p, ws1=ws1: lb.spmv(A1d, x1d, name, y=y1, workspace=ws1, **p), 50, 10)
-        key = name + ("" if not p else "_" + "_".join(f"{k}{v}" for k, v in p.items()))
-        small[key] = round(t * 1e3, 2)
-    result["uniform4096"] = small
-    log(f"[bench] uniform 4096: {small}")
-    del A1d, x1d, y1
-
-    # ------------------------------------------------------------ BF16 (accuracy is asserted by the GPU tests)
-    bf = {}
-    Ab = A.with_values(S.to_bf16_bits(A.values))
-    xb = S.to_bf16_bits(x)
-    Abd = lb.CSR.from_host(Ab, dev)
-    xbd = torch.from_numpy(xb.view(np.int16).copy()).view(torch.bfloat16).to(dev)
-    wsb = torch.empty(lb.workspace_size(Abd, "merge_path"), dtype=torch.uint8, device=dev)
-    t = timed(lambda: lb.spmv(Abd, xbd, "merge_path", y=y, workspace=wsb), extra_steps, 2)
-    Bb = spmv_bytes(A.m, A.n, A.nnz, 2, 2)
-    bf["powerlaw2M"] = {"ms": round(t, 4), "gbs": round(Bb / (t * 1e-3) / 1e9, 2), "fp32_gbs": round(value, 2)}
-    del Abd, xbd
-    L, xl = S.config_c3_laplacian()
-    Ld = lb.CSR.from_host(L, dev)
-    xld = torch.from_numpy(xl).to(dev)
-    yl = torch.empty(L.m, dtype=torch.float32, device=dev)
-    wsl = torch.empty(lb.workspace_size(Ld, "merge_path"), dtype=torch.uint8, device=dev)
-    tl = timed(lambda: lb.spmv(Ld, xld, "merge_path", y=yl, workspace=wsl), extra_steps, 2)
-    tlc = cold(lambda: lb.spmv(Ld, xld, "merge_path", y=yl, workspace=wsl), 5)
-    Lb = L.with_values(S.to_bf16_bits(L.values))
-    xlb = S.to_bf16_bits(xl)
-    Lbd = lb.CSR.from_host(Lb, dev)
-    xlbd = torch.from_numpy(xlb.view(np.int16).copy()).view(torch.bfloat16).to(dev)
-    tlb = timed(lambda: lb.spmv(Lbd, xlbd, "merge_path", y=yl, workspace=wsl), extra_steps, 2)
-    tlbc = cold(lambda: lb.spmv(Lbd, xlbd, "merge_path", y=yl, workspace=wsl), 5)
-    BL, BLb = spmv_bytes(L.m, L.n, L.nnz), spmv_bytes(L.m, L.n, L.nnz, 2, 2)
-    bf["laplacian2048"] = {"nnz": L.nnz, "fp32_ms": round(tl, 4), "fp32_gbs": round(BL / (tl * 1e-3) / 1e9, 2),
-                           "fp32_cold_gbs": round(BL / (tlc * 1e-3) / 1e9, 2),
-                           "bf16_ms": round(tlb, 4), "bf16_gbs": round(BLb / (tlb * 1e-3) / 1e9, 2),
-                           "bf16_cold_gbs": round(BLb / (tlbc * 1e-3) / 1e9, 2), "schedule": "merge_path"}
-    # the autotuned pick for each precision (what schedule="auto" runs after lb.tune)
-    for key, Md, xmd, Bm in (("fp32", Ld, xld, BL), ("bf16", Lbd, xlbd, BLb)):
+    if want("schedules"):
+        # ------------------------------------------------------------ per schedule on the same matrix
+        per = {}
+        for name, p in (("merge_path", {}), ("merge_path", {"block_size": 512, "items_per_thread": 8}),
+                        ("merge_path", {"x_bands": 2}), ("merge_path", {"block_size": 512, "items_per_thread": 8, "x_bands": 2}),
+                        ("thread_mapped", {}), ("group_mapped", {"group_size": 64}),
+                        ("group_mapped", {"group_size": 256}), ("group_mapped", {"group_size": 32, "tiles_per_group": 32}),
+                        ("group_mapped", {"group_size": 1024, "tiles_per_group": 1024}),
+                        ("work_queue", {"group_size": 1024})):
+            wsz = lb.workspace_size(Ad, name, **p)
+            w2 = torch.empty(max(wsz, 1), dtype=torch.uint8, device=dev)
+            f = (lambda name=name, p=p, w2=w2: lb.spmv(Ad, xd, name, y=y, workspace=w2, **p))
+            t = timed(f, 3 if name == "thread_mapped" else extra_steps, 1)
+            key = name + ("" if not p else "_" + "_".join(f"{k}{v}" for k, v in p.items()))
+            per[key] = {"ms": round(t, 4), "gbs": round(B / (t * 1e-3) / 1e9, 2),
+                        "pct_of_peak": round(100 * B / (t * 1e-3) / 1e9 / PEAK_GBS, 2)}
+            log(f"[bench] {key}: {t * 1e3:.1f} us")
         lb.autotune_clear()
-        pick = lb.tune(Md)
-        wst = torch.empty(max(lb.workspace_size(Md, "auto"), 1), dtype=torch.uint8, device=dev)
-        fl = (lambda Md=Md, xmd=xmd, wst=wst: lb.spmv(Md, xmd, "auto", y=yl, workspace=wst))
-        tt = timed(fl, extra_steps, 2)
-        tg = graph_timed(fl, yl, 20)  # a launch-bound size: the graph removes the gaps between launches
-        bf["laplacian2048"][f"{key}_tuned"] = {"ms": round(tt, 4), "gbs": round(Bm / (tt * 1e-3) / 1e9, 2),
-                                               "schedule": pick,
-                                               "hip_graph_ms": round(tg, 4) if tg is not None else None,
-                                               "hip_graph_gbs": round(Bm / (tg * 1e-3) / 1e9, 2) if tg else None}
+        pick = lb.tune(Ad)
+        wst = torch.empty(max(lb.workspace_size(Ad, "auto"), 1), dtype=torch.uint8, device=dev)
+        t = timed(lambda: lb.spmv(Ad, xd, "auto", y=y, workspace=wst), extra_steps, 1)
+        per["auto_tuned"] = {"ms": round(t, 4), "gbs": round(B / (t * 1e-3) / 1e9, 2),
+                             "pct_of_peak": round(100 * B / (t * 1e-3) / 1e9 / PEAK_GBS, 2), "schedule": pick}
+        lb.autotune_clear()
         del wst
-    lb.autotune_clear()
-    result["bf16"] = bf
-    log(f"[bench] bf16: {bf}")
-    del Ld, Lbd, xld, xlbd, yl
+        result["schedules_powerlaw2M"] = per
 
-    # ------------------------------------------------------------ forward + backward (1M)
-    C4, x4 = S.config_c4()
-    C4d = lb.CSR.from_host(C4, dev)
-    x4d = torch.from_numpy(x4).to(dev)
-    dy4 = torch.from_numpy(S.random_vector(44, C4.m)).to(dev)
-    y4 = torch.empty(C4.m, dtype=torch.float32, device=dev)
-    ws4 = torch.empty(lb.workspace_size(C4d, "merge_path"), dtype=torch.uint8, device=dev)
-    tf = timed(lambda: lb.spmv(C4d, x4d, "merge_path", y=y4, workspace=ws4), extra_steps, 2)
-    tb = timed(lambda: lb.spmv_backward(C4d, x4d, dy4), extra_steps, 2)
-    bw_ms, _ = kernel_avg_ms(lambda: lb.spmv_backward(C4d, x4d, dy4), extra_steps, "backward")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    tr4 = lb.transpose_pattern(C4d.pattern)  # once per pattern
-    torch.cuda.synchronize()
-    tbuild = (time.perf_counter() - t0) * 1e3
-    tbt = timed(lambda: lb.spmv_backward(C4d, x4d, dy4, transposed=tr4), extra_steps, 2)
-    Bf4, Bb4 = spmv_bytes(C4.m, C4.n, C4.nnz), backward_bytes(C4.m, C4.n, C4.nnz)
-    result["fwd_bwd_powerlaw1M"] = {"nnz": C4.nnz, "fwd_ms": round(tf, 4), "bwd_ms": round(tb, 4),
-                                    "fwd_gbs": round(Bf4 / (tf * 1e-3) / 1e9, 2),
-                                    "bwd_gbs": round(Bb4 / (tb * 1e-3) / 1e9, 2),
-                                    "bwd_kernel_ms": round(bw_ms, 4),
-                                    "bwd_transposed_ms": round(tbt, 4),
-                                    "bwd_transposed_gbs": round(Bb4 / (tbt * 1e-3) / 1e9, 2),
-                                    "transpose_build_ms": round(tbuild, 3),
-                                    "fwd_bwd_transposed_gbs": round((Bf4 + Bb4) / ((tf + tbt) * 1e-3) / 1e9, 2),
-                                    "fwd_bwd_gbs": round((Bf4 + Bb4) / ((tf + tb) * 1e-3) / 1e9, 2)}
-    log(f"[bench] fwd+bwd: {result['fwd_bwd_powerlaw1M']}")
+    if want("uniform"):
+        # ------------------------------------------------------------ the small uniform matrix (launch-bound)
+        A1, x1 = S.config_c1()
+        A1d = lb.CSR.from_host(A1, dev)
+        x1d = torch.from_numpy(x1).to(dev)
+        y1 = torch.empty(A1.m, dtype=torch.float32, device=dev)
+        small = {"m": A1.m, "nnz": A1.nnz, "note": "us per call, back to back; accuracy is asserted by the GPU tests"}
+        for name, p in (("thread_mapped", {}), ("group_mapped", {"group_size": 64}),
+                        ("group_mapped", {"group_size": 64, "tiles_per_group": 64}), ("merge_path", {})):
+            ws1 = torch.empty(max(lb.workspace_size(A1d, name, **p), 1), dtype=torch.uint8, device=dev)
+            t = timed(lambda name=name, p=p, ws1=ws1: lb.spmv(A1d, x1d, name, y=y1, workspace=ws1, **p), 50, 10)
+            key = name + ("" if not p else "_" + "_".join(f"{k}{v}" for k, v in p.items()))
+            small[key] = round(t * 1e3, 2)
+        result["uniform4096"] = small
+        log(f"[bench] uniform 4096: {small}")
+        del A1d, x1d, y1
 
-    # ------------------------------------------------------------ other tile sets (1M): COO and CSC
-    fm = {"nnz": C4.nnz, "note": "bytes: CSR nnz*8+(m+1)*4+n*4+m*4; COO nnz*12+n*4+m*4; CSC nnz*8+(n+1)*4+n*4+m*4"}
-    Bcoo = C4.nnz * 12 + C4.n * 4 + C4.m * 4
-    Bcsc = C4.nnz * 8 + (C4.n + 1) * 4 + C4.n * 4 + C4.m * 4
-    fm["csr_merge_path"] = {"ms": round(tf, 4), "gbs": round(Bf4 / (tf * 1e-3) / 1e9, 2)}
-    coo4 = lb.COO.from_host(S.to_coo(C4), dev)
-    for name, p in (("coo_merge_path", {}), ("coo_thread_mapped", {}), ("coo_group_mapped64", {"group_size": 64})):
-        sch = name[4:].replace("64", "")
-        wsz = torch.empty(max(1, lb.coo_workspace_size(coo4, sch, **p)), dtype=torch.uint8, device=dev)
-        t = timed(lambda: lb.spmv_coo(coo4, x4d, sch, y=y4, workspace=wsz, **p),
-                  3 if sch != "merge_path" else extra_steps, 1)
-        fm[name] = {"ms": round(t, 4), "gbs": round(Bcoo / (t * 1e-3) / 1e9, 2)}
-    del coo4
-    csc4 = lb.CSC.from_host(S.to_csc(C4), dev)
-    t = timed(lambda: lb.spmv_csc(csc4, x4d, "merge_path", y=y4), extra_steps, 1)
-    fm["csc_merge_path"] = {"ms": round(t, 4), "gbs": round(Bcsc / (t * 1e-3) / 1e9, 2)}
-    del csc4
-    result["formats_powerlaw1M"] = fm
-    log(f"[bench] formats: {fm}")
-    del C4d, x4d, dy4, y4, ws4
+    if want("bf16"):
+        # ------------------------------------------------------------ BF16 (accuracy is asserted by the GPU tests)
+        bf = {}
+        Ab = A.with_values(S.to_bf16_bits(A.values))
+        xb = S.to_bf16_bits(x)
+        Abd = lb.CSR.from_host(Ab, dev)
+        xbd = torch.from_numpy(xb.view(np.int16).copy()).view(torch.bfloat16).to(dev)
+        wsb = torch.empty(lb.workspace_size(Abd, "merge_path"), dtype=torch.uint8, device=dev)
+        t = timed(lambda: lb.spmv(Abd, xbd, "merge_path", y=y, workspace=wsb), extra_steps, 2)
+        Bb = spmv_bytes(A.m, A.n, A.nnz, 2, 2)
+        bf["powerlaw2M"] = {"ms": round(t, 4), "gbs": round(Bb / (t * 1e-3) / 1e9, 2),
+                            "fp32_gbs": round(value, 2) if value else None}
+        plb = lb.Plan(Abd)  # the planned call in BF16 (panels of 32768 BF16 columns)
+        wspb = torch.empty(max(plb.workspace_bytes, 1), dtype=torch.uint8, device=dev)
+        fpb = (lambda: lb.spmv_planned(Abd, plb, xbd, y=y, workspace=wspb))
+        tp, tpc = timed(fpb, extra_steps, 2), cold(fpb, 10)
+        bf["powerlaw2M"]["planned"] = {"warm_ms": round(tp, 4), "warm_gbs": round(Bb / (tp * 1e-3) / 1e9, 2),
+                                       "cold_ms": round(tpc, 4), "cold_gbs": round(Bb / (tpc * 1e-3) / 1e9, 2),
+                                       "long_rows": plb.info["long_rows"], "long_nnz": plb.info["long_nnz"]}
+        del Abd, xbd, plb, wspb
+        L, xl = S.config_c3_laplacian()
+        Ld = lb.CSR.from_host(L, dev)
+        xld = torch.from_numpy(xl).to(dev)
+        yl = torch.empty(L.m, dtype=torch.float32, device=dev)
+        wsl = torch.empty(lb.workspace_size(Ld, "merge_path"), dtype=torch.uint8, device=dev)
+        tl = timed(lambda: lb.spmv(Ld, xld, "merge_path", y=yl, workspace=wsl), extra_steps, 2)
+        tlc = cold(lambda: lb.spmv(Ld, xld, "merge_path", y=yl, workspace=wsl), 5)
+        Lb = L.with_values(S.to_bf16_bits(L.values))
+        xlb = S.to_bf16_bits(xl)
+        Lbd = lb.CSR.from_host(Lb, dev)
+        xlbd = torch.from_numpy(xlb.view(np.int16).copy()).view(torch.bfloat16).to(dev)
+        tlb = timed(lambda: lb.spmv(Lbd, xlbd, "merge_path", y=yl, workspace=wsl), extra_steps, 2)
+        tlbc = cold(lambda: lb.spmv(Lbd, xlbd, "merge_path", y=yl, workspace=wsl), 5)
+        BL, BLb = spmv_bytes(L.m, L.n, L.nnz), spmv_bytes(L.m, L.n, L.nnz, 2, 2)
+        bf["laplacian2048"] = {"nnz": L.nnz, "fp32_ms": round(tl, 4), "fp32_gbs": round(BL / (tl * 1e-3) / 1e9, 2),
+                               "fp32_cold_gbs": round(BL / (tlc * 1e-3) / 1e9, 2),
+                               "bf16_ms": round(tlb, 4), "bf16_gbs": round(BLb / (tlb * 1e-3) / 1e9, 2),
+                               "bf16_cold_gbs": round(BLb / (tlbc * 1e-3) / 1e9, 2), "schedule": "merge_path"}
+        # planned: no long rows here, so the merge path with the split precomputed (one launch fewer)
+        for key, Md, xmd, Bm in (("fp32", Ld, xld, BL), ("bf16", Lbd, xlbd, BLb)):
+            plm = lb.Plan(Md)
+            wsp = torch.empty(max(plm.workspace_bytes, 1), dtype=torch.uint8, device=dev)
+            fp = (lambda Md=Md, xmd=xmd, plm=plm, wsp=wsp: lb.spmv_planned(Md, plm, xmd, y=yl, workspace=wsp))
+            tp, tpc = timed(fp, extra_steps, 2), cold(fp, 10)
+            bf["laplacian2048"][f"{key}_planned"] = {"warm_ms": round(tp, 4), "warm_gbs": round(Bm / (tp * 1e-3) / 1e9, 2),
+                                                     "cold_ms": round(tpc, 4),
+                                                     "cold_gbs": round(Bm / (tpc * 1e-3) / 1e9, 2),
+                                                     "long_rows": plm.info["long_rows"]}
+            del plm, wsp
+        # the autotuned pick for each precision (what schedule="auto" runs after lb.tune)
+        for key, Md, xmd, Bm in (("fp32", Ld, xld, BL), ("bf16", Lbd, xlbd, BLb)):
+            lb.autotune_clear()
+            pick = lb.tune(Md)
+            wst = torch.empty(max(lb.workspace_size(Md, "auto"), 1), dtype=torch.uint8, device=dev)
+            fl = (lambda Md=Md, xmd=xmd, wst=wst: lb.spmv(Md, xmd, "auto", y=yl, workspace=wst))
+            tt = timed(fl, extra_steps, 2)
+            tg = graph_timed(fl, yl, 20)  # a launch-bound size: the graph removes the gaps between launches
+            bf["laplacian2048"][f"{key}_tuned"] = {"ms": round(tt, 4), "gbs": round(Bm / (tt * 1e-3) / 1e9, 2),
+                                                   "schedule": pick,
+                                                   "hip_graph_ms": round(tg, 4) if tg is not None else None,
+                                                   "hip_graph_gbs": round(Bm / (tg * 1e-3) / 1e9, 2) if tg else None}
+            del wst
+        lb.autotune_clear()
+        result["bf16"] = bf
+        log(f"[bench] bf16: {bf}")
+        del Ld, Lbd, xld, xlbd, yl
 
-    # ------------------------------------------------------------ batched (512 matrices)
-    t0 = time.time()
-    BH = S.config_c5()
-    log(f"[bench] batched generated: {BH.count} matrices, nnz={BH.nnz} in {time.time() - t0:.1f}s")
-    Bd = lb.Batch.from_host(BH, dev)
-    bres = {"count": BH.count, "total_rows": BH.total_rows, "nnz": BH.nnz}
-    for k in (1, 8):
-        Xk = torch.from_numpy(S.random_vector(55, BH.total_cols * k).reshape(-1, k)).to(dev)
-        Yk = torch.empty((BH.total_rows, k), dtype=torch.float32, device=dev)
-        tuned = lb.tune_batched(Bd, k)
-        tk = timed(lambda: lb.batched_spmm(Bd, Xk, "auto", Y=Yk), extra_steps, 2)
-        Bk = BH.nnz * 8 + (BH.total_rows + 1) * 4 + BH.total_cols * 4 * k + BH.total_rows * 4 * k
-        bres[f"k{k}"] = {"ms": round(tk, 4), "gbs": round(Bk / (tk * 1e-3) / 1e9, 2),
-                         "gflops": round(2 * BH.nnz * k / (tk * 1e-3) / 1e9, 2), "schedule": tuned}
-        del Xk, Yk
-        log(f"[bench] batched k={k}: {bres[f'k{k}']}")
-    result["batched_512"] = bres
-    del Bd
+    if want("fwdbwd"):
+        # ------------------------------------------------------------ forward + backward (1M)
+        C4, x4 = S.config_c4()
+        C4d = lb.CSR.from_host(C4, dev)
+        x4d = torch.from_numpy(x4).to(dev)
+        dy4 = torch.from_numpy(S.random_vector(44, C4.m)).to(dev)
+        y4 = torch.empty(C4.m, dtype=torch.float32, device=dev)
+        ws4 = torch.empty(lb.workspace_size(C4d, "merge_path"), dtype=torch.uint8, device=dev)
+        tf = timed(lambda: lb.spmv(C4d, x4d, "merge_path", y=y4, workspace=ws4), extra_steps, 2)
+        pl4 = lb.Plan(C4d)
+        wsp4 = torch.empty(max(pl4.workspace_bytes, 1), dtype=torch.uint8, device=dev)
+        tfp = timed(lambda: lb.spmv_planned(C4d, pl4, x4d, y=y4, workspace=wsp4), extra_steps, 2)
+        del pl4, wsp4
+        tb = timed(lambda: lb.spmv_backward(C4d, x4d, dy4), extra_steps, 2)
+        bw_ms, _ = kernel_avg_ms(lambda: lb.spmv_backward(C4d, x4d, dy4), extra_steps, "backward")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tr4 = lb.transpose_pattern(C4d.pattern)  # once per pattern
+        torch.cuda.synchronize()
+        tbuild = (time.perf_counter() - t0) * 1e3
+        tbt = timed(lambda: lb.spmv_backward(C4d, x4d, dy4, transposed=tr4), extra_steps, 2)
+        Bf4, Bb4 = spmv_bytes(C4.m, C4.n, C4.nnz), backward_bytes(C4.m, C4.n, C4.nnz)
+        result["fwd_bwd_powerlaw1M"] = {"nnz": C4.nnz, "fwd_ms": round(tf, 4), "bwd_ms": round(tb, 4),
+                                        "fwd_planned_ms": round(tfp, 4),
+                                        "fwd_planned_gbs": round(spmv_bytes(C4.m, C4.n, C4.nnz) / (tfp * 1e-3) / 1e9, 2),
+                                        "fwd_gbs": round(Bf4 / (tf * 1e-3) / 1e9, 2),
+                                        "bwd_gbs": round(Bb4 / (tb * 1e-3) / 1e9, 2),
+                                        "bwd_kernel_ms": round(bw_ms, 4),
+                                        "bwd_transposed_ms": round(tbt, 4),
+                                        "bwd_transposed_gbs": round(Bb4 / (tbt * 1e-3) / 1e9, 2),
+                                        "transpose_build_ms": round(tbuild, 3),
+                                        "fwd_bwd_transposed_gbs": round((Bf4 + Bb4) / ((tf + tbt) * 1e-3) / 1e9, 2),
+                                        "fwd_bwd_gbs": round((Bf4 + Bb4) / ((tf + tb) * 1e-3) / 1e9, 2)}
+        log(f"[bench] fwd+bwd: {result['fwd_bwd_powerlaw1M']}")
 
-    result["graph_powerlaw1M"] = run_graph(lb, S, dev, args.no_cpu)
+    if want("formats"):
+        # ------------------------------------------------------------ other tile sets (1M): COO and CSC
+        if "C4d" not in locals():  # the 1M matrix and its CSR forward, when fwdbwd did not run
+            C4, x4 = S.config_c4()
+            C4d = lb.CSR.from_host(C4, dev)
+            x4d = torch.from_numpy(x4).to(dev)
+            y4 = torch.empty(C4.m, dtype=torch.float32, device=dev)
+            ws4 = torch.empty(lb.workspace_size(C4d, "merge_path"), dtype=torch.uint8, device=dev)
+            dy4 = None
+            tf = timed(lambda: lb.spmv(C4d, x4d, "merge_path", y=y4, workspace=ws4), extra_steps, 2)
+            Bf4 = spmv_bytes(C4.m, C4.n, C4.nnz)
+        fm = {"nnz": C4.nnz, "note": "bytes: CSR nnz*8+(m+1)*4+n*4+m*4; COO nnz*12+n*4+m*4; CSC nnz*8+(n+1)*4+n*4+m*4"}
+        Bcoo = C4.nnz * 12 + C4.n * 4 + C4.m * 4
+        Bcsc = C4.nnz * 8 + (C4.n + 1) * 4 + C4.n * 4 + C4.m * 4
+        fm["csr_merge_path"] = {"ms": round(tf, 4), "gbs": round(Bf4 / (tf * 1e-3) / 1e9, 2)}
+        coo4 = lb.COO.from_host(S.to_coo(C4), dev)
+        for name, p in (("coo_merge_path", {}), ("coo_thread_mapped", {}), ("coo_group_mapped64", {"group_size": 64})):
+            sch = name[4:].replace("64", "")
+            wsz = torch.empty(max(1, lb.coo_workspace_size(coo4, sch, **p)), dtype=torch.uint8, device=dev)
+            t = timed(lambda: lb.spmv_coo(coo4, x4d, sch, y=y4, workspace=wsz, **p),
+                      3 if sch != "merge_path" else extra_steps, 1)
+            fm[name] = {"ms": round(t, 4), "gbs": round(Bcoo / (t * 1e-3) / 1e9, 2)}
+        del coo4
+        csc4 = lb.CSC.from_host(S.to_csc(C4), dev)
+        t = timed(lambda: lb.spmv_csc(csc4, x4d, "merge_path", y=y4), extra_steps, 1)
+        fm["csc_merge_path"] = {"ms": round(t, 4), "gbs": round(Bcsc / (t * 1e-3) / 1e9, 2)}
+        del csc4
+        result["formats_powerlaw1M"] = fm
+        log(f"[bench] formats: {fm}")
+        del C4d, x4d, dy4, y4, ws4
 
-    # ------------------------------------------------------------ SpGEMM
-    gm = {"note": "ms per whole C = A A (count, allocation, compute); products = sum over A entries of B row lengths"}
-    for name, A in (("laplacian1024_squared", S.laplacian_5pt(3, 1024)[0]),
-                    ("powerlaw100k_cap2000_squared", S.powerlaw_csr(80, 100_000, 100_000, 1.8, 2000, 0.1)[0])):
-        Ad = lb.CSR.from_host(A, dev)
-        prods = int(np.diff(A.row_offsets.astype(np.int64))[A.col_idx].sum())
-        C = lb.spgemm(Ad, Ad)
-        ms = []
-        for _ in range(5):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
+    if want("batched"):
+        # ------------------------------------------------------------ batched (512 matrices)
+        t0 = time.time()
+        BH = S.config_c5()
+        log(f"[bench] batched generated: {BH.count} matrices, nnz={BH.nnz} in {time.time() - t0:.1f}s")
+        Bd = lb.Batch.from_host(BH, dev)
+        bres = {"count": BH.count, "total_rows": BH.total_rows, "nnz": BH.nnz}
+        for k in (1, 8):
+            Xk = torch.from_numpy(S.random_vector(55, BH.total_cols * k).reshape(-1, k)).to(dev)
+            Yk = torch.empty((BH.total_rows, k), dtype=torch.float32, device=dev)
+            tuned = lb.tune_batched(Bd, k)
+            tk = timed(lambda: lb.batched_spmm(Bd, Xk, "auto", Y=Yk), extra_steps, 2)
+            Bk = BH.nnz * 8 + (BH.total_rows + 1) * 4 + BH.total_cols * 4 * k + BH.total_rows * 4 * k
+            bres[f"k{k}"] = {"ms": round(tk, 4), "gbs": round(Bk / (tk * 1e-3) / 1e9, 2),
+                             "gflops": round(2 * BH.nnz * k / (tk * 1e-3) / 1e9, 2), "schedule": tuned}
+            del Xk, Yk
+            log(f"[bench] batched k={k}: {bres[f'k{k}']}")
+        result["batched_512"] = bres
+        del Bd
+
+    if want("graph"):
+        result["graph_powerlaw1M"] = run_graph(lb, S, dev, args.no_cpu)
+
+    if want("spgemm"):
+        # ------------------------------------------------------------ SpGEMM
+        gm = {"note": "ms per whole C = A A (count, allocation, compute); products = sum over A entries of B row lengths"}
+        for name, A in (("laplacian1024_squared", S.laplacian_5pt(3, 1024)[0]),
+                        ("powerlaw100k_cap2000_squared", S.powerlaw_csr(80, 100_000, 100_000, 1.8, 2000, 0.1)[0])):
+            Ad = lb.CSR.from_host(A, dev)
+            prods = int(np.diff(A.row_offsets.astype(np.int64))[A.col_idx].sum())
             C = lb.spgemm(Ad, Ad)
-            torch.cuda.synchronize()
-            ms.append((time.perf_counter() - t0) * 1e3)
-        t = float(np.median(ms))
-        gm[name] = {"nnz_a": A.nnz, "products": prods, "nnz_c": C.nnz, "ms": round(t, 3),
-                    "gproducts_per_s": round(prods / (t * 1e-3) / 1e9, 3),
-                    "gflops": round(2 * prods / (t * 1e-3) / 1e9, 3)}
-        if not args.no_cpu:  # CPU baseline: the oracle, timed
-            import oracle
+            ms = []
+            for _ in range(5):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                C = lb.spgemm(Ad, Ad)
+                torch.cuda.synchronize()
+                ms.append((time.perf_counter() - t0) * 1e3)
+            t = float(np.median(ms))
+            gm[name] = {"nnz_a": A.nnz, "products": prods, "nnz_c": C.nnz, "ms": round(t, 3),
+                        "gproducts_per_s": round(prods / (t * 1e-3) / 1e9, 3),
+                        "gflops": round(2 * prods / (t * 1e-3) / 1e9, 3)}
+            if not args.no_cpu:  # CPU baseline: the oracle, timed
+                import oracle
 
-            t0 = time.perf_counter()
-            oracle.spgemm(A, A)
-            gm[name]["cpu_oracle_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
-        del Ad, C
-    result["spgemm"] = gm
-    log(f"[bench] spgemm: {gm}")
+                t0 = time.perf_counter()
+                oracle.spgemm(A, A)
+                gm[name]["cpu_oracle_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+            del Ad, C
+        result["spgemm"] = gm
+        log(f"[bench] spgemm: {gm}")
 
     print(json.dumps(result), flush=True)
     return 0

@@ -232,15 +232,16 @@ LB_API lb_status_t lb_spmv(const lb_csr_t *A, const void *x, lb_dtype_t x_dtype,
  *    left out: the split at every unit boundary is computed once, in the
  *    plan, and only the units holding short-row work are launched;
  *  - long rows run a panel schedule: x is cut into panels of panel_cols
- *    columns; a block stages one panel of x in LDS and consumes, for a
- *    chunk of long rows, each row's segment of nonzeros whose columns fall
- *    in the panel (contiguous in the row, as its columns are sorted).  The
- *    segments are cut into tasks of at most 512 nonzeros, which the block's
- *    wavefronts take from an LDS prefix sum of the segments' task counts
- *    (the group-mapped schedule with get_tile, Sec. 5.2.3).  So the x
- *    accesses of long rows hit LDS instead of the cache hierarchy.  Each
- *    task's sum is stored, and a long row's result is the sum of its
- *    tasks in (panel, task) order.
+ *    columns; each panel is served by panel_blocks blocks, each of which
+ *    stages the panel of x in LDS once and consumes an equal share of the
+ *    long rows' segments whose columns fall in the panel (a segment is
+ *    contiguous in its row, as the row's columns are sorted).  The segments
+ *    are cut into tasks of at most 252 nonzeros; a task spanning at most G
+ *    aligned groups of four nonzeros runs on a group of G lanes, G = 64, 32,
+ *    16 or 8 (the group-mapped schedule, Sec. 5.2.2, with the group size
+ *    matched to the tile), one 16-byte group per lane, so x is read from LDS
+ *    instead of the cache hierarchy.  Each task's sum is stored, and a long
+ *    row's result is the sum of its tasks in (panel, task) order.
  * No atomics: for a fixed plan the result is bit-reproducible run to run.
  *
  * The plan lives in a device buffer owned by the caller, read-only for the
@@ -249,7 +250,8 @@ LB_API lb_status_t lb_spmv(const lb_csr_t *A, const void *x, lb_dtype_t x_dtype,
  * memory.  Call it first with buffer == NULL: it fills the output fields
  * of *plan (plan_bytes is an upper bound then) and returns
  * LB_ERR_WORKSPACE_TOO_SMALL without touching the device beyond reading
- * row_offsets; then call it with a buffer of at least plan_bytes to build.
+ * row_offsets and a sample of col_idx; then call it with a buffer of at
+ * least plan_bytes to build.
  * Long rows must have strictly increasing columns (LB_ERR_INVALID_CSR
  * otherwise, checked by the build); short rows have no such requirement.
  *
@@ -257,16 +259,16 @@ LB_API lb_status_t lb_spmv(const lb_csr_t *A, const void *x, lb_dtype_t x_dtype,
  *  block_size, items_per_thread  the short rows' merge path, as for lb_spmv
  *                                (default 256 x 8); W = their product;
  *  x_bands       1 or 2, as for lb_spmv (default: 2 when x has at least
- *                4 MiB, else 1);
+ *                4 MiB and the columns are scattered -- the median column
+ *                span of up to 1024 sampled rows exceeds cols / 16 -- else 1);
  *  long_min      rows with at least this many nonzeros are long; at least
  *                W (a long row then never lies strictly inside one merge-path
  *                unit); default max(W, 16 * panels); -1 = no long rows;
  *  panel_cols    columns per panel, a multiple of 64 up to 16384 (float32
  *                x) or 32768 (BF16 x); default that maximum;
- *  chunk_atoms   long-row nonzeros per (chunk, panel) block on average (the
- *                plan groups consecutive long rows into chunks of about
- *                chunk_atoms * panels nonzeros, at most 512 rows); default
- *                16384;
+ *  panel_blocks  blocks per panel; default floor(4 * CUs / panels) for the
+ *                compute units of the device the plan is built on (two
+ *                rounds of two resident blocks per CU);
  *  streams       2: the long rows' launch runs on a second stream
  *                of the same device, owned by the library (one per device,
  *                created on first use, default priority), concurrently with
@@ -285,7 +287,7 @@ typedef struct lb_spmv_plan_t {
     int32_t x_bands;
     int32_t long_min;
     int32_t panel_cols;
-    int32_t chunk_atoms;
+    int32_t panel_blocks;
     int32_t streams;
     lb_dtype_t value_dtype;
     int64_t rows;
@@ -294,7 +296,6 @@ typedef struct lb_spmv_plan_t {
     int64_t long_nnz;    /* nonzeros in long rows */
     int32_t long_rows;   /* rows with at least long_min nonzeros */
     int32_t panels;      /* ceil(cols / panel_cols) */
-    int32_t chunks;      /* chunks of long rows (one block per chunk and panel) */
     int32_t tasks;       /* long-row tasks (one stored sum each) */
     int32_t units;       /* merge-path units of W items over the whole matrix */
     int32_t active_units;/* units holding short-row work */

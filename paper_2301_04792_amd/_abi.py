@@ -69,12 +69,12 @@ class CSC(ctypes.Structure):
 
 class SpmvPlan(ctypes.Structure):
     _fields_ = [("block_size", ctypes.c_int32), ("items_per_thread", ctypes.c_int32), ("x_bands", ctypes.c_int32),
-                ("long_min", ctypes.c_int32), ("panel_cols", ctypes.c_int32), ("chunk_atoms", ctypes.c_int32),
+                ("long_min", ctypes.c_int32), ("panel_cols", ctypes.c_int32), ("panel_blocks", ctypes.c_int32),
                 ("streams", ctypes.c_int32),
                 ("value_dtype", ctypes.c_int),
                 ("rows", ctypes.c_int64), ("cols", ctypes.c_int64), ("nnz", ctypes.c_int64),
                 ("long_nnz", ctypes.c_int64), ("long_rows", ctypes.c_int32), ("panels", ctypes.c_int32),
-                ("chunks", ctypes.c_int32), ("tasks", ctypes.c_int32), ("units", ctypes.c_int32),
+                ("tasks", ctypes.c_int32), ("units", ctypes.c_int32),
                 ("active_units", ctypes.c_int32), ("plan_bytes", ctypes.c_size_t),
                 ("workspace_bytes", ctypes.c_size_t), ("buffer", ctypes.c_void_p)]
 

@@ -7,22 +7,19 @@
 // schedule in which x is read from LDS:
 //
 //  * x is cut into panels of P columns.  With sorted columns, the nonzeros
-//    of long row q that fall in panel p are one contiguous segment
-//    [sb[q][p], sb[q][p+1]) of the row.
-//  * The long rows are grouped into chunks (consecutive long rows, about
-//    16K nonzeros per panel on average).  Block (chunk c, panel p) stages
-//    panel p of x in LDS and consumes the chunk's segments in panel p.
-//  * Each segment is cut into tasks of at most kPanelTask nonzeros (the
-//    plan's table tb holds each (row, panel) pair's first task, row-major,
-//    so a row's tasks are consecutive).  The block prefix-sums its segments'
-//    task counts in LDS; wavefront w takes tasks w, w + NW, ... and finds a
-//    task's segment by binary search in that prefix sum: the group-mapped
-//    schedule with get_tile (Sec. 5.2.3) over (row, panel) tiles whose
-//    atoms are tasks.  A task's lanes load its nonzeros coalesced, read x
-//    from LDS, and one wave sum (fixed order) is stored as the task's sum.
-//  * Blocks are dealt to the 8 XCDs round robin; panel p goes to XCD p mod 8
-//    (blocks of one chunk are consecutive), so an XCD's L2 only ever holds
-//    its eighth of x while it stages panels.
+//    of long row q that fall in panel p are one contiguous segment of the
+//    row.
+//  * R blocks serve each panel: a block stages its panel of x in LDS once
+//    and consumes an equal share of the panel's segments.
+//  * The plan cuts each segment into tasks of at most kPanelTask nonzeros
+//    and lists each panel's tasks by class: a task spanning at most G
+//    aligned groups of four nonzeros (G = 64, 32, 16 or 8) is served by a
+//    group of G lanes, one group of four per lane (the group-mapped
+//    schedule, Sec. 5.2.2, with the group size matched to the tile), so a
+//    wavefront step serves 64 / G tasks and a task's sum is a log2(G)-step
+//    reduction.  A lane loads its four nonzeros with one 16-byte column load
+//    and one value load, reads x from LDS, and the group's first lane stores
+//    the task's sum.
 //  * plan_finish adds, for every long row, its task sums in (panel, task)
 //    order, and completes the short rows cut by unit boundaries (the carries
 //    of the merge path and the second column band's sums).
@@ -37,49 +34,128 @@ using namespace lb;
 
 // ------------------------------------------------------------------ panel consume
 
-template <typename VT, typename XT>
-__global__ __launch_bounds__(kPanelBlock) void panel_spmv(int32_t NP, int32_t NC, int32_t P, int32_t cols,
-                                                          const int32_t *__restrict__ chunk_q,
-                                                          const int32_t *__restrict__ sb,
-                                                          const int32_t *__restrict__ tb,
+// The tasks [T0, T1) of class G: wavefront w serves tasks w * TPW + i * NW *
+// TPW + lane / G (TPW = 64 / G tasks per step; w rotated by `rot`, so the
+// wavefronts that get a last partial round differ from class to class),
+// kPanelBatch steps at a time with every load of them issued before the first
+// wait.
+// VEC = 4: lane l of a group loads the aligned group of four nonzeros
+// a0 / 4 + l; lanes past the task's last group reload it (no extra cache
+// lines).  Needs nnz >= 4 and col_idx / values aligned to their vectors; the
+// array's last nnz mod 4 nonzeros, outside every full group, are loaded one
+// by one by the task that holds them.  VEC = 1: lane l of a group loads
+// nonzeros l, l + G, l + 2G, l + 3G of the task.
+template <int G, int VEC, typename VT, typename XT>
+__device__ __forceinline__ void panel_class_tasks(int32_t T0, int32_t T1, int rot, const panel_task *__restrict__ tasks,
+                                                  int32_t nnz, int32_t col0, const int32_t *__restrict__ ci,
+                                                  const VT *__restrict__ val, const XT *xs, float *__restrict__ part) {
+    constexpr int NW = kPanelBlock / kWave;
+    constexpr int TPW = kWave / G;
+    constexpr int S = kPanelBatch;
+    const int lane = lane_id(), w = (wave_id() + rot) % NW;
+    const int gl = lane & (G - 1);
+    const int32_t last_full = (nnz >> 2) - 1;  // VEC 4: the last group of four inside the array
+    for (int32_t base = T0 + w * TPW + lane / G; base - lane / G < T1; base += NW * TPW * S) {
+        int32_t a0[S], len[S], out[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int32_t t = base + s * NW * TPW;
+            const panel_task d = tasks[t < T1 ? t : T0];  // a dead slot reads the first task and stores nothing
+            a0[s] = d.a0;
+            len[s] = t < T1 ? d.len : 0;
+            out[s] = d.out;
+        }
+        int32_t cc[S][4];
+        VT vv[S][4];
+        if constexpr (VEC == 4) {
+            using vec_t = typename vec4_of<VT>::type;
+            typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+            bool tail = false;  // some task reaches the nonzeros past the last full group
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int32_t glast = (a0[s] + (len[s] > 0 ? len[s] : 1) - 1) >> 2;
+                int32_t g = (a0[s] >> 2) + gl;
+                g = g < glast ? g : glast;
+                g = g < last_full ? g : last_full;
+                const i32x4 c4 = ld_stream(reinterpret_cast<const i32x4 *>(ci) + g);
+                const vec_t v4 = ld_stream(reinterpret_cast<const vec_t *>(val) + g);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    cc[s][e] = c4[e];
+                    vv[s][e] = v4[e];
+                }
+                tail = tail || (len[s] > 0 && glast > last_full);
+            }
+            if (__builtin_expect(__ballot(tail) != 0, 0)) {  // at most one task per launch
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    const int32_t g = (a0[s] >> 2) + gl;
+                    if (len[s] > 0 && g > last_full) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            const int32_t j = 4 * g + e < nnz ? 4 * g + e : nnz - 1;
+                            cc[s][e] = ci[j];
+                            vv[s][e] = val[j];
+                        }
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int32_t last = len[s] > 0 ? len[s] - 1 : 0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int32_t a = gl + u * G;
+                    const int32_t j = a0[s] + (a < last ? a : last);
+                    cc[s][u] = ld_stream(ci + j);
+                    vv[s][u] = ld_stream(val + j);
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            // the task-relative index of this lane's u-th nonzero
+            const int32_t a_base = VEC == 4 ? 4 * ((a0[s] >> 2) + gl) - a0[s] : gl;
+            float acc = 0.f;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int32_t a = a_base + (VEC == 4 ? u : u * G);
+                const bool live = a >= 0 && a < len[s];
+                const int32_t xi = live ? cc[s][u] - col0 : 0;
+                const float xv = to_f32(xs[xi]);
+                acc += live ? to_f32(vv[s][u]) * xv : 0.f;
+            }
+            acc = group_sum<G>(acc);
+            if (gl == 0 && len[s] > 0) part[out[s]] = acc;
+        }
+    }
+}
+
+// Block b serves panel p = b mod NP, share r = b / NP of R: the r-th of R
+// equal slices of each of the panel's class lists.
+template <typename VT, typename XT, int VEC>
+__global__ __launch_bounds__(kPanelBlock) void panel_spmv(int32_t NP, int32_t R, int32_t P, int32_t cols, int32_t nnz,
+                                                          const int32_t *__restrict__ pcls_off,
+                                                          const panel_task *__restrict__ tasks,
                                                           const int32_t *__restrict__ ci,
                                                           const VT *__restrict__ val, const XT *__restrict__ x,
                                                           float *__restrict__ part) {
     constexpr int PMAX = kPanelBytes / static_cast<int>(sizeof(XT));
-    constexpr int NW = kPanelBlock / kWave;
-    constexpr int U = kPanelTask / kWave;  // loads per lane and task
-    constexpr int S = kPanelBatch;         // tasks per wavefront and iteration
-    static_assert(kPanelRows == kPanelBlock, "one chunk row per thread in the setup");
-    static_assert(S <= kWave, "one search lane per task of a batch");
+    static_assert(kPanelClasses == 4 && kPanelTask <= 4 * kWave - 3, "a task spans at most 64 groups of 4");
     __shared__ XT xs[PMAX];
-    __shared__ int32_t s_scan[kPanelRows + 1];  // exclusive prefix of the rows' task counts
-    __shared__ int32_t s_beg[kPanelRows];       // segment of each chunk row in this panel
-    __shared__ int32_t s_end[kPanelRows];
-    __shared__ int32_t s_out[kPanelRows];       // first task (output slot) of each row in this panel
-    __shared__ int32_t s_wave[NW];
 
-    const int PG = (NP + kXcds - 1) / kXcds;  // panel groups: one panel per XCD each
-    const int xcd = static_cast<int>(blockIdx.x % kXcds);
-    const int sq = static_cast<int>(blockIdx.x / kXcds);
-    const int c = sq / PG;
-    const int p = kXcds * (sq % PG) + xcd;
-    if (c >= NC || p >= NP) return;  // uniform across the block, before any barrier
-    const int tid = threadIdx.x, lane = lane_id(), w = wave_id();
+    const int p = static_cast<int>(blockIdx.x % NP);
+    const int r = static_cast<int>(blockIdx.x / NP);  // < R: the grid is NP * R blocks
+    const int tid = threadIdx.x;
     const int32_t col0 = p * P;
     const int32_t ncol = P < cols - col0 ? P : cols - col0;
-
-    // The chunk's rows in this panel: segment, task count, first task.
-    const int32_t q0 = chunk_q[c];
-    const int32_t nq = chunk_q[c + 1] - q0;  // in [1, kPanelRows] (the plan's chunks)
-    const int64_t stride = static_cast<int64_t>(NP) + 1;
-    int32_t cnt = 0;
-    if (tid < nq) {
-        const int64_t e = (q0 + tid) * stride + p;
-        const int32_t b = sb[e], en = sb[e + 1], t0 = tb[e], t1 = tb[e + 1];
-        s_beg[tid] = b;
-        s_end[tid] = en;
-        s_out[tid] = t0;
-        cnt = t1 - t0;
+    const int32_t *off = pcls_off + static_cast<int64_t>(p) * kPanelClasses;  // classes 0..3 and the next panel's start
+    int32_t lo[kPanelClasses + 1];
+#pragma unroll
+    for (int k = 0; k < kPanelClasses; ++k) {
+        const int64_t n = off[k + 1] - off[k];
+        lo[k] = off[k] + static_cast<int32_t>(n * r / R);
     }
 
     // Stage the panel: 16-byte loads when the slice is 16-byte aligned, all
@@ -108,66 +184,12 @@ __global__ __launch_bounds__(kPanelBlock) void panel_spmv(int32_t NP, int32_t NC
         }
         for (int32_t i = done + tid; i < ncol; i += kPanelBlock) xs[i] = x[col0 + i];
     }
-    const int32_t inc = block_scan_incl<kPanelBlock>(cnt, s_wave);
-    if (tid < nq) s_scan[tid] = inc - cnt;
-    if (tid == kPanelBlock - 1) s_scan[nq] = inc;  // the last thread's inclusive sum is the total
     __syncthreads();
-    const int32_t NT = s_scan[nq];
-
-    // Wavefront w takes tasks w, w + NW, ...; S of them per iteration, with
-    // every load of the S tasks issued before the first wait.
-    for (int32_t base = w; base < NT; base += NW * S) {
-        // lane s < S finds the row of task base + s * NW (the last k < nq with
-        // s_scan[k] <= t: exact for a live task, as s_scan[nq] = NT > t, and
-        // in range for a dead one); the S searches run side by side
-        int32_t my_k = 0;
-        {
-            const int32_t t = base + (lane < S ? lane : 0) * NW;
-            int32_t lo = 0, hi = nq;
-            while (lo < hi) {
-                const int32_t mid = (lo + hi) >> 1;
-                if (s_scan[mid] <= t)
-                    lo = mid + 1;
-                else
-                    hi = mid;
-            }
-            my_k = lo - 1;
-        }
-        int32_t a0[S], len[S], out[S];
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int32_t t = base + s * NW;
-            const int32_t k = __shfl(my_k, s);
-            const int32_t sub = t - s_scan[k];
-            a0[s] = s_beg[k] + sub * kPanelTask;
-            const int32_t rest = s_end[k] - a0[s];
-            len[s] = t < NT ? (rest < kPanelTask ? rest : kPanelTask) : 0;  // >= 1 for a live task
-            out[s] = s_out[k] + sub;
-            if (t >= NT) a0[s] = a0[0];  // a dead slot reloads the first task's first nonzero
-        }
-        int32_t cc[S][U];
-        VT vv[S][U];
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int32_t last = len[s] > 0 ? len[s] - 1 : 0;
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int32_t a = lane + u * kWave;
-                const int32_t j = a0[s] + (a < last ? a : last);
-                cc[s][u] = ld_stream(ci + j);
-                vv[s][u] = ld_stream(val + j);
-            }
-        }
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            float acc = 0.f;
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (lane + u * kWave < len[s]) acc += to_f32(vv[s][u]) * to_f32(xs[cc[s][u] - col0]);
-            acc = group_sum<kWave>(acc);
-            if (lane == 0 && len[s] > 0) part[out[s]] = acc;
-        }
-    }
+    auto hi = [&](int k) { return off[k] + static_cast<int32_t>((static_cast<int64_t>(off[k + 1]) - off[k]) * (r + 1) / R); };
+    panel_class_tasks<64, VEC>(lo[0], hi(0), 0, tasks, nnz, col0, ci, val, xs, part);
+    panel_class_tasks<32, VEC>(lo[1], hi(1), 2, tasks, nnz, col0, ci, val, xs, part);
+    panel_class_tasks<16, VEC>(lo[2], hi(2), 4, tasks, nnz, col0, ci, val, xs, part);
+    panel_class_tasks<8, VEC>(lo[3], hi(3), 6, tasks, nnz, col0, ci, val, xs, part);
 }
 
 // ------------------------------------------------------------------ finish
@@ -188,15 +210,14 @@ __global__ __launch_bounds__(256) void plan_finish(int32_t NA, int32_t NL, const
                                                    const int32_t *__restrict__ ro, int32_t long_min,
                                                    const float *__restrict__ carry_val, float *__restrict__ y,
                                                    const float *__restrict__ y_hi, const int32_t *__restrict__ LR,
-                                                   const int32_t *__restrict__ tb, int32_t NP,
+                                                   const int32_t *__restrict__ row_task,
                                                    const float *__restrict__ part) {
     const int lane = lane_id();
     const int64_t item = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
     if (item >= static_cast<int64_t>(NA) + NL) return;  // uniform across the wavefront
     if (item >= NA) {
         const int64_t q = item - NA;
-        const int64_t stride = static_cast<int64_t>(NP) + 1;
-        const int32_t t0 = tb[q * stride], t1 = tb[q * stride + NP];
+        const int32_t t0 = row_task[q], t1 = row_task[q + 1];
         float s = 0.f;
         for (int32_t t = t0 + lane; t < t1; t += kWave) s += part[t];
         s = group_sum<kWave>(s);
@@ -227,6 +248,60 @@ __global__ __launch_bounds__(256) void plan_finish(int32_t NA, int32_t NL, const
     }
     if (BANDS == 2)
         for (int32_t r = r0 + kWave; r < i1; r += kWave) y[r] = y[r] + y_hi[r];
+}
+
+// One band: wavefronts [0, ceil(T / 64)) each take 64 consecutive carries
+// and add every run of equal carry rows that starts among them to its row
+// of y, as merge_fixup does (the carry of unit u belongs to row
+// part_i[u + 1]; runs of long rows, and the run of row `rows` that no row
+// owns, are skipped: their carries are not read as sums); the remaining
+// wavefronts sum the long rows' task sums.  One writer per row, fixed order.
+__global__ __launch_bounds__(256) void plan_finish_runs(int32_t T, int32_t rows, int32_t NL,
+                                                        const int32_t *__restrict__ part_i,
+                                                        const int32_t *__restrict__ ro, int32_t long_min,
+                                                        const float *__restrict__ carry_val, float *__restrict__ y,
+                                                        const int32_t *__restrict__ LR,
+                                                        const int32_t *__restrict__ row_task,
+                                                        const float *__restrict__ part) {
+    const int lane = lane_id();
+    const int64_t item = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+    const int64_t chunks = (static_cast<int64_t>(T) + kWave - 1) / kWave;
+    if (item >= chunks + NL) return;  // uniform across the wavefront
+    if (item >= chunks) {
+        const int64_t q = item - chunks;
+        const int32_t t0 = row_task[q], t1 = row_task[q + 1];
+        float s = 0.f;
+        for (int32_t t = t0 + lane; t < t1; t += kWave) s += part[t];
+        s = group_sum<kWave>(s);
+        if (lane == 0) y[LR[q]] = s;
+        return;
+    }
+    const int64_t base = item * kWave;
+    const int64_t b = base + lane;
+    const bool in = b < T;
+    const int32_t r = in ? part_i[b + 1] : -1;
+    const bool head = in && (b == 0 || part_i[b] != r);
+    const bool tail = in && (b + 1 == T || part_i[b + 2] != r);
+    const bool own = in && r < rows && ro[r + 1] - ro[r] < long_min;  // a short row: its carries are sums
+    // the last lane's run goes on into the next chunk
+    const bool open = __ballot(lane == kWave - 1 && in && !tail) != 0;
+    const int32_t r_open = __shfl(r, kWave - 1);
+    const bool own_open = __shfl(static_cast<int>(own), kWave - 1) != 0;
+    const seg_t sc = group_seg_scan_incl<kWave>(seg_t{own ? carry_val[b] : 0.f, head});
+    if (tail && sc.f && own) y[r] += sc.v;
+    if (open && own_open) {
+        const bool owned = __shfl(static_cast<int>(sc.f), kWave - 1) != 0;  // the run starts in this chunk
+        if (owned) {  // uniform
+            float total = __shfl(sc.v, kWave - 1);
+            for (int64_t s2 = base + kWave;; s2 += kWave) {
+                const int64_t q = s2 + lane;
+                const bool match = q < T && part_i[q + 1] == r_open;
+                total += group_sum<kWave>(match ? carry_val[q] : 0.f);
+                if (__popcll(__ballot(match)) < kWave) break;  // the run ends inside this chunk
+            }
+            if (lane == 0) y[r_open] += total;
+        }
+    }
 }
 
 // ------------------------------------------------------------------ plan building
@@ -328,19 +403,31 @@ static hipError_t side_for(hipStream_t s, side_stream **out) {
     return hipSuccess;
 }
 
+// Four nonzeros per lane and load need nnz >= 4 and col_idx / values aligned
+// to their vectors (16 bytes; BF16 values 8).
+static bool panel_vec4_ok(const csr_dev &A) {
+    const uintptr_t va = A.dt == LB_BF16 ? 8 : 16;
+    return A.nnz >= 4 && reinterpret_cast<uintptr_t>(A.ci) % 16 == 0 && reinterpret_cast<uintptr_t>(A.val) % va == 0;
+}
+
+template <typename T>
+static hipError_t launch_panel_t(const csr_dev &A, const plan_dev &pl, const void *x, float *part, hipStream_t s) {
+    const dim3 grid(static_cast<uint32_t>(static_cast<int64_t>(pl.NP) * pl.R));
+    const T *val = static_cast<const T *>(A.val);
+    const T *xx = static_cast<const T *>(x);
+    if (panel_vec4_ok(A))
+        hipLaunchKernelGGL((panel_spmv<T, T, 4>), grid, dim3(kPanelBlock), 0, s, pl.NP, pl.R, pl.P, A.cols, A.nnz,
+                           pl.pcls_off, pl.tasks, A.ci, val, xx, part);
+    else
+        hipLaunchKernelGGL((panel_spmv<T, T, 1>), grid, dim3(kPanelBlock), 0, s, pl.NP, pl.R, pl.P, A.cols, A.nnz,
+                           pl.pcls_off, pl.tasks, A.ci, val, xx, part);
+    return hipGetLastError();
+}
+
 static hipError_t launch_panel(const csr_dev &A, const plan_dev &pl, const void *x, float *part, hipStream_t s) {
     prof_scope pr(s, "panel_consume");
-    const int64_t PG = (pl.NP + kXcds - 1) / kXcds;
-    const int64_t grid = static_cast<int64_t>(kXcds) * PG * pl.NC;
-    if (A.dt == LB_BF16)
-        hipLaunchKernelGGL((panel_spmv<bf16_bits, bf16_bits>), dim3(static_cast<uint32_t>(grid)), dim3(kPanelBlock), 0,
-                           s, pl.NP, pl.NC, pl.P, A.cols, pl.chunk_q, pl.sb, pl.tb, A.ci,
-                           static_cast<const bf16_bits *>(A.val), static_cast<const bf16_bits *>(x), part);
-    else
-        hipLaunchKernelGGL((panel_spmv<float, float>), dim3(static_cast<uint32_t>(grid)), dim3(kPanelBlock), 0, s,
-                           pl.NP, pl.NC, pl.P, A.cols, pl.chunk_q, pl.sb, pl.tb, A.ci,
-                           static_cast<const float *>(A.val), static_cast<const float *>(x), part);
-    return hipGetLastError();
+    if (A.dt == LB_BF16) return launch_panel_t<bf16_bits>(A, pl, x, part, s);
+    return launch_panel_t<float>(A, pl, x, part, s);
 }
 
 hipError_t planned_spmv(const csr_dev &A, const plan_dev &pl, const void *x, float *y, void *ws, hipStream_t s) {
@@ -363,18 +450,19 @@ hipError_t planned_spmv(const csr_dev &A, const plan_dev &pl, const void *x, flo
         if (pl.NA > 0 && (e = merge_spmv_planned_consume(A, pl, x, y, w.carry_val, w.y_hi, s)) != hipSuccess)
             return e;
     }
+    prof_scope pr(s, "plan_finish");
+    if (pl.bands == 1) {
+        const int64_t items = (static_cast<int64_t>(pl.T) + kWave - 1) / kWave + pl.NL;
+        if (items == 0) return hipSuccess;
+        hipLaunchKernelGGL(plan_finish_runs, dim3(static_cast<uint32_t>((items + 3) / 4)), dim3(256), 0, s, pl.T,
+                           pl.rows, pl.NL, pl.part_i, A.ro, pl.long_min, w.carry_val, y, pl.LR, pl.row_task, w.part);
+        return hipGetLastError();
+    }
     const int64_t items = static_cast<int64_t>(pl.NA) + pl.NL;
     if (items == 0) return hipSuccess;
-    prof_scope pr(s, "plan_finish");
     const int64_t blocks = (items + 3) / 4;  // a wavefront per item
-    if (pl.bands == 2)
-        hipLaunchKernelGGL(plan_finish<2>, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, pl.NA, pl.NL,
-                           pl.active, pl.part_i, A.ro, pl.long_min, w.carry_val, y, w.y_hi, pl.LR, pl.tb, pl.NP,
-                           w.part);
-    else
-        hipLaunchKernelGGL(plan_finish<1>, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, pl.NA, pl.NL,
-                           pl.active, pl.part_i, A.ro, pl.long_min, w.carry_val, y, w.y_hi, pl.LR, pl.tb, pl.NP,
-                           w.part);
+    hipLaunchKernelGGL(plan_finish<2>, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, pl.NA, pl.NL, pl.active,
+                       pl.part_i, A.ro, pl.long_min, w.carry_val, y, w.y_hi, pl.LR, pl.row_task, w.part);
     return hipGetLastError();
 }
 

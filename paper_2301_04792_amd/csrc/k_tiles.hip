@@ -328,6 +328,19 @@ __global__ __launch_bounds__(256) void sample_kernel(const int32_t *__restrict__
     if (i < count) out[i] = n > 0 ? a[static_cast<int64_t>(i) * n / count] : 0;
 }
 
+__global__ __launch_bounds__(256) void gather_at_kernel(const int32_t *__restrict__ a, const int32_t *__restrict__ pos,
+                                                        int32_t count, int32_t *__restrict__ out) {
+    const int32_t i = static_cast<int32_t>(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < count) out[i] = a[pos[i]];
+}
+
+hipError_t gather_at(const int32_t *a, const int32_t *pos, int32_t count, int32_t *out, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_at_kernel, dim3(static_cast<uint32_t>((count + 255) / 256)), dim3(256), 0, s, a, pos,
+                       count, out);
+    return hipGetLastError();
+}
+
 hipError_t gather_samples(const int32_t *a, int64_t n, int32_t count, int32_t *out, hipStream_t s) {
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(sample_kernel, dim3(static_cast<uint32_t>((count + 255) / 256)), dim3(256), 0, s, a, n, count,

@@ -602,7 +602,6 @@ lb_status_t spmv_launch(const lb_csr_t *A, const void *x, float *y, const lb_sch
 
 // ------------------------------------------------------------------ planned SpMV
 
-constexpr int64_t kChunkAtomsPerPanel = 16384;  // long-row nonzeros per (chunk, panel) block, on average
 
 // Resolves the plan's inputs for A (defaults, checks) into *out; host only.
 lb_status_t plan_params(const lb_csr_t *A, const lb_spmv_plan_t *in, lb_spmv_plan_t *out) {
@@ -613,12 +612,13 @@ lb_status_t plan_params(const lb_csr_t *A, const lb_spmv_plan_t *in, lb_spmv_pla
     if (!lbk::merge_config_supported(p.block_size, p.items_per_thread)) return LB_ERR_UNSUPPORTED;
     const int64_t W = static_cast<int64_t>(p.block_size) * p.items_per_thread;
     const int64_t sx = A->value_dtype == LB_BF16 ? 2 : 4;
-    p.x_bands = in->x_bands ? in->x_bands : (A->cols * sx >= (int64_t(4) << 20) ? 2 : 1);
-    if (p.x_bands != 1 && p.x_bands != 2) return LB_ERR_INVALID_ARG;
+    p.x_bands = in->x_bands;  // 0: decided by the build (size of x, locality of the columns)
+    if (p.x_bands != 0 && p.x_bands != 1 && p.x_bands != 2) return LB_ERR_INVALID_ARG;
+    (void)sx;
     p.panel_cols = in->panel_cols ? in->panel_cols : static_cast<int32_t>(lbk::kPanelBytes / sx);
     p.streams = in->streams ? in->streams : 1;
-    p.chunk_atoms = in->chunk_atoms ? in->chunk_atoms : static_cast<int32_t>(kChunkAtomsPerPanel);
-    if (p.chunk_atoms < lbk::kPanelTask) return LB_ERR_INVALID_ARG;
+    p.panel_blocks = in->panel_blocks;  // 0: resolved by the build from the device's CUs
+    if (p.panel_blocks < 0) return LB_ERR_INVALID_ARG;
     if (p.streams != 1 && p.streams != 2) return LB_ERR_INVALID_ARG;
     if (!lbk::panel_cols_ok(p.panel_cols, A->value_dtype)) return LB_ERR_INVALID_ARG;
     const int64_t NP = (A->cols + p.panel_cols - 1) / p.panel_cols;
@@ -647,7 +647,7 @@ lbk::plan_dev plan_dev_of(const lb_spmv_plan_t &p) {
     d.NA = p.active_units;
     d.NL = p.long_rows;
     d.NP = p.panels;
-    d.NC = p.chunks;
+    d.R = p.panel_blocks;
     d.P = p.panel_cols;
     d.long_min = p.long_min;
     d.bands = p.x_bands;
@@ -655,15 +655,15 @@ lbk::plan_dev plan_dev_of(const lb_spmv_plan_t &p) {
     d.block = p.block_size;
     d.items = p.items_per_thread;
     d.ntasks = p.tasks;
-    const lbk::plan_layout L = lbk::plan_layout_of(p.units, p.units, p.long_rows, p.panels, p.chunks);
+    const lbk::plan_layout L = lbk::plan_layout_of(p.units, p.units, p.long_rows, p.panels, p.tasks);
     const char *b = static_cast<const char *>(p.buffer);
     d.part_i = reinterpret_cast<const int32_t *>(b + L.part_i);
     d.part_j = reinterpret_cast<const int32_t *>(b + L.part_j);
     d.active = reinterpret_cast<const int32_t *>(b + L.active);
     d.LR = reinterpret_cast<const int32_t *>(b + L.LR);
-    d.chunk_q = reinterpret_cast<const int32_t *>(b + L.chunk_q);
-    d.sb = reinterpret_cast<const int32_t *>(b + L.sb);
-    d.tb = reinterpret_cast<const int32_t *>(b + L.tb);
+    d.row_task = reinterpret_cast<const int32_t *>(b + L.row_task);
+    d.pcls_off = reinterpret_cast<const int32_t *>(b + L.pcls_off);
+    d.tasks = reinterpret_cast<const lbk::panel_task *>(b + L.tasks);
     return d;
 }
 
@@ -756,6 +756,25 @@ lb_status_t fingerprint(int64_t rows, int64_t cols, int64_t nnz, const int32_t *
     return LB_OK;
 }
 
+// out[i] = a[pos[i]] for a few thousand positions (at most
+// kFingerprintSamples), through the fingerprint sample buffer; synchronizes hs.
+lb_status_t device_gather(const int32_t *a, const std::vector<int32_t> &pos, std::vector<int32_t> &out,
+                          hipStream_t hs) {
+    const int32_t n = static_cast<int32_t>(std::min<size_t>(pos.size(), kFingerprintSamples / 2));
+    if (n == 0) return LB_OK;
+    std::lock_guard<std::mutex> g(g_fp_mu);
+    int32_t *d = nullptr;
+    hipError_t e = hipGetSymbolAddress(reinterpret_cast<void **>(&d), HIP_SYMBOL(g_fp_samples));
+    // the positions go in the buffer's upper half, the values in its lower half
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d + kFingerprintSamples / 2, pos.data(), static_cast<size_t>(n) * 4, hipMemcpyHostToDevice,
+                           hs);
+    if (e == hipSuccess) e = lbk::gather_at(a, d + kFingerprintSamples / 2, n, d, hs);
+    if (e == hipSuccess) e = hipMemcpyAsync(out.data(), d, static_cast<size_t>(n) * 4, hipMemcpyDeviceToHost, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    return hip_status(e);
+}
+
 }  // namespace
 
 // ================================================================== C ABI
@@ -842,38 +861,67 @@ LB_API lb_status_t lb_spmv_plan_build(const lb_csr_t *A, lb_spmv_plan_t *plan, v
     if (st != LB_OK) return st;
     hipStream_t hs = static_cast<hipStream_t>(stream);
     const int64_t rows = A->rows, NP = p.panels;
-    // row lengths on the host: the long rows, their chunks and a bound on the tasks
+    // row lengths on the host: the long rows and a bound on the tasks
     std::vector<int32_t> ro(static_cast<size_t>(rows) + 1, 0);
     if (rows > 0) {
         hipError_t e = hipMemcpyAsync(ro.data(), A->row_offsets, ro.size() * 4, hipMemcpyDeviceToHost, hs);
         if (e == hipSuccess) e = hipStreamSynchronize(hs);
         if (e != hipSuccess) return hip_status(e);
     }
-    std::vector<int32_t> LR, chunk_q{0};
-    int64_t long_nnz = 0, task_bound = 0, acc = 0;
-    const int64_t target = static_cast<int64_t>(p.chunk_atoms) * std::max<int64_t>(NP, 1);
+    if (p.x_bands == 0) {
+        // Two column bands pay when x is larger than an XCD's L2 (4 MiB) and
+        // the columns are scattered.  Scattered: the median column span
+        // (last - first) of up to 1024 sampled rows with two or more
+        // nonzeros exceeds cols / 16 (a stencil's rows span a few grid rows).
+        const int64_t sx = A->value_dtype == LB_BF16 ? 2 : 4;
+        p.x_bands = 1;
+        if (A->cols * sx >= (int64_t(4) << 20)) {
+            std::vector<int32_t> pos;
+            const int64_t step = std::max<int64_t>(1, rows / 1024);
+            for (int64_t r = 0; r < rows && pos.size() < 2048; r += step)
+                if (ro[r + 1] - ro[r] >= 2) {
+                    pos.push_back(ro[r]);
+                    pos.push_back(ro[r + 1] - 1);
+                }
+            std::vector<int32_t> cols(pos.size());
+            lb_status_t sst = device_gather(A->col_idx, pos, cols, hs);
+            if (sst != LB_OK) return sst;
+            std::vector<int64_t> span;
+            for (size_t i = 0; i + 1 < cols.size(); i += 2) span.push_back(static_cast<int64_t>(cols[i + 1]) - cols[i]);
+            if (!span.empty()) {
+                std::nth_element(span.begin(), span.begin() + span.size() / 2, span.end());
+                if (span[span.size() / 2] > A->cols / 16) p.x_bands = 2;
+            }
+        }
+    }
+    std::vector<int32_t> LR;
+    int64_t long_nnz = 0, task_bound = 0;
     for (int64_t r = 0; r < rows; ++r) {
         const int64_t len = static_cast<int64_t>(ro[r + 1]) - ro[r];
         if (len < p.long_min) continue;
-        if (acc >= target || static_cast<int64_t>(LR.size()) - chunk_q.back() >= lbk::kPanelRows) {
-            chunk_q.push_back(static_cast<int32_t>(LR.size()));
-            acc = 0;
-        }
         LR.push_back(static_cast<int32_t>(r));
         long_nnz += len;
-        acc += len;
         task_bound += (len + lbk::kPanelTask - 1) / lbk::kPanelTask + NP;
     }
-    if (!LR.empty()) chunk_q.push_back(static_cast<int32_t>(LR.size()));
     if (task_bound > kMaxCoord) return LB_ERR_OVERFLOW;
     p.long_rows = static_cast<int32_t>(LR.size());
     p.long_nnz = long_nnz;
-    p.chunks = static_cast<int32_t>(chunk_q.size()) - 1;
+    if (p.panel_blocks == 0) {
+        // two rounds of two resident blocks per CU, rounded down to whole
+        // panels: a last round that only a few blocks run would idle the rest
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 256;
+        (void)hipGetLastError();
+        p.panel_blocks = static_cast<int32_t>(std::max<int64_t>(1, 4 * static_cast<int64_t>(cus) / std::max<int64_t>(NP, 1)));
+    }
+    if (static_cast<int64_t>(p.panel_blocks) * NP >= kMaxCoord) return LB_ERR_OVERFLOW;
     const int64_t T = p.units;
-    const lbk::plan_layout L = lbk::plan_layout_of(T, T, p.long_rows, NP, p.chunks);
+    p.tasks = static_cast<int32_t>(task_bound);  // a bound until the build
+    p.active_units = static_cast<int32_t>(T);    // a bound until the build
+    const lbk::plan_layout L = lbk::plan_layout_of(T, T, p.long_rows, NP, task_bound);
     p.plan_bytes = L.total;
-    p.active_units = static_cast<int32_t>(T);  // bounds until the build
-    p.tasks = static_cast<int32_t>(task_bound);
     p.workspace_bytes = lbk::plan_ws_bytes(T, p.x_bands, rows, task_bound);
     p.buffer = nullptr;
     if (!buffer || buffer_bytes < p.plan_bytes) {
@@ -885,9 +933,7 @@ LB_API lb_status_t lb_spmv_plan_build(const lb_csr_t *A, lb_spmv_plan_t *plan, v
     int32_t *part_i = reinterpret_cast<int32_t *>(b + L.part_i);
     int32_t *part_j = reinterpret_cast<int32_t *>(b + L.part_j);
     int32_t *d_LR = reinterpret_cast<int32_t *>(b + L.LR);
-    int32_t *d_chunk = reinterpret_cast<int32_t *>(b + L.chunk_q);
     int32_t *sb = reinterpret_cast<int32_t *>(b + L.sb);
-    int32_t *tb = reinterpret_cast<int32_t *>(b + L.tb);
     int32_t *active = reinterpret_cast<int32_t *>(b + L.active);
     const int64_t nsb = static_cast<int64_t>(p.long_rows) * (NP + 1);
     std::vector<int32_t> h_sb(static_cast<size_t>(nsb)), h_part(static_cast<size_t>(T + 1));
@@ -897,8 +943,6 @@ LB_API lb_status_t lb_spmv_plan_build(const lb_csr_t *A, lb_spmv_plan_t *plan, v
         e = lbk::merge_partition(A->row_offsets, static_cast<int32_t>(rows), static_cast<int32_t>(A->nnz),
                                  p.block_size * p.items_per_thread, static_cast<int32_t>(T), part_i, part_j, hs);
     if (e == hipSuccess && !LR.empty()) e = hipMemcpyAsync(d_LR, LR.data(), LR.size() * 4, hipMemcpyHostToDevice, hs);
-    if (e == hipSuccess && !LR.empty())
-        e = hipMemcpyAsync(d_chunk, chunk_q.data(), chunk_q.size() * 4, hipMemcpyHostToDevice, hs);
     if (e == hipSuccess && nsb > 0)
         e = lbk::plan_segments_launch(p.long_rows, static_cast<int32_t>(NP), p.panel_cols, d_LR, A->row_offsets,
                                       A->col_idx, sb, flags, hs);
@@ -909,17 +953,46 @@ LB_API lb_status_t lb_spmv_plan_build(const lb_csr_t *A, lb_spmv_plan_t *plan, v
     if (e == hipSuccess) e = hipStreamSynchronize(hs);
     if (e != hipSuccess) return hip_status(e);
     if (h_flags & 1) return LB_ERR_INVALID_CSR;
-    // task table: row-major exclusive prefix of ceil(segment / kPanelTask)
-    std::vector<int32_t> h_tb(static_cast<size_t>(nsb));
-    int64_t ntasks = 0;
+    // Tasks: each (row, panel) segment cut into pieces of at most kPanelTask
+    // nonzeros; a piece's sum goes to slot row_task[q] + (pieces of row q in
+    // earlier panels) + its index, so a row's sums are consecutive.  Each
+    // panel lists its pieces by class (the aligned groups of four they span),
+    // in row order inside a class.
+    std::vector<int32_t> row_task(static_cast<size_t>(p.long_rows) + 1, 0);
+    std::vector<int32_t> slot(static_cast<size_t>(nsb));  // first slot of (row q, panel p)
     for (int64_t q = 0; q < p.long_rows; ++q) {
         const int32_t *sq = h_sb.data() + q * (NP + 1);
-        int32_t *tq = h_tb.data() + q * (NP + 1);
-        for (int64_t pp = 0; pp < NP; ++pp) {
-            tq[pp] = static_cast<int32_t>(ntasks);
-            ntasks += (static_cast<int64_t>(sq[pp + 1]) - sq[pp] + lbk::kPanelTask - 1) / lbk::kPanelTask;
+        int64_t o = row_task[q];
+        for (int64_t pp = 0; pp <= NP; ++pp) {
+            slot[q * (NP + 1) + pp] = static_cast<int32_t>(o);
+            if (pp < NP) o += (static_cast<int64_t>(sq[pp + 1]) - sq[pp] + lbk::kPanelTask - 1) / lbk::kPanelTask;
         }
-        tq[NP] = static_cast<int32_t>(ntasks);
+        row_task[q + 1] = static_cast<int32_t>(o);
+    }
+    const int64_t ntasks = p.long_rows > 0 ? row_task.back() : 0;
+    std::vector<int32_t> pcls_off(static_cast<size_t>(NP) * lbk::kPanelClasses + 1, 0);
+    std::vector<lbk::panel_task> tasks;
+    tasks.reserve(static_cast<size_t>(ntasks));
+    {
+        std::vector<lbk::panel_task> cls[lbk::kPanelClasses];
+        for (int64_t pp = 0; pp < NP; ++pp) {
+            for (auto &v : cls) v.clear();
+            for (int64_t q = 0; q < p.long_rows; ++q) {
+                const int64_t e2 = q * (NP + 1) + pp;
+                const int32_t sbeg = h_sb[e2], send = h_sb[e2 + 1];
+                int32_t out = slot[e2];
+                for (int32_t a0 = sbeg; a0 < send; a0 += lbk::kPanelTask, ++out) {
+                    const int32_t len = std::min<int32_t>(lbk::kPanelTask, send - a0);
+                    const int64_t ng = ((static_cast<int64_t>(a0) + len - 1) >> 2) - (a0 >> 2) + 1;
+                    cls[lbk::panel_class(ng)].push_back(lbk::panel_task{a0, len, out, 0});
+                }
+            }
+            for (int k = 0; k < lbk::kPanelClasses; ++k) {
+                pcls_off[pp * lbk::kPanelClasses + k] = static_cast<int32_t>(tasks.size());
+                tasks.insert(tasks.end(), cls[k].begin(), cls[k].end());
+            }
+        }
+        pcls_off.back() = static_cast<int32_t>(tasks.size());
     }
     // units with short-row work: a row strictly inside closes in it, or its
     // first closing row or its open row is short
@@ -932,9 +1005,13 @@ LB_API lb_status_t lb_spmv_plan_build(const lb_csr_t *A, lb_spmv_plan_t *plan, v
             h_active.push_back(static_cast<int32_t>(u));
     }
     e = hipSuccess;
-    if (nsb > 0) e = hipMemcpyAsync(tb, h_tb.data(), h_tb.size() * 4, hipMemcpyHostToDevice, hs);
-    if (e == hipSuccess && !h_active.empty())
-        e = hipMemcpyAsync(active, h_active.data(), h_active.size() * 4, hipMemcpyHostToDevice, hs);
+    auto up = [&](size_t off, const void *src, size_t bytes) {
+        if (e == hipSuccess && bytes > 0) e = hipMemcpyAsync(b + off, src, bytes, hipMemcpyHostToDevice, hs);
+    };
+    up(L.row_task, row_task.data(), row_task.size() * 4);
+    up(L.pcls_off, pcls_off.data(), pcls_off.size() * 4);
+    up(L.tasks, tasks.data(), tasks.size() * sizeof(lbk::panel_task));
+    up(L.active, h_active.data(), h_active.size() * 4);
     if (e == hipSuccess) e = hipStreamSynchronize(hs);
     if (e != hipSuccess) return hip_status(e);
     p.active_units = static_cast<int32_t>(h_active.size());
@@ -942,6 +1019,7 @@ LB_API lb_status_t lb_spmv_plan_build(const lb_csr_t *A, lb_spmv_plan_t *plan, v
     p.workspace_bytes = lbk::plan_ws_bytes(T, p.x_bands, rows, ntasks);
     p.buffer = buffer;
     *plan = p;
+    (void)active;
     return LB_OK;
 }
 

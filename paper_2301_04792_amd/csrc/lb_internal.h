@@ -102,21 +102,31 @@ hipError_t merge_spmv(const csr_dev &A, const void *x, float *y, int block, int 
                       hipStream_t s, const int32_t *vperm = nullptr, int vec = 1);
 
 // ---- planned SpMV (k_plan.hip) ----------------------------------------------------------
-// Long rows: a block of kPanelBlock threads per (chunk, panel) stages
-// kPanelBytes of x in LDS; a chunk holds at most kPanelRows long rows; a
-// task is at most kPanelTask nonzeros of one (row, panel) segment; a
-// wavefront works on kPanelBatch tasks at a time.
+// Long rows: a block of kPanelBlock threads stages kPanelBytes of x (one
+// panel) in LDS, R blocks per panel; a task is at most kPanelTask nonzeros
+// of one (row, panel) segment (252: any such range lies in 64 aligned groups
+// of four); a task of at most G groups runs on G lanes (G = 64, 32, 16, 8:
+// its class), one group per lane; a wavefront works on kPanelBatch steps of
+// 64 / G tasks at a time.
 constexpr int kPanelBlock = 512;
-constexpr int kPanelTask = 256;
-constexpr int kPanelBatch = 8;
-constexpr int kPanelRows = 512;
+constexpr int kPanelTask = 252;
+constexpr int kPanelBatch = 4;
 constexpr int kPanelBytes = 65536;
+constexpr int kPanelClasses = 4;
+// The class of a task spanning ng aligned groups: G = 64 >> class.
+inline int panel_class(int64_t ng) { return ng > 32 ? 0 : (ng > 16 ? 1 : (ng > 8 ? 2 : 3)); }
+
+// A task: nonzeros [a0, a0 + len) of one segment; its sum goes to part[out].
+struct alignas(16) panel_task {
+    int32_t a0, len, out, pad;
+};
 
 // The plan as the kernels see it (device pointers into the plan buffer).
 struct plan_dev {
     int32_t rows;
     int32_t T, NA;       // merge-path units, active units
-    int32_t NL, NP, NC;  // long rows, panels, chunks
+    int32_t NL, NP;      // long rows, panels
+    int32_t R;           // blocks per panel
     int32_t P;           // columns per panel
     int32_t long_min;
     int32_t bands, block, items;
@@ -125,35 +135,35 @@ struct plan_dev {
     const int32_t *part_i, *part_j;  // the split at every unit boundary, T + 1 each
     const int32_t *active;           // NA unit ids, ascending
     const int32_t *LR;               // NL long row ids, ascending
-    const int32_t *chunk_q;          // NC + 1: chunk c = long rows [chunk_q[c], chunk_q[c+1])
-    const int32_t *sb;               // NL x (NP + 1): segment bounds (nonzero positions)
-    const int32_t *tb;               // NL x (NP + 1): first task of each (row, panel), row-major
+    const int32_t *row_task;         // NL + 1: long row q's task sums are part[row_task[q] .. row_task[q + 1])
+    const int32_t *pcls_off;         // NP * 4 + 1: panel p's class-k tasks are [pcls_off[4p + k], pcls_off[4p + k + 1])
+    const panel_task *tasks;         // ntasks, grouped by panel, then class
 };
 
 // Plan buffer: a 256-byte header (build flags), then the tables above, each
-// 256-byte aligned; NA_cap entries are reserved for the active list.
+// 256-byte aligned; NA_cap entries are reserved for the active list and
+// ntask_cap for the tasks (the last table); sb (NL x (NP + 1) segment bounds)
+// is written by the build on the device and read back.
 struct plan_layout {
-    size_t flags, part_i, part_j, active, LR, chunk_q, sb, tb, total;
+    size_t flags, part_i, part_j, active, LR, row_task, pcls_off, tasks, sb, total;
 };
-inline plan_layout plan_layout_of(int64_t T, int64_t NA_cap, int64_t NL, int64_t NP, int64_t NC) {
+inline plan_layout plan_layout_of(int64_t T, int64_t NA_cap, int64_t NL, int64_t NP, int64_t ntask_cap) {
     plan_layout L{};
     size_t o = 0;
-    L.flags = o;
-    o += 256;
-    L.part_i = o;
-    o += align256(static_cast<size_t>(T + 1) * 4);
-    L.part_j = o;
-    o += align256(static_cast<size_t>(T + 1) * 4);
-    L.active = o;
-    o += align256(static_cast<size_t>(NA_cap) * 4);
-    L.LR = o;
-    o += align256(static_cast<size_t>(NL) * 4);
-    L.chunk_q = o;
-    o += align256(static_cast<size_t>(NC + 1) * 4);
-    L.sb = o;
-    o += align256(static_cast<size_t>(NL) * (NP + 1) * 4);
-    L.tb = o;
-    o += align256(static_cast<size_t>(NL) * (NP + 1) * 4);
+    auto take = [&o](size_t bytes) {
+        const size_t at = o;
+        o += align256(bytes);
+        return at;
+    };
+    L.flags = take(4);
+    L.part_i = take(static_cast<size_t>(T + 1) * 4);
+    L.part_j = take(static_cast<size_t>(T + 1) * 4);
+    L.active = take(static_cast<size_t>(NA_cap) * 4);
+    L.LR = take(static_cast<size_t>(NL) * 4);
+    L.row_task = take(static_cast<size_t>(NL + 1) * 4);
+    L.pcls_off = take(static_cast<size_t>(NP * kPanelClasses + 1) * 4);
+    L.sb = take(static_cast<size_t>(NL) * (NP + 1) * 4);
+    L.tasks = take(static_cast<size_t>(ntask_cap) * sizeof(panel_task));  // last: no other offset depends on it
     L.total = o;
     return L;
 }
@@ -351,6 +361,8 @@ hipError_t probe_gather(const int32_t *idx, int64_t n, const float *x, int32_t c
 hipError_t fill_f32(float *p, int64_t n, float v, hipStream_t s);
 // out[i] = a[i * n / count] for i < count (0 when n == 0).
 hipError_t gather_samples(const int32_t *a, int64_t n, int32_t count, int32_t *out, hipStream_t s);
+// out[i] = a[pos[i]] for i < count (device arrays).
+hipError_t gather_at(const int32_t *a, const int32_t *pos, int32_t count, int32_t *out, hipStream_t s);
 // Writes violation flags (bit 0: offsets, bit 1: columns) into *flags_dev.
 hipError_t validate_csr(const csr_dev &A, int32_t *flags_dev, hipStream_t s);
 

@@ -2,7 +2,7 @@
 the C ABI) with the FP64 oracle: short rows on the merge path with the long
 rows left out, long rows on LDS panels of x.  Plans are built with small
 units, long-row thresholds and panels so that modest matrices have many long
-rows, several chunks and many panels."""
+rows and many panels."""
 import ctypes
 
 import numpy as np
@@ -62,7 +62,7 @@ def matrices():
     out["all_long"] = SC._from_lengths(34, [5000] * 40, 20_000)
     out["one_long"] = SC._from_lengths(35, [60_000], 70_000)
     out["long_first_last"] = SC._from_lengths(36, [12_000] + [2] * 3000 + [12_000], 15_000)
-    out["many_long_rows"] = SC._from_lengths(37, [600] * 2500 + [1] * 100, 9000)  # > 1024 long rows per chunk
+    out["many_long_rows"] = SC._from_lengths(37, [600] * 2500 + [1] * 100, 9000)  # many short segments per block
     return out
 
 
@@ -190,10 +190,11 @@ def test_planned_rejects_other_shapes_and_small_workspace():
         assert st == _abi.ERR_WORKSPACE_TOO_SMALL
 
 
-def test_planned_second_stream_and_chunk_sizes():
-    """The long rows' launch on the library's second stream, and other chunk
-    sizes, give the same bits as one stream with the default chunks (same
-    tasks, same order), ordered on the caller's stream."""
+def test_planned_second_stream_and_block_counts():
+    """The long rows' launch on the library's second stream, and other
+    numbers of blocks per panel, give the same bits as one stream with the
+    default (the same tasks and sums, whichever block computes them), ordered
+    on the caller's stream."""
     A, x = S.powerlaw_csr(46, 120_000, 120_000, 1.6, 60_000, 0.1)
     Ad, xd = upload(A, x)
     base = lb.Plan(Ad, block_size=128, items_per_thread=8, long_min=1024, panel_cols=512)
@@ -204,8 +205,36 @@ def test_planned_second_stream_and_chunk_sizes():
         y.fill_(float("nan"))
         lb.spmv_planned(Ad, two, xd, y=y)
         assert torch.equal(y, y1)
-    for ca in (512, 4096, 1 << 20):
-        pl = lb.Plan(Ad, block_size=128, items_per_thread=8, long_min=1024, panel_cols=512, chunk_atoms=ca)
-        assert torch.equal(lb.spmv_planned(Ad, pl, xd), y1), ca
+    for pb in (1, 3, 1000):
+        pl = lb.Plan(Ad, block_size=128, items_per_thread=8, long_min=1024, panel_cols=512, panel_blocks=pb)
+        assert pl.c.panel_blocks == pb
+        assert torch.equal(lb.spmv_planned(Ad, pl, xd), y1), pb
     ref, scale = oracle_spmv(A, x)
     assert_rows_close(y1.cpu().numpy(), ref, scale, what="second stream")
+
+
+@pytest.mark.parametrize("extra", [0, 1, 2, 3])
+def test_planned_array_tail_and_misaligned(extra):
+    """A long last row ending at nnz = 4k + extra: the nonzeros past the last
+    full group of four are loaded one by one; and the same matrix in arrays
+    that start 4 bytes past a 16-byte boundary (the one-nonzero load form).
+    Integer inputs: every result bit-exact."""
+    lens = [5, 0, 3000, 7, 2] + [4000 + extra - (3014 % 4)]
+    A, x = SC._from_lengths(47 + extra, lens, 9000)
+    assert A.nnz % 4 == extra
+    A, x = S.integer_valued(A, 6)
+    ref, _ = oracle_spmv(A, x)
+    Ad, xd = upload(A, x)
+    plan = lb.Plan(Ad, block_size=128, items_per_thread=4, long_min=512, panel_cols=1024)
+    assert plan.c.long_rows == 2
+    got = lb.spmv_planned(Ad, plan, xd).cpu().numpy().astype(np.float64)
+    assert np.array_equal(got, ref)
+    # misaligned copies of col_idx and values (offset by one element inside a larger buffer)
+    ci = torch.zeros(A.nnz + 1, dtype=torch.int32, device=DEV)
+    vals = torch.zeros(A.nnz + 1, dtype=torch.float32, device=DEV)
+    ci[1:] = Ad.col_idx
+    vals[1:] = Ad.values
+    Am = lb.CSR(Ad.row_offsets, ci[1:], vals[1:], A.shape)
+    assert Am.col_idx.data_ptr() % 16 != 0
+    got2 = lb.spmv_planned(Am, plan, xd).cpu().numpy().astype(np.float64)
+    assert np.array_equal(got2, ref)
