@@ -9,9 +9,13 @@ path (256 threads x 8 items, two column bands over the XCDs, the split
 precomputed) and the long rows on LDS panels of x, then one finishing pass.
 `value` is effective HBM GB/s over algorithmic bytes
 B = nnz*(s_v + 4) + (m + 1)*4 + n*s_x + m*4 of the median of the K timed
-steps, each run cold: a 1 GiB write before it (outside its events) evicts
-L2 and the Infinity Cache, the inputs stay in HBM.  The warm figure (K
-back-to-back steps) and the unplanned merge path are reported beside it.
+steps, each run cold: a read of a 1 GiB buffer before it (outside its
+events) evicts L2 and the Infinity Cache, the inputs stay in HBM.  The
+buffer is written once beforehand, so the lines the eviction leaves behind
+are clean: a write right before each step would also charge the step with
+writing back up to 256 MB of the buffer's dirty lines (reported beside it
+as `cold_write_flush_ms`).  The warm figure (K back-to-back steps) and the
+unplanned merge path are reported beside it too.
 
 The same JSON line carries the roofline of the dominant kernel (timed by the
 library's HIP events on the launch stream) with every kernel of the call,
@@ -39,7 +43,7 @@ PEAK_GBS = 8000.0
 SECTIONS = {"schedules", "uniform", "bf16", "fwdbwd", "formats", "batched", "graph", "spgemm"}
 METRIC = "SpMV effective HBM GB/s (% of peak) per schedule; fwd+bwd and batched GB/s"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "planned_spmv_powerlaw2M_traffic.json")
-kPanelBytes = 65536  # LDS bytes of x per panel block (the library's default panel: 16384 FP32 columns)
+kPanelBytes = 163840  # LDS bytes of x per panel block (the library's default panel: 40960 FP32 columns)
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2301_04792_amd", "csrc", f)
                   for f in ("k_merge.hip", "k_plan.hip", "lb_device.h", "lb_internal.h")]
 
@@ -368,7 +372,14 @@ def main():
         print(json.dumps({"graph_powerlaw1M": run_graph(lb, S, dev, args.no_cpu)}), flush=True)
         return 0
     stream = torch.cuda.current_stream(dev)
-    flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB, larger than L2 + MALL
+    flush = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB, larger than L2 + MALL
+    sink = torch.empty((), dtype=torch.float32, device=dev)
+
+    def evict():
+        """Evict L2 and the Infinity Cache by reading the 1 GiB buffer (cached
+        loads): the lines left behind are clean, so the next call pays for its
+        own misses only, not for another buffer's write-back."""
+        torch.sum(flush, dim=0, out=sink)
 
     def timed(fn, steps, warmup):
         """ms per step over `steps` back-to-back calls (events on the launch stream)."""
@@ -384,11 +395,15 @@ def main():
         torch.cuda.synchronize()
         return a.elapsed_time(b) / steps
 
-    def cold(fn, reps):
-        """median ms of single calls, each after a 1 GiB write that evicts L2 and MALL."""
+    def cold(fn, reps, write=False):
+        """median ms of single calls, each after a 1 GiB read (or, with write,
+        a 1 GiB write) that evicts L2 and MALL."""
         out = []
         for r in range(reps):
-            flush.fill_(float(r))
+            if write:
+                flush.fill_(1.0)
+            else:
+                evict()
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
             a.record(stream)
@@ -525,13 +540,13 @@ def main():
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
-        # The K timed steps: each writes 1 GiB first (evicting L2 and the Infinity
+        # The K timed steps: each reads 1 GiB first (evicting L2 and the Infinity
         # Cache, outside its events), then one call between events on the launch
         # stream.  ms_per_step is their median: the cold figure.
         per_step = []
         t_region = time.perf_counter()
         for r in range(args.steps):
-            flush.fill_(float(r))
+            evict()
             a_ev = torch.cuda.Event(enable_timing=True)
             b_ev = torch.cuda.Event(enable_timing=True)
             a_ev.record(stream)
@@ -542,6 +557,7 @@ def main():
         region_s = time.perf_counter() - t_region
         ms = float(np.median(per_step))
         timing = "cold median"
+        ms_cold_write = cold(step, args.steps, write=True)  # the same after a 1 GiB write
         ms_warm = timed(step, args.steps, 2)  # back to back, caches warm
         ms_graph = None
         if args.graph:
@@ -643,6 +659,7 @@ def main():
             "warmup": args.warmup,
             "ms_per_step": round(ms, 5),
             "timing": timing,
+            "cold_write_flush_ms": round(ms_cold_write, 5),
             "warm_ms_per_step": round(ms_warm, 5),
             "warm_gbs": round(B / (ms_warm * 1e-3) / 1e9, 2),
             "timed_region_s": round(region_s, 3),
@@ -779,7 +796,7 @@ def main():
         Bb = spmv_bytes(A.m, A.n, A.nnz, 2, 2)
         bf["powerlaw2M"] = {"ms": round(t, 4), "gbs": round(Bb / (t * 1e-3) / 1e9, 2),
                             "fp32_gbs": round(value, 2) if value else None}
-        plb = lb.Plan(Abd)  # the planned call in BF16 (panels of 32768 BF16 columns)
+        plb = lb.Plan(Abd)  # the planned call in BF16 (panels of 81920 BF16 columns)
         wspb = torch.empty(max(plb.workspace_bytes, 1), dtype=torch.uint8, device=dev)
         fpb = (lambda: lb.spmv_planned(Abd, plb, xbd, y=y, workspace=wspb))
         tp, tpc = timed(fpb, extra_steps, 2), cold(fpb, 10)

@@ -264,11 +264,12 @@ LB_API lb_status_t lb_spmv(const lb_csr_t *A, const void *x, lb_dtype_t x_dtype,
  *  long_min      rows with at least this many nonzeros are long; at least
  *                W (a long row then never lies strictly inside one merge-path
  *                unit); default max(W, 16 * panels); -1 = no long rows;
- *  panel_cols    columns per panel, a multiple of 64 up to 16384 (float32
- *                x) or 32768 (BF16 x); default that maximum;
- *  panel_blocks  blocks per panel; default floor(4 * CUs / panels) for the
- *                compute units of the device the plan is built on (two
- *                rounds of two resident blocks per CU);
+ *  panel_cols    columns per panel, a multiple of 64 up to 40960 (float32
+ *                x) or 81920 (BF16 x): 160 KiB, the LDS of one compute
+ *                unit; default that maximum;
+ *  panel_blocks  blocks per panel; default max(1, floor(CUs / panels)) for
+ *                the compute units of the device the plan is built on (one
+ *                round of one resident block per CU);
  *  streams       2: the long rows' launch runs on a second stream
  *                of the same device, owned by the library (one per device,
  *                created on first use, default priority), concurrently with

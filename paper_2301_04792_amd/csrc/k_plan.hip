@@ -18,8 +18,8 @@
 //    schedule, Sec. 5.2.2, with the group size matched to the tile), so a
 //    wavefront step serves 64 / G tasks and a task's sum is a log2(G)-step
 //    reduction.  A lane loads its four nonzeros with one 16-byte column load
-//    and one value load, reads x from LDS, and the group's first lane stores
-//    the task's sum.
+//    and one value load, reads x from LDS, and the group's last lane stores
+//    the task's sum (a DPP reduction).
 //  * plan_finish adds, for every long row, its task sums in (panel, task)
 //    order, and completes the short rows cut by unit boundaries (the carries
 //    of the merge path and the second column band's sums).
@@ -55,16 +55,23 @@ __device__ __forceinline__ void panel_class_tasks(int32_t T0, int32_t T1, int ro
     const int lane = lane_id(), w = (wave_id() + rot) % NW;
     const int gl = lane & (G - 1);
     const int32_t last_full = (nnz >> 2) - 1;  // VEC 4: the last group of four inside the array
-    for (int32_t base = T0 + w * TPW + lane / G; base - lane / G < T1; base += NW * TPW * S) {
-        int32_t a0[S], len[S], out[S];
+    int32_t base = T0 + w * TPW + lane / G;
+    if (base - lane / G >= T1) return;
+    // descriptors of the current batch; the next batch's are loaded while
+    // this one's nonzeros are in flight
+    int32_t a0[S], len[S], out[S];
+    auto load_desc = [&](int32_t b, int32_t *da0, int32_t *dlen, int32_t *dout) {
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            const int32_t t = base + s * NW * TPW;
+            const int32_t t = b + s * NW * TPW;
             const panel_task d = tasks[t < T1 ? t : T0];  // a dead slot reads the first task and stores nothing
-            a0[s] = d.a0;
-            len[s] = t < T1 ? d.len : 0;
-            out[s] = d.out;
+            da0[s] = d.a0;
+            dlen[s] = t < T1 ? d.len : 0;
+            dout[s] = d.out;
         }
+    };
+    load_desc(base, a0, len, out);
+    for (;;) {
         int32_t cc[S][4];
         VT vv[S][4];
         if constexpr (VEC == 4) {
@@ -113,6 +120,10 @@ __device__ __forceinline__ void panel_class_tasks(int32_t T0, int32_t T1, int ro
                 }
             }
         }
+        const int32_t nbase = base + NW * TPW * S;
+        const bool more = nbase - lane / G < T1;  // uniform over the wavefront
+        int32_t na0[S], nlen[S], nout[S];
+        if (more) load_desc(nbase, na0, nlen, nout);
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             // the task-relative index of this lane's u-th nonzero
@@ -126,8 +137,16 @@ __device__ __forceinline__ void panel_class_tasks(int32_t T0, int32_t T1, int ro
                 const float xv = to_f32(xs[xi]);
                 acc += live ? to_f32(vv[s][u]) * xv : 0.f;
             }
-            acc = group_sum<G>(acc);
-            if (gl == 0 && len[s] > 0) part[out[s]] = acc;
+            acc = group_sum_dpp<G>(acc);
+            if (gl == G - 1 && len[s] > 0) part[out[s]] = acc;
+        }
+        if (!more) break;
+        base = nbase;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            a0[s] = na0[s];
+            len[s] = nlen[s];
+            out[s] = nout[s];
         }
     }
 }

@@ -907,14 +907,15 @@ LB_API lb_status_t lb_spmv_plan_build(const lb_csr_t *A, lb_spmv_plan_t *plan, v
     p.long_rows = static_cast<int32_t>(LR.size());
     p.long_nnz = long_nnz;
     if (p.panel_blocks == 0) {
-        // two rounds of two resident blocks per CU, rounded down to whole
-        // panels: a last round that only a few blocks run would idle the rest
+        // one round of one resident block per CU (a panel fills the CU's
+        // LDS), rounded down to whole panels: a second round that only some
+        // blocks run would idle the rest and restage panels
         int dev = 0, cus = 256;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             cus = 256;
         (void)hipGetLastError();
-        p.panel_blocks = static_cast<int32_t>(std::max<int64_t>(1, 4 * static_cast<int64_t>(cus) / std::max<int64_t>(NP, 1)));
+        p.panel_blocks = static_cast<int32_t>(std::max<int64_t>(1, static_cast<int64_t>(cus) / std::max<int64_t>(NP, 1)));
     }
     if (static_cast<int64_t>(p.panel_blocks) * NP >= kMaxCoord) return LB_ERR_OVERFLOW;
     const int64_t T = p.units;

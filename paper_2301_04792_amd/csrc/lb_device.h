@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "lb_schedule.hpp"  // ranges, tile sets, thread- and group-mapped schedules, int scans
 
 namespace lb {
@@ -143,6 +145,37 @@ template <int G>
 __device__ __forceinline__ float group_sum(float v) {
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+    return v;
+}
+
+// Sum over aligned groups of G lanes (G = 8, 16, 32 or 64) with DPP lane
+// moves, which run on the VALU instead of the LDS crossbar that __shfl_xor
+// (ds_bpermute) occupies.  The group's last lane gets the total (for G <= 16
+// every lane of the group does).  Steps: swaps inside quads (quad_perm
+// [1,0,3,2] and [2,3,0,1]), the mirror inside each half-row of 8 lanes, the
+// mirror inside each row of 16, then lane 15 of rows 0 and 2 added into rows
+// 1 and 3 (row_bcast15, row mask 0b1010) and lane 31 into rows 2 and 3
+// (row_bcast31, row mask 0b1100).  Fixed order: deterministic.
+template <int G>
+__device__ __forceinline__ float group_sum_dpp(float v) {
+    static_assert(G == 8 || G == 16 || G == 32 || G == 64, "groups of 8 to 64 lanes");
+    auto mov = [](float a, auto ctrl, auto row_mask) {
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(a), decltype(ctrl)::value,
+                                                          decltype(row_mask)::value, 0xF, false));
+    };
+    using qp_1032 = std::integral_constant<int, 0xB1>;
+    using qp_2301 = std::integral_constant<int, 0x4E>;
+    using half_mirror = std::integral_constant<int, 0x141>;
+    using mirror = std::integral_constant<int, 0x140>;
+    using bcast15 = std::integral_constant<int, 0x142>;
+    using bcast31 = std::integral_constant<int, 0x143>;
+    using all_rows = std::integral_constant<int, 0xF>;
+    v += mov(v, qp_1032{}, all_rows{});
+    v += mov(v, qp_2301{}, all_rows{});
+    v += mov(v, half_mirror{}, all_rows{});
+    if constexpr (G >= 16) v += mov(v, mirror{}, all_rows{});
+    if constexpr (G >= 32) v += mov(v, bcast15{}, std::integral_constant<int, 0xA>{});
+    if constexpr (G >= 64) v += mov(v, bcast31{}, std::integral_constant<int, 0xC>{});
     return v;
 }
 

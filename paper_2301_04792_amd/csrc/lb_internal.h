@@ -103,15 +103,16 @@ hipError_t merge_spmv(const csr_dev &A, const void *x, float *y, int block, int 
 
 // ---- planned SpMV (k_plan.hip) ----------------------------------------------------------
 // Long rows: a block of kPanelBlock threads stages kPanelBytes of x (one
-// panel) in LDS, R blocks per panel; a task is at most kPanelTask nonzeros
+// panel, the whole 160 KiB LDS of a CU: one resident block per CU, 16
+// wavefronts) in LDS, R blocks per panel; a task is at most kPanelTask nonzeros
 // of one (row, panel) segment (252: any such range lies in 64 aligned groups
 // of four); a task of at most G groups runs on G lanes (G = 64, 32, 16, 8:
 // its class), one group per lane; a wavefront works on kPanelBatch steps of
 // 64 / G tasks at a time.
-constexpr int kPanelBlock = 512;
+constexpr int kPanelBlock = 1024;
 constexpr int kPanelTask = 252;
 constexpr int kPanelBatch = 4;
-constexpr int kPanelBytes = 65536;
+constexpr int kPanelBytes = 163840;
 constexpr int kPanelClasses = 4;
 // The class of a task spanning ng aligned groups: G = 64 >> class.
 inline int panel_class(int64_t ng) { return ng > 32 ? 0 : (ng > 16 ? 1 : (ng > 8 ? 2 : 3)); }

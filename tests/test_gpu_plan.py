@@ -213,6 +213,26 @@ def test_planned_second_stream_and_block_counts():
     assert_rows_close(y1.cpu().numpy(), ref, scale, what="second stream")
 
 
+@pytest.mark.parametrize("bf16", [False, True])
+def test_planned_widest_panel(bf16):
+    """Panels of 160 KiB of x (40960 FP32 or 81920 BF16 columns, the largest
+    accepted) over a matrix three panels wide, the last one partial; one
+    column more per panel is rejected.  Integer inputs: bit-exact."""
+    pmax = 81920 if bf16 else 40960
+    A, x = S.powerlaw_csr(48, 3000, 2 * pmax + 5000, 1.4, 60_000, 0.1)
+    A, x = S.integer_valued(A, 4)
+    ref, _ = oracle_spmv(A, x)
+    dt = torch.bfloat16 if bf16 else torch.float32
+    Ad, xd = upload(A, x, dt)
+    plan = lb.Plan(Ad, block_size=128, items_per_thread=8, long_min=1024)
+    assert plan.c.panel_cols == pmax and plan.c.panels == 3 and plan.c.long_rows > 0
+    got = lb.spmv_planned(Ad, plan, xd).cpu().numpy().astype(np.float64)
+    assert np.array_equal(got, ref)
+    with pytest.raises(_abi.LBError) as e:
+        lb.Plan(Ad, block_size=128, items_per_thread=8, long_min=1024, panel_cols=pmax + 64)
+    assert e.value.status == _abi.ERR_INVALID_ARG
+
+
 @pytest.mark.parametrize("extra", [0, 1, 2, 3])
 def test_planned_array_tail_and_misaligned(extra):
     """A long last row ending at nnz = 4k + extra: the nonzeros past the last
