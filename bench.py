@@ -167,10 +167,12 @@ def _short_name(name, width=100):
 
 def _copy_calibration(rows):
     """(fetch factor, write factor) from the 256 MiB device copy run with --pmc-calib, or None."""
-    f = [float(r["Counter_Value"]) for r in rows if r.get("Counter_Name") == "FETCH_SIZE"
-         and "copy" in r.get("Kernel_Name", "").lower()]
-    w = [float(r["Counter_Value"]) for r in rows if r.get("Counter_Name") == "WRITE_SIZE"
-         and "copy" in r.get("Kernel_Name", "").lower()]
+    def torch_copy(r):  # the calibration copy: torch's device copy kernel, not the runtime's blits
+        name = r.get("Kernel_Name", "").lower()
+        return "copy" in name and "rocclr" not in name
+
+    f = [float(r["Counter_Value"]) for r in rows if r.get("Counter_Name") == "FETCH_SIZE" and torch_copy(r)]
+    w = [float(r["Counter_Value"]) for r in rows if r.get("Counter_Name") == "WRITE_SIZE" and torch_copy(r)]
     known = float(1 << 28)
     return (known / (max(f) * 1024.0) if f else None, known / (max(w) * 1024.0) if w else None,
             max(f) if f else None, max(w) if w else None)
@@ -381,6 +383,13 @@ def main():
         own misses only, not for another buffer's write-back."""
         torch.sum(flush, dim=0, out=sink)
 
+    if args.pmc_calib:  # a device copy of known size for the counter runs' calibration
+        src = torch.ones(1 << 26, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)  # reads and writes exactly 256 MiB
+        torch.cuda.synchronize()
+        del src, dst
+
     def timed(fn, steps, warmup):
         """ms per step over `steps` back-to-back calls (events on the launch stream)."""
         for _ in range(warmup):
@@ -569,13 +578,6 @@ def main():
         kt = {n: v for n, v in kt.items() if v[1] > 0}
         dominant = max(kt, key=lambda n: kt[n][0])
         dom_ms, launches = kt[dominant]
-        if args.pmc_calib:
-            src = torch.ones(1 << 26, dtype=torch.float32, device=dev)
-            dst = torch.empty_like(src)
-            dst.copy_(src)  # reads and writes exactly 256 MiB
-            torch.cuda.synchronize()
-            del src, dst
-
         # algorithmic bytes of each kernel of the call (the planned call's parts)
         lens = np.diff(A.row_offsets.astype(np.int64))
         kernel_bytes = {}
@@ -866,11 +868,9 @@ def main():
         del pl4, wsp4
         tb = timed(lambda: lb.spmv_backward(C4d, x4d, dy4), extra_steps, 2)
         bw_ms, _ = kernel_avg_ms(lambda: lb.spmv_backward(C4d, x4d, dy4), extra_steps, "backward")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        tr4 = lb.transpose_pattern(C4d.pattern)  # once per pattern
-        torch.cuda.synchronize()
-        tbuild = (time.perf_counter() - t0) * 1e3
+        tr4 = lb.transpose_pattern(C4d.pattern)  # once per pattern; then its rebuild timed on the stream
+        tbuild = timed(lambda: lb.transpose_pattern(C4d.pattern, rebuild=True), 5, 1)
+        tr4 = lb.transpose_pattern(C4d.pattern)
         tbt = timed(lambda: lb.spmv_backward(C4d, x4d, dy4, transposed=tr4), extra_steps, 2)
         Bf4, Bb4 = spmv_bytes(C4.m, C4.n, C4.nnz), backward_bytes(C4.m, C4.n, C4.nnz)
         result["fwd_bwd_powerlaw1M"] = {"nnz": C4.nnz, "fwd_ms": round(tf, 4), "bwd_ms": round(tb, 4),

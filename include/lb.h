@@ -362,13 +362,17 @@ LB_API lb_status_t lb_spmv_backward(const lb_csr_t *A, const void *x, lb_dtype_t
 /* Backward without atomics, for a pattern reused across calls (a training
  * loop): lb_transpose_pattern builds A^T's pattern once --
  * at_row_offsets[cols + 1], at_col_idx[nnz] (the rows of A) and perm[nnz]
- * (entry p of A^T is entry perm[p] of A); the order inside a row of A^T
- * comes from atomics and varies from build to build.  Workspace from
- * lb_transpose_workspace_size.  cols + nnz < 2^31 - 1.
+ * (entry p of A^T is entry perm[p] of A).  The result is the canonical
+ * CSC of A: a row of A^T lists its entries in their order in A (so by
+ * increasing row of A), the same for every build; it is computed by a
+ * stable radix sort of the entries by column (digits of at most 7 bits:
+ * three passes for cols <= 2^21), with block-local histograms, tiles
+ * sorted in LDS and written as runs, and no global atomics.  Workspace from lb_transpose_workspace_size (24 bytes per
+ * nonzero plus the histograms).  cols + nnz < 2^31 - 1.
  * lb_spmv_backward_transposed then computes dvalues as lb_spmv_backward
  * does (bit-exact) and dx = A^T dy by the merge-path SpMV on A^T, which
  * reads the current values of A through perm (a gather, no atomics, no
- * permuted copy); for a fixed pattern build dx is bit-reproducible.  s as for
+ * permuted copy); dx is bit-reproducible (the transpose is canonical).  s as for
  * lb_spmv_backward (merge-path block_size / items_per_thread); workspace
  * from lb_backward_transposed_workspace_size. */
 LB_API lb_status_t lb_transpose_workspace_size(const lb_csr_t *A, size_t *bytes);

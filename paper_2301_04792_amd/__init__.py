@@ -239,11 +239,12 @@ def spmm(A: CSR, X: torch.Tensor, schedule="merge_path", Y: torch.Tensor | None 
     return Y
 
 
-def transpose_pattern(P: Pattern):
+def transpose_pattern(P: Pattern, rebuild: bool = False):
     """A^T's pattern for the transposed backward: (at_row_offsets, at_col_idx, perm),
-    entry p of A^T being entry perm[p] of A.  Built once per pattern and cached on it."""
+    entry p of A^T being entry perm[p] of A (the canonical CSC of A).  Built once
+    per pattern and cached on it; rebuild=True builds it again (and caches that)."""
     cached = getattr(P, "_transposed", None)
-    if cached is not None:
+    if cached is not None and not rebuild:
         return cached
     c = _abi.CSR(P.shape[0], P.shape[1], P.nnz, P.row_offsets.data_ptr(), P.col_idx.data_ptr(),
                  P.col_idx.data_ptr(), _abi.F32)  # the values are not read

@@ -327,13 +327,10 @@ __global__ __launch_bounds__(256) void plan_finish_runs(int32_t T, int32_t rows,
 
 // sb[q][p] for p in [0, NP): the first nonzero of long row LR[q] whose column
 // is at least p * P (lower bound in the row's sorted columns); sb[q][NP] =
-// the row's end.  Also flags (bit 0) a long row whose columns do not
-// strictly increase.  One thread per (row, panel) pair; thread (q, NP) checks
-// the order.
+// the row's end.  One thread per (row, panel) pair.
 __global__ __launch_bounds__(256) void plan_segments(int32_t NL, int32_t NP, int32_t P,
                                                      const int32_t *__restrict__ LR, const int32_t *__restrict__ ro,
-                                                     const int32_t *__restrict__ ci, int32_t *__restrict__ sb,
-                                                     int32_t *__restrict__ flags) {
+                                                     const int32_t *__restrict__ ci, int32_t *__restrict__ sb) {
     const int64_t stride = static_cast<int64_t>(NP) + 1;
     for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < NL * stride;
          e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
@@ -343,9 +340,6 @@ __global__ __launch_bounds__(256) void plan_segments(int32_t NL, int32_t NP, int
         const int32_t b = ro[r], en = ro[r + 1];
         if (p == NP) {
             sb[e] = en;
-            bool bad = false;
-            for (int32_t j = b + 1; j < en && !bad; ++j) bad = ci[j] <= ci[j - 1];
-            if (bad) atomicOr(flags, 1);
             continue;
         }
         const int32_t key = p * P;
@@ -358,6 +352,22 @@ __global__ __launch_bounds__(256) void plan_segments(int32_t NL, int32_t NP, int
                 hi = mid;
         }
         sb[e] = lo;
+    }
+}
+
+// Flags (bit 0) a long row whose columns do not strictly increase: block q
+// (grid stride) checks the consecutive pairs of row LR[q], strided by its
+// threads.
+__global__ __launch_bounds__(256) void plan_order_check(int32_t NL, const int32_t *__restrict__ LR,
+                                                        const int32_t *__restrict__ ro,
+                                                        const int32_t *__restrict__ ci, int32_t *__restrict__ flags) {
+    for (int32_t q = blockIdx.x; q < NL; q += gridDim.x) {
+        const int32_t r = LR[q];
+        const int32_t b = ro[r], en = ro[r + 1];
+        bool bad = false;
+        for (int32_t j = b + 1 + static_cast<int32_t>(threadIdx.x); j < en; j += blockDim.x)
+            bad = bad || ci[j] <= ci[j - 1];
+        if (bad) atomicOr(flags, 1);
     }
 }
 
@@ -375,7 +385,9 @@ hipError_t plan_segments_launch(int32_t NL, int32_t NP, int32_t P, const int32_t
     int64_t blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(plan_segments, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, NL, NP, P, LR, ro, ci,
-                       sb, flags);
+                       sb);
+    hipLaunchKernelGGL(plan_order_check, dim3(static_cast<uint32_t>(NL < 65536 ? NL : 65536)), dim3(256), 0, s, NL, LR,
+                       ro, ci, flags);
     return hipGetLastError();
 }
 

@@ -55,6 +55,46 @@ def test_powerlaw2m_tuned(powerlaw2m):
     lb.autotune_clear()
 
 
+def test_powerlaw2m_planned(powerlaw2m):
+    """The planned call with the default plan (the bench's headline launch
+    configuration): every row against the oracle, run-to-run bit-equal."""
+    A, x, ref, scale = powerlaw2m
+    Ad = lb.CSR.from_host(A, DEV)
+    xd = torch.from_numpy(x).to(DEV)
+    plan = lb.Plan(Ad)
+    print(f"[powerlaw2M planned {plan.info}]", flush=True)
+    assert plan.c.long_rows > 0 and plan.c.panels > 1
+    y1 = lb.spmv_planned(Ad, plan, xd)
+    y2 = lb.spmv_planned(Ad, plan, xd)
+    worst = assert_rows_close(y1.cpu().numpy(), ref, scale, what="powerlaw2M planned")
+    assert torch.equal(y1, y2)
+    print(f"  max err / sum|a x| = {worst:.3e}", flush=True)
+
+
+def test_powerlaw2m_planned_integer_bit_exact():
+    """Integer values and x on the 2M pattern: every partial sum is exact in
+    FP32 (row sums stay below 2^24), so the planned result equals the
+    oracle bit for bit, long rows over every panel included."""
+    A, _ = S.config_c2()
+    A, x = S.integer_valued(A, 9, vmax=2, xmax=2)
+    ref, _ = oracle_spmv(A, x)
+    assert float(np.abs(ref).max()) < 2.0 ** 24
+    Ad = lb.CSR.from_host(A, DEV)
+    y = lb.spmv_planned(Ad, lb.Plan(Ad), torch.from_numpy(x).to(DEV)).cpu().numpy().astype(np.float64)
+    assert np.array_equal(y, ref), f"{int((y != ref).sum())} rows differ"
+
+
+def test_powerlaw2m_bf16_planned(powerlaw2m):
+    A, x, _, _ = powerlaw2m
+    Ab = A.with_values(S.to_bf16_bits(A.values))
+    xb = S.to_bf16_bits(x)
+    Ad = lb.CSR.from_host(Ab, DEV)
+    xd = torch.from_numpy(xb.view(np.int16).copy()).view(torch.bfloat16).to(DEV)
+    y = lb.spmv_planned(Ad, lb.Plan(Ad), xd).cpu().numpy()
+    ref, scale = oracle_spmv(Ab, xb)
+    assert_rows_close(y, ref, scale, what="powerlaw2M bf16 planned")
+
+
 def test_powerlaw2m_bf16(powerlaw2m):
     A, x, ref32, scale32 = powerlaw2m
     Ab = A.with_values(S.to_bf16_bits(A.values))

@@ -6,6 +6,7 @@ import pytest
 
 import oracle
 import synthetic as S
+import synthetic.csr as SC
 from tests.gpu_util import assert_rows_close, oracle_spmm, oracle_spmv
 
 torch = pytest.importorskip("torch")
@@ -368,23 +369,35 @@ def test_work_queue_equals_static_rounds(g, grid):
 def _transpose_cases():
     out = {"c1": S.config_c1()[0], "powerlaw": S.powerlaw_csr(37, 30_000, 20_000, 1.5, 8000, 0.2)[0]}
     out.update({k: v[0] for k, v in S.special_matrices().items() if k != "m0"})
+    # column counts around the radix digit sizes: 2^11 (one pass), 2^11 + 1
+    # (two passes of 6 bits), 5M (23 bits: three passes); tiles of 8192
+    # entries with a ragged last one
+    out["cols2048"] = S.powerlaw_csr(60, 3000, 2048, 1.5, 2000, 0.1)[0]
+    out["cols2049"] = S.powerlaw_csr(61, 3000, 2049, 1.5, 2000, 0.1)[0]
+    out["cols5M"] = S.powerlaw_csr(62, 20_000, 5_000_000, 1.5, 30_000, 0.1)[0]
+    out["one_col"] = SC._from_lengths(63, [1] * 9000 + [0, 1], 1)[0]
     return out
 
 
 @pytest.mark.parametrize("name", sorted(_transpose_cases().keys()))
 def test_transpose_pattern(name):
+    """A^T's pattern is the canonical CSC: entries ordered by column, then
+    by their position in A (so by row), the same for every build; checked
+    against a stable argsort of the columns."""
     A = _transpose_cases()[name]
     Ad = lb.CSR.from_host(A, DEV)
+    print(f"[transpose {name} {A.m}x{A.n} nnz={A.nnz}]", flush=True)
     at_ro, at_ci, perm = [t.cpu().numpy() for t in lb.transpose_pattern(Ad.pattern)]
     nnz = A.nnz
     at_ci, perm = at_ci[:nnz], perm[:nnz]
     counts = np.bincount(A.col_idx, minlength=A.n)
     assert np.array_equal(np.diff(at_ro.astype(np.int64)), counts) and at_ro[0] == 0
-    assert np.array_equal(np.sort(perm), np.arange(nnz))  # a permutation of A's entries
+    order = np.argsort(A.col_idx, kind="stable")
+    assert np.array_equal(perm, order)
     rows = np.repeat(np.arange(A.m), np.diff(A.row_offsets.astype(np.int64)))
-    at_row = np.repeat(np.arange(A.n), counts)
-    assert np.array_equal(A.col_idx[perm], at_row)  # entry p of A^T lies in A^T row col(perm[p])
-    assert np.array_equal(rows[perm], at_ci)  # and its column is the row of that A entry
+    assert np.array_equal(at_ci, rows[order])
+    again = [t.cpu().numpy() for t in lb.transpose_pattern(Ad.pattern, rebuild=True)]
+    assert all(np.array_equal(a[:len(b)], b) for a, b in zip(again, (at_ro, at_ci, perm)))
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
