@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define LB_ABI_VERSION 3
+#define LB_ABI_VERSION 4
 #define LB_API __attribute__((visibility("default")))
 
 typedef enum lb_status_t {
@@ -230,7 +230,10 @@ LB_API lb_status_t lb_spmv(const lb_csr_t *A, const void *x, lb_dtype_t x_dtype,
  *  - short rows (fewer than long_min nonzeros) run the merge path of
  *    lb_spmv (Sec. 5.2.1) over the whole matrix with the long rows' work
  *    left out: the split at every unit boundary is computed once, in the
- *    plan, and only the units holding short-row work are launched;
+ *    plan, and only the units in which a short row closes are launched.
+ *    The unit where a row closes owns it whole: its block also sums the
+ *    row's nonzeros that lie in earlier units, so no carries remain and
+ *    with one band (and no long rows) the call is a single launch;
  *  - long rows run a panel schedule: x is cut into panels of panel_cols
  *    columns; each panel is served by panel_blocks blocks, each of which
  *    stages the panel of x in LDS once and consumes an equal share of the
@@ -257,7 +260,9 @@ LB_API lb_status_t lb_spmv(const lb_csr_t *A, const void *x, lb_dtype_t x_dtype,
  *
  * Inputs of lb_spmv_plan_t (0 = default):
  *  block_size, items_per_thread  the short rows' merge path, as for lb_spmv
- *                                (default 256 x 8); W = their product;
+ *                                (default 256 x 8, or 256 x 12 when the
+ *                                default vector_width is 4); W = their
+ *                                product;
  *  x_bands       1 or 2, as for lb_spmv (default: 2 when x has at least
  *                4 MiB and the columns are scattered -- the median column
  *                span of up to 1024 sampled rows exceeds cols / 16 -- else 1);
@@ -270,6 +275,12 @@ LB_API lb_status_t lb_spmv(const lb_csr_t *A, const void *x, lb_dtype_t x_dtype,
  *  panel_blocks  blocks per panel; default max(1, floor(CUs / panels)) for
  *                the compute units of the device the plan is built on (one
  *                round of one resident block per CU);
+ *  vector_width  1 or 4: the short rows' consume loads one or four
+ *                consecutive nonzeros per lane and load (4: one band only;
+ *                used when col_idx and the values are aligned to their
+ *                4-vectors and nnz >= 4, else 1); default 4 when the
+ *                columns are local (the sampled median span is at most
+ *                cols / 16) and one band is used, else 1;
  *  streams       2: the long rows' launch runs on a second stream
  *                of the same device, owned by the library (one per device,
  *                created on first use, default priority), concurrently with
@@ -290,6 +301,7 @@ typedef struct lb_spmv_plan_t {
     int32_t panel_cols;
     int32_t panel_blocks;
     int32_t streams;
+    int32_t vector_width;
     lb_dtype_t value_dtype;
     int64_t rows;
     int64_t cols;

@@ -180,13 +180,14 @@ class Plan:
     values may change between calls, the pattern may not."""
 
     def __init__(self, A: CSR, block_size=0, items_per_thread=0, x_bands=0, long_min=0, panel_cols=0, panel_blocks=0,
-                 streams=0):
+                 streams=0, vector_width=0):
         self.shape = tuple(A.shape)
         self.nnz = A.nnz
         self.device = A.device
         p = _abi.SpmvPlan()
         p.block_size, p.items_per_thread, p.x_bands = block_size, items_per_thread, x_bands
         p.long_min, p.panel_cols, p.panel_blocks, p.streams = long_min, panel_cols, panel_blocks, streams
+        p.vector_width = vector_width
         c = A.c_struct()
         st = _lib.lb_spmv_plan_build(ctypes.byref(c), ctypes.byref(p), None, 0, _stream(A.device))
         if st not in (_abi.OK, _abi.ERR_WORKSPACE_TOO_SMALL):

@@ -16,7 +16,7 @@ LIB_PATH = os.environ.get("LB_LIBRARY", os.path.join(_PKG, "liblb.so"))
  ERR_NOT_CONVERGED, ERR_SCRATCH_LIMIT) = range(9)
 # static scratch of lb_spmv_noalloc per GPU (LB_NOALLOC_SCRATCH_BYTES)
 NOALLOC_SCRATCH_BYTES = 16 << 20
-ABI_VERSION = 3
+ABI_VERSION = 4
 # lb_dtype_t
 F32, BF16, F64 = 0, 1, 2
 # lb_sched_kind_t
@@ -70,7 +70,7 @@ class CSC(ctypes.Structure):
 class SpmvPlan(ctypes.Structure):
     _fields_ = [("block_size", ctypes.c_int32), ("items_per_thread", ctypes.c_int32), ("x_bands", ctypes.c_int32),
                 ("long_min", ctypes.c_int32), ("panel_cols", ctypes.c_int32), ("panel_blocks", ctypes.c_int32),
-                ("streams", ctypes.c_int32),
+                ("streams", ctypes.c_int32), ("vector_width", ctypes.c_int32),
                 ("value_dtype", ctypes.c_int),
                 ("rows", ctypes.c_int64), ("cols", ctypes.c_int64), ("nnz", ctypes.c_int64),
                 ("long_nnz", ctypes.c_int64), ("long_rows", ctypes.c_int32), ("panels", ctypes.c_int32),

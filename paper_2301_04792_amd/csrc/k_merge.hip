@@ -112,14 +112,18 @@ hipError_t merge_partition(const int32_t *ro, int32_t rows, int32_t nnz, int32_t
 // gathers get from long sorted rows, so this form pays only where columns
 // are local (a stencil).  The launcher requires nnz >= 4 and aligned
 // col_idx / values.
-// PLAN (planned SpMV, short rows only): the block's unit is active[b] (T is
-// then the number of active units), the split comes from the plan, and the
-// long rows (at least long_min nonzeros) are left out: their nonzeros give
-// zero products and their y and carries are not this kernel's.  As
-// long_min >= W, only the unit's first row i0 (begun before the unit) and
-// its open row i1 can be long, so the short nonzeros are the one range
-// [ja, jb); carry_row is not written (the carry of unit u belongs to row
-// part_i[u + 1]).
+// PLAN (planned SpMV, short rows only): block b takes the b-th active unit
+// (T is then the number of active units) and reads its record from the
+// plan (the split, the product range, the head, the long flag); each
+// block owns the short rows that close in its unit, whole: it adds the head
+// of its first row i0 (the nonzeros [ro[i0], j0) before the unit, summed
+// by the whole block and handed to thread 0's walk) and leaves out its open
+// row i1 (that row is owned by the unit where it closes).  So no carries
+// exist and every short row has one writer.  Long rows (at least long_min
+// nonzeros) are left out too: as long_min >= W only i0 can be long among
+// the closing rows, and then the block neither writes y[i0] nor reads its
+// head.  The nonzeros whose products the walk sums are the one range
+// [ja, jb).
 template <int BLOCK, int ITEMS, typename VT, typename XT, int BANDS, bool VPERM = false, int VEC = 1,
           bool PLAN = false>
 __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
@@ -127,14 +131,15 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
     const XT *__restrict__ x, float *__restrict__ y, const int32_t *__restrict__ part_i,
     const int32_t *__restrict__ part_j, int32_t *__restrict__ carry_row, float *__restrict__ carry_val,
     int32_t T, int32_t cb, float *__restrict__ y_hi, const int32_t *__restrict__ vperm,
-    const int32_t *__restrict__ active = nullptr, int32_t long_min = 0) {
+    const plan_unit *__restrict__ units = nullptr) {
     static_assert(BANDS == 1 || BANDS == 2, "one or two column bands");
     static_assert(!(VPERM && BANDS != 1), "permuted values with one band only");
     static_assert(VEC == 1 || (VEC == 4 && BANDS == 1 && !VPERM && ITEMS % 4 == 0), "vector loads: one band");
-    static_assert(!PLAN || (VEC == 1 && !VPERM), "planned form: one nonzero per lane, own values");
+    static_assert(!PLAN || !VPERM, "planned form: own values");
     constexpr int W = BLOCK * ITEMS;
     __shared__ int32_t s_buf[W];  // row ends [0, nrows), then products [nrows, nrows + nnzs)
     __shared__ seg_t s_wave[BLOCK / kWave];
+    __shared__ float s_head[PLAN ? BLOCK / kWave : 1];
 
     const int tid = threadIdx.x;
     int b = blockIdx.x, band = 0;
@@ -145,25 +150,24 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
         if (b >= T) return;  // uniform across the block, before any barrier
         if (band == 1) y = y_hi;
     }
-    const int slot = b;  // carry slot (the unit index; the active-list index when planned)
-    if constexpr (PLAN) b = active[b];
-    const int32_t i0 = part_i[b], j0 = part_j[b];
-    const int32_t i1 = part_i[b + 1], j1 = part_j[b + 1];
+    // the unit's split; planned: its record (one load), which also gives
+    // [ja, jb), the nonzeros whose products this block sums, row i0's head
+    // [h0, j0) and skip_first (row i0 is long, its y is not written here)
+    int32_t i0, i1, j0, j1, ja, jb, h0;
+    bool skip_first = false, short_rows = false;
+    if constexpr (PLAN) {
+        const plan_unit u = units[b];
+        i0 = u.i0, i1 = u.i1, j0 = u.j0, j1 = u.j1, ja = u.ja, jb = u.jb, h0 = u.h0;
+        skip_first = (u.flags & 1) != 0;
+        short_rows = (u.flags & 2) != 0;
+    } else {
+        i0 = part_i[b], j0 = part_j[b];
+        i1 = part_i[b + 1], j1 = part_j[b + 1];
+        ja = j0, jb = j1, h0 = j0;
+    }
     const int32_t nrows = i1 - i0, nnzs = j1 - j0;
     int32_t *s_re = s_buf;
     float *s_pv = reinterpret_cast<float *>(s_buf + nrows);
-    // [ja, jb): the nonzeros whose products this block sums (all of the unit's
-    // unless planned); skip_first: row i0 is long, its y is not written here
-    int32_t ja = j0, jb = j1;
-    bool skip_first = false;
-    if constexpr (PLAN) {
-        if (i0 < i1 && ro[i0 + 1] - ro[i0] >= long_min) {
-            skip_first = true;
-            ja = ro[i0 + 1];
-        }
-        if (i1 < rows && i1 > i0 && ro[i1 + 1] - ro[i1] >= long_min) jb = ro[i1];
-        if (jb < ja) jb = ja;
-    }
 
     // Setup: row ends relative to j0 (in [0, nnzs]) and products, coalesced;
     // consecutive lanes take consecutive nonzeros so that the x gathers of a
@@ -179,6 +183,19 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
     const int32_t nz_first = ja < nz_last ? ja : nz_last;
     int32_t re[ITEMS], c[ITEMS];
     float pv[ITEMS];
+    // planned: each thread's first nonzero of row i0's head goes out before
+    // the stream loads, its x gather right after them
+    const bool has_head = PLAN && h0 + tid < j0;
+    int32_t hc = 0;
+    VT hv{};
+    float hx = 0.f;
+    if (has_head) {
+        hc = ci[h0 + tid];
+        hv = val[h0 + tid];
+    }
+    auto head_gather = [&]() {
+        if (has_head && (BANDS == 1 || (hc >= cb) == (band == 1))) hx = to_f32(x[hc]);
+    };
     if constexpr (VEC == 4) {
         using vec_t = typename vec4_of<VT>::type;
         typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
@@ -206,6 +223,7 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
                 v[4 * q + e] = v4[e];
             }
         }
+        head_gather();
 #pragma unroll
         for (int u = 0; u < ITEMS; ++u) pv[u] = to_f32(v[u]) * to_f32(x[c[u]]);
 #pragma unroll
@@ -214,13 +232,14 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
             if (k < nrows) s_re[k] = re[u] - j0;
             const int32_t vs = base + 4 * (tid + (u / 4) * BLOCK);
             const int32_t kp = vs + (u % 4) - j0;
-            if (vs <= vmax && kp >= 0 && kp < nnzs) s_pv[kp] = pv[u];
+            if (vs <= vmax && kp >= 0 && kp < nnzs) s_pv[kp] = PLAN && (kp + j0 < ja || kp + j0 >= jb) ? 0.f : pv[u];
         }
         // nonzeros past the used groups (the unit running past base + W, or
         // the array's last nnz mod 4 entries): at most 3
         const int32_t cov_end = base + W < vmax + 4 ? base + W : vmax + 4;
         const int32_t g = (cov_end > j0 ? cov_end : j0) + tid;
-        if (tid < 3 && g < j1) s_pv[g - j0] = to_f32(val[g]) * to_f32(x[ci[g]]);
+        if (tid < 3 && g < j1)
+            s_pv[g - j0] = PLAN && (g < ja || g >= jb) ? 0.f : to_f32(val[g]) * to_f32(x[ci[g]]);
     } else if constexpr (BANDS == 1) {
         VT v[ITEMS];
         float xv[ITEMS];
@@ -238,6 +257,7 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
             else
                 v[u] = ld_stream(val + jc);
         }
+        head_gather();
 #pragma unroll
         for (int u = 0; u < ITEMS; ++u) {
             if constexpr (VPERM) v[u] = val[vp[u]];
@@ -265,6 +285,7 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
             c[u] = ci[jc];
             v[u] = val[jc];
         }
+        head_gather();
 #pragma unroll
         for (int u = 0; u < ITEMS; ++u) {
             bool mine = (c[u] >= cb) == (band == 1);
@@ -283,7 +304,38 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
             if (k < nnzs) s_pv[k] = pv[u];
         }
     }
+    if constexpr (PLAN) {
+        // this thread's share of row i0's head, in its band (hx is 0 outside it)
+        float head = has_head ? to_f32(hv) * hx : 0.f;
+        for (int32_t j = h0 + tid + BLOCK; j < j0; j += BLOCK) {  // heads longer than the block
+            const int32_t cj = ci[j];
+            if (BANDS == 1 || (cj >= cb) == (band == 1)) head += to_f32(val[j]) * to_f32(x[cj]);
+        }
+        head = group_sum_dpp<kWave>(head);
+        if (lane_id() == kWave - 1) s_head[wave_id()] = head;
+    }
     __syncthreads();
+
+    // Planned unit whose rows each hold at most kRowPerThreadMax of its
+    // nonzeros (flag bit 1, from the plan): every row closes here and no
+    // row is long enough to need balancing, so thread t sums rows t, t +
+    // BLOCK, ... straight from LDS, left to right (row i0 after its head),
+    // with no search, walk or scan.
+    if constexpr (PLAN) {
+        if (short_rows) {  // uniform across the block
+            for (int32_t k = tid; k < nrows; k += BLOCK) {
+                float acc = 0.f;
+                if (k == 0) {
+#pragma unroll
+                    for (int w = 0; w < BLOCK / kWave; ++w) acc += s_head[w];
+                }
+                const int32_t lo = k == 0 ? 0 : s_re[k - 1], hi = s_re[k];
+                for (int32_t j = lo; j < hi; ++j) acc += s_pv[j];
+                if (!(k == 0 && skip_first)) y[i0 + k] = acc;
+            }
+            return;
+        }
+    }
 
     // Thread diagonal inside the block's window: local row end k sits at
     // local merged position k + s_re[k].
@@ -302,7 +354,14 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
     int32_t it = lo, jt = d - lo;
 
     // Walk: complete rows are written; the first one waits for the carry-in.
+    // Planned: thread 0 starts with row i0's head, in wavefront order.
     float acc = 0.f;
+    if constexpr (PLAN) {
+        if (tid == 0) {
+#pragma unroll
+            for (int k = 0; k < BLOCK / kWave; ++k) acc += s_head[k];
+        }
+    }
     int32_t first = -1;
     float first_sum = 0.f;
     for (int32_t q = d; q < dend; ++q) {
@@ -324,9 +383,11 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
     seg_t tot;
     const seg_t in = block_seg_scan_excl<BLOCK>(seg_t{acc, first >= 0}, s_wave, tot);
     if (first >= 0 && !(skip_first && first == 0)) y[i0 + first] = first_sum + in.v;
-    if (tid == 0) {
-        if constexpr (!PLAN) carry_row[slot * BANDS + band] = i1;  // the row still open at the block's end (rows if none)
-        carry_val[(PLAN ? b : slot) * BANDS + band] = tot.v;
+    if constexpr (!PLAN) {
+        if (tid == 0) {
+            carry_row[b * BANDS + band] = i1;  // the row still open at the block's end (rows if none)
+            carry_val[b * BANDS + band] = tot.v;
+        }
     }
 }
 
@@ -477,8 +538,8 @@ static hipError_t run_merge_spmv(const csr_dev &A, const void *x, float *y, int 
 }
 
 template <int BLOCK, int ITEMS, typename VT>
-static hipError_t run_planned_consume(const csr_dev &A, const plan_dev &pl, const void *x, float *y,
-                                      float *carry_val, float *y_hi, hipStream_t s) {
+static hipError_t run_planned_consume(const csr_dev &A, const plan_dev &pl, const void *x, float *y, float *y_hi,
+                                      hipStream_t s) {
     prof_scope p(s, "merge_consume");
     const VT *val = static_cast<const VT *>(A.val);
     const VT *xx = static_cast<const VT *>(x);
@@ -488,22 +549,25 @@ static hipError_t run_planned_consume(const csr_dev &A, const plan_dev &pl, cons
         const int64_t grid = (pl.NA + per - 1) / per * kXcds;
         hipLaunchKernelGGL((merge_spmv_consume<BLOCK, ITEMS, VT, VT, 2, false, 1, true>),
                            dim3(static_cast<uint32_t>(grid)), dim3(BLOCK), 0, s, A.rows, A.nnz, A.ro, A.ci, val, xx, y,
-                           pl.part_i, pl.part_j, nullptr, carry_val, pl.NA, cb, y_hi, nullptr, pl.active, pl.long_min);
+                           pl.part_i, pl.part_j, nullptr, nullptr, pl.NA, cb, y_hi, nullptr, pl.units);
+    } else if (pl.vec == 4 && vector_loads_ok(A)) {
+        hipLaunchKernelGGL((merge_spmv_consume<BLOCK, ITEMS, VT, VT, 1, false, 4, true>),
+                           dim3(static_cast<uint32_t>(pl.NA)), dim3(BLOCK), 0, s, A.rows, A.nnz, A.ro, A.ci, val, xx,
+                           y, pl.part_i, pl.part_j, nullptr, nullptr, pl.NA, cb, nullptr, nullptr, pl.units);
     } else {
         hipLaunchKernelGGL((merge_spmv_consume<BLOCK, ITEMS, VT, VT, 1, false, 1, true>),
                            dim3(static_cast<uint32_t>(pl.NA)), dim3(BLOCK), 0, s, A.rows, A.nnz, A.ro, A.ci, val, xx,
-                           y, pl.part_i, pl.part_j, nullptr, carry_val, pl.NA, cb, nullptr, nullptr, pl.active,
-                           pl.long_min);
+                           y, pl.part_i, pl.part_j, nullptr, nullptr, pl.NA, cb, nullptr, nullptr, pl.units);
     }
     return hipGetLastError();
 }
 
-hipError_t merge_spmv_planned_consume(const csr_dev &A, const plan_dev &pl, const void *x, float *y,
-                                      float *carry_val, float *y_hi, hipStream_t s) {
-#define X(B, I)                                                                                    \
-    if (pl.block == B && pl.items == I) {                                                          \
-        if (A.dt == LB_BF16) return run_planned_consume<B, I, bf16_bits>(A, pl, x, y, carry_val, y_hi, s); \
-        return run_planned_consume<B, I, float>(A, pl, x, y, carry_val, y_hi, s);                  \
+hipError_t merge_spmv_planned_consume(const csr_dev &A, const plan_dev &pl, const void *x, float *y, float *y_hi,
+                                      hipStream_t s) {
+#define X(B, I)                                                                              \
+    if (pl.block == B && pl.items == I) {                                                    \
+        if (A.dt == LB_BF16) return run_planned_consume<B, I, bf16_bits>(A, pl, x, y, y_hi, s); \
+        return run_planned_consume<B, I, float>(A, pl, x, y, y_hi, s);                      \
     }
     LB_MERGE_CONFIGS(X)
 #undef X

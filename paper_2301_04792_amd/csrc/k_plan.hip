@@ -20,10 +20,14 @@
 //    reduction.  A lane loads its four nonzeros with one 16-byte column load
 //    and one value load, reads x from LDS, and the group's last lane stores
 //    the task's sum (a DPP reduction).
-//  * plan_finish adds, for every long row, its task sums in (panel, task)
-//    order, and completes the short rows cut by unit boundaries (the carries
-//    of the merge path and the second column band's sums).
+//  * The short rows' merge-path blocks own whole rows (a block adds the head
+//    of its first row and leaves its open row to the unit where it closes),
+//    so they leave no carries.
+//  * plan_combine sums, for every long row, its task sums in (panel, task)
+//    order, and with two column bands adds each short row's second band.
+//    With one band and no long rows the consume is the whole call.
 // No atomics anywhere: the result is bit-reproducible for a fixed plan.
+#include <algorithm>
 #include <mutex>
 
 #include "lb_device.h"
@@ -211,116 +215,42 @@ __global__ __launch_bounds__(kPanelBlock) void panel_spmv(int32_t NP, int32_t R,
     panel_class_tasks<8, VEC>(lo[3], hi(3), 6, tasks, nnz, col0, ci, val, xs, part);
 }
 
-// ------------------------------------------------------------------ finish
+// ------------------------------------------------------------------ combine
 
-// One wavefront per item: items [0, NA) are the active merge-path units,
-// items [NA, NA + NL) the long rows.
-//  * Unit v (active): the rows that close in it, [i0, i1), are short except
-//    possibly i0.  A short i0 gets the carries of the units before v that
-//    ended inside it (the run of units u < v with part_i[u + 1] == i0, every
-//    one of them active, read backwards 64 carries at a time); with two
-//    bands every closing short row also gets the second band's sum.
-//  * Long row q: y[LR[q]] = sum of its task sums, in order (lanes stride,
-//    then a fixed butterfly).
-// Each row has exactly one writer.
-template <int BANDS>
-__global__ __launch_bounds__(256) void plan_finish(int32_t NA, int32_t NL, const int32_t *__restrict__ active,
-                                                   const int32_t *__restrict__ part_i,
-                                                   const int32_t *__restrict__ ro, int32_t long_min,
-                                                   const float *__restrict__ carry_val, float *__restrict__ y,
-                                                   const float *__restrict__ y_hi, const int32_t *__restrict__ LR,
-                                                   const int32_t *__restrict__ row_task,
-                                                   const float *__restrict__ part) {
-    const int lane = lane_id();
-    const int64_t item = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
-    if (item >= static_cast<int64_t>(NA) + NL) return;  // uniform across the wavefront
-    if (item >= NA) {
-        const int64_t q = item - NA;
-        const int32_t t0 = row_task[q], t1 = row_task[q + 1];
-        float s = 0.f;
-        for (int32_t t = t0 + lane; t < t1; t += kWave) s += part[t];
-        s = group_sum<kWave>(s);
-        if (lane == 0) y[LR[q]] = s;
+// After the consume and the panel launch.  Two bands: every short row adds
+// its second band's sum (y += y_hi; long rows, flagged in long_bits, are
+// skipped), blocks [0, EB), one row per thread.  Every long row gets the sum
+// of its task sums in (panel, task) order (lanes stride, then a fixed
+// butterfly), one wavefront per long row in the blocks after EB.  Each row
+// has one writer.
+__global__ __launch_bounds__(256) void plan_combine(int32_t rows, int32_t EB, int32_t NL,
+                                                    const uint32_t *__restrict__ long_bits, float *__restrict__ y,
+                                                    const float *__restrict__ y_hi, const int32_t *__restrict__ LR,
+                                                    const int32_t *__restrict__ row_task,
+                                                    const float *__restrict__ part) {
+    if (static_cast<int32_t>(blockIdx.x) < EB) {
+        for (int64_t r = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; r < rows;
+             r += static_cast<int64_t>(EB) * 256) {
+            const float a = y[r], h = y_hi[r];  // loaded whatever the flag: no dependent wait
+            if (((long_bits[r >> 5] >> (r & 31)) & 1u) == 0) y[r] = a + h;
+        }
         return;
     }
-    const int32_t v = active[item];
-    const int32_t i0 = part_i[v], i1 = part_i[v + 1];
-    if (i0 >= i1) return;  // no row closes in this unit
-    const bool long0 = ro[i0 + 1] - ro[i0] >= long_min;
-    const int32_t r0 = i0 + lane;
-    float first = 0.f;
-    if (r0 < i1) first = BANDS == 2 ? y[r0] + y_hi[r0] : y[r0];
-    float carried = 0.f;
-    if (!long0) {
-        for (int64_t hi = static_cast<int64_t>(v) * BANDS;; hi -= kWave) {  // carries [0, BANDS v) precede v
-            const int64_t q = hi - 1 - lane;
-            const bool match = q >= 0 && part_i[q / BANDS + 1] == i0;
-            carried += group_sum<kWave>(match ? carry_val[q] : 0.f);
-            if (__popcll(__ballot(match)) < kWave) break;  // the run started inside this chunk
-        }
-    }
-    if (r0 < i1 && !(lane == 0 && long0)) {
-        if (lane == 0)
-            y[r0] = first + carried;
-        else if (BANDS == 2)
-            y[r0] = first;
-    }
-    if (BANDS == 2)
-        for (int32_t r = r0 + kWave; r < i1; r += kWave) y[r] = y[r] + y_hi[r];
-}
-
-// One band: wavefronts [0, ceil(T / 64)) each take 64 consecutive carries
-// and add every run of equal carry rows that starts among them to its row
-// of y, as merge_fixup does (the carry of unit u belongs to row
-// part_i[u + 1]; runs of long rows, and the run of row `rows` that no row
-// owns, are skipped: their carries are not read as sums); the remaining
-// wavefronts sum the long rows' task sums.  One writer per row, fixed order.
-__global__ __launch_bounds__(256) void plan_finish_runs(int32_t T, int32_t rows, int32_t NL,
-                                                        const int32_t *__restrict__ part_i,
-                                                        const int32_t *__restrict__ ro, int32_t long_min,
-                                                        const float *__restrict__ carry_val, float *__restrict__ y,
-                                                        const int32_t *__restrict__ LR,
-                                                        const int32_t *__restrict__ row_task,
-                                                        const float *__restrict__ part) {
+    const int64_t q = static_cast<int64_t>(blockIdx.x - EB) * 4 + wave_id();
+    if (q >= NL) return;  // uniform across the wavefront
     const int lane = lane_id();
-    const int64_t item = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
-    const int64_t chunks = (static_cast<int64_t>(T) + kWave - 1) / kWave;
-    if (item >= chunks + NL) return;  // uniform across the wavefront
-    if (item >= chunks) {
-        const int64_t q = item - chunks;
-        const int32_t t0 = row_task[q], t1 = row_task[q + 1];
-        float s = 0.f;
-        for (int32_t t = t0 + lane; t < t1; t += kWave) s += part[t];
-        s = group_sum<kWave>(s);
-        if (lane == 0) y[LR[q]] = s;
-        return;
+    const int32_t t0 = row_task[q], t1 = row_task[q + 1];
+    constexpr int U = 8;  // loads in flight per lane
+    float s = 0.f;
+    for (int32_t t = t0 + lane; t < t1; t += U * kWave) {
+        float v[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) v[k] = t + k * kWave < t1 ? part[t + k * kWave] : 0.f;
+#pragma unroll
+        for (int k = 0; k < U; ++k) s += v[k];  // the lane's sums in task order
     }
-    const int64_t base = item * kWave;
-    const int64_t b = base + lane;
-    const bool in = b < T;
-    const int32_t r = in ? part_i[b + 1] : -1;
-    const bool head = in && (b == 0 || part_i[b] != r);
-    const bool tail = in && (b + 1 == T || part_i[b + 2] != r);
-    const bool own = in && r < rows && ro[r + 1] - ro[r] < long_min;  // a short row: its carries are sums
-    // the last lane's run goes on into the next chunk
-    const bool open = __ballot(lane == kWave - 1 && in && !tail) != 0;
-    const int32_t r_open = __shfl(r, kWave - 1);
-    const bool own_open = __shfl(static_cast<int>(own), kWave - 1) != 0;
-    const seg_t sc = group_seg_scan_incl<kWave>(seg_t{own ? carry_val[b] : 0.f, head});
-    if (tail && sc.f && own) y[r] += sc.v;
-    if (open && own_open) {
-        const bool owned = __shfl(static_cast<int>(sc.f), kWave - 1) != 0;  // the run starts in this chunk
-        if (owned) {  // uniform
-            float total = __shfl(sc.v, kWave - 1);
-            for (int64_t s2 = base + kWave;; s2 += kWave) {
-                const int64_t q = s2 + lane;
-                const bool match = q < T && part_i[q + 1] == r_open;
-                total += group_sum<kWave>(match ? carry_val[q] : 0.f);
-                if (__popcll(__ballot(match)) < kWave) break;  // the run ends inside this chunk
-            }
-            if (lane == 0) y[r_open] += total;
-        }
-    }
+    s = group_sum<kWave>(s);
+    if (lane == 0) y[LR[q]] = s;
 }
 
 // ------------------------------------------------------------------ plan building
@@ -474,26 +404,19 @@ hipError_t planned_spmv(const csr_dev &A, const plan_dev &pl, const void *x, flo
         if ((e = hipStreamWaitEvent(ss->s, ss->fork, 0)) != hipSuccess) return e;
         if ((e = launch_panel(A, pl, x, w.part, ss->s)) != hipSuccess) return e;
         if ((e = hipEventRecord(ss->join, ss->s)) != hipSuccess) return e;
-        if ((e = merge_spmv_planned_consume(A, pl, x, y, w.carry_val, w.y_hi, s)) != hipSuccess) return e;
+        if ((e = merge_spmv_planned_consume(A, pl, x, y, w.y_hi, s)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(s, ss->join, 0)) != hipSuccess) return e;
     } else {
         if (pl.NL > 0 && (e = launch_panel(A, pl, x, w.part, s)) != hipSuccess) return e;
-        if (pl.NA > 0 && (e = merge_spmv_planned_consume(A, pl, x, y, w.carry_val, w.y_hi, s)) != hipSuccess)
+        if (pl.NA > 0 && (e = merge_spmv_planned_consume(A, pl, x, y, w.y_hi, s)) != hipSuccess)
             return e;
     }
     prof_scope pr(s, "plan_finish");
-    if (pl.bands == 1) {
-        const int64_t items = (static_cast<int64_t>(pl.T) + kWave - 1) / kWave + pl.NL;
-        if (items == 0) return hipSuccess;
-        hipLaunchKernelGGL(plan_finish_runs, dim3(static_cast<uint32_t>((items + 3) / 4)), dim3(256), 0, s, pl.T,
-                           pl.rows, pl.NL, pl.part_i, A.ro, pl.long_min, w.carry_val, y, pl.LR, pl.row_task, w.part);
-        return hipGetLastError();
-    }
-    const int64_t items = static_cast<int64_t>(pl.NA) + pl.NL;
-    if (items == 0) return hipSuccess;
-    const int64_t blocks = (items + 3) / 4;  // a wavefront per item
-    hipLaunchKernelGGL(plan_finish<2>, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, pl.NA, pl.NL, pl.active,
-                       pl.part_i, A.ro, pl.long_min, w.carry_val, y, w.y_hi, pl.LR, pl.row_task, w.part);
+    const int64_t eb = pl.bands == 2 ? std::min<int64_t>((static_cast<int64_t>(pl.rows) + 255) / 256, 8192) : 0;
+    const int64_t blocks = eb + (static_cast<int64_t>(pl.NL) + 3) / 4;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(plan_combine, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, pl.rows,
+                       static_cast<int32_t>(eb), pl.NL, pl.long_bits, y, w.y_hi, pl.LR, pl.row_task, w.part);
     return hipGetLastError();
 }
 

@@ -27,6 +27,7 @@ namespace {
 constexpr int64_t kMaxCoord = 0x7ffffffe;  // rows + nnz must stay below this (int32 merge coordinates)
 constexpr int kDefaultBlock = 256;
 constexpr int kDefaultItems = 8;
+constexpr int kLocalItems = 12;  // planned SpMV with local columns (four nonzeros per lane)
 constexpr int kDefaultGroup = 64;
 constexpr int kMaxK = 64;
 
@@ -617,6 +618,10 @@ lb_status_t plan_params(const lb_csr_t *A, const lb_spmv_plan_t *in, lb_spmv_pla
     (void)sx;
     p.panel_cols = in->panel_cols ? in->panel_cols : static_cast<int32_t>(lbk::kPanelBytes / sx);
     p.streams = in->streams ? in->streams : 1;
+    p.vector_width = in->vector_width;  // 0: decided by the build (locality of the columns)
+    if (p.vector_width != 0 && p.vector_width != 1 && p.vector_width != 4) return LB_ERR_INVALID_ARG;
+    if (p.vector_width == 4 && p.x_bands == 2) return LB_ERR_UNSUPPORTED;
+    if (p.vector_width == 4) p.x_bands = 1;
     p.panel_blocks = in->panel_blocks;  // 0: resolved by the build from the device's CUs
     if (p.panel_blocks < 0) return LB_ERR_INVALID_ARG;
     if (p.streams != 1 && p.streams != 2) return LB_ERR_INVALID_ARG;
@@ -654,13 +659,16 @@ lbk::plan_dev plan_dev_of(const lb_spmv_plan_t &p) {
     d.streams = p.streams;
     d.block = p.block_size;
     d.items = p.items_per_thread;
+    d.vec = p.vector_width;
     d.ntasks = p.tasks;
-    const lbk::plan_layout L = lbk::plan_layout_of(p.units, p.units, p.long_rows, p.panels, p.tasks);
+    const lbk::plan_layout L = lbk::plan_layout_of(p.units, p.units, p.long_rows, p.panels, p.tasks, p.rows);
     const char *b = static_cast<const char *>(p.buffer);
     d.part_i = reinterpret_cast<const int32_t *>(b + L.part_i);
     d.part_j = reinterpret_cast<const int32_t *>(b + L.part_j);
     d.active = reinterpret_cast<const int32_t *>(b + L.active);
+    d.units = reinterpret_cast<const lbk::plan_unit *>(b + L.units);
     d.LR = reinterpret_cast<const int32_t *>(b + L.LR);
+    d.long_bits = reinterpret_cast<const uint32_t *>(b + L.long_bits);
     d.row_task = reinterpret_cast<const int32_t *>(b + L.row_task);
     d.pcls_off = reinterpret_cast<const int32_t *>(b + L.pcls_off);
     d.tasks = reinterpret_cast<const lbk::panel_task *>(b + L.tasks);
@@ -868,30 +876,42 @@ LB_API lb_status_t lb_spmv_plan_build(const lb_csr_t *A, lb_spmv_plan_t *plan, v
         if (e == hipSuccess) e = hipStreamSynchronize(hs);
         if (e != hipSuccess) return hip_status(e);
     }
-    if (p.x_bands == 0) {
-        // Two column bands pay when x is larger than an XCD's L2 (4 MiB) and
-        // the columns are scattered.  Scattered: the median column span
-        // (last - first) of up to 1024 sampled rows with two or more
+    if (p.x_bands == 0 || p.vector_width == 0) {
+        // Column locality: the columns are scattered when the median column
+        // span (last - first) of up to 1024 sampled rows with two or more
         // nonzeros exceeds cols / 16 (a stencil's rows span a few grid rows).
-        const int64_t sx = A->value_dtype == LB_BF16 ? 2 : 4;
-        p.x_bands = 1;
-        if (A->cols * sx >= (int64_t(4) << 20)) {
-            std::vector<int32_t> pos;
-            const int64_t step = std::max<int64_t>(1, rows / 1024);
-            for (int64_t r = 0; r < rows && pos.size() < 2048; r += step)
-                if (ro[r + 1] - ro[r] >= 2) {
-                    pos.push_back(ro[r]);
-                    pos.push_back(ro[r + 1] - 1);
-                }
-            std::vector<int32_t> cols(pos.size());
-            lb_status_t sst = device_gather(A->col_idx, pos, cols, hs);
-            if (sst != LB_OK) return sst;
-            std::vector<int64_t> span;
-            for (size_t i = 0; i + 1 < cols.size(); i += 2) span.push_back(static_cast<int64_t>(cols[i + 1]) - cols[i]);
-            if (!span.empty()) {
-                std::nth_element(span.begin(), span.begin() + span.size() / 2, span.end());
-                if (span[span.size() / 2] > A->cols / 16) p.x_bands = 2;
+        // Two column bands pay when x is larger than an XCD's L2 (4 MiB) and
+        // the columns are scattered; four nonzeros per lane and load pay when
+        // they are local (one band).
+        bool scattered = false;
+        std::vector<int32_t> pos;
+        const int64_t step = std::max<int64_t>(1, rows / 1024);
+        for (int64_t r = 0; r < rows && pos.size() < 2048; r += step)
+            if (ro[r + 1] - ro[r] >= 2) {
+                pos.push_back(ro[r]);
+                pos.push_back(ro[r + 1] - 1);
             }
+        std::vector<int32_t> cols(pos.size());
+        lb_status_t sst = device_gather(A->col_idx, pos, cols, hs);
+        if (sst != LB_OK) return sst;
+        std::vector<int64_t> span;
+        for (size_t i = 0; i + 1 < cols.size(); i += 2) span.push_back(static_cast<int64_t>(cols[i + 1]) - cols[i]);
+        if (!span.empty()) {
+            std::nth_element(span.begin(), span.begin() + span.size() / 2, span.end());
+            scattered = span[span.size() / 2] > A->cols / 16;
+        }
+        const int64_t sx = A->value_dtype == LB_BF16 ? 2 : 4;
+        if (p.x_bands == 0) p.x_bands = scattered && A->cols * sx >= (int64_t(4) << 20) ? 2 : 1;
+        if (p.vector_width == 0) p.vector_width = !scattered && p.x_bands == 1 ? 4 : 1;
+        if (plan->items_per_thread == 0 && p.vector_width == 4) {
+            // local columns: longer units (12 items per thread) amortize each
+            // block's fixed latency (split, search, scan) over more nonzeros
+            lb_spmv_plan_t in2 = *plan;
+            in2.items_per_thread = kLocalItems;
+            in2.x_bands = p.x_bands;
+            in2.vector_width = p.vector_width;
+            st = plan_params(A, &in2, &p);
+            if (st != LB_OK) return st;
         }
     }
     std::vector<int32_t> LR;
@@ -921,9 +941,9 @@ LB_API lb_status_t lb_spmv_plan_build(const lb_csr_t *A, lb_spmv_plan_t *plan, v
     const int64_t T = p.units;
     p.tasks = static_cast<int32_t>(task_bound);  // a bound until the build
     p.active_units = static_cast<int32_t>(T);    // a bound until the build
-    const lbk::plan_layout L = lbk::plan_layout_of(T, T, p.long_rows, NP, task_bound);
+    const lbk::plan_layout L = lbk::plan_layout_of(T, T, p.long_rows, NP, task_bound, rows);
     p.plan_bytes = L.total;
-    p.workspace_bytes = lbk::plan_ws_bytes(T, p.x_bands, rows, task_bound);
+    p.workspace_bytes = lbk::plan_ws_bytes(p.x_bands, rows, task_bound);
     p.buffer = nullptr;
     if (!buffer || buffer_bytes < p.plan_bytes) {
         *plan = p;
@@ -937,7 +957,8 @@ LB_API lb_status_t lb_spmv_plan_build(const lb_csr_t *A, lb_spmv_plan_t *plan, v
     int32_t *sb = reinterpret_cast<int32_t *>(b + L.sb);
     int32_t *active = reinterpret_cast<int32_t *>(b + L.active);
     const int64_t nsb = static_cast<int64_t>(p.long_rows) * (NP + 1);
-    std::vector<int32_t> h_sb(static_cast<size_t>(nsb)), h_part(static_cast<size_t>(T + 1));
+    std::vector<int32_t> h_sb(static_cast<size_t>(nsb)), h_part(static_cast<size_t>(T + 1)),
+        h_partj(static_cast<size_t>(T + 1));
     int32_t h_flags = 0;
     hipError_t e = hipMemsetAsync(flags, 0, 4, hs);
     if (e == hipSuccess && rows > 0)
@@ -950,6 +971,8 @@ LB_API lb_status_t lb_spmv_plan_build(const lb_csr_t *A, lb_spmv_plan_t *plan, v
     if (e == hipSuccess && nsb > 0) e = hipMemcpyAsync(h_sb.data(), sb, h_sb.size() * 4, hipMemcpyDeviceToHost, hs);
     if (e == hipSuccess && rows > 0)
         e = hipMemcpyAsync(h_part.data(), part_i, h_part.size() * 4, hipMemcpyDeviceToHost, hs);
+    if (e == hipSuccess && rows > 0)
+        e = hipMemcpyAsync(h_partj.data(), part_j, h_partj.size() * 4, hipMemcpyDeviceToHost, hs);
     if (e == hipSuccess) e = hipMemcpyAsync(&h_flags, flags, 4, hipMemcpyDeviceToHost, hs);
     if (e == hipSuccess) e = hipStreamSynchronize(hs);
     if (e != hipSuccess) return hip_status(e);
@@ -995,16 +1018,38 @@ LB_API lb_status_t lb_spmv_plan_build(const lb_csr_t *A, lb_spmv_plan_t *plan, v
         }
         pcls_off.back() = static_cast<int32_t>(tasks.size());
     }
-    // units with short-row work: a row strictly inside closes in it, or its
-    // first closing row or its open row is short
+    // units with short-row work: a short row closes in it (only its first
+    // closing row can be long); a short row is owned, whole, by the unit
+    // where it closes
     std::vector<int32_t> h_active;
     h_active.reserve(static_cast<size_t>(T));
     auto is_short = [&](int64_t r) { return static_cast<int64_t>(ro[r + 1]) - ro[r] < p.long_min; };
+    std::vector<lbk::plan_unit> h_units;
+    h_units.reserve(static_cast<size_t>(T));
     for (int64_t u = 0; u < T; ++u) {
-        const int64_t i0 = h_part[u], i1 = h_part[u + 1];
-        if (i1 > i0 + 1 || (i0 < i1 && is_short(i0)) || (i1 < rows && is_short(i1)))
-            h_active.push_back(static_cast<int32_t>(u));
+        const int32_t i0 = h_part[u], i1 = h_part[u + 1];
+        if (!(i1 > i0 + 1 || (i0 < i1 && is_short(i0)))) continue;
+        h_active.push_back(static_cast<int32_t>(u));
+        // the record its block reads: products of [ja, jb) (a long first row
+        // and the open row left out), the head of row i0 (ro[i0] <= j0)
+        lbk::plan_unit r{i0, i1, h_partj[u], h_partj[u + 1], h_partj[u], h_partj[u + 1], ro[i0], 0};
+        if (!is_short(i0)) {
+            r.flags = 1;
+            r.ja = ro[i0 + 1];
+            r.h0 = r.j0;
+        }
+        if (i1 < rows) r.jb = std::min(ro[i1], r.j1);
+        if (r.jb < r.ja) r.jb = r.ja;
+        if (!r.flags) {  // a long row i0 keeps the merge walk (its nonzeros are skipped there)
+            int64_t most = 0;
+            for (int32_t q = i0; q < i1 && most <= lbk::kRowPerThreadMax; ++q)
+                most = std::max<int64_t>(most, static_cast<int64_t>(ro[q + 1]) - std::max(ro[q], r.j0));
+            if (most <= lbk::kRowPerThreadMax) r.flags |= 2;
+        }
+        h_units.push_back(r);
     }
+    std::vector<uint32_t> long_bits(static_cast<size_t>((rows + 31) / 32), 0u);
+    for (int32_t r : LR) long_bits[static_cast<size_t>(r) >> 5] |= 1u << (r & 31);
     e = hipSuccess;
     auto up = [&](size_t off, const void *src, size_t bytes) {
         if (e == hipSuccess && bytes > 0) e = hipMemcpyAsync(b + off, src, bytes, hipMemcpyHostToDevice, hs);
@@ -1013,11 +1058,13 @@ LB_API lb_status_t lb_spmv_plan_build(const lb_csr_t *A, lb_spmv_plan_t *plan, v
     up(L.pcls_off, pcls_off.data(), pcls_off.size() * 4);
     up(L.tasks, tasks.data(), tasks.size() * sizeof(lbk::panel_task));
     up(L.active, h_active.data(), h_active.size() * 4);
+    up(L.units, h_units.data(), h_units.size() * sizeof(lbk::plan_unit));
+    up(L.long_bits, long_bits.data(), long_bits.size() * 4);
     if (e == hipSuccess) e = hipStreamSynchronize(hs);
     if (e != hipSuccess) return hip_status(e);
     p.active_units = static_cast<int32_t>(h_active.size());
     p.tasks = static_cast<int32_t>(ntasks);
-    p.workspace_bytes = lbk::plan_ws_bytes(T, p.x_bands, rows, ntasks);
+    p.workspace_bytes = lbk::plan_ws_bytes(p.x_bands, rows, ntasks);
     p.buffer = buffer;
     *plan = p;
     (void)active;

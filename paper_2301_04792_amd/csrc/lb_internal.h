@@ -117,6 +117,16 @@ constexpr int kPanelClasses = 4;
 // The class of a task spanning ng aligned groups: G = 64 >> class.
 inline int panel_class(int64_t ng) { return ng > 32 ? 0 : (ng > 16 ? 1 : (ng > 8 ? 2 : 3)); }
 
+// An active unit of the short rows' merge path, as its block needs it: the
+// split at both ends, the nonzeros whose products it sums [ja, jb), the
+// first nonzero h0 of row i0's head [h0, j0) (h0 = j0: none) and flags
+// (bit 0: row i0 is long, its y is not this block's; bit 1: every row that
+// closes in the unit has at most kRowPerThreadMax of its nonzeros in it).
+struct alignas(16) plan_unit {
+    int32_t i0, i1, j0, j1, ja, jb, h0, flags;
+};
+constexpr int kRowPerThreadMax = 16;
+
 // A task: nonzeros [a0, a0 + len) of one segment; its sum goes to part[out].
 struct alignas(16) panel_task {
     int32_t a0, len, out, pad;
@@ -131,11 +141,14 @@ struct plan_dev {
     int32_t P;           // columns per panel
     int32_t long_min;
     int32_t bands, block, items;
+    int32_t vec;         // 4: the short rows' consume loads four nonzeros per lane (one band)
     int32_t streams;     // 2: the long rows' launch on the library's second stream
     int32_t ntasks;
     const int32_t *part_i, *part_j;  // the split at every unit boundary, T + 1 each
     const int32_t *active;           // NA unit ids, ascending
+    const plan_unit *units;          // NA records, one per active unit, in the same order
     const int32_t *LR;               // NL long row ids, ascending
+    const uint32_t *long_bits;       // ceil(rows / 32) words: bit r % 32 of word r / 32 set for a long row r
     const int32_t *row_task;         // NL + 1: long row q's task sums are part[row_task[q] .. row_task[q + 1])
     const int32_t *pcls_off;         // NP * 4 + 1: panel p's class-k tasks are [pcls_off[4p + k], pcls_off[4p + k + 1])
     const panel_task *tasks;         // ntasks, grouped by panel, then class
@@ -146,9 +159,10 @@ struct plan_dev {
 // ntask_cap for the tasks (the last table); sb (NL x (NP + 1) segment bounds)
 // is written by the build on the device and read back.
 struct plan_layout {
-    size_t flags, part_i, part_j, active, LR, row_task, pcls_off, tasks, sb, total;
+    size_t flags, part_i, part_j, active, units, LR, long_bits, row_task, pcls_off, tasks, sb, total;
 };
-inline plan_layout plan_layout_of(int64_t T, int64_t NA_cap, int64_t NL, int64_t NP, int64_t ntask_cap) {
+inline plan_layout plan_layout_of(int64_t T, int64_t NA_cap, int64_t NL, int64_t NP, int64_t ntask_cap,
+                                  int64_t rows) {
     plan_layout L{};
     size_t o = 0;
     auto take = [&o](size_t bytes) {
@@ -160,7 +174,9 @@ inline plan_layout plan_layout_of(int64_t T, int64_t NA_cap, int64_t NL, int64_t
     L.part_i = take(static_cast<size_t>(T + 1) * 4);
     L.part_j = take(static_cast<size_t>(T + 1) * 4);
     L.active = take(static_cast<size_t>(NA_cap) * 4);
+    L.units = take(static_cast<size_t>(NA_cap) * sizeof(plan_unit));
     L.LR = take(static_cast<size_t>(NL) * 4);
+    L.long_bits = take(static_cast<size_t>((rows + 31) / 32) * 4);
     L.row_task = take(static_cast<size_t>(NL + 1) * 4);
     L.pcls_off = take(static_cast<size_t>(NP * kPanelClasses + 1) * 4);
     L.sb = take(static_cast<size_t>(NL) * (NP + 1) * 4);
@@ -169,21 +185,17 @@ inline plan_layout plan_layout_of(int64_t T, int64_t NA_cap, int64_t NL, int64_t
     return L;
 }
 
-// Per-call workspace: carry_val[T * bands], y_hi[rows] (two bands), part[ntasks].
+// Per-call workspace: y_hi[rows] (two bands), part[ntasks].
 struct plan_ws {
-    float *carry_val;
     float *y_hi;
     float *part;
 };
-inline size_t plan_ws_bytes(int64_t T, int bands, int64_t rows, int64_t ntasks) {
-    return align256(static_cast<size_t>(T) * bands * 4) + (bands == 2 ? align256(static_cast<size_t>(rows) * 4) : 0) +
-           align256(static_cast<size_t>(ntasks) * 4);
+inline size_t plan_ws_bytes(int bands, int64_t rows, int64_t ntasks) {
+    return (bands == 2 ? align256(static_cast<size_t>(rows) * 4) : 0) + align256(static_cast<size_t>(ntasks) * 4);
 }
 inline plan_ws plan_ws_carve(void *base, const plan_dev &pl) {
     char *p = static_cast<char *>(base);
     plan_ws w{};
-    w.carry_val = reinterpret_cast<float *>(p);
-    p += align256(static_cast<size_t>(pl.T) * pl.bands * 4);
     if (pl.bands == 2) {
         w.y_hi = reinterpret_cast<float *>(p);
         p += align256(static_cast<size_t>(pl.rows) * 4);
@@ -198,8 +210,8 @@ bool panel_cols_ok(int64_t P, lb_dtype_t xt);
 hipError_t plan_segments_launch(int32_t NL, int32_t NP, int32_t P, const int32_t *LR, const int32_t *ro,
                                 const int32_t *ci, int32_t *sb, int32_t *flags, hipStream_t s);
 // The short rows' merge-path consume over the active units (k_merge.hip).
-hipError_t merge_spmv_planned_consume(const csr_dev &A, const plan_dev &pl, const void *x, float *y,
-                                      float *carry_val, float *y_hi, hipStream_t s);
+hipError_t merge_spmv_planned_consume(const csr_dev &A, const plan_dev &pl, const void *x, float *y, float *y_hi,
+                                      hipStream_t s);
 // y = A x with a built plan; ws holds plan_ws_bytes(...).
 hipError_t planned_spmv(const csr_dev &A, const plan_dev &pl, const void *x, float *y, void *ws, hipStream_t s);
 

@@ -35,7 +35,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_version_and_status_strings():
     L = _abi.load()
-    assert L.lb_abi_version() == 3
+    assert L.lb_abi_version() == 4
     for st in range(9):
         assert L.lb_status_string(st) not in (b"", b"unknown status")
     assert L.lb_status_string(99) == b"unknown status"

@@ -23,18 +23,22 @@ from paper_2301_04792_amd import _abi  # noqa: E402
 
 DEV = "cuda:0"
 
-# (block_size, items_per_thread, x_bands, long_min, panel_cols); 0 = default
+# (block_size, items_per_thread, x_bands, long_min, panel_cols, vector_width); 0 = default
 PLANS = [
-    (128, 4, 1, 512, 64),
-    (128, 4, 2, 512, 256),
-    (128, 8, 1, 1024, 128),
-    (256, 8, 2, 2048, 1024),
-    (256, 8, 1, 0, 0),
-    (256, 8, 2, 0, 0),
-    (512, 16, 1, 8192, 4096),
-    (256, 8, 1, -1, 0),  # no long rows: the merge path with the split precomputed
+    (128, 4, 1, 512, 64, 1),
+    (128, 4, 2, 512, 256, 0),
+    (128, 8, 1, 1024, 128, 0),
+    (256, 8, 2, 2048, 1024, 0),
+    (256, 8, 1, 0, 0, 1),
+    (256, 8, 2, 0, 0, 0),
+    (512, 16, 1, 8192, 4096, 1),
+    (256, 8, 1, -1, 0, 1),  # no long rows: the merge path with the split precomputed
+    (128, 4, 1, 512, 64, 4),  # four nonzeros per lane and load in the short rows' consume
+    (256, 12, 1, 0, 0, 4),
+    (512, 16, 1, 8192, 4096, 4),  # heads of short rows longer than a unit
+    (256, 8, 1, -1, 0, 4),
 ]
-PLAN_IDS = [f"b{b}i{i}x{x}L{l}P{p}" for b, i, x, l, p in PLANS]
+PLAN_IDS = [f"b{b}i{i}x{x}L{l}P{p}v{v}" for b, i, x, l, p, v in PLANS]
 
 
 def upload(A, x, dtype=torch.float32):
@@ -47,9 +51,11 @@ def upload(A, x, dtype=torch.float32):
 
 
 def planned(A, x, cfg, dtype=torch.float32):
-    b, i, xb, lm, p = cfg
+    b, i, xb, lm, p, v = cfg
     Ad, xd = upload(A, x, dtype)
-    plan = lb.Plan(Ad, block_size=b, items_per_thread=i, x_bands=xb, long_min=lm, panel_cols=p)
+    plan = lb.Plan(Ad, block_size=b, items_per_thread=i, x_bands=xb, long_min=lm, panel_cols=p, vector_width=v)
+    if v:
+        assert plan.c.vector_width == v
     return Ad, xd, plan, lb.spmv_planned(Ad, plan, xd)
 
 
@@ -80,7 +86,8 @@ def test_planned_matches_oracle(mname, cfg):
 
 
 @pytest.mark.parametrize("mname", sorted(S.special_matrices().keys()))
-@pytest.mark.parametrize("cfg", [PLANS[0], PLANS[1], PLANS[4]], ids=[PLAN_IDS[0], PLAN_IDS[1], PLAN_IDS[4]])
+@pytest.mark.parametrize("cfg", [PLANS[0], PLANS[1], PLANS[4], PLANS[8]],
+                         ids=[PLAN_IDS[0], PLAN_IDS[1], PLAN_IDS[4], PLAN_IDS[8]])
 def test_planned_special_shapes(mname, cfg):
     A, x = S.special_matrices()[mname]
     print(f"[plan special {mname} {cfg}]", flush=True)
@@ -105,7 +112,7 @@ def test_planned_integer_bit_exact(cfg):
     assert np.array_equal(got, ref), f"{cfg}: {int((got != ref).sum())} rows differ"
 
 
-@pytest.mark.parametrize("cfg", [PLANS[1], PLANS[5]], ids=[PLAN_IDS[1], PLAN_IDS[5]])
+@pytest.mark.parametrize("cfg", [PLANS[1], PLANS[5], PLANS[9]], ids=[PLAN_IDS[1], PLAN_IDS[5], PLAN_IDS[9]])
 def test_planned_bf16(cfg):
     A, x = S.powerlaw_csr(39, 100_000, 100_000, 1.8, 30_000, 0.1)
     Ab = A.with_values(S.to_bf16_bits(A.values))
@@ -120,7 +127,7 @@ def test_planned_reproducible_and_values_change():
     the pattern only, so new values (and x) on the same pattern give the
     oracle's result for them."""
     A, x = S.powerlaw_csr(40, 150_000, 150_000, 1.8, 50_000, 0.1)
-    cfg = (128, 8, 2, 1024, 512)
+    cfg = (128, 8, 2, 1024, 512, 0)
     Ad, xd, plan, y1 = planned(A, x, cfg)
     y2 = lb.spmv_planned(Ad, plan, xd)
     assert torch.equal(y1, y2)
@@ -134,25 +141,24 @@ def test_planned_reproducible_and_values_change():
 
 
 def test_planned_matches_merge_path_on_short_rows_only():
-    """With no long rows the planned call runs the same merge-path consume
-    with the same split.  With two bands its finishing pass also sums the
-    carries in the same order as lb_spmv's, so the two agree bit for bit;
-    with one band lb_spmv's fix-up sums carry runs in another order, so only
-    the rows that no unit boundary cuts must agree bit for bit."""
+    """With no long rows the planned call uses the same split as lb_spmv.  A
+    row whose merge items all fall in one thread's share (ITEMS items) is
+    summed left to right from zero by lb_spmv's walk and by the planned
+    block (its walk, or its row-per-thread pass), so those rows agree bit for
+    bit (one or two bands).  Other rows are combined in another order (a
+    unit's head, the block scan): within tolerance."""
     A, x = S.powerlaw_csr(43, 100_000, 100_000, 1.8, 30_000, 0.1)
     ref, scale = oracle_spmv(A, x)
+    ITEMS = 8
+    ro = A.row_offsets.astype(np.int64)
+    start = ro[:-1] + np.arange(A.m)  # merge position of each row's first item
+    end = ro[1:] + np.arange(A.m)     # merge position of each row's end
+    uncut = start // ITEMS == end // ITEMS
+    assert uncut.sum() > A.m // 4 and (~uncut).sum() > 10
     for bands in (1, 2):
-        Ad, xd, plan, y = planned(A, x, (256, 8, bands, -1, 0))
+        Ad, xd, plan, y = planned(A, x, (256, 8, bands, -1, 0, 1))
         y_ref = lb.spmv(Ad, xd, "merge_path", block_size=256, items_per_thread=8, x_bands=bands)
-        if bands == 2:
-            assert torch.equal(y, y_ref)
-        else:
-            W = 256 * 8
-            ro = A.row_offsets.astype(np.int64)
-            start = ro[:-1] + np.arange(A.m)  # merge position of each row's first item
-            end = ro[1:] + np.arange(A.m)     # merge position of each row's end
-            uncut = start // W == end // W
-            assert np.array_equal(y.cpu().numpy()[uncut], y_ref.cpu().numpy()[uncut])
+        assert np.array_equal(y.cpu().numpy()[uncut], y_ref.cpu().numpy()[uncut]), bands
         assert_rows_close(y.cpu().numpy(), ref, scale, what=f"bands {bands}")
 
 
@@ -249,6 +255,9 @@ def test_planned_array_tail_and_misaligned(extra):
     assert plan.c.long_rows == 2
     got = lb.spmv_planned(Ad, plan, xd).cpu().numpy().astype(np.float64)
     assert np.array_equal(got, ref)
+    plan4 = lb.Plan(Ad, block_size=128, items_per_thread=4, long_min=512, panel_cols=1024, vector_width=4)
+    got = lb.spmv_planned(Ad, plan4, xd).cpu().numpy().astype(np.float64)
+    assert np.array_equal(got, ref)
     # misaligned copies of col_idx and values (offset by one element inside a larger buffer)
     ci = torch.zeros(A.nnz + 1, dtype=torch.int32, device=DEV)
     vals = torch.zeros(A.nnz + 1, dtype=torch.float32, device=DEV)
@@ -258,3 +267,39 @@ def test_planned_array_tail_and_misaligned(extra):
     assert Am.col_idx.data_ptr() % 16 != 0
     got2 = lb.spmv_planned(Am, plan, xd).cpu().numpy().astype(np.float64)
     assert np.array_equal(got2, ref)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_planned_local_columns(dtype):
+    """A stencil (local columns): the plan picks one band and four nonzeros
+    per lane and load by default; with no long rows the call is the consume
+    alone.  Integer inputs: bit-exact; random inputs: the oracle's tolerance."""
+    L, x = S.config_c3_laplacian(N=300)
+    Li, xi = S.integer_valued(L, 11)
+    Ad, xd = upload(Li, xi, dtype)
+    plan = lb.Plan(Ad)
+    assert plan.c.x_bands == 1 and plan.c.vector_width == 4 and plan.c.long_rows == 0
+    ref, _ = oracle_spmv(Li, xi)
+    got = lb.spmv_planned(Ad, plan, xd).cpu().numpy().astype(np.float64)
+    assert np.array_equal(got, ref)
+    if dtype == torch.bfloat16:
+        L = L.with_values(S.to_bf16_bits(L.values))
+        x = S.to_bf16_bits(x)
+    Ad, xd = upload(L, x, dtype)
+    for cfg in ((256, 8, 0, 0, 0, 0), (512, 16, 1, 0, 0, 4), (128, 4, 1, -1, 0, 4)):
+        _, _, plan, y = planned(L, x, cfg, dtype)
+        ref, scale = oracle_spmv(L, x)
+        assert_rows_close(y.cpu().numpy(), ref, scale, what=f"stencil {cfg}")
+
+
+def test_plan_vector_width_args():
+    A, x = S.config_c1()
+    Ad, xd = upload(A, x)
+    with pytest.raises(lb.LBError) as e:
+        lb.Plan(Ad, x_bands=2, vector_width=4)
+    assert e.value.status == _abi.ERR_UNSUPPORTED
+    with pytest.raises(lb.LBError) as e:
+        lb.Plan(Ad, vector_width=2)
+    assert e.value.status == _abi.ERR_INVALID_ARG
+    p4 = lb.Plan(Ad, vector_width=4)
+    assert p4.c.x_bands == 1 and p4.c.vector_width == 4
