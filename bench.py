@@ -139,6 +139,8 @@ TRACES = {
     "batched512": ("batched SpMM over 512 power-law matrices, k = 1 and k = 8 (autotuned)",
                    "--only batched --no-cpu"),
     "spgemm": ("SpGEMM (Laplacian 1024^2 squared, power-law 100k squared)", "--only spgemm --no-cpu"),
+    "uniform4096": ("the 4096^2 uniform matrix (launch-bound): every schedule and the planned call",
+                    "--only uniform --no-cpu"),
     "traversal_powerlaw1M": ("SSSP and BFS on the 1M-vertex power-law graph, every schedule",
                              "--graph-only --no-cpu"),
 }
@@ -158,6 +160,10 @@ COUNTERS = {
     "batched512": ("--only batched --no-cpu --steps 3 --pmc-calib",
                    ["FETCH_SIZE", "WRITE_SIZE", "TCC_HIT_sum TCC_MISS_sum",
                     "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_ACTIVE_INST_LDS"]),
+    "bf16_laplacian_powerlaw2M": ("--only bf16 --no-cpu --steps 3 --pmc-calib",
+                                  ["FETCH_SIZE", "WRITE_SIZE", "TCC_HIT_sum TCC_MISS_sum",
+                                   "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY "
+                                   "SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_SALU"]),
 }
 
 
@@ -166,13 +172,12 @@ def _short_name(name, width=100):
 
 
 def _copy_calibration(rows):
-    """(fetch factor, write factor) from the 256 MiB device copy run with --pmc-calib, or None."""
-    def torch_copy(r):  # the calibration copy: torch's device copy kernel, not the runtime's blits
-        name = r.get("Kernel_Name", "").lower()
-        return "copy" in name and "rocclr" not in name
+    """(fetch factor, write factor) from the 256 MiB probe copy run with --pmc-calib, or None."""
+    def probe_copy(r):  # the calibration copy: the library's probe_copy_kernel
+        return "probe_copy" in r.get("Kernel_Name", "")
 
-    f = [float(r["Counter_Value"]) for r in rows if r.get("Counter_Name") == "FETCH_SIZE" and torch_copy(r)]
-    w = [float(r["Counter_Value"]) for r in rows if r.get("Counter_Name") == "WRITE_SIZE" and torch_copy(r)]
+    f = [float(r["Counter_Value"]) for r in rows if r.get("Counter_Name") == "FETCH_SIZE" and probe_copy(r)]
+    w = [float(r["Counter_Value"]) for r in rows if r.get("Counter_Name") == "WRITE_SIZE" and probe_copy(r)]
     known = float(1 << 28)
     return (known / (max(f) * 1024.0) if f else None, known / (max(w) * 1024.0) if w else None,
             max(f) if f else None, max(w) if w else None)
@@ -386,7 +391,7 @@ def main():
     if args.pmc_calib:  # a device copy of known size for the counter runs' calibration
         src = torch.ones(1 << 26, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)  # reads and writes exactly 256 MiB
+        lb.probe_copy(src, dst)  # reads and writes exactly 256 MiB, as probe_copy_kernel
         torch.cuda.synchronize()
         del src, dst
 
@@ -586,7 +591,8 @@ def main():
             short_nnz = A.nnz - long_nnz
             kernel_bytes["merge_consume"] = short_nnz * 8 + (A.m + 1) * 4 + A.m * 4 + A.n * 4
             kernel_bytes["panel_consume"] = long_nnz * 8 + A.n * 4 + int(plan_info["tasks"]) * 4
-            kernel_bytes["plan_finish"] = int(plan_info["tasks"]) * 4 + int(plan_info["long_rows"]) * 4
+            kernel_bytes["plan_finish"] = (int(plan_info["tasks"]) * 4 + int(plan_info["long_rows"]) * 4 +
+                                           (A.m * 12 + A.m // 8 if int(plan_info["x_bands"]) == 2 else 0))
         else:
             kernel_bytes[dominant] = B
         B_dom = kernel_bytes.get(dominant, B)
@@ -782,6 +788,9 @@ def main():
             t = timed(lambda name=name, p=p, ws1=ws1: lb.spmv(A1d, x1d, name, y=y1, workspace=ws1, **p), 50, 10)
             key = name + ("" if not p else "_" + "_".join(f"{k}{v}" for k, v in p.items()))
             small[key] = round(t * 1e3, 2)
+        pl1 = lb.Plan(A1d)
+        wsp1 = torch.empty(max(pl1.workspace_bytes, 1), dtype=torch.uint8, device=dev)
+        small["planned"] = round(timed(lambda: lb.spmv_planned(A1d, pl1, x1d, y=y1, workspace=wsp1), 50, 10) * 1e3, 2)
         result["uniform4096"] = small
         log(f"[bench] uniform 4096: {small}")
         del A1d, x1d, y1

@@ -548,7 +548,7 @@ LB_API lb_status_t lb_spgemm_compute(const lb_csr_t *A, const lb_csr_t *B, const
  * Each iteration takes the current frontier (a device list of vertex ids:
  * an indexed tile set) and relaxes every out-edge of its vertices under the
  * schedule s; the vertices that improve form the next frontier, each listed
- * once.  The host repeats until the frontier is empty (Sec. 5.3), reading
+ * once.  The host launches again while the frontier holds vertices (Sec. 5.3), reading
  * the frontier size from the device once per batch of iterations, so these
  * calls synchronize `stream`.
  * Schedules: LB_THREAD_MAPPED (a thread per frontier vertex, block_size as
@@ -607,8 +607,13 @@ LB_API lb_status_t lb_bfs(const lb_csr_t *G, int64_t source, int32_t *depth, con
  *    gathering only the entries of its band of x (columns [b * cb, (b + 1) *
  *    cb), cb = ceil(cols / bands)), XCD x serving band x mod bands (grid
  *    rounded down to a multiple of 8, at least 8).
- * Both are asynchronous on `stream`; idx values must lie in [0, cols). */
+ *  lb_probe_copy: copies `bytes` (a multiple of 16, both buffers 16-byte
+ *    aligned, not overlapping) from src to dst with 16-byte loads and
+ *    stores; a copy of known size under this kernel's own name, against
+ *    which hardware traffic counters are calibrated.
+ * All are asynchronous on `stream`; idx values must lie in [0, cols). */
 LB_API lb_status_t lb_probe_stream_read(const void *buf, size_t bytes, float *out, int32_t grid, void *stream);
+LB_API lb_status_t lb_probe_copy(const void *src, void *dst, size_t bytes, void *stream);
 LB_API lb_status_t lb_probe_gather(const int32_t *idx, int64_t n, const float *x, int64_t cols, float *out,
                                    int32_t grid, int32_t bands, void *stream);
 LB_API int32_t lb_probe_default_grid(void);

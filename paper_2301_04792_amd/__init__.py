@@ -493,6 +493,16 @@ def probe_stream_read(buf: torch.Tensor, out: torch.Tensor | None = None) -> tor
     return out
 
 
+def probe_copy(src: torch.Tensor, dst: torch.Tensor) -> torch.Tensor:
+    """Copy src to dst with the library's copy probe (a kernel of its own name
+    for calibrating traffic counters; measurement hook)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst differ in size")
+    _abi.check(_lib.lb_probe_copy(_ptr(src), _ptr(dst), nbytes, _stream(src.device)), "lb_probe_copy")
+    return dst
+
+
 def probe_gather(idx: torch.Tensor, x: torch.Tensor, out: torch.Tensor | None = None, bands: int = 1) -> torch.Tensor:
     """Launch the gather probe: partial sums of x[idx], one band over all
     XCDs, or 2, 4 or 8 column bands spread over the XCDs (measurement hook)."""

@@ -143,6 +143,7 @@ SIGNATURES = {
     "lb_sssp": (ST, [PCSR, I64, P, PSCHED, I32, ctypes.POINTER(I32), P, SZ, P]),
     "lb_bfs": (ST, [PCSR, I64, P, PSCHED, I32, ctypes.POINTER(I32), P, SZ, P]),
     "lb_probe_stream_read": (ST, [P, SZ, P, I32, P]),
+    "lb_probe_copy": (ST, [P, P, SZ, P]),
     "lb_probe_gather": (ST, [P, I64, P, I64, P, I32, I32, P]),
     "lb_probe_default_grid": (I32, []),
     "lb_profile_enable": (None, [ctypes.c_int]),

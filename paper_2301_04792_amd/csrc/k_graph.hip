@@ -6,7 +6,7 @@
 // Iteration i takes frontier F_i, a compacted list of vertex ids (the tiles
 // of an indexed_tile_set), and relaxes every out-edge of its vertices under
 // the chosen schedule; the vertices that improve form F_{i+1}, each listed
-// once.  The host repeats until the frontier is empty (Sec. 5.3).
+// once.  The host launches again while the frontier holds vertices (Sec. 5.3).
 //  * SSSP: dist is float32.  The offer dist[u] + w is one float32 addition
 //    and an atomic minimum on the bit pattern keeps the smaller value
 //    (non-negative floats order like their int32 bit patterns).  A vertex

@@ -35,6 +35,20 @@ __global__ __launch_bounds__(256) void probe_gather_kernel(const int32_t *__rest
     out[static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x] = (a0 + a1) + (a2 + a3);
 }
 
+__global__ __launch_bounds__(256) void probe_copy_kernel(const f32x4 *__restrict__ src, f32x4 *__restrict__ dst,
+                                                         int64_t n4) {
+    for (int64_t i : grid_stride_range(0, n4)) dst[i] = src[i];
+}
+
+hipError_t probe_copy(const void *src, void *dst, size_t bytes, hipStream_t s) {
+    const int64_t n4 = static_cast<int64_t>(bytes / 16);
+    int64_t grid = (n4 + 255) / 256;
+    if (grid > 65536) grid = 65536;
+    hipLaunchKernelGGL(probe_copy_kernel, dim3(static_cast<uint32_t>(grid)), dim3(256), 0, s,
+                       static_cast<const f32x4 *>(src), static_cast<f32x4 *>(dst), n4);
+    return hipGetLastError();
+}
+
 hipError_t probe_stream_read(const void *buf, size_t bytes, float *out, int grid, hipStream_t s) {
     prof_scope p(s, "probe_stream");
     hipLaunchKernelGGL(probe_stream_kernel, dim3(grid), dim3(256), 0, s, static_cast<const f32x4 *>(buf),

@@ -1638,6 +1638,16 @@ LB_API lb_status_t lb_probe_stream_read(const void *buf, size_t bytes, float *ou
     return hip_status(lbk::probe_stream_read(buf, bytes, out, grid, static_cast<hipStream_t>(stream)));
 }
 
+LB_API lb_status_t lb_probe_copy(const void *src, void *dst, size_t bytes, void *stream) {
+    if (!src || !dst || bytes % 16 != 0 || reinterpret_cast<uintptr_t>(src) % 16 != 0 ||
+        reinterpret_cast<uintptr_t>(dst) % 16 != 0)
+        return LB_ERR_INVALID_ARG;
+    const uintptr_t a = reinterpret_cast<uintptr_t>(src), b = reinterpret_cast<uintptr_t>(dst);
+    if (bytes > 0 && a < b + bytes && b < a + bytes) return LB_ERR_INVALID_ARG;  // overlapping
+    if (bytes == 0) return LB_OK;
+    return hip_status(lbk::probe_copy(src, dst, bytes, static_cast<hipStream_t>(stream)));
+}
+
 LB_API lb_status_t lb_probe_gather(const int32_t *idx, int64_t n, const float *x, int64_t cols, float *out,
                                    int32_t grid, int32_t bands, void *stream) {
     if (n < 0 || cols < 0 || grid < 0 || !out || (n > 0 && (!idx || !x || cols == 0))) return LB_ERR_INVALID_ARG;

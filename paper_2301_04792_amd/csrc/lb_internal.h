@@ -367,6 +367,7 @@ hipError_t bfs(const csr_dev &G, int32_t source, int32_t *depth, const trav_cfg 
 
 // ---- measurement probes -----------------------------------------------------------------
 hipError_t probe_stream_read(const void *buf, size_t bytes, float *out, int grid, hipStream_t s);
+hipError_t probe_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 hipError_t probe_gather(const int32_t *idx, int64_t n, const float *x, int32_t cb, float *out, int grid, int bands,
                         hipStream_t s);
 

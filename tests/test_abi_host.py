@@ -387,6 +387,10 @@ def test_probe_host_checks():
     assert L.lb_probe_gather(FAKE, -1, FAKE, 10, FAKE, 8, 1, None) == _abi.ERR_INVALID_ARG
     assert L.lb_probe_gather(FAKE, 0, FAKE, 10, FAKE, 8, 2, None) == _abi.OK  # nothing to launch
     assert L.lb_probe_stream_read(FAKE, 10, FAKE, 8, None) == _abi.ERR_INVALID_ARG  # not a multiple of 16
+    assert L.lb_probe_copy(FAKE, FAKE + 4096, 10, None) == _abi.ERR_INVALID_ARG  # not a multiple of 16
+    assert L.lb_probe_copy(FAKE, FAKE + 64, 128, None) == _abi.ERR_INVALID_ARG  # overlapping
+    assert L.lb_probe_copy(None, FAKE, 16, None) == _abi.ERR_INVALID_ARG
+    assert L.lb_probe_copy(FAKE, FAKE + 4096, 0, None) == _abi.OK  # nothing to copy
 
 
 def test_vector_width_host_checks():

@@ -461,6 +461,14 @@ def test_gather_probe_sums(bands):
     assert out.double().sum().item() == expect
 
 
+def test_copy_probe():
+    """The calibration copy moves every byte (a ragged grid-stride tail)."""
+    src = torch.arange(4 * 100_003, dtype=torch.float32, device=DEV)
+    dst = torch.zeros_like(src)
+    lb.probe_copy(src, dst)
+    assert torch.equal(src, dst)
+
+
 @pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
 def test_vector_loads_unaligned_and_tails(dtype):
     """Four-nonzero loads: arrays one element off their vector alignment run
