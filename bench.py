@@ -649,6 +649,11 @@ def main():
                     "kernels_ms": {n: round(v[0], 5) for n, v in kt.items()},
                     "kernels_gbs": {n: round(kernel_bytes[n] / (kt[n][0] * 1e-3) / 1e9, 1)
                                     for n in kt if n in kernel_bytes}}
+        # the whole call on the same footing: B over the cold and warm step times
+        roofline["call"] = {"bytes": B, "cold_gbs": round(B / (ms * 1e-3) / 1e9, 1),
+                            "cold_frac": round(B / (ms * 1e-3) / 1e9 / PEAK_GBS, 4),
+                            "warm_gbs": round(B / (ms_warm * 1e-3) / 1e9, 1),
+                            "warm_frac": round(B / (ms_warm * 1e-3) / 1e9 / PEAK_GBS, 4)}
         if head == "planned" and short_gather_ms:
             roofline["gather_floor_ms"] = round(short_gather_ms, 5)
             roofline["frac_of_gather_floor"] = round(short_gather_ms / dom_ms, 4) if dominant == "merge_consume" else None

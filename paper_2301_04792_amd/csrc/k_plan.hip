@@ -219,7 +219,8 @@ __global__ __launch_bounds__(kPanelBlock) void panel_spmv(int32_t NP, int32_t R,
 
 // After the consume and the panel launch.  Two bands: every short row adds
 // its second band's sum (y += y_hi; long rows, flagged in long_bits, are
-// skipped), blocks [0, EB), one row per thread.  Every long row gets the sum
+// skipped), blocks [0, EB), four rows per thread with 16-byte accesses when
+// y and y_hi are 16-byte aligned.  Every long row gets the sum
 // of its task sums in (panel, task) order (lanes stride, then a fixed
 // butterfly), one wavefront per long row in the blocks after EB.  Each row
 // has one writer.
@@ -229,7 +230,22 @@ __global__ __launch_bounds__(256) void plan_combine(int32_t rows, int32_t EB, in
                                                     const int32_t *__restrict__ row_task,
                                                     const float *__restrict__ part) {
     if (static_cast<int32_t>(blockIdx.x) < EB) {
-        for (int64_t r = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; r < rows;
+        typedef float f32x4 __attribute__((ext_vector_type(4)));
+        const bool vec = ((reinterpret_cast<uintptr_t>(y) | reinterpret_cast<uintptr_t>(y_hi)) & 15) == 0;
+        const int64_t quads = vec ? rows / 4 : 0;  // rows [0, 4 * quads) four at a time
+        for (int64_t g = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; g < quads;
+             g += static_cast<int64_t>(EB) * 256) {
+            const f32x4 a = reinterpret_cast<const f32x4 *>(y)[g];
+            const f32x4 h = reinterpret_cast<const f32x4 *>(y_hi)[g];
+            const uint32_t lb = (long_bits[g >> 3] >> ((g & 7) * 4)) & 15u;  // rows 4g .. 4g + 3
+            if (lb == 0) {
+                reinterpret_cast<f32x4 *>(y)[g] = a + h;
+            } else {  // a long row's y is the long-row pass's: store the short ones only
+                for (int e = 0; e < 4; ++e)
+                    if (((lb >> e) & 1u) == 0) y[4 * g + e] = a[e] + h[e];
+            }
+        }
+        for (int64_t r = 4 * quads + static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; r < rows;
              r += static_cast<int64_t>(EB) * 256) {
             const float a = y[r], h = y_hi[r];  // loaded whatever the flag: no dependent wait
             if (((long_bits[r >> 5] >> (r & 31)) & 1u) == 0) y[r] = a + h;
@@ -412,7 +428,7 @@ hipError_t planned_spmv(const csr_dev &A, const plan_dev &pl, const void *x, flo
             return e;
     }
     prof_scope pr(s, "plan_finish");
-    const int64_t eb = pl.bands == 2 ? std::min<int64_t>((static_cast<int64_t>(pl.rows) + 255) / 256, 8192) : 0;
+    const int64_t eb = pl.bands == 2 ? std::min<int64_t>((static_cast<int64_t>(pl.rows) / 4 + 255) / 256 + 1, 4096) : 0;
     const int64_t blocks = eb + (static_cast<int64_t>(pl.NL) + 3) / 4;
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(plan_combine, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, pl.rows,
