@@ -156,10 +156,29 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
     int32_t i0, i1, j0, j1, ja, jb, h0;
     bool skip_first = false, short_rows = false;
     if constexpr (PLAN) {
-        const plan_unit u = units[b];
-        i0 = u.i0, i1 = u.i1, j0 = u.j0, j1 = u.j1, ja = u.ja, jb = u.jb, h0 = u.h0;
-        skip_first = (u.flags & 1) != 0;
-        short_rows = (u.flags & 2) != 0;
+        if (units) {
+            const plan_unit u = units[b];
+            i0 = u.i0, i1 = u.i1, j0 = u.j0, j1 = u.j1, ja = u.ja, jb = u.jb, h0 = u.h0;
+            skip_first = (u.flags & 1) != 0;
+            short_rows = (u.flags & 2) != 0;
+        } else {
+            // no plan (a small matrix, one launch): wavefronts 0 and 1 find
+            // the split at the unit's two ends; every unit is launched and
+            // owns the rows that close in it, no row is treated as long
+            __shared__ int32_t s_split[4];
+            if (wave_id() < 2) {
+                const int64_t dd = static_cast<int64_t>(b + wave_id()) * W;
+                const int32_t d = static_cast<int32_t>(dd < static_cast<int64_t>(rows) + nnz ? dd : rows + nnz);
+                const int32_t i = wave_merge_search(ro, rows, nnz, d);
+                if (lane_id() == 0) s_split[2 * wave_id()] = i, s_split[2 * wave_id() + 1] = d - i;
+            }
+            __syncthreads();
+            i0 = s_split[0], j0 = s_split[1], i1 = s_split[2], j1 = s_split[3];
+            if (i0 == i1) return;  // uniform: no row closes in this unit
+            h0 = ro[i0];
+            ja = j0;
+            jb = i1 < rows ? (ro[i1] < j1 ? ro[i1] : j1) : j1;
+        }
     } else {
         i0 = part_i[b], j0 = part_j[b];
         i1 = part_i[b + 1], j1 = part_j[b + 1];
@@ -307,9 +326,19 @@ __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(
     if constexpr (PLAN) {
         // this thread's share of row i0's head, in its band (hx is 0 outside it)
         float head = has_head ? to_f32(hv) * hx : 0.f;
-        for (int32_t j = h0 + tid + BLOCK; j < j0; j += BLOCK) {  // heads longer than the block
-            const int32_t cj = ci[j];
-            if (BANDS == 1 || (cj >= cb) == (band == 1)) head += to_f32(val[j]) * to_f32(x[cj]);
+        constexpr int HU = 8;  // head nonzeros in flight per thread
+        for (int32_t j = h0 + tid + BLOCK; j < j0; j += HU * BLOCK) {  // heads longer than the block
+            int32_t cj[HU];
+            float vj[HU];
+#pragma unroll
+            for (int k = 0; k < HU; ++k) {
+                const int32_t jk = j + k * BLOCK;
+                cj[k] = jk < j0 ? ci[jk] : -1;
+                vj[k] = jk < j0 ? to_f32(val[jk]) : 0.f;
+            }
+#pragma unroll
+            for (int k = 0; k < HU; ++k)
+                if (cj[k] >= 0 && (BANDS == 1 || (cj[k] >= cb) == (band == 1))) head += vj[k] * to_f32(x[cj[k]]);
         }
         head = group_sum_dpp<kWave>(head);
         if (lane_id() == kWave - 1) s_head[wave_id()] = head;
@@ -481,6 +510,12 @@ hipError_t launch_fixup(int64_t T, int32_t rows, int32_t kc, const int32_t *carr
 
 // ------------------------------------------------------------------ dispatch
 
+// Up to this many units a one-band lb_spmv runs as one launch whose blocks
+// find their own split and own whole rows (a row longer than a unit is
+// summed by the block where it closes, at most kSelfSplitUnits * W
+// nonzeros).
+constexpr int64_t kSelfSplitUnits = 256;  // one block per CU at most
+
 // The four-nonzero load form needs whole aligned groups: nnz >= 4, col_idx
 // 16-byte aligned and the values aligned to their 4-element vector.
 static bool vector_loads_ok(const csr_dev &A) {
@@ -496,6 +531,23 @@ static hipError_t run_merge_spmv(const csr_dev &A, const void *x, float *y, int 
     const bool two = bands == 2;
     merge_ws w = merge_ws_carve(ws, two ? 2 * T : T);
     float *y_hi = two ? reinterpret_cast<float *>(static_cast<char *>(ws) + merge_ws_bytes(2 * T, 1)) : nullptr;
+    if (!two && !vperm && T <= kSelfSplitUnits) {
+        // a small matrix: one launch, no split launch, no carries, no fix-up
+        prof_scope p(s, "merge_consume");
+        const VT *val = static_cast<const VT *>(A.val);
+        const int32_t cb = static_cast<int32_t>((A.cols + 1) / 2);
+        if (vec == 4 && vector_loads_ok(A))
+            hipLaunchKernelGGL((merge_spmv_consume<BLOCK, ITEMS, VT, VT, 1, false, 4, true>),
+                               dim3(static_cast<uint32_t>(T)), dim3(BLOCK), 0, s, A.rows, A.nnz, A.ro, A.ci, val,
+                               static_cast<const VT *>(x), y, nullptr, nullptr, nullptr, nullptr,
+                               static_cast<int32_t>(T), cb, nullptr, nullptr, nullptr);
+        else
+            hipLaunchKernelGGL((merge_spmv_consume<BLOCK, ITEMS, VT, VT, 1, false, 1, true>),
+                               dim3(static_cast<uint32_t>(T)), dim3(BLOCK), 0, s, A.rows, A.nnz, A.ro, A.ci, val,
+                               static_cast<const VT *>(x), y, nullptr, nullptr, nullptr, nullptr,
+                               static_cast<int32_t>(T), cb, nullptr, nullptr, nullptr);
+        return hipGetLastError();
+    }
     hipError_t e = merge_partition(A.ro, A.rows, A.nnz, W, static_cast<int32_t>(T), w.part_i, w.part_j, s);
     if (e != hipSuccess) return e;
     {

@@ -40,3 +40,14 @@ def oracle_spmv(A: CSRHost, x):
 def oracle_spmm(A: CSRHost, X):
     return (oracle.spmm(A.row_offsets, A.col_idx, A.values, X),
             oracle.spmm(A.row_offsets, A.col_idx, A.values, X, abs_terms=True))
+
+
+def rows_in_one_share(A: CSRHost, items: int):
+    """Rows whose merge items (their nonzeros and their row end) all fall in
+    one thread's share of `items` consecutive merge items.  Every merge-path
+    form sums such a row left to right from zero in one thread, so it comes
+    out bit for bit the same whichever way the cut rows are combined."""
+    ro = A.row_offsets.astype(np.int64)
+    start = ro[:-1] + np.arange(A.m)
+    end = ro[1:] + np.arange(A.m)
+    return start // items == end // items

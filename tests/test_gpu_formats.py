@@ -4,7 +4,7 @@ import pytest
 
 import oracle
 import synthetic as S
-from tests.gpu_util import assert_rows_close
+from tests.gpu_util import assert_rows_close, oracle_spmv, rows_in_one_share
 
 pytestmark = pytest.mark.gpu
 
@@ -87,11 +87,23 @@ def test_coo_partition_equals_csr_walk():
 
 @pytest.mark.parametrize("params", [{}, {"block_size": 512, "items_per_thread": 12}], ids=["default", "512x12"])
 def test_coo_merge_bit_equal_to_csr(params):
-    # the same split and the same consume arithmetic: identical y bit for bit
+    """The same split and the same consume arithmetic: identical y bit for
+    bit, on matrices of more than 256 units.  Smaller ones run the CSR path
+    as one launch whose blocks own whole rows (no carries), so a row cut by
+    a unit or a thread's share is combined in another order: the rows in
+    one thread's share stay bit-equal, the rest within the tolerance."""
+    block, items = params.get("block_size", 256), params.get("items_per_thread", 8)
     for name, (A, x) in matrices().items():
         yc = lb.spmv_coo(lb.COO.from_host(S.to_coo(A), DEV), xdev(x), "merge_path", **params)
         yr = lb.spmv(lb.CSR.from_host(A, DEV), xdev(x), "merge_path", **params)
-        assert torch.equal(yc, yr), name
+        if -(-(A.m + A.nnz) // (block * items)) > 256:
+            assert torch.equal(yc, yr), name
+        else:
+            one = rows_in_one_share(A, items)
+            assert np.array_equal(yc.cpu().numpy()[one], yr.cpu().numpy()[one]), name
+            ref, scale = oracle_spmv(A, x)
+            assert_rows_close(yc.cpu().numpy(), ref, scale, what=f"coo {name}")
+            assert_rows_close(yr.cpu().numpy(), ref, scale, what=f"csr {name}")
 
 
 def test_csc():
