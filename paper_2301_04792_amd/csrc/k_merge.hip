@@ -123,7 +123,9 @@ hipError_t merge_partition(const int32_t *ro, int32_t rows, int32_t nnz, int32_t
 // nonzeros) are left out too: as long_min >= W only i0 can be long among
 // the closing rows, and then the block neither writes y[i0] nor reads its
 // head.  The nonzeros whose products the walk sums are the one range
-// [ja, jb).
+// [ja, jb).  With units == nullptr (a small one-band lb_spmv, no plan) the
+// block finds its unit's split itself, every unit is launched, and no row
+// is treated as long.
 template <int BLOCK, int ITEMS, typename VT, typename XT, int BANDS, bool VPERM = false, int VEC = 1,
           bool PLAN = false>
 __global__ __launch_bounds__(BLOCK) void merge_spmv_consume(

@@ -491,3 +491,27 @@ def test_noalloc_rejects_inputs_beyond_its_scratch():
     empty = csr(0, 5, 0, ro=0, ci=0, val=0)
     assert L.lb_spmv_noalloc(ctypes.byref(empty), None, _abi.F32, None, ctypes.byref(sched()), None) == _abi.OK
     assert b"static" in L.lb_status_string(_abi.ERR_SCRATCH_LIMIT)
+
+
+def test_plan_build_host_checks():
+    """lb_spmv_plan_build rejects bad inputs of the plan struct before any
+    device access (the matrix pointers here are never dereferenced)."""
+    L = _abi.load()
+    A = csr(1000, 800, 5000)
+
+    def build(**kw):
+        p = _abi.SpmvPlan()
+        for k, v in kw.items():
+            setattr(p, k, v)
+        return L.lb_spmv_plan_build(ctypes.byref(A), ctypes.byref(p), None, 0, None)
+
+    assert build(vector_width=2) == _abi.ERR_INVALID_ARG
+    assert build(vector_width=4, x_bands=2) == _abi.ERR_UNSUPPORTED
+    assert build(x_bands=3) == _abi.ERR_INVALID_ARG
+    assert build(streams=3) == _abi.ERR_INVALID_ARG
+    assert build(panel_blocks=-1) == _abi.ERR_INVALID_ARG
+    assert build(panel_cols=40960 + 64) == _abi.ERR_INVALID_ARG  # more than 160 KiB of float x
+    assert build(panel_cols=100) == _abi.ERR_INVALID_ARG          # not a multiple of 64
+    assert build(long_min=100) == _abi.ERR_INVALID_ARG            # below W = 256 x 8
+    assert build(block_size=100) == _abi.ERR_UNSUPPORTED
+    assert L.lb_spmv_plan_build(ctypes.byref(A), None, None, 0, None) == _abi.ERR_INVALID_ARG
