@@ -5,7 +5,7 @@ One step = one y = A x over the power-law matrix (m = n = 2,000,000, row
 lengths min(Zipf(1.8), 200,000), 10 % empty rows, uniform columns, FP32)
 through lb_spmv_planned: a plan built once for the pattern (outside the
 timed region; its build time is reported) runs the short rows on the merge
-path (256 threads x 8 items, two column bands over the XCDs, the split
+path (128 threads x 8 items, two column bands over the XCDs, the split
 precomputed) and the long rows on LDS panels of x, then one finishing pass.
 `value` is effective HBM GB/s over algorithmic bytes
 B = nnz*(s_v + 4) + (m + 1)*4 + n*s_x + m*4 of the median of the K timed

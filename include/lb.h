@@ -260,9 +260,10 @@ LB_API lb_status_t lb_spmv(const lb_csr_t *A, const void *x, lb_dtype_t x_dtype,
  *
  * Inputs of lb_spmv_plan_t (0 = default):
  *  block_size, items_per_thread  the short rows' merge path, as for lb_spmv
- *                                (default 256 x 8, or 256 x 12 when the
- *                                default vector_width is 4); W = their
- *                                product;
+ *                                (default: 256 x 12 when the columns are
+ *                                local and four nonzeros per lane are
+ *                                used; else 128 x 8 with two bands and
+ *                                128 x 4 with one); W = their product;
  *  x_bands       1 or 2, as for lb_spmv (default: 2 when x has at least
  *                4 MiB and the columns are scattered -- the median column
  *                span of up to 1024 sampled rows exceeds cols / 16 -- else 1);

@@ -27,7 +27,8 @@ namespace {
 constexpr int64_t kMaxCoord = 0x7ffffffe;  // rows + nnz must stay below this (int32 merge coordinates)
 constexpr int kDefaultBlock = 256;
 constexpr int kDefaultItems = 8;
-constexpr int kLocalItems = 12;  // planned SpMV with local columns (four nonzeros per lane)
+constexpr int kLocalItems = 12;    // planned SpMV with local columns (four nonzeros per lane)
+constexpr int kScatteredBlock = 128;  // planned SpMV with scattered columns
 constexpr int kDefaultGroup = 64;
 constexpr int kMaxK = 64;
 
@@ -903,13 +904,25 @@ LB_API lb_status_t lb_spmv_plan_build(const lb_csr_t *A, lb_spmv_plan_t *plan, v
         const int64_t sx = A->value_dtype == LB_BF16 ? 2 : 4;
         if (p.x_bands == 0) p.x_bands = scattered && A->cols * sx >= (int64_t(4) << 20) ? 2 : 1;
         if (p.vector_width == 0) p.vector_width = !scattered && p.x_bands == 1 ? 4 : 1;
+        lb_spmv_plan_t in2 = *plan;
+        in2.x_bands = p.x_bands;
+        in2.vector_width = p.vector_width;
+        bool again = false;
         if (plan->items_per_thread == 0 && p.vector_width == 4) {
             // local columns: longer units (12 items per thread) amortize each
             // block's fixed latency (split, search, scan) over more nonzeros
-            lb_spmv_plan_t in2 = *plan;
             in2.items_per_thread = kLocalItems;
-            in2.x_bands = p.x_bands;
-            in2.vector_width = p.vector_width;
+            again = true;
+        } else if (plan->items_per_thread == 0 && plan->block_size == 0 && p.vector_width == 1) {
+            // scattered columns: shorter units (128 threads; 8 items with two
+            // bands, 4 with one) spread the gather-bound short rows over more
+            // blocks and lower the default long_min, moving rows of W to 2047
+            // nonzeros to the panels
+            in2.block_size = kScatteredBlock;
+            in2.items_per_thread = p.x_bands == 2 ? 8 : 4;
+            again = true;
+        }
+        if (again) {
             st = plan_params(A, &in2, &p);
             if (st != LB_OK) return st;
         }
