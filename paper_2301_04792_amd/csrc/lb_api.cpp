@@ -666,7 +666,6 @@ lbk::plan_dev plan_dev_of(const lb_spmv_plan_t &p) {
     const char *b = static_cast<const char *>(p.buffer);
     d.part_i = reinterpret_cast<const int32_t *>(b + L.part_i);
     d.part_j = reinterpret_cast<const int32_t *>(b + L.part_j);
-    d.active = reinterpret_cast<const int32_t *>(b + L.active);
     d.units = reinterpret_cast<const lbk::plan_unit *>(b + L.units);
     d.LR = reinterpret_cast<const int32_t *>(b + L.LR);
     d.long_bits = reinterpret_cast<const uint32_t *>(b + L.long_bits);
@@ -968,7 +967,6 @@ LB_API lb_status_t lb_spmv_plan_build(const lb_csr_t *A, lb_spmv_plan_t *plan, v
     int32_t *part_j = reinterpret_cast<int32_t *>(b + L.part_j);
     int32_t *d_LR = reinterpret_cast<int32_t *>(b + L.LR);
     int32_t *sb = reinterpret_cast<int32_t *>(b + L.sb);
-    int32_t *active = reinterpret_cast<int32_t *>(b + L.active);
     const int64_t nsb = static_cast<int64_t>(p.long_rows) * (NP + 1);
     std::vector<int32_t> h_sb(static_cast<size_t>(nsb)), h_part(static_cast<size_t>(T + 1)),
         h_partj(static_cast<size_t>(T + 1));
@@ -1034,15 +1032,12 @@ LB_API lb_status_t lb_spmv_plan_build(const lb_csr_t *A, lb_spmv_plan_t *plan, v
     // units with short-row work: a short row closes in it (only its first
     // closing row can be long); a short row is owned, whole, by the unit
     // where it closes
-    std::vector<int32_t> h_active;
-    h_active.reserve(static_cast<size_t>(T));
     auto is_short = [&](int64_t r) { return static_cast<int64_t>(ro[r + 1]) - ro[r] < p.long_min; };
     std::vector<lbk::plan_unit> h_units;
     h_units.reserve(static_cast<size_t>(T));
     for (int64_t u = 0; u < T; ++u) {
         const int32_t i0 = h_part[u], i1 = h_part[u + 1];
         if (!(i1 > i0 + 1 || (i0 < i1 && is_short(i0)))) continue;
-        h_active.push_back(static_cast<int32_t>(u));
         // the record its block reads: products of [ja, jb) (a long first row
         // and the open row left out), the head of row i0 (ro[i0] <= j0)
         lbk::plan_unit r{i0, i1, h_partj[u], h_partj[u + 1], h_partj[u], h_partj[u + 1], ro[i0], 0};
@@ -1070,17 +1065,15 @@ LB_API lb_status_t lb_spmv_plan_build(const lb_csr_t *A, lb_spmv_plan_t *plan, v
     up(L.row_task, row_task.data(), row_task.size() * 4);
     up(L.pcls_off, pcls_off.data(), pcls_off.size() * 4);
     up(L.tasks, tasks.data(), tasks.size() * sizeof(lbk::panel_task));
-    up(L.active, h_active.data(), h_active.size() * 4);
     up(L.units, h_units.data(), h_units.size() * sizeof(lbk::plan_unit));
     up(L.long_bits, long_bits.data(), long_bits.size() * 4);
     if (e == hipSuccess) e = hipStreamSynchronize(hs);
     if (e != hipSuccess) return hip_status(e);
-    p.active_units = static_cast<int32_t>(h_active.size());
+    p.active_units = static_cast<int32_t>(h_units.size());
     p.tasks = static_cast<int32_t>(ntasks);
     p.workspace_bytes = lbk::plan_ws_bytes(p.x_bands, rows, ntasks);
     p.buffer = buffer;
     *plan = p;
-    (void)active;
     return LB_OK;
 }
 

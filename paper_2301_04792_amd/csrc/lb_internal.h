@@ -144,9 +144,8 @@ struct plan_dev {
     int32_t vec;         // 4: the short rows' consume loads four nonzeros per lane (one band)
     int32_t streams;     // 2: the long rows' launch on the library's second stream
     int32_t ntasks;
-    const int32_t *part_i, *part_j;  // the split at every unit boundary, T + 1 each
-    const int32_t *active;           // NA unit ids, ascending
-    const plan_unit *units;          // NA records, one per active unit, in the same order
+    const int32_t *part_i, *part_j;  // the split at every unit boundary, T + 1 each (written by the build)
+    const plan_unit *units;          // NA records, one per active unit, in unit order
     const int32_t *LR;               // NL long row ids, ascending
     const uint32_t *long_bits;       // ceil(rows / 32) words: bit r % 32 of word r / 32 set for a long row r
     const int32_t *row_task;         // NL + 1: long row q's task sums are part[row_task[q] .. row_task[q + 1])
@@ -155,11 +154,12 @@ struct plan_dev {
 };
 
 // Plan buffer: a 256-byte header (build flags), then the tables above, each
-// 256-byte aligned; NA_cap entries are reserved for the active list and
-// ntask_cap for the tasks (the last table); sb (NL x (NP + 1) segment bounds)
-// is written by the build on the device and read back.
+// 256-byte aligned; NA_cap entries are reserved for the unit records and
+// ntask_cap for the tasks (the last table); the split (part_i, part_j) and
+// sb (NL x (NP + 1) segment bounds) are written by the build on the device
+// and read back.
 struct plan_layout {
-    size_t flags, part_i, part_j, active, units, LR, long_bits, row_task, pcls_off, tasks, sb, total;
+    size_t flags, part_i, part_j, units, LR, long_bits, row_task, pcls_off, tasks, sb, total;
 };
 inline plan_layout plan_layout_of(int64_t T, int64_t NA_cap, int64_t NL, int64_t NP, int64_t ntask_cap,
                                   int64_t rows) {
@@ -173,7 +173,6 @@ inline plan_layout plan_layout_of(int64_t T, int64_t NA_cap, int64_t NL, int64_t
     L.flags = take(4);
     L.part_i = take(static_cast<size_t>(T + 1) * 4);
     L.part_j = take(static_cast<size_t>(T + 1) * 4);
-    L.active = take(static_cast<size_t>(NA_cap) * 4);
     L.units = take(static_cast<size_t>(NA_cap) * sizeof(plan_unit));
     L.LR = take(static_cast<size_t>(NL) * 4);
     L.long_bits = take(static_cast<size_t>((rows + 31) / 32) * 4);
