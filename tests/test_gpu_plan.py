@@ -303,3 +303,42 @@ def test_plan_vector_width_args():
     assert e.value.status == _abi.ERR_INVALID_ARG
     p4 = lb.Plan(Ad, vector_width=4)
     assert p4.c.x_bands == 1 and p4.c.vector_width == 4
+
+
+@pytest.mark.parametrize("cfg", [dict(x_bands=1, long_min=1024, panel_cols=4096),
+                                 dict(x_bands=2, long_min=1024, panel_cols=4096),
+                                 dict(x_bands=2, long_min=1024, panel_cols=4096, streams=2)],
+                         ids=["one_band", "two_bands", "second_stream"])
+def test_planned_in_hip_graph(cfg):
+    """The planned call captured in a HIP graph (three calls): every replay,
+    with eager work and synchronizations between replays, equals the eager
+    result bit for bit."""
+    A, x = S.powerlaw_csr(52, 150_000, 150_000, 1.8, 40_000, 0.1)
+    Ad, xd = upload(A, x)
+    plan = lb.Plan(Ad, block_size=128, items_per_thread=8, **cfg)
+    assert plan.c.long_rows > 0
+    ws = torch.empty(max(plan.workspace_bytes, 1), dtype=torch.uint8, device=DEV)
+    y = torch.empty(A.m, dtype=torch.float32, device=DEV)
+    lb.spmv_planned(Ad, plan, xd, y=y, workspace=ws)
+    torch.cuda.synchronize()
+    eager = y.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        lb.spmv_planned(Ad, plan, xd, y=y, workspace=ws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(3):
+            lb.spmv_planned(Ad, plan, xd, y=y, workspace=ws)
+    for rep in range(4):
+        y.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(y, eager), (cfg, rep)
+        z = lb.spmv_planned(Ad, plan, xd * 2)  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(z, 2 * eager), (cfg, rep)  # scaling x by 2 is exact
+    ref, scale = oracle_spmv(A, x)
+    assert_rows_close(eager.cpu().numpy(), ref, scale, what=f"graph {cfg}")
