@@ -40,7 +40,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_GBS = 8000.0
-SECTIONS = {"schedules", "uniform", "bf16", "fwdbwd", "formats", "batched", "graph", "spgemm"}
+# the optional sections and the key of the output line each one fills
+SECTION_KEYS = {"schedules": "schedules_powerlaw2M", "uniform": "uniform4096", "bf16": "bf16",
+                "fwdbwd": "fwd_bwd_powerlaw1M", "formats": "formats_powerlaw1M", "batched": "batched_512",
+                "graph": "graph_powerlaw1M", "spgemm": "spgemm"}
+SECTIONS = set(SECTION_KEYS)
 METRIC = "SpMV effective HBM GB/s (% of peak) per schedule; fwd+bwd and batched GB/s"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "planned_spmv_powerlaw2M_traffic.json")
 kPanelBytes = 163840  # LDS bytes of x per panel block (the library's default panel: 40960 FP32 columns)
@@ -81,6 +85,38 @@ def kernel_source_hash():
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+class Records:
+    """Measurement records appended to a JSONL file: one line per finished
+    section (every configuration, schedule and parameter set it timed, with
+    their figures) and one for the headline, each tagged with the kernel
+    sources' hash, the device and the host.  With `resume`, a section already
+    recorded for the same sources and device is read back instead of measured
+    again, so an interrupted sweep continues where it stopped; the headline is
+    always measured."""
+
+    def __init__(self, path, resume, device):
+        self.path = path
+        self.tag = {"kernel_sources": kernel_source_hash(), "device": device}
+        self.done = {}
+        if path and resume and os.path.exists(path):
+            with open(path) as f:
+                for line in f:
+                    try:
+                        r = json.loads(line)
+                    except ValueError:  # a line cut short by an interrupted run
+                        continue
+                    if r.get("section") in SECTION_KEYS and all(r.get(k) == v for k, v in self.tag.items()):
+                        self.done[r["section"]] = r["result"]
+
+    def append(self, section, result):
+        if not self.path:
+            return
+        line = {"section": section, **self.tag, "host": host_facts(),
+                "time": time.strftime("%Y-%m-%dT%H:%M:%S"), "result": result}
+        with open(self.path, "a") as f:
+            f.write(json.dumps(line) + "\n")
 
 
 # ---------------------------------------------------------------- rocprofv3 summaries
@@ -355,9 +391,17 @@ def main():
                     help="comma-separated sections to run without the headline: " + ", ".join(sorted(SECTIONS)))
     ap.add_argument("--graph-only", action="store_true",
                     help="run only the graph traversals (SSSP, BFS) and print their figures")
+    ap.add_argument("--record", metavar="FILE",
+                    help="append one JSONL record per finished section (and the headline) to FILE")
+    ap.add_argument("--resume", action="store_true",
+                    help="with --record: read back sections FILE holds for the same kernel sources and device "
+                         "instead of measuring them again")
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="write profiles/ summaries from rocprofv3 CSV output under DIR and exit")
     args = ap.parse_args()
+    if args.resume and not args.record:
+        print("--resume needs --record FILE", file=sys.stderr)
+        return 2
     if args.summarize_profiles:
         return summarize_profiles(os.path.join(ROOT, "profiles"), args.summarize_profiles)
 
@@ -375,6 +419,8 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    props = torch.cuda.get_device_properties(dev)
+    rec = Records(args.record, args.resume, f"{props.gcnArchName} {props.multi_processor_count} CUs")
     if args.graph_only:
         print(json.dumps({"graph_powerlaw1M": run_graph(lb, S, dev, args.no_cpu)}), flush=True)
         return 0
@@ -743,12 +789,24 @@ def main():
             result["accuracy"] = {"max_err_over_sum_abs_terms": ratio, "tolerance": 1e-5,
                                   "zero_rows_exact": bool(np.all(err[scale == 0] == 0))}
             log(f"[bench] cpu oracle: {cpu_s * 1e3:.0f} ms/call on {orc.num_threads()} threads; max err ratio {ratio:.2e}")
+        rec.append("headline", dict(result))
         if args.quick:
             print(json.dumps(result), flush=True)
             return 0
 
+    resumed = []
+
     def want(name):
-        return wanted is None or name in wanted
+        if wanted is not None and name not in wanted:
+            return False
+        if name in rec.done:  # measured by an earlier run of the same kernels on this device
+            result[SECTION_KEYS[name]] = rec.done[name]
+            resumed.append(name)
+            return False
+        return True
+
+    def finish(name):
+        rec.append(name, result[SECTION_KEYS[name]])
 
 
     extra_steps = max(3, min(args.steps, 10))
@@ -779,6 +837,7 @@ def main():
         lb.autotune_clear()
         del wst
         result["schedules_powerlaw2M"] = per
+        finish("schedules")
 
     if want("uniform"):
         # ------------------------------------------------------------ the small uniform matrix (launch-bound)
@@ -797,6 +856,7 @@ def main():
         wsp1 = torch.empty(max(pl1.workspace_bytes, 1), dtype=torch.uint8, device=dev)
         small["planned"] = round(timed(lambda: lb.spmv_planned(A1d, pl1, x1d, y=y1, workspace=wsp1), 50, 10) * 1e3, 2)
         result["uniform4096"] = small
+        finish("uniform")
         log(f"[bench] uniform 4096: {small}")
         del A1d, x1d, y1
 
@@ -864,6 +924,7 @@ def main():
             del wst
         lb.autotune_clear()
         result["bf16"] = bf
+        finish("bf16")
         log(f"[bench] bf16: {bf}")
         del Ld, Lbd, xld, xlbd, yl
 
@@ -898,6 +959,7 @@ def main():
                                         "transpose_build_ms": round(tbuild, 3),
                                         "fwd_bwd_transposed_gbs": round((Bf4 + Bb4) / ((tf + tbt) * 1e-3) / 1e9, 2),
                                         "fwd_bwd_gbs": round((Bf4 + Bb4) / ((tf + tb) * 1e-3) / 1e9, 2)}
+        finish("fwdbwd")
         log(f"[bench] fwd+bwd: {result['fwd_bwd_powerlaw1M']}")
 
     if want("formats"):
@@ -928,6 +990,7 @@ def main():
         fm["csc_merge_path"] = {"ms": round(t, 4), "gbs": round(Bcsc / (t * 1e-3) / 1e9, 2)}
         del csc4
         result["formats_powerlaw1M"] = fm
+        finish("formats")
         log(f"[bench] formats: {fm}")
         del C4d, x4d, dy4, y4, ws4
 
@@ -949,10 +1012,12 @@ def main():
             del Xk, Yk
             log(f"[bench] batched k={k}: {bres[f'k{k}']}")
         result["batched_512"] = bres
+        finish("batched")
         del Bd
 
     if want("graph"):
         result["graph_powerlaw1M"] = run_graph(lb, S, dev, args.no_cpu)
+        finish("graph")
 
     if want("spgemm"):
         # ------------------------------------------------------------ SpGEMM
@@ -981,8 +1046,11 @@ def main():
                 gm[name]["cpu_oracle_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
             del Ad, C
         result["spgemm"] = gm
+        finish("spgemm")
         log(f"[bench] spgemm: {gm}")
 
+    if resumed:
+        result["resumed_sections"] = resumed
     print(json.dumps(result), flush=True)
     return 0
 

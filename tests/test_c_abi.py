@@ -27,3 +27,39 @@ def test_bench_refuses_several_gpus():
     r = subprocess.run(["python", os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
                        timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_bench_records_resume(tmp_path):
+    """bench.py's JSONL records: each finished section is appended with the
+    kernel sources' hash and the device; with resume, only sections recorded
+    for the same sources and device are read back, and a line cut short by an
+    interrupted run is skipped."""
+    import importlib.util
+
+    spec = importlib.util.spec_from_file_location("_bench", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    path = tmp_path / "records.jsonl"
+    w = bench.Records(str(path), False, "gfx950 256 CUs")
+    w.append("headline", {"value": 1.0})
+    w.append("uniform", {"planned": 7.8})
+    w.append("batched", {"k1": {"ms": 1.1}})
+    bench.Records(str(path), False, "gfx942 304 CUs").append("schedules", {"merge_path": {"ms": 0.4}})
+    with open(path, "a") as f:
+        f.write('{"section": "spgemm", "kernel_sources": "')  # the run stopped mid-line
+    r = bench.Records(str(path), True, "gfx950 256 CUs")
+    assert r.done == {"uniform": {"planned": 7.8}, "batched": {"k1": {"ms": 1.1}}}  # no headline, no other device
+    assert bench.Records(str(path), False, "gfx950 256 CUs").done == {}  # resume off: nothing read back
+    lines = path.read_text().splitlines()
+    assert len(lines) == 5
+    import json
+
+    first = json.loads(lines[0])
+    assert first["section"] == "headline" and first["kernel_sources"] == bench.kernel_source_hash()
+    assert set(first["host"]) == {"cpu_model", "logical_cpus"}
+
+
+def test_bench_resume_needs_record():
+    r = subprocess.run(["python", os.path.join(ROOT, "bench.py"), "--resume"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2 and "--record" in r.stderr
