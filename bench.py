@@ -1001,6 +1001,13 @@ def main():
         log(f"[bench] batched generated: {BH.count} matrices, nnz={BH.nnz} in {time.time() - t0:.1f}s")
         Bd = lb.Batch.from_host(BH, dev)
         bres = {"count": BH.count, "total_rows": BH.total_rows, "nnz": BH.nnz}
+        # context: the same products as one lb_spmm call per matrix (merge
+        # path, default tiles) on views of the batch's arrays
+        rb, zb, cb = (t.cpu().tolist() for t in (Bd.mat_row_base, Bd.mat_nnz_base, Bd.mat_col_base))
+        mats = [lb.CSR(Bd.row_offsets[rb[b]:rb[b + 1] + 1] - zb[b], Bd.col_idx[zb[b]:zb[b + 1]],
+                       Bd.values[zb[b]:zb[b + 1]], (rb[b + 1] - rb[b], cb[b + 1] - cb[b])) for b in range(BH.count)]
+        wsl = torch.empty(max(lb.workspace_size(M, "merge_path", k=kk) for M in mats for kk in (1, 8)),
+                          dtype=torch.uint8, device=dev)
         for k in (1, 8):
             Xk = torch.from_numpy(S.random_vector(55, BH.total_cols * k).reshape(-1, k)).to(dev)
             Yk = torch.empty((BH.total_rows, k), dtype=torch.float32, device=dev)
@@ -1009,8 +1016,21 @@ def main():
             Bk = BH.nnz * 8 + (BH.total_rows + 1) * 4 + BH.total_cols * 4 * k + BH.total_rows * 4 * k
             bres[f"k{k}"] = {"ms": round(tk, 4), "gbs": round(Bk / (tk * 1e-3) / 1e9, 2),
                              "gflops": round(2 * BH.nnz * k / (tk * 1e-3) / 1e9, 2), "schedule": tuned}
+
+            def per_matrix(Xk=Xk, Yk=Yk):
+                for b, M in enumerate(mats):
+                    lb.spmm(M, Xk[cb[b]:cb[b + 1]], "merge_path", Y=Yk[rb[b]:rb[b + 1]], workspace=wsl)
+
+            tl = timed(per_matrix, 3, 1)
+            tlg = graph_timed(per_matrix, Yk, 1)
+            bres[f"k{k}"]["per_matrix_loop"] = {
+                "ms": round(tl, 4), "gbs": round(Bk / (tl * 1e-3) / 1e9, 2),
+                "hip_graph_ms": round(tlg, 4) if tlg is not None else None,
+                "note": f"{BH.count} lb_spmm calls, one per matrix (merge path), eager from Python and as one "
+                        "HIP graph replay"}
             del Xk, Yk
             log(f"[bench] batched k={k}: {bres[f'k{k}']}")
+        del mats, wsl
         result["batched_512"] = bres
         finish("batched")
         del Bd
