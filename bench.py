@@ -703,6 +703,11 @@ def main():
         if head == "planned" and short_gather_ms:
             roofline["gather_floor_ms"] = round(short_gather_ms, 5)
             roofline["frac_of_gather_floor"] = round(short_gather_ms / dom_ms, 4) if dominant == "merge_consume" else None
+            roofline["note"] = ("the dominant kernel is the short rows' consume: about 9 nonzeros per row with "
+                                "uniformly random columns, one random x gather per nonzero, so the gather request "
+                                "rate, not HBM, bounds it (gather_floor_ms: the gather alone over the same columns in "
+                                "the same band form); the long rows' panel kernel streams at "
+                                "kernels_gbs.panel_consume; call: the whole call against 8 TB/s")
         else:
             roofline["gather_ceiling_gbs"] = ceilings[ceiling_key]
             roofline["frac_of_gather_ceiling"] = round(achieved / ceilings[ceiling_key], 4)
