@@ -180,6 +180,13 @@ TRACES = {
     "traversal_powerlaw1M": ("SSSP and BFS on the 1M-vertex power-law graph, every schedule",
                              "--graph-only --no-cpu"),
 }
+# L2-to-memory read requests by size (32, 64 and 128 bytes) and in total:
+# their byte sum is the read traffic counted without a scale factor
+# (FETCH_SIZE counts 128-byte requests through TCC_BUBBLE, which does not see
+# them on this chip, so it reads half a copy's bytes).
+RDREQ_SET = "TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum"
+RDREQ_SIZES = (("TCC_EA0_RDREQ_32B_sum", 32), ("TCC_EA0_RDREQ_64B_sum", 64), ("TCC_EA0_RDREQ_128B_sum", 128))
+
 # Counter passes: tag -> (bench.py arguments, counter sets); each set is one
 # `rocprofv3 --pmc <set> --output-format csv -d prof_out/<tag>_<i> -o c --
 # python3 bench.py <arguments>` run, summarised into profiles/<tag>_counters.md.
@@ -189,13 +196,14 @@ COUNTERS = {
                                  "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY "
                                  "SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS SQ_INSTS_VALU",
                                  "TCC_HIT_sum TCC_MISS_sum", "TA_BUSY_avr TA_ADDR_STALLED_BY_TC_CYCLES_sum "
-                                 "TCP_PENDING_STALL_CYCLES_sum TCP_TCC_READ_REQ_sum"]),
+                                 "TCP_PENDING_STALL_CYCLES_sum TCP_TCC_READ_REQ_sum", RDREQ_SET]),
     "fwd_bwd_powerlaw1M": ("--only fwdbwd --no-cpu --steps 3 --pmc-calib",
                            ["FETCH_SIZE", "WRITE_SIZE", "TCC_ATOMIC_sum TCC_EA0_ATOMIC_sum",
                             "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY"]),
     "batched512": ("--only batched --no-cpu --steps 3 --pmc-calib",
                    ["FETCH_SIZE", "WRITE_SIZE", "TCC_HIT_sum TCC_MISS_sum",
-                    "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_ACTIVE_INST_LDS"]),
+                    "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_ACTIVE_INST_LDS",
+                    RDREQ_SET]),
     "bf16_laplacian_powerlaw2M": ("--only bf16 --no-cpu --steps 3 --pmc-calib",
                                   ["FETCH_SIZE", "WRITE_SIZE", "TCC_HIT_sum TCC_MISS_sum",
                                    "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY "
@@ -217,6 +225,15 @@ def _copy_calibration(rows):
     known = float(1 << 28)
     return (known / (max(f) * 1024.0) if f else None, known / (max(w) * 1024.0) if w else None,
             max(f) if f else None, max(w) if w else None)
+
+
+def _rdreq_bytes(counters):
+    """(read bytes, requests not in a size class) from the per-size request
+    counts of one kernel, or None without them."""
+    if not all(c in counters for c, _ in RDREQ_SIZES) or "TCC_EA0_RDREQ_sum" not in counters:
+        return None
+    sized = sum(counters[c] for c, _ in RDREQ_SIZES)
+    return sum(counters[c] * b for c, b in RDREQ_SIZES), counters["TCC_EA0_RDREQ_sum"] - sized
 
 
 def summarize_profiles(out_dir, prof_root):
@@ -261,6 +278,14 @@ def summarize_profiles(out_dir, prof_root):
         if not per:
             continue
         ff, fw, cf, cw = _copy_calibration(all_rows)
+        copy_k = [k for k in per if "probe_copy" in k]
+        copy_rd = _rdreq_bytes(per[copy_k[0]]) if copy_k else None
+        sized = False
+        for k in per:
+            rb = _rdreq_bytes(per[k])
+            if rb:
+                per[k]["rdreq_bytes"], per[k]["rdreq_unsized"] = rb
+                sized = True
         counters = sorted({c for k in per for c in per[k]})
         lines = [f"# Counters per dispatch: {TRACES.get(tag, (tag,))[0]}", ""] + [f"Command: `{c}`" for c in cmds] + [
             "", "Mean value per dispatch of each kernel (FETCH_SIZE / WRITE_SIZE in KiB; the SQ cycle counters "
@@ -269,6 +294,12 @@ def summarize_profiles(out_dir, prof_root):
             lines += [f"Copy calibration (a 256 MiB device copy that reads and writes 2^28 bytes): FETCH_SIZE "
                       f"{cf:.0f} KiB, WRITE_SIZE {cw:.0f} KiB, so HBM bytes = FETCH_SIZE x 1024 x {ff:.3f} and "
                       f"WRITE_SIZE x 1024 x {fw:.3f}.", ""]
+        if sized:
+            lines += ["Read bytes counted by request size: 32 x TCC_EA0_RDREQ_32B + 64 x TCC_EA0_RDREQ_64B + "
+                      "128 x TCC_EA0_RDREQ_128B per dispatch (`rdreq_bytes`, no scale factor; "
+                      "`rdreq_unsized` = requests outside the three classes)." +
+                      (f" On the calibration copy they give {copy_rd[0]:.6g} bytes against the 2^28 = "
+                       f"{float(1 << 28):.6g} it reads." if copy_rd else ""), ""]
         lines += ["| kernel | dispatches | " + " | ".join(counters) + " |", "|---|---|" + "---|" * len(counters)]
         for k in sorted(per, key=lambda k: -per[k].get("FETCH_SIZE", 0)):
             if "copy" in k.lower() or "fill" in k.lower():
@@ -283,13 +314,20 @@ def summarize_profiles(out_dir, prof_root):
             if cand:
                 k = max(cand, key=lambda k: calls[k])
                 m = _consume_config(k) or (None, None, None)
-                read_b, write_b = per[k]["FETCH_SIZE"] * 1024.0 * ff, per[k]["WRITE_SIZE"] * 1024.0 * fw
+                fetch_b, write_b = per[k]["FETCH_SIZE"] * 1024.0 * ff, per[k]["WRITE_SIZE"] * 1024.0 * fw
+                # reads: counted by request size where that pass ran, else FETCH_SIZE scaled by the copy
+                read_b = per[k].get("rdreq_bytes", fetch_b)
                 data = {"kernel": "merge_consume", "schedule": "planned", "kernel_name": k,
                         "workload": "powerlaw_m2M_zipf1.8_cap200k_empty10pct",
                         "kernel_source_hash": kernel_source_hash(), "block_size": m[0], "items_per_thread": m[1],
                         "x_bands": m[2], "long_min": None,
                         "fetch_kb_per_dispatch": per[k]["FETCH_SIZE"], "write_kb_per_dispatch": per[k]["WRITE_SIZE"],
                         "copy_calibration": {"fetch_factor": ff, "write_factor": fw},
+                        "read_bytes_source": "rdreq_by_size" if "rdreq_bytes" in per[k] else "fetch_size_scaled",
+                        "fetch_scaled_read_bytes_per_launch": fetch_b,
+                        "rdreq_by_size": {c: per[k].get(c) for c in ["TCC_EA0_RDREQ_sum"] +
+                                          [c for c, _ in RDREQ_SIZES]},
+                        "copy_rdreq_bytes": copy_rd[0] if copy_rd else None,
                         "hbm_read_bytes_per_launch": read_b, "hbm_write_bytes_per_launch": write_b,
                         "hbm_bytes_per_launch": read_b + write_b, "commands": cmds}
                 try:

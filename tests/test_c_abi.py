@@ -63,3 +63,54 @@ def test_bench_resume_needs_record():
     r = subprocess.run(["python", os.path.join(ROOT, "bench.py"), "--resume"], capture_output=True, text=True,
                        timeout=120)
     assert r.returncode == 2 and "--record" in r.stderr
+
+
+def test_profile_summary_counts_reads_by_request_size(tmp_path, monkeypatch):
+    """The counter summary turns the per-size L2 read requests into bytes
+    (32, 64 and 128 per request, no scale factor), checks them on the
+    calibration copy, and the headline's traffic record takes them as its
+    read bytes (FETCH_SIZE scaled by the copy stays beside them)."""
+    import csv
+    import importlib.util
+    import json
+
+    import synthetic
+
+    spec = importlib.util.spec_from_file_location("_bench", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    traffic = tmp_path / "traffic.json"
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(traffic))
+    monkeypatch.setattr(synthetic, "config_c2", lambda: (synthetic.config_c1()[0], None))
+    consume = "void lbk::merge_spmv_consume<128, 8, float, float, 2, false, 1, true>(int, int)"
+    copy = "lbk::probe_copy_kernel(float const*, float*, long)"
+    # the copy reads 2^28 bytes in 128-byte requests: FETCH_SIZE sees half
+    copy_vals = {"FETCH_SIZE": 131072.0, "WRITE_SIZE": 262144.0, "TCC_EA0_RDREQ_sum": 2.0 ** 21,
+                 "TCC_EA0_RDREQ_32B_sum": 0.0, "TCC_EA0_RDREQ_64B_sum": 0.0, "TCC_EA0_RDREQ_128B_sum": 2.0 ** 21}
+    cons_vals = {"FETCH_SIZE": 300000.0, "WRITE_SIZE": 20000.0, "TCC_EA0_RDREQ_sum": 5.0e6,
+                 "TCC_EA0_RDREQ_32B_sum": 1.0e6, "TCC_EA0_RDREQ_64B_sum": 3.0e6, "TCC_EA0_RDREQ_128B_sum": 0.9e6}
+    tag = "planned_spmv_powerlaw2M"
+    for i, cset in enumerate(bench.COUNTERS[tag][1]):
+        names = cset.split()
+        d = tmp_path / "prof" / f"{tag}_{i}" / "host"
+        d.mkdir(parents=True)
+        with open(d / "c_counter_collection.csv", "w", newline="") as f:
+            w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+            w.writeheader()
+            for kname, vals in ((copy, copy_vals), (consume, cons_vals)):
+                for c in names:
+                    for _ in range(3 if kname == consume else 1):
+                        w.writerow({"Kernel_Name": kname, "Counter_Name": c, "Counter_Value": vals.get(c, 1.0)})
+    bench.summarize_profiles(str(tmp_path / "profiles"), str(tmp_path / "prof"))
+    md = (tmp_path / "profiles" / f"{tag}_counters.md").read_text()
+    assert "On the calibration copy they give 2.68435e+08 bytes against the 2^28 = 2.68435e+08" in md
+    assert "rdreq_bytes" in md and "rdreq_unsized" in md
+    t = json.loads(traffic.read_text())
+    want_read = 32 * 1.0e6 + 64 * 3.0e6 + 128 * 0.9e6
+    assert t["read_bytes_source"] == "rdreq_by_size"
+    assert t["hbm_read_bytes_per_launch"] == want_read
+    assert t["fetch_scaled_read_bytes_per_launch"] == 300000.0 * 1024 * 2.0
+    assert t["hbm_write_bytes_per_launch"] == 20000.0 * 1024
+    assert t["hbm_bytes_per_launch"] == want_read + 20000.0 * 1024
+    assert t["copy_rdreq_bytes"] == 2.0 ** 28
+    assert t["kernel_source_hash"] == bench.kernel_source_hash()
