@@ -181,9 +181,10 @@ TRACES = {
                              "--graph-only --no-cpu"),
 }
 # L2-to-memory read requests by size (32, 64 and 128 bytes) and in total:
-# their byte sum is the read traffic counted without a scale factor
-# (FETCH_SIZE counts 128-byte requests through TCC_BUBBLE, which does not see
-# them on this chip, so it reads half a copy's bytes).
+# their byte sum counts the reads without a scale factor, which checks the
+# copy-derived FETCH_SIZE factor on each kernel (FETCH_SIZE counts 128-byte
+# requests through TCC_BUBBLE, which does not see them on this chip, so it
+# reads half a copy's bytes).
 RDREQ_SET = "TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum"
 RDREQ_SIZES = (("TCC_EA0_RDREQ_32B_sum", 32), ("TCC_EA0_RDREQ_64B_sum", 64), ("TCC_EA0_RDREQ_128B_sum", 128))
 
@@ -314,19 +315,19 @@ def summarize_profiles(out_dir, prof_root):
             if cand:
                 k = max(cand, key=lambda k: calls[k])
                 m = _consume_config(k) or (None, None, None)
-                fetch_b, write_b = per[k]["FETCH_SIZE"] * 1024.0 * ff, per[k]["WRITE_SIZE"] * 1024.0 * fw
-                # reads: counted by request size where that pass ran, else FETCH_SIZE scaled by the copy
-                read_b = per[k].get("rdreq_bytes", fetch_b)
+                read_b, write_b = per[k]["FETCH_SIZE"] * 1024.0 * ff, per[k]["WRITE_SIZE"] * 1024.0 * fw
+                # the copy-calibrated FETCH_SIZE, checked against the reads counted by request size
+                rd = per[k].get("rdreq_bytes")
                 data = {"kernel": "merge_consume", "schedule": "planned", "kernel_name": k,
                         "workload": "powerlaw_m2M_zipf1.8_cap200k_empty10pct",
                         "kernel_source_hash": kernel_source_hash(), "block_size": m[0], "items_per_thread": m[1],
                         "x_bands": m[2], "long_min": None,
                         "fetch_kb_per_dispatch": per[k]["FETCH_SIZE"], "write_kb_per_dispatch": per[k]["WRITE_SIZE"],
                         "copy_calibration": {"fetch_factor": ff, "write_factor": fw},
-                        "read_bytes_source": "rdreq_by_size" if "rdreq_bytes" in per[k] else "fetch_size_scaled",
-                        "fetch_scaled_read_bytes_per_launch": fetch_b,
                         "rdreq_by_size": {c: per[k].get(c) for c in ["TCC_EA0_RDREQ_sum"] +
                                           [c for c, _ in RDREQ_SIZES]},
+                        "rdreq_read_bytes_per_launch": rd,
+                        "rdreq_over_fetch_scaled": rd / read_b if rd else None,
                         "copy_rdreq_bytes": copy_rd[0] if copy_rd else None,
                         "hbm_read_bytes_per_launch": read_b, "hbm_write_bytes_per_launch": write_b,
                         "hbm_bytes_per_launch": read_b + write_b, "commands": cmds}

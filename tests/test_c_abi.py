@@ -67,9 +67,10 @@ def test_bench_resume_needs_record():
 
 def test_profile_summary_counts_reads_by_request_size(tmp_path, monkeypatch):
     """The counter summary turns the per-size L2 read requests into bytes
-    (32, 64 and 128 per request, no scale factor), checks them on the
-    calibration copy, and the headline's traffic record takes them as its
-    read bytes (FETCH_SIZE scaled by the copy stays beside them)."""
+    (32, 64 and 128 per request, no scale factor) and checks them on the
+    calibration copy; the headline's traffic record keeps FETCH_SIZE and
+    WRITE_SIZE scaled by the copy and reports the size-counted reads beside
+    them."""
     import csv
     import importlib.util
     import json
@@ -107,10 +108,11 @@ def test_profile_summary_counts_reads_by_request_size(tmp_path, monkeypatch):
     assert "rdreq_bytes" in md and "rdreq_unsized" in md
     t = json.loads(traffic.read_text())
     want_read = 32 * 1.0e6 + 64 * 3.0e6 + 128 * 0.9e6
-    assert t["read_bytes_source"] == "rdreq_by_size"
-    assert t["hbm_read_bytes_per_launch"] == want_read
-    assert t["fetch_scaled_read_bytes_per_launch"] == 300000.0 * 1024 * 2.0
+    fetch = 300000.0 * 1024 * 2.0  # the copy's FETCH_SIZE is half its bytes: factor 2
+    assert t["hbm_read_bytes_per_launch"] == fetch
+    assert t["rdreq_read_bytes_per_launch"] == want_read
+    assert abs(t["rdreq_over_fetch_scaled"] - want_read / fetch) < 1e-12
     assert t["hbm_write_bytes_per_launch"] == 20000.0 * 1024
-    assert t["hbm_bytes_per_launch"] == want_read + 20000.0 * 1024
+    assert t["hbm_bytes_per_launch"] == fetch + 20000.0 * 1024
     assert t["copy_rdreq_bytes"] == 2.0 ** 28
     assert t["kernel_source_hash"] == bench.kernel_source_hash()
