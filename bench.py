@@ -723,6 +723,8 @@ def main():
                                                          "long_min")}
                     traffic_cfg["unscaled_bytes"] = round((tr.get("fetch_kb_per_dispatch", 0) +
                                                            tr.get("write_kb_per_dispatch", 0)) * 1024)
+                    # the read bytes counted by request size, over the copy-scaled FETCH_SIZE
+                    traffic_cfg["rdreq_over_fetch_scaled"] = tr.get("rdreq_over_fetch_scaled")
             except (OSError, ValueError):
                 traffic = None
 
