@@ -891,16 +891,26 @@ def main():
         A1d = lb.CSR.from_host(A1, dev)
         x1d = torch.from_numpy(x1).to(dev)
         y1 = torch.empty(A1.m, dtype=torch.float32, device=dev)
-        small = {"m": A1.m, "nnz": A1.nnz, "note": "us per call, back to back; accuracy is asserted by the GPU tests"}
+        small = {"m": A1.m, "nnz": A1.nnz,
+                 "note": "us per call: eager back-to-back calls from Python (bound by the host's per-call work), "
+                         "and hip_graph_us: 100 calls captured in one HIP graph and replayed (the GPU's own time "
+                         "per call, launch gaps included); accuracy is asserted by the GPU tests",
+                 "hip_graph_us": {}}
+        calls = []
         for name, p in (("thread_mapped", {}), ("group_mapped", {"group_size": 64}),
                         ("group_mapped", {"group_size": 64, "tiles_per_group": 64}), ("merge_path", {})):
             ws1 = torch.empty(max(lb.workspace_size(A1d, name, **p), 1), dtype=torch.uint8, device=dev)
-            t = timed(lambda name=name, p=p, ws1=ws1: lb.spmv(A1d, x1d, name, y=y1, workspace=ws1, **p), 50, 10)
             key = name + ("" if not p else "_" + "_".join(f"{k}{v}" for k, v in p.items()))
-            small[key] = round(t * 1e3, 2)
+            calls.append((key, lambda name=name, p=p, ws1=ws1: lb.spmv(A1d, x1d, name, y=y1, workspace=ws1, **p)))
+        small["merge_path_units"] = {k: v for k, v in lb.resolve_schedule(A1d, "merge_path").items()
+                                     if k in ("block_size", "items_per_thread")}
         pl1 = lb.Plan(A1d)
         wsp1 = torch.empty(max(pl1.workspace_bytes, 1), dtype=torch.uint8, device=dev)
-        small["planned"] = round(timed(lambda: lb.spmv_planned(A1d, pl1, x1d, y=y1, workspace=wsp1), 50, 10) * 1e3, 2)
+        calls.append(("planned", lambda: lb.spmv_planned(A1d, pl1, x1d, y=y1, workspace=wsp1)))
+        for key, f in calls:
+            small[key] = round(timed(f, 50, 10) * 1e3, 2)
+            tg = graph_timed(f, y1, 100)
+            small["hip_graph_us"][key] = round(tg * 1e3, 2) if tg is not None else None
         result["uniform4096"] = small
         finish("uniform")
         log(f"[bench] uniform 4096: {small}")

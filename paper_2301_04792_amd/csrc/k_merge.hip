@@ -512,12 +512,6 @@ hipError_t launch_fixup(int64_t T, int32_t rows, int32_t kc, const int32_t *carr
 
 // ------------------------------------------------------------------ dispatch
 
-// Up to this many units a one-band lb_spmv runs as one launch whose blocks
-// find their own split and own whole rows (a row longer than a unit is
-// summed by the block where it closes, at most kSelfSplitUnits * W
-// nonzeros).
-constexpr int64_t kSelfSplitUnits = 256;  // one block per CU at most
-
 // The four-nonzero load form needs whole aligned groups: nnz >= 4, col_idx
 // 16-byte aligned and the values aligned to their 4-element vector.
 static bool vector_loads_ok(const csr_dev &A) {

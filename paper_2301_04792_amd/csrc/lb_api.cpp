@@ -316,6 +316,20 @@ lb_status_t resolve(const lb_csr_t *A, int32_t k, const lb_schedule_t *in, lb_sc
     if (st != LB_OK) return st;
     // column bands and vector loads: lb_spmv only
     if ((out->x_bands != 1 || out->vector_width != 1) && k != 1) return LB_ERR_UNSUPPORTED;
+    if (out->kind == LB_MERGE_PATH && k == 1 && s.block_size == 0 && s.items_per_thread == 0 && out->x_bands == 1 &&
+        out->vector_width == 1) {
+        // Default units on a small matrix: the shortest unit (128 x 4, 256 x 4
+        // or 256 x 8 items) that keeps the one-launch form (at most
+        // kSelfSplitUnits units) spreads the matrix over the most CUs, each
+        // block with less to load, sum and search before its first write.
+        for (const auto &bi : {std::pair<int, int>{128, 4}, {256, 4}, {256, 8}}) {
+            if (lbk::merge_units(A->rows, A->nnz, static_cast<int64_t>(bi.first) * bi.second) <= lbk::kSelfSplitUnits) {
+                out->block_size = bi.first;
+                out->items_per_thread = bi.second;
+                break;
+            }
+        }
+    }
     return LB_OK;
 }
 

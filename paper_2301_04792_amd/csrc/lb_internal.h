@@ -46,6 +46,11 @@ inline size_t align256(size_t b) { return (b + 255) & ~static_cast<size_t>(255);
 // ---- merge-path split ---------------------------------------------------------------
 // Work units of W merge items; T = ceil((rows + nnz) / W) units.
 inline int64_t merge_units(int64_t rows, int64_t nnz, int64_t W) { return (rows + nnz + W - 1) / W; }
+// Up to this many units a one-band lb_spmv runs as one launch whose blocks
+// find their own split and own whole rows (a row longer than a unit is
+// summed by the block where it closes, at most kSelfSplitUnits * W
+// nonzeros): one block per CU at most.
+constexpr int64_t kSelfSplitUnits = 256;
 
 // Workspace: part_i[T+1], part_j[T+1], carry_row[T], carry_val[T * kc].
 struct merge_ws {

@@ -21,7 +21,8 @@ int main(void)
     lb_csr_t A = {1000, 1000, 5000, fake, fake, fake, LB_F32};
     lb_schedule_t in = {LB_AUTO, 0, 0, 0, 0, 0}, out;
     CHECK(lb_resolve_schedule(&A, 1, &in, &out) == LB_OK);
-    CHECK(out.kind == LB_MERGE_PATH && out.block_size == 256 && out.items_per_thread == 8);
+    /* a small matrix (6000 merge items): the shortest default units, 128 x 4 */
+    CHECK(out.kind == LB_MERGE_PATH && out.block_size == 128 && out.items_per_thread == 4);
     size_t ws = 0;
     CHECK(lb_workspace_size(&A, &out, 1, &ws) == LB_OK && ws > 0);
     lb_schedule_t bad = {LB_GROUP_MAPPED, 3, 0, 0, 0, 0};

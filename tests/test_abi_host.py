@@ -515,3 +515,37 @@ def test_plan_build_host_checks():
     assert build(long_min=100) == _abi.ERR_INVALID_ARG            # below W = 256 x 8
     assert build(block_size=100) == _abi.ERR_UNSUPPORTED
     assert L.lb_spmv_plan_build(ctypes.byref(A), None, None, 0, None) == _abi.ERR_INVALID_ARG
+
+
+def test_small_matrix_default_units():
+    """Default merge-path units on a small matrix (lb_spmv, lb_spmm with one
+    column): the shortest of 128 x 4, 256 x 4, 256 x 8 items that gives at
+    most 256 units; explicit sizes, two bands, four-wide loads, several
+    columns and larger matrices keep 256 x 8."""
+    def units_of(A, s, k=1):
+        st, out = resolve(A, s, k)
+        assert st == _abi.OK
+        return out.block_size, out.items_per_thread
+
+    assert units_of(csr(4096, 4096, 64248), sched("merge_path")) == (128, 4)   # 134 units of 512
+    assert units_of(csr(50_000, 50_000, 80_000), sched("merge_path")) == (128, 4)  # 254 units
+    assert units_of(csr(50_000, 50_000, 90_000), sched("merge_path")) == (256, 4)  # 274 of 512, 137 of 1024
+    assert units_of(csr(100_000, 100_000, 400_000), sched("merge_path")) == (256, 8)  # 245 of 2048
+    assert units_of(csr(100_000, 100_000, 500_000), sched("merge_path")) == (256, 8)  # 293: three launches
+    assert units_of(csr(4096, 4096, 64248), sched("merge_path", block_size=512)) == (512, 8)
+    assert units_of(csr(4096, 4096, 64248), sched("merge_path", items_per_thread=12)) == (256, 12)
+    assert units_of(csr(4096, 4096, 64248), sched("merge_path", x_bands=2)) == (256, 8)
+    assert units_of(csr(4096, 4096, 64248), sched("merge_path", vector_width=4)) == (256, 8)
+    assert units_of(csr(4096, 4096, 64248), sched("merge_path"), k=8) == (256, 8)
+    assert units_of(csr(4096, 4096, 64248), sched("merge_path"), k=0) == (256, 8)
+    assert units_of(csr(1000, 1000, 20_000), sched("auto")) == (128, 4)  # the Sec. 6.2 rule picks merge path
+    # the workspace follows the resolved units
+    n = ctypes.c_size_t(0)
+    A = csr(4096, 4096, 64248)
+    assert _abi.load().lb_workspace_size(ctypes.byref(A), ctypes.byref(sched("merge_path")), 1, ctypes.byref(n)) \
+        == _abi.OK
+    m = ctypes.c_size_t(0)
+    assert _abi.load().lb_workspace_size(ctypes.byref(A), ctypes.byref(sched("merge_path", block_size=128,
+                                                                             items_per_thread=4)), 1,
+                                         ctypes.byref(m)) == _abi.OK
+    assert n.value == m.value
