@@ -532,3 +532,37 @@ def test_hip_graph_replays_match_eager(name, params):
         assert torch.equal(z, 2 * eager) or np.allclose(z.cpu().numpy(), 2 * eager.cpu().numpy(), rtol=1e-5, atol=1e-6)
     ref, scale = oracle_spmv(A, x)
     assert_rows_close(eager.cpu().numpy(), ref, scale, what=f"graph {name}")
+
+
+def _sized_matrix(seed, items, long_row):
+    """rows + nnz == items: rows of 3 nonzeros, one row of `long_row`
+    nonzeros (longer than several units) in the middle, and the last row
+    taking what is left over."""
+    rows = (items - long_row) // 4
+    lengths = [3] * rows
+    lengths[rows // 2] = long_row
+    lengths[-1] += items - rows - sum(lengths)
+    return SC._from_lengths(seed, lengths, 200_000)
+
+
+@pytest.mark.parametrize("items,units", [(131_072, (128, 4)), (131_073, (256, 4)), (262_144, (256, 4)),
+                                         (262_145, (256, 8)), (524_288, (256, 8)), (524_289, (256, 8))])
+def test_small_matrix_default_units_at_the_bounds(items, units):
+    """The default merge-path units of a small matrix at the bounds of the
+    rule: exactly 256 units of 512, 1024 or 2048 items (one launch, 256
+    blocks, a row longer than several units summed by the block where it
+    closes), and one item past each bound; against the oracle, and the same
+    result for the explicit units."""
+    A, x = _sized_matrix(71, items, 5000)
+    assert A.m + A.nnz == items
+    Ad, xd = upload(A, x)
+    r = lb.resolve_schedule(Ad, "merge_path")
+    assert (r["block_size"], r["items_per_thread"]) == units
+    print(f"[default units: items={items} units={units} T={-(-items // (units[0] * units[1]))}]", flush=True)
+    y = lb.spmv(Ad, xd, "merge_path")
+    ref, scale = oracle_spmv(A, x)
+    assert_rows_close(y.cpu().numpy(), ref, scale, what=f"items={items}")
+    ye = lb.spmv(Ad, xd, "merge_path", block_size=units[0], items_per_thread=units[1])
+    assert torch.equal(y, ye)
+    Y = lb.spmm(Ad, xd.reshape(-1, 1))  # lb_spmm with one column resolves the same units
+    assert_rows_close(Y.cpu().numpy()[:, 0], ref, scale, what=f"spmm k=1 items={items}")
