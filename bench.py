@@ -200,7 +200,7 @@ COUNTERS = {
                                  "TCP_PENDING_STALL_CYCLES_sum TCP_TCC_READ_REQ_sum", RDREQ_SET]),
     "fwd_bwd_powerlaw1M": ("--only fwdbwd --no-cpu --steps 3 --pmc-calib",
                            ["FETCH_SIZE", "WRITE_SIZE", "TCC_ATOMIC_sum TCC_EA0_ATOMIC_sum",
-                            "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY"]),
+                            "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY", RDREQ_SET]),
     "batched512": ("--only batched --no-cpu --steps 3 --pmc-calib",
                    ["FETCH_SIZE", "WRITE_SIZE", "TCC_HIT_sum TCC_MISS_sum",
                     "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_ACTIVE_INST_LDS",
@@ -208,7 +208,7 @@ COUNTERS = {
     "bf16_laplacian_powerlaw2M": ("--only bf16 --no-cpu --steps 3 --pmc-calib",
                                   ["FETCH_SIZE", "WRITE_SIZE", "TCC_HIT_sum TCC_MISS_sum",
                                    "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY "
-                                   "SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_SALU"]),
+                                   "SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_SALU", RDREQ_SET]),
 }
 
 
