@@ -107,9 +107,8 @@ typedef struct lb_csr_t {
  *                    both are 0 in lb_spmv or lb_spmm with k = 1 (one column
  *                    band), a matrix with rows + nnz <= 256 * 2048 gets the
  *                    shortest unit of 128 x 4, 256 x 4 and 256 x 8 items
- *                    that gives at most 256 units (lb_spmv runs those
- *                    as one launch);
- *                    lb_resolve_schedule reports the choice.  SpMM
+ *                    that gives at most 256 units, which lb_spmv runs as
+ *                    one launch; lb_resolve_schedule reports the choice.  SpMM
  *                    and batched passes take up to 8 columns of X at a
  *                    time, fewer for large block_size * items_per_thread;
  *                    group-mapped derived from group_size (ignored).
