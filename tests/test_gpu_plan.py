@@ -342,3 +342,53 @@ def test_planned_in_hip_graph(cfg):
         assert torch.equal(z, 2 * eager), (cfg, rep)  # scaling x by 2 is exact
     ref, scale = oracle_spmv(A, x)
     assert_rows_close(eager.cpu().numpy(), ref, scale, what=f"graph {cfg}")
+
+
+
+def _banded(seed, n, half, fill):
+    """n x n, row r holding a random `fill` share of the columns
+    [r - half, r + half] (at least its diagonal), sorted."""
+    rng = np.random.default_rng(seed)
+    cols, ro = [], [0]
+    for r in range(n):
+        lo, hi = max(0, r - half), min(n, r + half + 1)
+        c = np.flatnonzero(rng.random(hi - lo) < fill) + lo
+        if c.size == 0:
+            c = np.array([r])
+        cols.append(c)
+        ro.append(ro[-1] + c.size)
+    ci = np.concatenate(cols).astype(np.int32)
+    vals = rng.uniform(-1, 1, ci.size).astype(np.float32)
+    return SC.CSRHost(np.asarray(ro, np.int32), ci, vals, (n, n)), rng.uniform(-1, 1, n).astype(np.float32)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16], ids=["f32", "bf16"])
+@pytest.mark.parametrize("mname", ["grid300", "band40", "band9000"])
+@pytest.mark.parametrize("bi", [(256, 12), (128, 16), (512, 8)], ids=["256x12", "128x16", "512x8"])
+def test_planned_four_wide_bit_equal_to_one_wide(dtype, mname, bi):
+    """A four-nonzero plan loads aligned groups of four per lane, masks the
+    neighbours outside its units and places each product at its nonzero's
+    LDS slot; the one-nonzero plan over the same units places the same
+    products at the same slots and sums them in the same order, so the two
+    give the same y bit for bit (stencil, narrow and wide bands, three unit
+    shapes), and both match the oracle."""
+    if mname == "grid300":
+        A, x = S.laplacian_5pt(81, 300)
+    elif mname == "band40":
+        A, x = _banded(82, 40_000, 40, 0.3)
+    else:
+        A, x = _banded(83, 12_000, 4500, 0.002)
+    if dtype == torch.bfloat16:
+        A = A.with_values(S.to_bf16_bits(A.values))
+        x = S.to_bf16_bits(x)
+    Ad, xd = upload(A, x, dtype)
+    b, i = bi
+    p4 = lb.Plan(Ad, block_size=b, items_per_thread=i, x_bands=1, vector_width=4)
+    p1 = lb.Plan(Ad, block_size=b, items_per_thread=i, x_bands=1, vector_width=1)
+    print(f"[four-wide vs one-wide {mname} {bi} {dtype}] {p4.info}", flush=True)
+    assert p4.c.vector_width == 4 and p1.c.vector_width == 1 and p4.c.active_units == p1.c.active_units
+    y4 = lb.spmv_planned(Ad, p4, xd)
+    y1 = lb.spmv_planned(Ad, p1, xd)
+    assert torch.equal(y4, y1)
+    ref, scale = oracle_spmv(A, x)
+    assert_rows_close(y4.cpu().numpy(), ref, scale, what=f"{mname} {bi}")
